@@ -1,0 +1,333 @@
+"""Pins of the CPU oracle against things other than itself: closed forms,
+hand-worked examples, brute force on tiny inputs, invariants and library
+routines (matching, MILP).  CPU only."""
+import os
+import itertools
+
+import numpy as np
+import pytest
+from hypothesis import given, settings, strategies as st
+
+import instances as I
+from oracle import brute, tm, ve, value, semiring, device_ops, crt, config
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+# ----------------------------------------------------------------- semiring laws
+elem = st.tuples(st.integers(-20, 20), st.integers(0, 5))
+
+
+def _norm(x):
+    return (None, 0) if x[1] == 0 else x
+
+
+@settings(max_examples=200, deadline=None)
+@given(elem, elem, elem)
+def test_semiring_laws(a, b, c):
+    op, ot = semiring.oplus, semiring.otimes
+    assert _norm(op(a, b)) == _norm(op(b, a))
+    assert _norm(op(op(a, b), c)) == _norm(op(a, op(b, c)))
+    assert _norm(ot(ot(a, b), c)) == _norm(ot(a, ot(b, c)))
+    assert _norm(ot(a, op(b, c))) == _norm(op(ot(a, b), ot(a, c)))
+    assert _norm(op(a, semiring.ZERO)) == _norm(a)
+    assert _norm(ot(a, semiring.ONE)) == _norm(a)
+    assert _norm(ot(a, semiring.ZERO)) == (None, 0)
+
+
+# ----------------------------------------------------------------- closed forms
+def _lattice(L, Jval):
+    g = I.spin_glass_square(L, 0)
+    g["J"] = np.full_like(g["J"], Jval)
+    return g
+
+
+@pytest.mark.parametrize("solver", ["brute", "tm", "ve"])
+def test_ferromagnet_and_antiferromagnet(solver):
+    for Jval in (1, -1):           # the square lattice is bipartite
+        g = _lattice(4, Jval)
+        if solver == "brute":
+            r = brute.spin_glass(g["n"], g["edges"], g["J"])[:2]
+        elif solver == "tm":
+            r = tm.spin_glass_square(g)
+        else:
+            r = ve.spin_glass(g["n"], g["edges"], g["J"])
+        assert r == (-24, 2)
+
+
+@pytest.mark.parametrize("neg", [[3], [0], [0, 1, 2]])
+def test_frustrated_plaquette(neg):
+    edges = [(0, 1), (1, 3), (3, 2), (2, 0)]
+    J = [(-1 if i in neg else 1) for i in range(4)]
+    assert brute.spin_glass(4, edges, J)[:2] == (-2, 8)
+    assert ve.spin_glass(4, edges, J) == (-2, 8)
+
+
+def test_tree_any_couplings():
+    rng = np.random.default_rng(5)
+    n = 12
+    edges = [(i, int(rng.integers(0, i))) for i in range(1, n)]
+    J = rng.choice([-2, -1, 1, 3], size=n - 1)
+    e0 = -int(np.abs(J).sum())
+    assert brute.spin_glass(n, edges, J)[:2] == (e0, 2)
+    assert ve.spin_glass(n, edges, J) == (e0, 2)
+
+
+def test_strong_field_unique():
+    g = I.spin_glass_square(3, 1)
+    h = np.full(g["n"], int(np.abs(g["J"]).sum()) + 1)
+    e0, deg, arg = brute.spin_glass(g["n"], g["edges"], g["J"], h)
+    assert deg == 1 and np.all(arg == 1)
+    assert ve.spin_glass(g["n"], g["edges"], g["J"], h) == (e0, 1)
+    assert tm.spin_glass_lattice(3, 3, g["edges"], g["J"], h) == (e0, 1)
+
+
+def test_mis_closed_forms():
+    for n in range(1, 9):
+        assert brute.mwis(n, np.zeros((0, 2)), None)[:2] == (n, 1)
+        assert ve.mwis(n, np.zeros((0, 2), int)) == (n, 1)
+        kn = list(itertools.combinations(range(n), 2))
+        if kn:
+            assert brute.mwis(n, kn)[:2] == (1, n)
+            assert ve.mwis(n, kn) == (1, n)
+    for n in range(2, 12):
+        path = [(i, i + 1) for i in range(n - 1)]
+        want = ((n + 1) // 2, 1) if n % 2 else (n // 2, n // 2 + 1)
+        assert brute.mwis(n, path)[:2] == want
+        assert ve.mwis(n, path) == want
+    for n in range(3, 12):
+        cyc = [(i, (i + 1) % n) for i in range(n)]
+        want = (n // 2, 2) if n % 2 == 0 else ((n - 1) // 2, n)
+        assert brute.mwis(n, cyc)[:2] == want
+        assert ve.mwis(n, cyc) == want
+
+
+@pytest.mark.parametrize("L", [3, 5, 7])
+def test_full_kings_odd(L):
+    g = I.full_kings_graph(L)
+    assert g["n"] == L * L
+    want = (((L + 1) // 2) ** 2, 1)
+    assert tm.kings_subgraph(g) == want
+    assert ve.mwis(g["n"], g["edges"]) == want
+    if L <= 3:
+        assert brute.mwis(g["n"], g["edges"])[:2] == want
+
+
+# ----------------------------------------------------- exact solvers vs brute force
+@pytest.mark.parametrize("seed", range(5))
+def test_sg_4x4_three_ways(seed):
+    g = I.spin_glass_square(4, seed)
+    b = brute.spin_glass(g["n"], g["edges"], g["J"])
+    assert tm.spin_glass_square(g) == b[:2]
+    assert ve.spin_glass(g["n"], g["edges"], g["J"]) == b[:2]
+    assert config.spin_glass_energy(b[2], g["edges"], g["J"]) == b[0]
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_sg_rect_with_field(seed):
+    g = I.spin_glass_rect(4, 5, seed)
+    h = np.random.default_rng(seed).integers(-1, 2, size=g["n"])
+    b = brute.spin_glass(g["n"], g["edges"], g["J"], h)
+    assert tm.spin_glass_lattice(4, 5, g["edges"], g["J"], h) == b[:2]
+    assert ve.spin_glass(g["n"], g["edges"], g["J"], h) == b[:2]
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_ksg_small_three_ways(seed):
+    g = I.kings_subgraph(5, seed)
+    b = brute.mwis(g["n"], g["edges"], g["w"])
+    assert tm.kings_subgraph(g) == b[:2]
+    assert ve.mwis(g["n"], g["edges"], g["w"]) == b[:2]
+    assert config.independent_set_weight(b[2], g["edges"], g["w"]) == b[0]
+
+
+def test_weighted_ksg():
+    g = I.kings_subgraph(4, 3, weights="1..10")
+    b = brute.mwis(g["n"], g["edges"], g["w"])
+    assert tm.kings_subgraph(g) == b[:2]
+    assert ve.mwis(g["n"], g["edges"], g["w"]) == b[:2]
+
+
+def test_random_graphs_ve_vs_brute():
+    rng = np.random.default_rng(11)
+    for trial in range(4):
+        n = 14
+        edges = [(i, j) for i in range(n) for j in range(i + 1, n) if rng.random() < 0.25]
+        J = rng.choice([-1, 1], size=len(edges))
+        assert ve.spin_glass(n, edges, J) == brute.spin_glass(n, edges, J)[:2]
+        assert ve.mwis(n, edges) == brute.mwis(n, edges)[:2]
+
+
+# ------------------------------------------------------------------ invariants
+@pytest.mark.parametrize("seed", range(3))
+def test_sg_invariants_8x8(seed):
+    g = I.spin_glass_square(8, seed)
+    e0, deg = tm.spin_glass_square(g)
+    m = len(g["J"])
+    assert deg % 2 == 0                     # Z2 spin-flip symmetry at h = 0
+    assert (e0 - m) % 2 == 0                # E0 = -|E| + 2 * (#broken bonds)
+    # each frustrated plaquette needs a broken bond; a bond borders <= 2 of them
+    L = 8
+    Jm = {(int(a), int(b)): int(j) for (a, b), j in zip(g["edges"], g["J"])}
+    F = 0
+    for r in range(L - 1):
+        for c in range(L - 1):
+            p = r * L + c
+            neg = sum(Jm[e] < 0 for e in [(p, p + 1), (p + L, p + L + 1), (p, p + L), (p + 1, p + L + 1)])
+            F += neg % 2
+    assert e0 >= -m + 2 * ((F + 1) // 2)
+    # gauge invariance J'_ij = tau_i J_ij tau_j
+    tau = np.random.default_rng(100 + seed).choice([-1, 1], size=g["n"])
+    Jg = g["J"] * tau[g["edges"][:, 0]] * tau[g["edges"][:, 1]]
+    assert tm.spin_glass_lattice(L, L, g["edges"], Jg) == (e0, deg)
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_sg_value_matches_matching(seed):
+    for L in (8, 12):
+        g = I.spin_glass_square(L, seed)
+        e0, _ = tm.spin_glass_square(g)
+        assert value.spin_glass_planar_e0(L, g["edges"], g["J"]) == e0
+
+
+def test_sg_value_matches_milp_with_field():
+    g = I.spin_glass_rect(5, 6, 2)
+    h = np.random.default_rng(2).integers(-2, 3, size=g["n"])
+    e0, _ = tm.spin_glass_lattice(5, 6, g["edges"], g["J"], h)
+    assert value.spin_glass_milp(g["n"], g["edges"], g["J"], h) == e0
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_ksg_value_matches_milp(seed):
+    for L in (8, 12):
+        g = I.kings_subgraph(L, seed)
+        w, cnt = tm.kings_subgraph(g)
+        assert value.mwis_milp(g["n"], g["edges"], g["w"]) == w
+        assert cnt >= 1
+
+
+# --------------------------------------------------------- device-encoding ops
+def _read_hand_tgemm():
+    rows = {}
+    with open(os.path.join(GOLDEN, "tgemm_hand.txt")) as f:
+        for line in f:
+            if line.startswith("#") or not line.strip():
+                continue
+            key, *vals = line.split()
+            rows[key] = vals
+    p = int(rows["p"][0])
+
+    def parse(items):
+        v, c = [], []
+        for it in items:
+            a, b = it.split(",")
+            v.append(device_ops.NEG if a == "NEG" else int(a))
+            c.append(int(b))
+        return np.array(v, np.int64).reshape(2, 2), np.array(c, np.uint64).reshape(2, 2)
+    return p, parse(rows["A"]), parse(rows["B"]), parse(rows["C"])
+
+
+def test_tgemm_hand_example():
+    p, (Av, Ac), (Bv, Bc), (Cv, Cc) = _read_hand_tgemm()
+    gv, gr = device_ops.tgemm(Av[None], Ac[None, None], Bv[None], Bc[None, None], [p])
+    assert np.array_equal(gv[0], Cv) and np.array_equal(gr[0, 0], Cc)
+
+
+def _tgemm_loops(Av, Ar, Bv, Br, primes):
+    """Exact counts with Python integers and explicit loops (no modulus
+    until the end)."""
+    nb, M, K = Av.shape
+    N = Bv.shape[2]
+    outv = np.zeros((nb, M, N), np.int64)
+    outc = [[[None] * N for _ in range(M)] for _ in range(nb)]
+    for b in range(nb):
+        for m in range(M):
+            for n in range(N):
+                best, cnt = None, [0] * len(primes)
+                for q in range(K):
+                    a, bb = int(Av[b, m, q]), int(Bv[b, q, n])
+                    if a <= device_ops.NEG_CUT or bb <= device_ops.NEG_CUT or a + bb <= device_ops.NEG_CUT:
+                        continue
+                    prods = [int(Ar[i, b, m, q]) * int(Br[i, b, q, n]) for i in range(len(primes))]
+                    if best is None or a + bb > best:
+                        best, cnt = a + bb, prods
+                    elif a + bb == best:
+                        cnt = [x + y for x, y in zip(cnt, prods)]
+                outv[b, m, n] = device_ops.NEG if best is None else best
+                outc[b][m][n] = [0] * len(primes) if best is None else [x % p for x, p in zip(cnt, primes)]
+    return outv, outc
+
+
+@pytest.mark.parametrize("shape", [(1, 3, 4, 5), (2, 4, 3, 7), (3, 1, 1, 9)])
+def test_tgemm_vs_loops(shape):
+    nb, M, N, K = shape
+    primes = I.PRIMES_31[:3]
+    Av, Ar = I.random_entries((nb, M, K), 3, seed=1, vrange=3)
+    Bv, Br = I.random_entries((nb, K, N), 3, seed=2, vrange=3)
+    gv, gr = device_ops.tgemm(Av, Ar, Bv, Br, primes)
+    lv, lc = _tgemm_loops(Av, Ar, Bv, Br, primes)
+    assert np.array_equal(gv, lv)
+    for b in range(nb):
+        for m in range(M):
+            for n in range(N):
+                assert [int(gr[i, b, m, n]) for i in range(3)] == lc[b][m][n]
+
+
+def test_tgemm_identity_and_associativity():
+    primes = I.PRIMES_31[:2]
+    Av, Ar = I.random_entries((1, 4, 6), 2, seed=3)
+    # tropical identity: (0, 1) on the diagonal, zero elsewhere
+    Iv = np.full((1, 4, 4), device_ops.NEG, np.int32)
+    Ir = np.zeros((2, 1, 4, 4), np.uint32)
+    for d in range(4):
+        Iv[0, d, d] = 0
+        Ir[:, 0, d, d] = 1
+    gv, gr = device_ops.tgemm(Iv, Ir, Av, Ar, primes)
+    assert np.array_equal(gv, Av) and np.array_equal(gr, Ar)
+    Bv, Br = I.random_entries((1, 6, 5), 2, seed=4)
+    Cv, Cr = I.random_entries((1, 5, 3), 2, seed=5)
+    ABv, ABr = device_ops.tgemm(Av, Ar, Bv, Br, primes)
+    BCv, BCr = device_ops.tgemm(Bv, Br, Cv, Cr, primes)
+    l = device_ops.tgemm(ABv, ABr, Cv, Cr, primes)
+    r = device_ops.tgemm(Av, Ar, BCv, BCr, primes)
+    assert np.array_equal(l[0], r[0]) and np.array_equal(l[1], r[1])
+
+
+def test_gather_definition():
+    # tensor over 3 variables, entry = flat index
+    flat = np.arange(8)
+    # identity
+    assert np.array_equal(device_ops.gather(flat, 3, [0, 1, 2]), flat)
+    # output var j = input var src[j]: swap vars 0 and 2
+    out = device_ops.gather(flat, 3, [2, 1, 0])
+    want = [((i >> 2) & 1) | (((i >> 1) & 1) << 1) | ((i & 1) << 2) for i in range(8)]
+    assert list(out) == want
+    # fix input var 1 to 1; output vars = (input 2, input 0)
+    out = device_ops.gather(flat, 3, [2, 0], fixed={1: 1})
+    want = [(((i >> 0) & 1) << 2) | (1 << 1) | (((i >> 1) & 1) << 0) for i in range(4)]
+    assert list(out) == want
+
+
+def test_reduce_and_merge():
+    primes = I.PRIMES_31[:2]
+    v, r = I.random_entries((16,), 2, seed=9, vrange=2)
+    ov, orr = device_ops.reduce_bits((v, r), 4, primes, [1, 3])
+    for o in range(4):
+        b0, b2 = o & 1, (o >> 1) & 1
+        members = [i for i in range(16) if (i & 1) == b0 and ((i >> 2) & 1) == b2]
+        mv, mr = device_ops.merge(v[members], r[:, members], primes)
+        assert ov[o] == mv and list(orr[:, o]) == mr
+    full = device_ops.reduce_bits((v, r), 4, primes, [0, 1, 2, 3])
+    mv, mr = device_ops.merge(v, r, primes)
+    assert full[0][0] == mv and list(full[1][:, 0]) == mr
+
+
+# ------------------------------------------------------------------------- CRT
+def test_crt_round_trip():
+    rng = np.random.default_rng(0)
+    primes = I.PRIMES_31[:4]
+    M = 1
+    for p in primes:
+        M *= p
+    for x in [0, 1, 2, M - 1, M // 3] + [int(rng.integers(0, 2**62)) * int(rng.integers(0, 2**60)) % M for _ in range(50)]:
+        assert crt.crt([x % p for p in primes], primes) == x
