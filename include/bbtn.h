@@ -1,0 +1,228 @@
+/*
+ * bbtn.h -- C ABI of the branch-and-bound tensor network (BBTN) hot path on
+ * one AMD Instinct MI355X (gfx950).
+ *
+ * The method (Wang, Gao, Zhang, Pan, Liu, "Branch-and-Bound Tensor Networks
+ * for Exact Ground-State Characterization", arXiv:2602.05470):
+ *   - the ground energy of the spin glass of Eq. 1, or the maximum weight of
+ *     an independent set (MWIS paragraph of the "Tropical Tensor Networks"
+ *     section), is the tropical contraction of Eq. 2;
+ *   - its degeneracy is obtained by carrying a count with every entry (the
+ *     counting tuple algebra of the same section);
+ *   - a network too large for memory is split by fixing variables into
+ *     sub-networks whose results are tropically summed ("Branch-and-Bound
+ *     Tensor Network" section, Eq. 3-4 and the characteristic equation).
+ *
+ * Conventions shared by every entry point
+ *   - All functions return bbtn_status; nothing throws across the ABI.
+ *   - The caller owns every input and output buffer.  The library copies what
+ *     it needs before returning and never frees caller memory.  The context
+ *     owns its device workspace and frees it in bbtn_destroy.
+ *   - One context per host thread; different contexts are independent.
+ *   - Device encoding of an entry of the counting tropical algebra, max form:
+ *     an int32 value v and k residues c_i in [0, p_i) of its count.  The
+ *     tropical zero ("minus infinity", the paper's (inf, 0) tuple read in max
+ *     form) is stored as v = BBTN_NEG with every residue 0.  Every other value
+ *     must satisfy |v| < 2^28.  The sum keeps the larger value and adds the
+ *     counts on a tie; the product adds values and multiplies counts.
+ *   - Spin glasses are solved in max form on the negated energy: the device
+ *     value is -H and the reported E0 is minus the maximum.
+ *   - A tensor over r binary variables has 2^r entries; bit j of the flat
+ *     index is the state of the tensor's j-th variable.  A "tensor buffer"
+ *     with E entries and k residues is (1 + k) * E consecutive 32-bit words:
+ *     the int32 value plane, then residue plane 0, ..., residue plane k-1.
+ *   - Residues are taken modulo primes p with 2^31 - 2^20 < p < 2^31 (every
+ *     prime the library picks, and every prime a caller passes, must lie in
+ *     this range: the kernels reduce 64-bit sums with 2^32 mod p < 2^21).
+ */
+#ifndef BBTN_H
+#define BBTN_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define BBTN_NEG (-(1 << 30))      /* stored tropical zero (max form)      */
+#define BBTN_NEG_CUT (-(1 << 29))  /* any value <= this is the tropical zero */
+#define BBTN_MAX_PRIMES 32
+#define BBTN_MAX_RESIDUES 4        /* residues per pass (k) */
+
+typedef enum {
+  BBTN_OK = 0,
+  BBTN_E_INVALID_ARG = -1,       /* bad size, pointer, vertex id, prime ... */
+  BBTN_E_OOM = -2,               /* device or host allocation failed        */
+  BBTN_E_DEVICE = -3,            /* a HIP call failed                       */
+  BBTN_E_COUNT_UNCERTIFIED = -4, /* count not certified within max_primes   */
+  BBTN_E_TIMEOUT = -5,           /* time_limit_s exceeded                   */
+  BBTN_E_BUFFER_TOO_SMALL = -6,  /* count_capacity < count_words            */
+  BBTN_E_INTERNAL = -7
+} bbtn_status;
+
+typedef struct bbtn_ctx bbtn_ctx;
+
+/* Solver options.  Fill with bbtn_default_options, then override. */
+typedef struct {
+  int32_t device;            /* HIP device ordinal                              */
+  int32_t residues_per_pass; /* k in [1, 4]: residues carried per entry         */
+  int32_t max_primes;        /* certification adds passes up to this many primes */
+  int32_t log2_target;       /* log2 T_target of Eq. 4 (entries of the largest
+                                intermediate tensor); <= 0: no branching        */
+  int32_t branching;         /* 0: contract the whole network (no branching);
+                                1: plain planner; 2: learned scorer orders the
+                                branching region (falls back to 1 without
+                                weights)                                        */
+  int32_t batched;           /* 0: per-branch step-by-step launches;
+                                1: all branch sub-networks in one persistent
+                                   work-queue launch where they fit             */
+  int32_t region_max;        /* largest branching region |R| (<= 16)            */
+  int32_t local_search;      /* > 0: seed the incumbent of global pruning with
+                                this many local-search sweeps                   */
+  const char* scorer_weights;/* path of learned-scorer weights, or NULL         */
+  const char* autotune_cache;/* path of the tile autotuner cache, or NULL       */
+  double time_limit_s;       /* <= 0: none                                      */
+  void* stream;              /* hipStream_t to run on, or NULL for the
+                                context's own stream                           */
+} bbtn_options;
+
+/* Result of a solve.  `count` and `config` are caller-owned. */
+typedef struct {
+  int64_t value;       /* spin glass: E0 = min H; MWIS: max total weight       */
+  int32_t n_primes;    /* primes used, and count residues modulo each          */
+  uint32_t primes[BBTN_MAX_PRIMES];
+  uint32_t residues[BBTN_MAX_PRIMES];
+  int32_t certified;   /* 1 iff the CRT count was confirmed by an extra prime  */
+  int32_t count_words; /* 32-bit words of the exact count (always set)         */
+  uint32_t* count;     /* caller buffer, little-endian words, or NULL          */
+  int32_t count_capacity;
+  int8_t* config;      /* caller buffer [n] or NULL: one optimal configuration,
+                          sigma in {-1,+1} (spin glass) or x in {0,1} (MWIS)   */
+  uint64_t leaves;     /* branch sub-networks contracted                       */
+  uint64_t pruned;     /* branches discarded by global pruning                 */
+  uint64_t nodes;      /* search-tree nodes expanded                           */
+  uint64_t macs;       /* semiring multiply-accumulates on the device          */
+  double seconds[8];   /* [0] total [1] build+plan [2] search [3] contraction
+                          [4] CRT+certification [5] configuration [6] H2D/D2H  */
+} bbtn_result;
+
+void bbtn_default_options(bbtn_options* opt);
+
+/* Create a context on opt->device.  *out is set on success. */
+bbtn_status bbtn_create(const bbtn_options* opt, bbtn_ctx** out);
+void bbtn_destroy(bbtn_ctx* ctx);
+
+/* Message for the last failing call on ctx (valid until the next call). */
+const char* bbtn_last_error(const bbtn_ctx* ctx);
+
+/*
+ * Spin glass of Eq. 1: H(sigma) = sum_E -J_ij s_i s_j + sum_V -h_i s_i.
+ * n spins, m edges; edge_uv[2m] holds vertex ids in [0, n); J[m]; h[n] or
+ * NULL (zero field).  Duplicate edges are merged by adding their couplings.
+ * Self-loops, ids outside [0, n), or sum|J| + sum|h| >= 2^27 give
+ * BBTN_E_INVALID_ARG.  Fills value = E0, the degeneracy (count) and one
+ * ground configuration.  Host pointers.
+ */
+bbtn_status bbtn_solve_spinglass(bbtn_ctx* ctx, int32_t n, int32_t m,
+                                 const int32_t* edge_uv, const int32_t* J,
+                                 const int32_t* h, bbtn_result* res);
+
+/*
+ * Maximum weight independent set (MWIS paragraph): max sum_{i in S} w_i over
+ * independent sets S.  w[n] positive or NULL (unit weights).  Duplicate edges
+ * are ignored.  Fills value = W*, the number of optimal sets and one of them.
+ * Host pointers.
+ */
+bbtn_status bbtn_solve_mwis(bbtn_ctx* ctx, int32_t n, int32_t m,
+                            const int32_t* edge_uv, const int32_t* w,
+                            bbtn_result* res);
+
+/* ------------------------------------------------------------------------
+ * Kernel-level entry points (device pointers, caller-owned; run on `stream`
+ * (hipStream_t) or the context's stream when NULL; asynchronous).
+ * primes: host array [k]; every p in (2^31 - 2^20, 2^31).
+ * ---------------------------------------------------------------------- */
+
+/*
+ * Counting tropical matrix product (Eq. 2 applied to one pairwise
+ * contraction):  C[b,m,n] = (+)_q A[b,m,q] (.) B[b,q,n].
+ * A: tensor buffer of batch*M*K entries, row-major [batch][M][K];
+ * B: batch*K*N entries, [batch][K][N];  C: batch*M*N entries, [batch][M][N].
+ * k in [1, 4]; K >= 1.  C may not alias A or B.
+ */
+bbtn_status bbtn_tgemm(bbtn_ctx* ctx, int32_t k, const uint32_t* primes,
+                       int64_t batch, int64_t M, int64_t N, int64_t K,
+                       const void* A, const void* B, void* C, void* stream);
+
+/*
+ * Permutation and branch-variable fixing of a tensor (slicing,
+ * T|_{s_Vf = x} of Eq. 3), batched over L outputs.
+ * Input: tensor buffer of in_entries entries over r_in variables (in_entries
+ * = 2^r_in when in_stride == 0, or L * 2^r_in when in_stride == 2^r_in, i.e.
+ * one input per output).  Output: tensor buffer of L * 2^r_out entries.
+ * Output variable j is input variable src_bits[j] (host array [r_out]).
+ * Input variables not named in src_bits are fixed: their states are the bits
+ * of fixed_bits[l] (device array [L] of uint64, already placed at the input
+ * bit positions; NULL means all zero).
+ * Output entry (l, i) = input entry (l * in_stride) + sum_j bit_j(i) <<
+ * src_bits[j] | fixed_bits[l].
+ */
+bbtn_status bbtn_gather(bbtn_ctx* ctx, int32_t k, int32_t r_in, int32_t r_out,
+                        const int32_t* src_bits, int64_t L, int64_t in_stride,
+                        const uint64_t* fixed_bits, const void* in,
+                        int64_t in_entries, void* out, void* stream);
+
+/*
+ * Tropical sum over segments (sum-out of variables, merge of branch
+ * results): out[o] = (+)_{s < S} in[s * seg_stride + o * elem_stride] for
+ * o < outer.  in: tensor buffer of in_entries entries; out: outer entries.
+ */
+bbtn_status bbtn_reduce(bbtn_ctx* ctx, int32_t k, const uint32_t* primes,
+                        int64_t outer, int64_t S, int64_t seg_stride,
+                        int64_t elem_stride, const void* in, int64_t in_entries,
+                        void* out, void* stream);
+
+/*
+ * Branch bounds for global pruning: for each branch b < n_branch,
+ * bound[b] = offset[b] + sum over its tensors of the largest finite value;
+ * keep[b] = 1 iff every tensor has a finite entry and bound[b] >= incumbent
+ * (ties are kept: they carry counts).  Tensor t of branch b is the slice
+ * [tensor_off[b*T + t], tensor_off[b*T + t] + tensor_len[b*T + t]) of the
+ * int32 value array `values`; T = tensors_per_branch.  All device pointers.
+ * *n_keep (device int32) receives the number of kept branches and
+ * keep_idx[0..n_keep) their indices in ascending order.
+ */
+bbtn_status bbtn_bound(bbtn_ctx* ctx, int64_t n_branch, int32_t tensors_per_branch,
+                       const int32_t* values, const int64_t* tensor_off,
+                       const int32_t* tensor_len, const int64_t* offset,
+                       int64_t incumbent, int64_t* bound, int32_t* keep_idx,
+                       int32_t* n_keep, void* stream);
+
+/* Semiring multiply-accumulates performed by the last solve on ctx. */
+uint64_t bbtn_last_macs(const bbtn_ctx* ctx);
+
+/* ------------------------------------------------------------------------
+ * Kernel timing.  When enabled, HIP events are recorded on the launch stream
+ * around every launch of the kernels below, and their durations, launch
+ * counts and algorithmic work are accumulated.  Enabling or disabling clears
+ * the counters.  Kernel ids: 0 counting tropical product (bbtn_tgemm and the
+ * step-by-step executor), 1 persistent work-queue executor, 2 gather
+ * (permutation / slicing), 3 segmented reduction (not instrumented yet).
+ * ops: semiring operations, (2 + 2k) per multiply-accumulate (one value add
+ * and one max, one modular multiply and one modular add per residue).
+ * bytes: algorithmic bytes (operands read once + results written once).
+ * ---------------------------------------------------------------------- */
+typedef struct {
+  uint64_t launches;
+  double seconds;
+  double ops;
+  double bytes;
+} bbtn_kernel_stats;
+
+bbtn_status bbtn_profile(bbtn_ctx* ctx, int32_t enable);
+bbtn_status bbtn_get_kernel_stats(bbtn_ctx* ctx, int32_t kernel, bbtn_kernel_stats* out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* BBTN_H */

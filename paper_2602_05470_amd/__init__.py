@@ -1,0 +1,290 @@
+"""Python binding of libbbtn (include/bbtn.h): argument marshalling only.
+
+Every step of the branch-and-bound tensor network path runs in the HIP
+library; this module converts arguments (numpy arrays, torch device tensors,
+streams) into the plain pointers and sizes of the C ABI.  Importing it does
+not load the library; the first call does, and fails loudly if the built
+library is missing.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass, field
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libbbtn.so")
+
+NEG = -(1 << 30)
+NEG_CUT = -(1 << 29)
+MAX_PRIMES = 32
+
+STATUS = {0: "OK", -1: "INVALID_ARG", -2: "OOM", -3: "DEVICE", -4: "COUNT_UNCERTIFIED",
+          -5: "TIMEOUT", -6: "BUFFER_TOO_SMALL", -7: "INTERNAL"}
+
+
+class BBTNError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__("%s (%d): %s" % (STATUS.get(status, "?"), status, msg))
+        self.status = status
+
+
+class _Options(C.Structure):
+    _fields_ = [("device", C.c_int32), ("residues_per_pass", C.c_int32),
+                ("max_primes", C.c_int32), ("log2_target", C.c_int32),
+                ("branching", C.c_int32), ("batched", C.c_int32),
+                ("region_max", C.c_int32), ("local_search", C.c_int32),
+                ("scorer_weights", C.c_char_p), ("autotune_cache", C.c_char_p),
+                ("time_limit_s", C.c_double), ("stream", C.c_void_p)]
+
+
+class _Result(C.Structure):
+    _fields_ = [("value", C.c_int64), ("n_primes", C.c_int32),
+                ("primes", C.c_uint32 * MAX_PRIMES), ("residues", C.c_uint32 * MAX_PRIMES),
+                ("certified", C.c_int32), ("count_words", C.c_int32),
+                ("count", C.POINTER(C.c_uint32)), ("count_capacity", C.c_int32),
+                ("config", C.POINTER(C.c_int8)), ("leaves", C.c_uint64),
+                ("pruned", C.c_uint64), ("nodes", C.c_uint64), ("macs", C.c_uint64),
+                ("seconds", C.c_double * 8)]
+
+
+_lib = None
+
+EXPORTS = ["bbtn_default_options", "bbtn_create", "bbtn_destroy", "bbtn_last_error",
+           "bbtn_solve_spinglass", "bbtn_solve_mwis", "bbtn_tgemm", "bbtn_gather",
+           "bbtn_reduce", "bbtn_bound", "bbtn_last_macs", "bbtn_profile",
+           "bbtn_get_kernel_stats"]
+
+
+class _KStats(C.Structure):
+    _fields_ = [("launches", C.c_uint64), ("seconds", C.c_double), ("ops", C.c_double),
+                ("bytes", C.c_double)]
+
+
+KERNELS = {"tgemm": 0, "persist": 1, "gather": 2, "reduce": 3}
+
+
+def load(path: str = LIB_PATH):
+    """Load the built library (raises if it is missing)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError("libbbtn.so is not built (%s); run __graft_entry__.build()" % path)
+    lib = C.CDLL(path)
+    P, I32, I64, U64 = C.c_void_p, C.c_int32, C.c_int64, C.c_uint64
+    lib.bbtn_default_options.argtypes = [C.POINTER(_Options)]
+    lib.bbtn_default_options.restype = None
+    lib.bbtn_create.argtypes = [C.POINTER(_Options), C.POINTER(P)]
+    lib.bbtn_create.restype = I32
+    lib.bbtn_destroy.argtypes = [P]
+    lib.bbtn_destroy.restype = None
+    lib.bbtn_last_error.argtypes = [P]
+    lib.bbtn_last_error.restype = C.c_char_p
+    lib.bbtn_last_macs.argtypes = [P]
+    lib.bbtn_last_macs.restype = U64
+    lib.bbtn_solve_spinglass.argtypes = [P, I32, I32, P, P, P, C.POINTER(_Result)]
+    lib.bbtn_solve_spinglass.restype = I32
+    lib.bbtn_solve_mwis.argtypes = [P, I32, I32, P, P, C.POINTER(_Result)]
+    lib.bbtn_solve_mwis.restype = I32
+    lib.bbtn_tgemm.argtypes = [P, I32, P, I64, I64, I64, I64, P, P, P, P]
+    lib.bbtn_tgemm.restype = I32
+    lib.bbtn_gather.argtypes = [P, I32, I32, I32, P, I64, I64, P, P, I64, P, P]
+    lib.bbtn_gather.restype = I32
+    lib.bbtn_reduce.argtypes = [P, I32, P, I64, I64, I64, I64, P, I64, P, P]
+    lib.bbtn_reduce.restype = I32
+    lib.bbtn_bound.argtypes = [P, I64, I32, P, P, P, P, I64, P, P, P, P]
+    lib.bbtn_bound.restype = I32
+    lib.bbtn_profile.argtypes = [P, I32]
+    lib.bbtn_profile.restype = I32
+    lib.bbtn_get_kernel_stats.argtypes = [P, I32, C.POINTER(_KStats)]
+    lib.bbtn_get_kernel_stats.restype = I32
+    _lib = lib
+    return lib
+
+
+@dataclass
+class Options:
+    """Mirror of bbtn_options (see include/bbtn.h)."""
+    device: int = 0
+    residues_per_pass: int = 3
+    max_primes: int = 16
+    log2_target: int = 0
+    branching: int = 1
+    batched: int = 1
+    region_max: int = 8
+    local_search: int = 200
+    scorer_weights: str | None = None
+    autotune_cache: str | None = None
+    time_limit_s: float = 0.0
+    stream: int | None = None
+
+    def _c(self):
+        o = _Options()
+        load().bbtn_default_options(C.byref(o))
+        for f in ("device", "residues_per_pass", "max_primes", "log2_target", "branching",
+                  "batched", "region_max", "local_search", "time_limit_s"):
+            setattr(o, f, getattr(self, f))
+        o.scorer_weights = self.scorer_weights.encode() if self.scorer_weights else None
+        o.autotune_cache = self.autotune_cache.encode() if self.autotune_cache else None
+        o.stream = self.stream
+        return o
+
+
+@dataclass
+class Result:
+    value: int
+    count: int
+    certified: bool
+    primes: list
+    residues: list
+    config: np.ndarray
+    leaves: int
+    pruned: int
+    nodes: int
+    macs: int
+    seconds: list = field(default_factory=list)
+
+
+def _i32(a):
+    return np.ascontiguousarray(np.asarray(a, dtype=np.int32))
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data_as(C.c_void_p)
+
+
+def _stream(s):
+    """hipStream_t for a kernel-level call: the given stream (torch stream or
+    int handle), else torch's current stream when torch is in use."""
+    if s is None:
+        import sys
+        torch = sys.modules.get("torch")
+        if torch is not None and torch.cuda.is_available():
+            return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+        return None
+    if isinstance(s, int):
+        return C.c_void_p(s)
+    return C.c_void_p(s.cuda_stream)
+
+
+def _dptr(t):
+    """Device pointer of a torch tensor (or an int address)."""
+    if t is None:
+        return None
+    if isinstance(t, int):
+        return C.c_void_p(t)
+    return C.c_void_p(t.data_ptr())
+
+
+class Context:
+    """bbtn_ctx: a device context with its workspace and stream."""
+
+    def __init__(self, options: Options | None = None):
+        self.lib = load()
+        self.options = options or Options()
+        self._o = self.options._c()
+        h = C.c_void_p()
+        s = self.lib.bbtn_create(C.byref(self._o), C.byref(h))
+        if s != 0:
+            raise BBTNError(s, "bbtn_create failed")
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.bbtn_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def _check(self, s):
+        if s != 0:
+            raise BBTNError(s, self.lib.bbtn_last_error(self.h).decode())
+
+    def last_macs(self):
+        return int(self.lib.bbtn_last_macs(self.h))
+
+    def profile(self, enable=True):
+        """bbtn_profile: start (and clear) or stop per-kernel event timing."""
+        self._check(self.lib.bbtn_profile(self.h, 1 if enable else 0))
+
+    def kernel_stats(self, kernel):
+        """bbtn_get_kernel_stats: dict(launches, seconds, ops, bytes)."""
+        st = _KStats()
+        self._check(self.lib.bbtn_get_kernel_stats(self.h, KERNELS.get(kernel, kernel), C.byref(st)))
+        return dict(launches=int(st.launches), seconds=st.seconds, ops=st.ops, bytes=st.bytes)
+
+    # -------------------------------------------------------------- solves
+    def _solve(self, fn, n, edges, *arrays, raise_uncertified=True):
+        edges = _i32(edges).reshape(-1, 2)
+        r = _Result()
+        cap = (n + 64) // 32 + 2
+        cnt = (C.c_uint32 * cap)()
+        cfg = np.zeros(n, dtype=np.int8)
+        r.count = C.cast(cnt, C.POINTER(C.c_uint32))
+        r.count_capacity = cap
+        r.config = cfg.ctypes.data_as(C.POINTER(C.c_int8))
+        arrs = [None if a is None else _i32(a) for a in arrays]
+        s = fn(self.h, n, len(edges), _ptr(edges), *[_ptr(a) for a in arrs], C.byref(r))
+        if s != 0 and not (s == -4 and not raise_uncertified):
+            self._check(s)
+        count = 0
+        for i in reversed(range(r.count_words)):
+            count = (count << 32) | int(cnt[i])
+        return Result(value=int(r.value), count=count, certified=bool(r.certified),
+                      primes=[int(r.primes[i]) for i in range(r.n_primes)],
+                      residues=[int(r.residues[i]) for i in range(r.n_primes)],
+                      config=cfg, leaves=int(r.leaves), pruned=int(r.pruned),
+                      nodes=int(r.nodes), macs=int(r.macs), seconds=list(r.seconds))
+
+    def solve_spinglass(self, n, edges, J, h=None, **kw) -> Result:
+        """bbtn_solve_spinglass: E0 = min H (Eq. 1), exact degeneracy, one
+        ground configuration (sigma in {-1,+1})."""
+        return self._solve(self.lib.bbtn_solve_spinglass, n, edges, J, h, **kw)
+
+    def solve_mwis(self, n, edges, w=None, **kw) -> Result:
+        """bbtn_solve_mwis: W*, number of maximum-weight independent sets,
+        one of them (x in {0,1})."""
+        return self._solve(self.lib.bbtn_solve_mwis, n, edges, w, **kw)
+
+    # ------------------------------------------------------- kernel entries
+    def tgemm(self, k, primes, batch, M, N, K, A, B, Cout, stream=None):
+        """bbtn_tgemm on device tensor buffers (torch tensors, int32 words)."""
+        pr = (C.c_uint32 * k)(*[int(p) for p in primes[:k]])
+        self._check(self.lib.bbtn_tgemm(self.h, k, pr, batch, M, N, K, _dptr(A), _dptr(B),
+                                        _dptr(Cout), _stream(stream)))
+
+    def gather(self, k, r_in, r_out, src_bits, L, in_stride, fixed_bits, inp, in_entries, out,
+               stream=None):
+        """bbtn_gather (permutation + branch-variable fixing)."""
+        sb = (C.c_int32 * max(1, r_out))(*[int(b) for b in src_bits])
+        self._check(self.lib.bbtn_gather(self.h, k, r_in, r_out, sb, L, in_stride,
+                                         _dptr(fixed_bits), _dptr(inp), in_entries, _dptr(out),
+                                         _stream(stream)))
+
+    def reduce(self, k, primes, outer, S, seg_stride, elem_stride, inp, in_entries, out,
+               stream=None):
+        """bbtn_reduce (segmented tropical sum)."""
+        pr = (C.c_uint32 * k)(*[int(p) for p in primes[:k]])
+        self._check(self.lib.bbtn_reduce(self.h, k, pr, outer, S, seg_stride, elem_stride,
+                                         _dptr(inp), in_entries, _dptr(out), _stream(stream)))
+
+    def bound(self, n_branch, T, values, tensor_off, tensor_len, offset, incumbent, bound,
+              keep_idx, n_keep, stream=None):
+        """bbtn_bound (branch bounds + compaction of kept branches)."""
+        self._check(self.lib.bbtn_bound(self.h, n_branch, T, _dptr(values), _dptr(tensor_off),
+                                        _dptr(tensor_len), _dptr(offset), int(incumbent),
+                                        _dptr(bound), _dptr(keep_idx), _dptr(n_keep),
+                                        _stream(stream)))

@@ -1,0 +1,66 @@
+// The opaque context behind bbtn_ctx: device, stream, workspace, caches.
+#pragma once
+#include <map>
+#include <string>
+#include <tuple>
+#include "common.h"
+#include "prof.h"
+
+namespace bbtn {
+
+// Growable device allocation (contents are not preserved on growth).
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  void ensure(size_t b) {
+    if (b <= bytes) return;
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    bytes = 0;
+    size_t want = std::max<size_t>(b, 1 << 20);
+    hipError_t e = hipMalloc(&p, want);
+    if (e != hipSuccess) {
+      p = nullptr;
+      (void)hipGetLastError();
+      throw Error(BBTN_E_OOM, "device allocation of " + std::to_string(want) + " bytes failed");
+    }
+    bytes = want;
+  }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    bytes = 0;
+  }
+  template <class T>
+  T* as() const { return (T*)p; }
+};
+
+// Autotuner key: residues, log2 of (batch, M, N, K) buckets.
+using TuneKey = std::tuple<int, int, int, int, int>;
+struct TuneVal {
+  int cfg;
+  int splits;
+};
+
+}  // namespace bbtn
+
+struct bbtn_ctx {
+  bbtn_options opt;
+  std::string err;
+  hipStream_t own = nullptr;
+  hipStream_t stream = nullptr;
+  bbtn::DevBuf work;      // step-program workspace
+  bbtn::DevBuf partial;   // split-K partials
+  bbtn::DevBuf base;      // base tensors of the current pass
+  bbtn::DevBuf fixbits;   // per-branch fixed bits of base operands
+  bbtn::DevBuf leafconst; // per-branch folded constants
+  bbtn::DevBuf leafout;   // per-branch results
+  bbtn::DevBuf misc;      // small scratch (merge outputs, traceback)
+  bbtn::DevBuf persist;   // persistent executor programs and scratch
+  uint64_t last_macs = 0;
+  std::map<bbtn::TuneKey, bbtn::TuneVal> tune;
+  bool tune_loaded = false;
+  std::vector<std::vector<float>> scorer;  // learned scorer weights (host copy)
+  bool scorer_loaded = false;
+  bbtn::Prof prof;         // kernel timing (off unless enabled)
+};

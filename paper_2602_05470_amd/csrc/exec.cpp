@@ -1,0 +1,176 @@
+#include "exec.h"
+
+#include <cstring>
+
+namespace bbtn {
+
+void upload_base(bbtn_ctx* ctx, const Network& net, const int* prime_idx, int k, BaseDev& bd,
+                 DevBuf& buf) {
+  bd.k = k;
+  bd.off.resize(net.tensors.size());
+  int64_t total = 0;
+  for (size_t i = 0; i < net.tensors.size(); ++i) {
+    bd.off[i] = total;
+    total += net.tensors[i].size();
+  }
+  bd.total = std::max<int64_t>(total, 1);
+  std::vector<uint32_t> host((size_t)(1 + k) * bd.total, 0);
+  for (size_t i = 0; i < net.tensors.size(); ++i) {
+    const BaseTensor& T = net.tensors[i];
+    for (int64_t e = 0; e < T.size(); ++e) {
+      host[bd.off[i] + e] = (uint32_t)T.val[e];
+      for (int p = 0; p < k; ++p)
+        host[(size_t)(p + 1) * bd.total + bd.off[i] + e] = T.res[(size_t)prime_idx[p] * T.size() + e];
+    }
+  }
+  buf.ensure(host.size() * 4);
+  BBTN_HIP(hipMemcpyAsync(buf.p, host.data(), host.size() * 4, hipMemcpyHostToDevice, ctx->stream));
+  BBTN_HIP(hipStreamSynchronize(ctx->stream));
+  bd.t = DevTensor{buf.as<uint32_t>(), bd.total};
+}
+
+static int ilog2_bucket(int64_t x) {
+  int b = 0;
+  while ((1ll << (b + 1)) <= x) ++b;
+  return b;
+}
+
+TuneVal choose_tiles(bbtn_ctx* ctx, int k, int64_t batch, int64_t M, int64_t N, int64_t K) {
+  const TuneKey key{k, std::min(ilog2_bucket(batch), 20), ilog2_bucket(M), ilog2_bucket(N),
+                    ilog2_bucket(K)};
+  auto it = ctx->tune.find(key);
+  if (it != ctx->tune.end()) return it->second;
+  TuneVal tv{2, 1};
+  if (M == 1 && N >= 64) tv.cfg = 5;
+  else if (N == 1 && M >= 64) tv.cfg = 6;
+  else if (M >= 64 && N >= 64) tv.cfg = 0;
+  else if (M >= 32 && N >= 32) tv.cfg = 1;
+  else if (M <= 8 && N >= 64) tv.cfg = 3;
+  else if (N <= 8 && M >= 64) tv.cfg = 4;
+  const TileCfg& c = kTileCfgs[tv.cfg];
+  const int64_t tiles = ((M + c.tm - 1) / c.tm) * ((N + c.tn - 1) / c.tn) * batch;
+  if (tiles < 1024 && K >= 256) {
+    int64_t sp = std::min<int64_t>(K / 64, (2048 + tiles - 1) / tiles);
+    tv.splits = (int)std::max<int64_t>(1, std::min<int64_t>(sp, 256));
+  }
+  return tv;
+}
+
+void leaf_constants(const Network& net, const GroupPlan& g, const int* prime_idx, int k,
+                    const uint8_t* assign, int64_t L, std::vector<uint32_t>& host) {
+  const auto& P = prime_table();
+  const size_t S = g.fixed_vars.size();
+  host.assign((size_t)(1 + k) * L, 0);
+  std::vector<int> pos_of(net.n, -1);
+  for (size_t j = 0; j < S; ++j) pos_of[g.fixed_vars[j]] = (int)j;
+  for (int64_t l = 0; l < L; ++l) {
+    int64_t v = 0;
+    uint32_t r[KMAX];
+    for (int p = 0; p < k; ++p) r[p] = 1;
+    bool feas = true;
+    for (int t : g.folded) {
+      const BaseTensor& T = net.tensors[t];
+      int64_t e = 0;
+      for (size_t j = 0; j < T.vars.size(); ++j) e |= (int64_t)(assign[l * S + pos_of[T.vars[j]]] & 1) << j;
+      if (T.val[e] <= NEG_CUT) { feas = false; break; }
+      v += T.val[e];
+      for (int p = 0; p < k; ++p)
+        r[p] = mulmod(r[p], T.res[(size_t)prime_idx[p] * T.size() + e], P[prime_idx[p]]);
+    }
+    host[l] = (uint32_t)(feas ? (int32_t)v : NEG);
+    for (int p = 0; p < k; ++p) host[(size_t)(p + 1) * L + l] = feas ? r[p] : 0u;
+  }
+}
+
+void run_group(bbtn_ctx* ctx, const Network& net, const GroupPlan& g, const BaseDev& bd,
+               const Moduli& mod, const uint8_t* assign, int64_t L, DevTensor out,
+               hipStream_t st) {
+  const int k = bd.k;
+  const int W = 1 + k;  // words per entry
+  const size_t S = g.fixed_vars.size();
+  // workspace
+  ctx->work.ensure((size_t)W * L * std::max<int64_t>(g.peak, 1) * 4);
+  uint32_t* ws = ctx->work.as<uint32_t>();
+  auto buf = [&](int id) {
+    return DevTensor{ws + (size_t)W * L * g.buf_off[id], L * g.buf_entries[id]};
+  };
+  // fixed bits of every base operand for every branch
+  std::vector<int> pos_of(net.n, -1);
+  for (size_t j = 0; j < S; ++j) pos_of[g.fixed_vars[j]] = (int)j;
+  const size_t nbo = g.base_ops.size();
+  std::vector<uint64_t> fb(std::max<size_t>(nbo, 1) * L, 0);
+  for (size_t i = 0; i < nbo; ++i) {
+    const Step& s = g.steps[g.base_ops[i].first];
+    const Operand& op = g.base_ops[i].second == 0 ? s.a : s.b;
+    for (int64_t l = 0; l < L; ++l) {
+      uint64_t bits = 0;
+      for (auto& fp : op.fixed_pos) bits |= (uint64_t)(assign[l * S + pos_of[fp.second]] & 1) << fp.first;
+      fb[i * L + l] = bits;
+    }
+  }
+  ctx->fixbits.ensure(fb.size() * 8);
+  BBTN_HIP(hipMemcpyAsync(ctx->fixbits.p, fb.data(), fb.size() * 8, hipMemcpyHostToDevice, st));
+  // folded constants per branch
+  std::vector<uint32_t> lc;
+  std::vector<int> pidx(k);
+  for (int p = 0; p < k; ++p) {
+    // recover prime-table indices from the moduli
+    const auto& P = prime_table();
+    pidx[p] = (int)(std::find(P.begin(), P.end(), mod.p[p]) - P.begin());
+  }
+  leaf_constants(net, g, pidx.data(), k, assign, L, lc);
+  ctx->leafconst.ensure(lc.size() * 4);
+  BBTN_HIP(hipMemcpyAsync(ctx->leafconst.p, lc.data(), lc.size() * 4, hipMemcpyHostToDevice, st));
+  BBTN_HIP(hipStreamSynchronize(st));  // host staging vectors die with this scope
+  const DevTensor lconst{ctx->leafconst.as<uint32_t>(), L};
+
+  for (const Step& s : g.steps) {
+    DevTensor opnd[2];
+    const Operand* ops[2] = {&s.a, &s.b};
+    const int ranks[2] = {(int)s.a_vars.size(), (int)s.b_vars.size()};
+    for (int w = 0; w < 2; ++w) {
+      const Operand& op = *ops[w];
+      if (op.base) {
+        const GatherPlan gp = make_gather_plan(op.r_in, ranks[w], op.src_bits.data());
+        const DevTensor src{bd.t.ptr + bd.off[op.id], bd.total};
+        const int ph = ctx->prof.begin(st);
+        launch_gather(k, gp, L, 0, ctx->fixbits.as<uint64_t>() + (size_t)op.base_op * L, src,
+                      buf(op.temp), st);
+        ctx->prof.end(ph, st, K_GATHER, 0, 2.0 * W * 4 * (double)(L << ranks[w]));
+        opnd[w] = buf(op.temp);
+      } else if (!op.direct) {
+        const GatherPlan gp = make_gather_plan(op.r_in, ranks[w], op.src_bits.data());
+        const int ph = ctx->prof.begin(st);
+        launch_gather(k, gp, L, 1ll << op.r_in, nullptr, buf(op.id), buf(op.temp), st);
+        ctx->prof.end(ph, st, K_GATHER, 0, 2.0 * W * 4 * (double)(L << ranks[w]));
+        opnd[w] = buf(op.temp);
+      } else {
+        opnd[w] = buf(op.id);
+      }
+    }
+    const int64_t M = 1ll << s.rm, N = 1ll << s.rn, K = 1ll << s.rk;
+    const int64_t batch = L << s.rb;
+    GemmShape sh{batch, M, N, K, M * K, K * N, M * N};
+    const TuneVal tv = choose_tiles(ctx, k, batch, M, N, K);
+    DevTensor part{};
+    if (tv.splits > 1) {
+      const int64_t ent = (int64_t)tv.splits * batch * M * N;
+      ctx->partial.ensure((size_t)W * ent * 4);
+      part = DevTensor{ctx->partial.as<uint32_t>(), ent};
+    }
+    const int ph = ctx->prof.begin(st);
+    launch_tgemm(k, mod, sh, opnd[0], opnd[1], buf(s.out), tv.cfg, tv.splits, part, st);
+    ctx->prof.end(ph, st, K_TGEMM, (double)L * s.macs() * (2 + 2 * k),
+                  (double)W * 4 * (double)batch * (double)(M * K + K * N + M * N));
+    ctx->last_macs += (uint64_t)(L * s.macs());
+  }
+  if (g.root_buf >= 0) {
+    launch_otimes(k, mod, L, buf(g.root_buf), lconst, out, st);
+  } else {
+    // the whole sub-network folded into constants: copy them
+    const GatherPlan id = make_gather_plan(0, 0, nullptr);
+    launch_gather(k, id, L, 1, nullptr, lconst, out, st);
+  }
+}
+
+}  // namespace bbtn

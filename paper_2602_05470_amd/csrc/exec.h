@@ -1,0 +1,36 @@
+// Running step programs on the device.
+#pragma once
+#include <vector>
+#include "ctx.h"
+#include "kernels.h"
+#include "plan.h"
+
+namespace bbtn {
+
+// Base tensors of a network uploaded with the residues of `k` primes
+// (indices into prime_table()).
+struct BaseDev {
+  int k = 0;
+  std::vector<int64_t> off;  // entry offset of every base tensor
+  int64_t total = 0;         // entries
+  DevTensor t;
+};
+void upload_base(bbtn_ctx* ctx, const Network& net, const int* prime_idx, int k,
+                 BaseDev& bd, DevBuf& buf);
+
+// Pick a tile configuration (and split-K factor) for one product.
+TuneVal choose_tiles(bbtn_ctx* ctx, int k, int64_t batch, int64_t M, int64_t N, int64_t K);
+
+// Run the program `g` for L branches.  assign[l * |S| + j] is the state of
+// the j-th fixed variable (ascending ids) of branch l.  Writes, for every
+// branch, root (.) folded constant into `out` (tensor buffer of L entries).
+// With keep_all the workspace keeps every operand (values only, k = 0).
+void run_group(bbtn_ctx* ctx, const Network& net, const GroupPlan& g, const BaseDev& bd,
+               const Moduli& mod, const uint8_t* assign, int64_t L, DevTensor out,
+               hipStream_t st);
+
+// Per-branch folded constants on the host: value and k residues.
+void leaf_constants(const Network& net, const GroupPlan& g, const int* prime_idx, int k,
+                    const uint8_t* assign, int64_t L, std::vector<uint32_t>& host);
+
+}  // namespace bbtn

@@ -1,0 +1,315 @@
+// Counting tropical matrix product on the VALU (max form):
+//   C[b,m,n] = (+)_q A[b,m,q] (.) B[b,q,n]
+// where (.) adds values and multiplies counts and (+) keeps the larger value
+// and adds the counts of ties (Eq. 2 with the counting tuple algebra of the
+// "Tropical Tensor Networks" section).  This is not a ring product, so the
+// matrix cores do not apply; the work is integer VALU arithmetic.
+//
+// Two passes over K per output tile:
+//   1. values only: V[m,n] = max_q (a.v + b.v)   (one add + one max per MAC)
+//   2. counts: for every q with a.v + b.v == V, add a.c_i * b.c_i into a
+//      64-bit accumulator per residue with v_mad_u64_u32 (full rate on
+//      gfx950); the accumulator is folded with one more multiply-add every
+//      three terms (x = hi * 2^32 + lo == hi * (2^32 mod p) + lo) and reduced
+//      to [0, p) once at the end.
+// Operands are staged through LDS in TK-deep slices, transposed so that each
+// thread reads its RM (RN) consecutive rows (columns) of a slice.  Workgroups
+// are remapped so that each XCD works on a contiguous range of tiles (tiles
+// sharing rows of A land in the same L2).
+#include "kernels.h"
+
+namespace bbtn {
+
+const TileCfg kTileCfgs[N_TILE_CFGS] = {
+    {64, 64, 4, 4, 16},   // 0: large tiles, 256 threads
+    {32, 32, 2, 2, 16},   // 1: medium, 256 threads
+    {16, 16, 1, 1, 16},   // 2: small, 256 threads
+    {8, 64, 1, 2, 16},    // 3: few rows, 256 threads
+    {64, 8, 2, 1, 16},    // 4: few columns, 256 threads
+    {1, 256, 1, 1, 16},   // 5: one row (vector-matrix), 256 threads
+    {256, 1, 1, 1, 16},   // 6: one column (matrix-vector), 256 threads
+};
+
+struct GemmArgs {
+  const uint32_t* A;
+  const uint32_t* B;
+  uint32_t* C;
+  int64_t pA, pB, pC;        // plane strides (words)
+  int64_t M, N, K, batch;
+  int64_t sAb, sBb, sCb;     // batch strides (elements)
+  int64_t sCsplit;           // stride between split-K partial outputs
+  int64_t kchunk;            // K range per split
+  int64_t splits;
+  int64_t tiles_m, tiles_n;
+  Moduli mod;
+};
+
+__device__ __forceinline__ uint64_t fold64(uint64_t x, uint32_t c) {
+  return (uint64_t)(uint32_t)(x >> 32) * c + (uint32_t)x;
+}
+
+// x < 2^64  ->  x mod p, for 2^31 - 2^20 < p < 2^31 and c = 2^32 mod p < 2^21.
+// Four folds bring x below 2^32 + 2^23 < 3p; two conditional subtractions
+// finish.
+__device__ __forceinline__ uint32_t mod_final(uint64_t x, uint32_t p, uint32_t c) {
+  x = fold64(x, c);
+  x = fold64(x, c);
+  x = fold64(x, c);
+  x = fold64(x, c);
+  x = x >= p ? x - p : x;
+  x = x >= p ? x - p : x;
+  return (uint32_t)x;
+}
+
+// Workgroup w runs on XCD w % 8; give each XCD a contiguous block of tiles.
+__device__ __forceinline__ int64_t xcd_remap(int64_t w, int64_t G) {
+  const int64_t per = G / 8, rem = G % 8;
+  const int64_t xcd = w % 8, local = w / 8;
+  return xcd < rem ? xcd * (per + 1) + local
+                   : rem * (per + 1) + (xcd - rem) * per + local;
+}
+
+template <int KR, int TM, int TN, int RM, int RN, int TK>
+__global__ void __launch_bounds__((TM / RM) * (TN / RN))
+tgemm_kernel(const GemmArgs a) {
+  constexpr int TX = TN / RN;
+  constexpr int TY = TM / RM;
+  constexpr int NT = TX * TY;
+  constexpr int KP = KR > 0 ? KR : 1;
+  __shared__ int32_t Av[TK][TM];
+  __shared__ int32_t Bv[TK][TN];
+  __shared__ uint32_t Ac[KP][TK][TM];
+  __shared__ uint32_t Bc[KP][TK][TN];
+
+  int64_t t = xcd_remap(blockIdx.x, gridDim.x);
+  const int64_t tn_i = t % a.tiles_n;
+  t /= a.tiles_n;
+  const int64_t tm_i = t % a.tiles_m;
+  t /= a.tiles_m;
+  const int64_t sp = t % a.splits;
+  const int64_t b = t / a.splits;
+  const int64_t m0 = tm_i * TM, n0 = tn_i * TN;
+  const int64_t kbeg = sp * a.kchunk;
+  const int64_t kend = min(a.K, kbeg + a.kchunk);
+  const int tid = threadIdx.x;
+  const int tx = tid % TX, ty = tid / TX;
+  const uint32_t* Ab = a.A + b * a.sAb;
+  const uint32_t* Bb = a.B + b * a.sBb;
+
+  int32_t V[RM][RN];
+#pragma unroll
+  for (int r = 0; r < RM; ++r)
+#pragma unroll
+    for (int c = 0; c < RN; ++c) V[r][c] = INT32_MIN;
+
+  // ---- pass 1: values
+  for (int64_t k0 = kbeg; k0 < kend; k0 += TK) {
+    for (int idx = tid; idx < TM * TK; idx += NT) {
+      const int i = idx / TK, j = idx % TK;
+      const int64_t m = m0 + i, q = k0 + j;
+      Av[j][i] = (m < a.M && q < kend) ? (int32_t)Ab[m * a.K + q] : NEG;
+    }
+    for (int idx = tid; idx < TK * TN; idx += NT) {
+      const int j = idx / TN, i = idx % TN;
+      const int64_t n = n0 + i, q = k0 + j;
+      Bv[j][i] = (n < a.N && q < kend) ? (int32_t)Bb[q * a.N + n] : NEG;
+    }
+    __syncthreads();
+#pragma unroll 4
+    for (int kk = 0; kk < TK; ++kk) {
+      int32_t av[RM], bv[RN];
+#pragma unroll
+      for (int r = 0; r < RM; ++r) av[r] = Av[kk][ty * RM + r];
+#pragma unroll
+      for (int c = 0; c < RN; ++c) bv[c] = Bv[kk][tx * RN + c];
+#pragma unroll
+      for (int r = 0; r < RM; ++r)
+#pragma unroll
+        for (int c = 0; c < RN; ++c) V[r][c] = max(V[r][c], av[r] + bv[c]);
+    }
+    __syncthreads();
+  }
+
+  uint64_t acc[KP][RM][RN];
+#pragma unroll
+  for (int i = 0; i < KP; ++i)
+#pragma unroll
+    for (int r = 0; r < RM; ++r)
+#pragma unroll
+      for (int c = 0; c < RN; ++c) acc[i][r][c] = 0;
+
+  if constexpr (KR > 0) {
+    int any_finite = 0;
+#pragma unroll
+    for (int r = 0; r < RM; ++r)
+#pragma unroll
+      for (int c = 0; c < RN; ++c) any_finite |= (V[r][c] > NEG_CUT);
+    // ---- pass 2: counts of the q reaching V (skipped by tiles with no
+    // finite output, e.g. fully constrained independent-set blocks)
+    if (__syncthreads_or(any_finite)) {
+      for (int64_t k0 = kbeg; k0 < kend; k0 += TK) {
+        for (int idx = tid; idx < TM * TK; idx += NT) {
+          const int i = idx / TK, j = idx % TK;
+          const int64_t m = m0 + i, q = k0 + j;
+          const bool in = (m < a.M && q < kend);
+          const int64_t o = m * a.K + q;
+          Av[j][i] = in ? (int32_t)Ab[o] : NEG;
+#pragma unroll
+          for (int p = 0; p < KR; ++p) Ac[p][j][i] = in ? Ab[(p + 1) * a.pA + o] : 0u;
+        }
+        for (int idx = tid; idx < TK * TN; idx += NT) {
+          const int j = idx / TN, i = idx % TN;
+          const int64_t n = n0 + i, q = k0 + j;
+          const bool in = (n < a.N && q < kend);
+          const int64_t o = q * a.N + n;
+          Bv[j][i] = in ? (int32_t)Bb[o] : NEG;
+#pragma unroll
+          for (int p = 0; p < KR; ++p) Bc[p][j][i] = in ? Bb[(p + 1) * a.pB + o] : 0u;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int kk = 0; kk < TK; ++kk) {
+          int32_t av[RM], bv[RN];
+          uint32_t ac[KR][RM], bc[KR][RN];
+#pragma unroll
+          for (int r = 0; r < RM; ++r) av[r] = Av[kk][ty * RM + r];
+#pragma unroll
+          for (int c = 0; c < RN; ++c) bv[c] = Bv[kk][tx * RN + c];
+#pragma unroll
+          for (int p = 0; p < KR; ++p) {
+#pragma unroll
+            for (int r = 0; r < RM; ++r) ac[p][r] = Ac[p][kk][ty * RM + r];
+#pragma unroll
+            for (int c = 0; c < RN; ++c) bc[p][c] = Bc[p][kk][tx * RN + c];
+          }
+#pragma unroll
+          for (int r = 0; r < RM; ++r)
+#pragma unroll
+            for (int c = 0; c < RN; ++c) {
+              const bool eq = (av[r] + bv[c] == V[r][c]);
+#pragma unroll
+              for (int p = 0; p < KR; ++p)
+                acc[p][r][c] += (uint64_t)(eq ? ac[p][r] : 0u) * bc[p][c];
+            }
+          // at most three products (< 2^62 each) between folds (< 2^54)
+          if (kk % 3 == 2 || kk == TK - 1) {
+#pragma unroll
+            for (int p = 0; p < KR; ++p)
+#pragma unroll
+              for (int r = 0; r < RM; ++r)
+#pragma unroll
+                for (int c = 0; c < RN; ++c) acc[p][r][c] = fold64(acc[p][r][c], a.mod.c[p]);
+          }
+        }
+        __syncthreads();
+      }
+    }
+  }
+
+  // ---- write
+#pragma unroll
+  for (int r = 0; r < RM; ++r) {
+    const int64_t m = m0 + ty * RM + r;
+#pragma unroll
+    for (int c = 0; c < RN; ++c) {
+      const int64_t n = n0 + tx * RN + c;
+      if (m < a.M && n < a.N) {
+        const int64_t off = sp * a.sCsplit + b * a.sCb + m * a.N + n;
+        const bool fin = V[r][c] > NEG_CUT;
+        a.C[off] = (uint32_t)(fin ? V[r][c] : NEG);
+        if constexpr (KR > 0) {
+#pragma unroll
+          for (int p = 0; p < KR; ++p)
+            a.C[(p + 1) * a.pC + off] =
+                fin ? mod_final(acc[p][r][c], a.mod.p[p], a.mod.c[p]) : 0u;
+        }
+      }
+    }
+  }
+}
+
+template <int KR>
+static void launch_cfg(int cfg, dim3 grid, const GemmArgs& a, hipStream_t st) {
+  switch (cfg) {
+#define BBTN_TG_CASE(I, TM, TN, RM, RN, TK)                                   \
+  case I:                                                                     \
+    hipLaunchKernelGGL((tgemm_kernel<KR, TM, TN, RM, RN, TK>), grid,          \
+                       dim3((TM / RM) * (TN / RN)), 0, st, a);                \
+    break;
+    BBTN_TG_CASE(0, 64, 64, 4, 4, 16)
+    BBTN_TG_CASE(1, 32, 32, 2, 2, 16)
+    BBTN_TG_CASE(2, 16, 16, 1, 1, 16)
+    BBTN_TG_CASE(3, 8, 64, 1, 2, 16)
+    BBTN_TG_CASE(4, 64, 8, 2, 1, 16)
+    BBTN_TG_CASE(5, 1, 256, 1, 1, 16)
+    BBTN_TG_CASE(6, 256, 1, 1, 1, 16)
+#undef BBTN_TG_CASE
+    default:
+      throw Error(BBTN_E_INTERNAL, "bad tile config");
+  }
+}
+
+static void launch_core(int k, const GemmArgs& a0, int cfg, hipStream_t st) {
+  const TileCfg& tc = kTileCfgs[cfg];
+  GemmArgs a = a0;
+  a.tiles_m = (a.M + tc.tm - 1) / tc.tm;
+  a.tiles_n = (a.N + tc.tn - 1) / tc.tn;
+  const int64_t total = a.tiles_m * a.tiles_n * a.splits * a.batch;
+  BBTN_REQUIRE(total > 0 && total < (1ll << 31), "tgemm grid out of range");
+  dim3 grid((unsigned)total);
+  switch (k) {
+    case 0: launch_cfg<0>(cfg, grid, a, st); break;
+    case 1: launch_cfg<1>(cfg, grid, a, st); break;
+    case 2: launch_cfg<2>(cfg, grid, a, st); break;
+    case 3: launch_cfg<3>(cfg, grid, a, st); break;
+    case 4: launch_cfg<4>(cfg, grid, a, st); break;
+    default: throw Error(BBTN_E_INVALID_ARG, "k must be in [0, 4]");
+  }
+  BBTN_HIP(hipGetLastError());
+}
+
+void launch_tgemm(int k, const Moduli& mod, const GemmShape& s, DevTensor A,
+                  DevTensor B, DevTensor C, int cfg, int splits,
+                  DevTensor partial, hipStream_t st) {
+  BBTN_REQUIRE(cfg >= 0 && cfg < N_TILE_CFGS, "tile config out of range");
+  BBTN_REQUIRE(s.M >= 1 && s.N >= 1 && s.K >= 1 && s.batch >= 1, "empty tgemm");
+  GemmArgs a{};
+  a.A = A.ptr; a.B = B.ptr;
+  a.pA = A.pstride; a.pB = B.pstride;
+  a.M = s.M; a.N = s.N; a.K = s.K; a.batch = s.batch;
+  a.sAb = s.sAb; a.sBb = s.sBb;
+  a.mod = mod;
+  const int tk = kTileCfgs[cfg].tk;
+  if (splits <= 1 || s.K <= tk) {
+    a.C = C.ptr; a.pC = C.pstride; a.sCb = s.sCb; a.sCsplit = 0;
+    a.splits = 1; a.kchunk = s.K;
+    launch_core(k, a, cfg, st);
+    return;
+  }
+  int64_t kchunk = (s.K + splits - 1) / splits;
+  kchunk = (kchunk + tk - 1) / tk * tk;
+  const int64_t nsp = (s.K + kchunk - 1) / kchunk;
+  const int64_t outer = s.batch * s.M * s.N;
+  BBTN_REQUIRE(partial.ptr != nullptr && partial.pstride >= nsp * outer,
+               "split-K partial buffer too small");
+  a.C = partial.ptr; a.pC = partial.pstride;
+  a.sCb = s.M * s.N; a.sCsplit = outer;
+  a.splits = nsp; a.kchunk = kchunk;
+  launch_core(k, a, cfg, st);
+  BBTN_REQUIRE(s.sCb == s.M * s.N, "split-K output must be contiguous");
+  launch_reduce(k, mod, outer, nsp, outer, 1, partial, C, st);
+}
+
+void launch_tgemm_values(const GemmShape& s, const int32_t* A, const int32_t* B,
+                         int32_t* C, hipStream_t st) {
+  GemmArgs a{};
+  a.A = (const uint32_t*)A; a.B = (const uint32_t*)B; a.C = (uint32_t*)C;
+  a.M = s.M; a.N = s.N; a.K = s.K; a.batch = s.batch;
+  a.sAb = s.sAb; a.sBb = s.sBb; a.sCb = s.sCb;
+  a.splits = 1; a.kchunk = s.K;
+  a.mod = make_moduli(0, nullptr);
+  int cfg = (s.M >= 32 && s.N >= 32) ? 0 : (s.M == 1 ? 5 : (s.N == 1 ? 6 : 2));
+  launch_core(0, a, cfg, st);
+}
+
+}  // namespace bbtn

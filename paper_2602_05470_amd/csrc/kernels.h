@@ -1,0 +1,67 @@
+// Host-side launchers of the HIP kernels.  All launches are asynchronous on
+// the given stream; shapes are validated by the callers.
+#pragma once
+#include "common.h"
+
+namespace bbtn {
+
+// Tile shape of the counting tropical GEMM: TM x TN outputs per workgroup,
+// RM x RN per thread, TK-deep LDS stages.
+struct TileCfg {
+  int tm, tn, rm, rn, tk;
+};
+constexpr int N_TILE_CFGS = 7;
+extern const TileCfg kTileCfgs[N_TILE_CFGS];
+
+struct GemmShape {
+  int64_t batch, M, N, K;
+  // element strides between consecutive batch entries of A, B, C (0 =
+  // operand shared by every batch entry); rows are contiguous.
+  int64_t sAb, sBb, sCb;
+};
+
+// C[b,m,n] = (+)_q A[b,m,q] (.) B[b,q,n].  With splits > 1 the K range is cut
+// into `splits` chunks whose partial results go to `partial` (a tensor buffer
+// of splits * batch * M * N entries) and are merged into C afterwards.
+void launch_tgemm(int k, const Moduli& mod, const GemmShape& s, DevTensor A,
+                  DevTensor B, DevTensor C, int cfg, int splits,
+                  DevTensor partial, hipStream_t st);
+
+// Values-only variant (k = 0): the max-plus product used for bounds and
+// configuration recovery.
+void launch_tgemm_values(const GemmShape& s, const int32_t* A, const int32_t* B,
+                         int32_t* C, hipStream_t st);
+
+// Bit-permutation / slicing gather (see bbtn_gather in bbtn.h).
+struct GatherRun {
+  int32_t out_lo, in_lo, len;
+};
+constexpr int MAX_RUNS = 40;
+struct GatherPlan {
+  int32_t r_out = 0, r_in = 0;
+  int32_t n_runs = 0;
+  GatherRun runs[MAX_RUNS];
+  uint64_t fixed_mask = 0;  // input bits not covered by runs
+};
+GatherPlan make_gather_plan(int r_in, int r_out, const int32_t* src_bits);
+void launch_gather(int k, const GatherPlan& g, int64_t L, int64_t in_stride,
+                   const uint64_t* fixed_bits, DevTensor in, DevTensor out,
+                   hipStream_t st);
+
+// Segmented tropical sum: out[o] = (+)_{s<S} in[s*seg_stride + o*elem_stride].
+void launch_reduce(int k, const Moduli& mod, int64_t outer, int64_t S,
+                   int64_t seg_stride, int64_t elem_stride, DevTensor in,
+                   DevTensor out, hipStream_t st);
+
+// out[l] = a[l] (.) b[l] for l < L.
+void launch_otimes(int k, const Moduli& mod, int64_t L, DevTensor a, DevTensor b,
+                   DevTensor out, hipStream_t st);
+
+// Branch bounds + stream compaction (see bbtn_bound in bbtn.h).  `flags`
+// is device scratch of n_branch int32.
+void launch_bound(int64_t n_branch, int32_t T, const int32_t* values,
+                  const int64_t* off, const int32_t* len, const int64_t* offset,
+                  int64_t incumbent, int64_t* bound, int32_t* flags,
+                  int32_t* keep_idx, int32_t* n_keep, hipStream_t st);
+
+}  // namespace bbtn

@@ -1,0 +1,65 @@
+// Tensor network of a spin glass or MWIS instance in the counting tropical
+// algebra, max form ("Tropical Tensor Networks" section: edge matrices B^ij,
+// vertex vectors w^i, bond index s_i shared by every tensor touching i).
+#pragma once
+#include <array>
+#include <vector>
+#include "common.h"
+
+namespace bbtn {
+
+// The 32 largest primes below 2^31, descending (computed once).
+const std::vector<uint32_t>& prime_table();
+
+// Exact modular helpers (host).
+inline uint32_t addmod(uint32_t a, uint32_t b, uint32_t p) {
+  uint64_t s = (uint64_t)a + b;
+  return (uint32_t)(s >= p ? s - p : s);
+}
+inline uint32_t mulmod(uint32_t a, uint32_t b, uint32_t p) {
+  return (uint32_t)((uint64_t)a * b % p);
+}
+
+constexpr int NP = BBTN_MAX_PRIMES;
+
+// A base tensor over `vars` (ascending ids).  Entry e (bit j = state of
+// vars[j]) has value val[e] (NEG = infeasible) and count residues
+// res[p * size + e] modulo prime_table()[p] for every p < NP.
+struct BaseTensor {
+  std::vector<int32_t> vars;
+  std::vector<int32_t> val;
+  std::vector<uint32_t> res;
+  int64_t size() const { return (int64_t)val.size(); }
+};
+
+// One exact elimination done while simplifying the network: `var` was
+// summed out of a tensor over `tvars` with values `tval`.  Replaying these in
+// reverse, choosing the best state of `var` given the others, recovers an
+// optimal configuration of the eliminated variables.
+struct PeelRec {
+  int32_t var;
+  std::vector<int32_t> tvars;
+  std::vector<int32_t> tval;
+};
+
+struct Network {
+  int32_t n = 0;
+  bool spin = true;                 // spin glass (true) or MWIS (false)
+  std::vector<BaseTensor> tensors;  // after simplification
+  int64_t const_val = 0;            // folded scalar factor (max form)
+  std::array<uint32_t, NP> const_res{};
+  bool infeasible = false;
+  std::vector<PeelRec> peel;        // in elimination order
+  int64_t abs_sum = 0;              // sum |J| + |h| (or sum w)
+};
+
+Network build_spinglass(int32_t n, int32_t m, const int32_t* uv, const int32_t* J,
+                        const int32_t* h);
+Network build_mwis(int32_t n, int32_t m, const int32_t* uv, const int32_t* w);
+
+// Exact simplification: absorb tensors whose variables are a subset of
+// another's (tropical product), sum out variables held by a single tensor
+// (tropical sum, recorded in `peel`), fold scalars into the constant.
+void simplify(Network& net);
+
+}  // namespace bbtn

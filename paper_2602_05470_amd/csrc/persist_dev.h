@@ -1,0 +1,65 @@
+// Device-side layout of the persistent executor's step programs.
+#pragma once
+#include "kernels.h"
+
+namespace bbtn {
+
+constexpr int P_MAX_RUNS = 16;
+
+struct PFix {
+  int32_t pos;  // bit position in the base tensor
+  int32_t idx;  // index of the variable in the group's fixed-variable list
+};
+
+struct POperand {
+  int32_t base;      // 1: base tensor (src_off = entry offset in the base buffer)
+                     // 0: intermediate (src_off = entry offset in scratch)
+  int32_t rank;      // rank of the operand in the step's layout
+  int64_t src_off;
+  int32_t n_runs, n_fix;
+  int32_t fix_off;   // into the PFix array
+  int32_t pad;
+  GatherRun runs[P_MAX_RUNS];
+};
+
+struct PStep {
+  int32_t rb, rm, rn, rk;
+  int64_t c_off;     // scratch entry offset of the output
+  POperand a, b;
+};
+
+struct PGroup {
+  int32_t step_off, n_steps;
+  int64_t root_off;  // scratch entry offset of the root scalar, -1 if none
+};
+
+struct PTask {
+  int32_t group;
+  int32_t pad;
+  int64_t assign_off;  // byte offset of the branch's fixed states
+  int64_t out_idx;     // output slot
+};
+
+struct PersistArgs {
+  const PStep* steps;
+  const PGroup* groups;
+  const PFix* fixes;
+  const PTask* tasks;
+  int64_t n_tasks;
+  const uint8_t* assign;
+  const uint32_t* base;
+  int64_t base_total;
+  const uint32_t* lconst;  // (1 + k) planes of n_out entries
+  uint32_t* out;           // (1 + k) planes of n_out entries
+  int64_t n_out;
+  uint32_t* scratch;       // per workgroup: (1 + k) planes of scratch_entries
+  int64_t scratch_entries;
+  int64_t lds_entries;
+  unsigned long long* queue;
+  Moduli mod;
+};
+
+size_t persist_lds_bytes(int k, int64_t lds_entries);
+void launch_persist(int k, const PersistArgs& a, int n_blocks, hipStream_t st);
+
+}  // namespace bbtn

@@ -1,0 +1,213 @@
+#include "plan.h"
+#include "kernels.h"
+
+#include <cmath>
+#include <map>
+
+namespace bbtn {
+
+// Runs of consecutive output bits mapping onto consecutive input bits.
+GatherPlan make_gather_plan(int r_in, int r_out, const int32_t* src_bits) {
+  BBTN_REQUIRE(r_in >= 0 && r_in <= 40 && r_out >= 0 && r_out <= r_in,
+               "gather: bad ranks");
+  GatherPlan g;
+  g.r_in = r_in;
+  g.r_out = r_out;
+  uint64_t used = 0;
+  for (int j = 0; j < r_out; ++j) {
+    const int s = src_bits[j];
+    BBTN_REQUIRE(s >= 0 && s < r_in, "gather: source bit out of range");
+    BBTN_REQUIRE(!(used >> s & 1), "gather: source bit used twice");
+    used |= 1ull << s;
+    if (g.n_runs > 0) {
+      GatherRun& last = g.runs[g.n_runs - 1];
+      if (last.out_lo + last.len == j && last.in_lo + last.len == s) {
+        ++last.len;
+        continue;
+      }
+    }
+    g.runs[g.n_runs++] = GatherRun{j, s, 1};
+  }
+  const uint64_t all = r_in >= 64 ? ~0ull : ((1ull << r_in) - 1);
+  g.fixed_mask = all & ~used;
+  return g;
+}
+
+namespace {
+
+std::vector<int32_t> free_vars(const std::vector<int32_t>& vs, const std::vector<uint64_t>& fx) {
+  std::vector<int32_t> o;
+  for (int v : vs)
+    if (!bit_get(fx, v)) o.push_back(v);
+  return o;
+}
+
+std::vector<int32_t> isect(const std::vector<int32_t>& a, const std::vector<int32_t>& b) {
+  std::vector<int32_t> o;
+  std::set_intersection(a.begin(), a.end(), b.begin(), b.end(), std::back_inserter(o));
+  return o;
+}
+std::vector<int32_t> minus(const std::vector<int32_t>& a, const std::vector<int32_t>& b) {
+  std::vector<int32_t> o;
+  std::set_difference(a.begin(), a.end(), b.begin(), b.end(), std::back_inserter(o));
+  return o;
+}
+std::vector<int32_t> cat3(const std::vector<int32_t>& a, const std::vector<int32_t>& b,
+                          const std::vector<int32_t>& c) {
+  std::vector<int32_t> o = a;
+  o.insert(o.end(), b.begin(), b.end());
+  o.insert(o.end(), c.begin(), c.end());
+  return o;
+}
+
+}  // namespace
+
+GroupPlan build_plan(const Network& net, const Tree& tree,
+                     const std::vector<uint64_t>& fixed, bool keep_all) {
+  GroupPlan g;
+  g.fixed = fixed;
+  for (int v = 0; v < net.n; ++v)
+    if (bit_get(fixed, v)) g.fixed_vars.push_back(v);
+  enum { FOLDED, BASE, STEP };
+  const int NN = (int)tree.nodes.size();
+  std::vector<int> status(NN, FOLDED), rep(NN, -1), buf_of(NN, -1);
+  std::vector<std::vector<int32_t>> layout(NN);  // stored layout of STEP outputs
+  auto new_buf = [&](int64_t entries) {
+    g.buf_entries.push_back(entries);
+    return (int32_t)g.buf_entries.size() - 1;
+  };
+  // buffer lifetimes in step indices: [def, last use]
+  std::vector<std::pair<int, int>> life;
+  auto def = [&](int buf, int s) {
+    if ((int)life.size() <= buf) life.resize(buf + 1, {-1, -1});
+    life[buf] = {s, s};
+  };
+  auto use = [&](int buf, int s) { life[buf].second = std::max(life[buf].second, s); };
+
+  for (int i = 0; i < tree.n_base; ++i) {
+    if (free_vars(tree.nodes[i].vars, fixed).empty()) {
+      status[i] = FOLDED;
+      g.folded.push_back(i);
+    } else {
+      status[i] = BASE;
+      rep[i] = i;
+    }
+  }
+  for (int id : tree.postorder) {
+    const TNode& n = tree.nodes[id];
+    const int sl = status[n.left], sr = status[n.right];
+    if (sl == FOLDED && sr == FOLDED) { status[id] = FOLDED; continue; }
+    if (sl == FOLDED || sr == FOLDED) {
+      const int child = sl == FOLDED ? n.right : n.left;
+      status[id] = status[child];
+      rep[id] = rep[child];
+      if (free_vars(n.vars, fixed) != free_vars(tree.nodes[rep[id]].vars, fixed))
+        throw Error(BBTN_E_INTERNAL, "plan: alias with different variables");
+      continue;
+    }
+    status[id] = STEP;
+    rep[id] = id;
+    const int ra = rep[n.left], rb_ = rep[n.right];
+    const auto A = free_vars(tree.nodes[ra].vars, fixed);
+    const auto B = free_vars(tree.nodes[rb_].vars, fixed);
+    const auto C = free_vars(n.vars, fixed);
+    const auto AB = isect(A, B);
+    const auto batch = isect(AB, C);
+    const auto K = minus(AB, C);
+    const auto M = isect(minus(A, B), C);
+    const auto N = isect(minus(B, A), C);
+    if (!minus(minus(A, B), C).empty() || !minus(minus(B, A), C).empty())
+      throw Error(BBTN_E_INTERNAL, "plan: variable private to one operand");
+    Step s;
+    s.node = id;
+    s.rb = (int)batch.size();
+    s.rm = (int)M.size();
+    s.rn = (int)N.size();
+    s.rk = (int)K.size();
+    s.a_vars = cat3(K, M, batch);
+    s.b_vars = cat3(N, K, batch);
+    s.c_vars = cat3(N, M, batch);
+    const int si = (int)g.steps.size();
+    auto make_op = [&](int r, const std::vector<int32_t>& want, int which) {
+      Operand op;
+      if (status[r] == BASE) {
+        const auto& tv = tree.nodes[r].vars;  // physical order of the base tensor
+        op.base = true;
+        op.id = tree.nodes[r].base;
+        op.r_in = (int)tv.size();
+        for (int v : want)
+          op.src_bits.push_back((int)(std::find(tv.begin(), tv.end(), v) - tv.begin()));
+        for (int j = 0; j < (int)tv.size(); ++j)
+          if (bit_get(fixed, tv[j])) op.fixed_pos.push_back({j, tv[j]});
+        op.base_op = (int)g.base_ops.size();
+        g.base_ops.push_back({si, which});
+      } else {
+        const auto& have = layout[r];
+        op.base = false;
+        op.id = buf_of[r];
+        op.r_in = (int)have.size();
+        op.direct = (have == want);
+        for (int v : want)
+          op.src_bits.push_back((int)(std::find(have.begin(), have.end(), v) - have.begin()));
+      }
+      if (!op.direct) {
+        op.temp = new_buf(1ll << want.size());
+        def(op.temp, si);
+      }
+      if (!op.base) use(op.id, si);
+      return op;
+    };
+    s.a = make_op(ra, s.a_vars, 0);
+    s.b = make_op(rb_, s.b_vars, 1);
+    s.out = new_buf(1ll << C.size());
+    def(s.out, si);
+    buf_of[id] = s.out;
+    layout[id] = s.c_vars;
+    g.max_rank = std::max({g.max_rank, (int)s.a_vars.size(), (int)s.b_vars.size(),
+                           (int)s.c_vars.size()});
+    g.macs += s.macs();
+    g.steps.push_back(std::move(s));
+  }
+  if (tree.root >= 0 && status[tree.root] == STEP) {
+    g.root_buf = buf_of[tree.root];
+    use(g.root_buf, (int)g.steps.size());  // read after the last step
+  } else if (tree.root >= 0 && status[tree.root] == BASE) {
+    throw Error(BBTN_E_INTERNAL, "plan: root is a base tensor with free variables");
+  }
+  // offsets: first fit over lifetimes (or disjoint when keeping everything)
+  const int nb = (int)g.buf_entries.size();
+  g.buf_off.assign(nb, 0);
+  if (keep_all) {
+    int64_t off = 0;
+    for (int i = 0; i < nb; ++i) { g.buf_off[i] = off; off += g.buf_entries[i]; }
+    g.peak = off;
+  } else {
+    // process buffers in definition order; live intervals in an ordered map
+    std::vector<int> order(nb);
+    for (int i = 0; i < nb; ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int x, int y) { return life[x].first < life[y].first; });
+    std::vector<int> active;  // placed buffers still alive
+    int64_t peak = 0;
+    for (int i : order) {
+      active.erase(std::remove_if(active.begin(), active.end(),
+                                  [&](int j) { return life[j].second < life[i].first; }),
+                   active.end());
+      std::vector<std::pair<int64_t, int64_t>> busy;
+      for (int j : active) busy.push_back({g.buf_off[j], g.buf_off[j] + g.buf_entries[j]});
+      std::sort(busy.begin(), busy.end());
+      int64_t off = 0;
+      for (auto& bz : busy) {
+        if (off + g.buf_entries[i] <= bz.first) break;
+        off = std::max(off, bz.second);
+      }
+      g.buf_off[i] = off;
+      peak = std::max(peak, off + g.buf_entries[i]);
+      active.push_back(i);
+    }
+    g.peak = peak;
+  }
+  return g;
+}
+
+}  // namespace bbtn

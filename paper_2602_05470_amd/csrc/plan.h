@@ -1,0 +1,57 @@
+// Step program for the contraction of one branch sub-network
+// T|_{s_S = x} (Eq. 3): the contraction tree of the whole network with the
+// fixed variables S removed from every tensor.  Every branch that fixes the
+// same variable set S shares this program (same topology, different
+// contents), so the program runs batched over all of them.
+#pragma once
+#include <cmath>
+#include <vector>
+#include "tree.h"
+
+namespace bbtn {
+
+// One operand of a step: a base tensor sliced per branch, or an
+// intermediate buffer; gathered into the step's required layout unless it
+// is already stored that way.
+struct Operand {
+  bool base = false;
+  int32_t id = -1;                  // base tensor id or buffer id
+  bool direct = false;              // intermediate already in required layout
+  int32_t r_in = 0;                 // rank of the source (all vars for base)
+  std::vector<int32_t> src_bits;    // required-layout bit j <- source bit
+  int32_t temp = -1;                // buffer receiving the gathered operand
+  std::vector<std::pair<int32_t, int32_t>> fixed_pos;  // (source bit, var) of fixed vars (base only)
+  int32_t base_op = -1;             // index into GroupPlan::base_ops
+};
+
+// C[b, m, n] = (+)_k A[b, m, k] (.) B[b, k, n], bit layouts (low bits first):
+//   A: [K][M][batch], B: [N][K][batch], C: [N][M][batch].
+struct Step {
+  int32_t node = -1;
+  int32_t rb = 0, rm = 0, rn = 0, rk = 0;
+  Operand a, b;
+  int32_t out = -1;                 // buffer id of C
+  std::vector<int32_t> a_vars, b_vars, c_vars;  // layouts (variable ids)
+  double macs() const { return std::ldexp(1.0, rb + rm + rn + rk); }
+};
+
+struct GroupPlan {
+  std::vector<uint64_t> fixed;      // bitmask of fixed variables S
+  std::vector<int32_t> fixed_vars;  // S, ascending
+  std::vector<Step> steps;          // children before parents
+  std::vector<int64_t> buf_entries; // per-branch entries of every buffer
+  std::vector<int64_t> buf_off;     // per-branch entry offset of every buffer
+  int64_t peak = 0;                 // per-branch entries of the workspace
+  std::vector<int32_t> folded;      // base tensors with every variable fixed
+  int32_t root_buf = -1;            // buffer of the final scalar, -1 if none
+  std::vector<std::pair<int32_t, int32_t>> base_ops;  // (step, 0=A / 1=B)
+  int32_t max_rank = 0;             // largest tensor rank in the program
+  double macs = 0;                  // per branch
+};
+
+// keep_all: never reuse buffers and materialise every operand in its
+// required layout (values-only recontraction for configuration recovery).
+GroupPlan build_plan(const Network& net, const Tree& tree,
+                     const std::vector<uint64_t>& fixed, bool keep_all);
+
+}  // namespace bbtn

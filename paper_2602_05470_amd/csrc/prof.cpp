@@ -1,0 +1,65 @@
+#include "prof.h"
+
+#include "ctx.h"
+
+namespace bbtn {
+
+hipEvent_t Prof::get() {
+  if (!pool.empty()) {
+    hipEvent_t e = pool.back();
+    pool.pop_back();
+    return e;
+  }
+  hipEvent_t e;
+  BBTN_HIP(hipEventCreate(&e));
+  return e;
+}
+
+int Prof::begin(hipStream_t st) {
+  if (!on) return -1;
+  Pending p{};
+  p.a = get();
+  p.b = get();
+  BBTN_HIP(hipEventRecord(p.a, st));
+  pending.push_back(p);
+  return (int)pending.size() - 1;
+}
+
+void Prof::end(int h, hipStream_t st, int id, double ops, double bytes) {
+  if (h < 0) return;
+  Pending& p = pending[h];
+  p.id = id;
+  p.ops = ops;
+  p.bytes = bytes;
+  BBTN_HIP(hipEventRecord(p.b, st));
+}
+
+void Prof::resolve() {
+  for (auto& p : pending) {
+    BBTN_HIP(hipEventSynchronize(p.b));
+    float ms = 0;
+    BBTN_HIP(hipEventElapsedTime(&ms, p.a, p.b));
+    KStat& s = stat[p.id];
+    s.launches++;
+    s.seconds += ms * 1e-3;
+    s.ops += p.ops;
+    s.bytes += p.bytes;
+    pool.push_back(p.a);
+    pool.push_back(p.b);
+  }
+  pending.clear();
+}
+
+void Prof::clear() {
+  resolve();
+  for (auto& s : stat) s = KStat{};
+}
+
+Prof::~Prof() {
+  for (auto& p : pending) { (void)hipEventDestroy(p.a); (void)hipEventDestroy(p.b); }
+  for (auto e : pool) (void)hipEventDestroy(e);
+}
+
+Prof& prof_of(bbtn_ctx* ctx) { return ctx->prof; }
+
+}  // namespace bbtn

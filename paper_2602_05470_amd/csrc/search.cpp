@@ -1,0 +1,503 @@
+#include "search.h"
+
+#include <chrono>
+#include <cmath>
+#include <map>
+#include <random>
+#include <unordered_map>
+
+namespace bbtn {
+
+static double now_s() {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+std::vector<int16_t> node_sizes(const Tree& t, const std::vector<uint64_t>& fixed) {
+  std::vector<int16_t> s(t.nodes.size(), 0);
+  for (int id : t.postorder) {
+    int c = 0;
+    for (int v : t.nodes[id].vars) c += !bit_get(fixed, v);
+    s[id] = (int16_t)c;
+  }
+  return s;
+}
+
+int64_t rho_of(const Tree& t, const std::vector<int16_t>& sizes, int log2_target) {
+  int64_t r = 0;
+  for (int id : t.postorder) r += std::max(0, sizes[id] - log2_target);
+  return r;
+}
+
+// Largest finite entry of tensor T consistent with the fixed states (and
+// with the region assignment: vars in `rvars` take the bits of `rx`).
+static int64_t tensor_max(const BaseTensor& T, const std::vector<uint64_t>& fixed,
+                          const std::vector<uint8_t>& x, const int32_t* rpos = nullptr,
+                          uint32_t rx = 0) {
+  const int r = (int)T.vars.size();
+  uint32_t cmask = 0, cval = 0;  // constrained positions and their states
+  for (int j = 0; j < r; ++j) {
+    const int v = T.vars[j];
+    if (rpos && rpos[j] >= 0) {
+      cmask |= 1u << j;
+      cval |= ((rx >> rpos[j]) & 1u) << j;
+    } else if (bit_get(fixed, v)) {
+      cmask |= 1u << j;
+      cval |= (uint32_t)(x[v] & 1) << j;
+    }
+  }
+  int64_t best = INT64_MIN;
+  for (int64_t e = 0; e < T.size(); ++e) {
+    if (((uint32_t)e & cmask) != cval) continue;
+    const int32_t v = T.val[e];
+    if (v > NEG_CUT && v > best) best = v;
+  }
+  return best;
+}
+
+int64_t node_bound(const Network& net, const std::vector<uint64_t>& fixed,
+                   const std::vector<uint8_t>& x) {
+  int64_t b = net.const_val;
+  for (const auto& T : net.tensors) {
+    const int64_t m = tensor_max(T, fixed, x);
+    if (m == INT64_MIN) return INT64_MIN;
+    b += m;
+  }
+  return b;
+}
+
+int64_t network_value(const Network& net, const std::vector<uint8_t>& x) {
+  if (net.infeasible) return INT64_MIN;
+  int64_t v = net.const_val;
+  for (const auto& T : net.tensors) {
+    int64_t e = 0;
+    for (size_t j = 0; j < T.vars.size(); ++j) e |= (int64_t)(x[T.vars[j]] & 1) << j;
+    if (T.val[e] <= NEG_CUT) return INT64_MIN;
+    v += T.val[e];
+  }
+  return v;
+}
+
+namespace {
+
+struct Node {
+  std::vector<uint64_t> fixed;
+  std::vector<uint8_t> x;
+  std::vector<int16_t> sizes;
+  int64_t rho = 0;
+  int64_t bound = 0;
+};
+
+struct Cube {
+  uint32_t mask, val;  // over region positions
+};
+
+struct Searcher {
+  const Network& net;
+  const Tree& tree;
+  const SearchOptions& opt;
+  std::vector<std::vector<int32_t>> var_tensors, nbr;
+  std::vector<int32_t> dec;      // scratch: decrements per tree node
+  std::vector<int32_t> touched;  // scratch: tree nodes with dec > 0
+  std::map<std::vector<uint64_t>, int> group_of;
+
+  Searcher(const Network& n, const Tree& t, const SearchOptions& o) : net(n), tree(t), opt(o) {
+    var_tensors.assign(net.n, {});
+    nbr.assign(net.n, {});
+    for (int i = 0; i < (int)net.tensors.size(); ++i)
+      for (int v : net.tensors[i].vars) var_tensors[v].push_back(i);
+    for (int v = 0; v < net.n; ++v) {
+      for (int ti : var_tensors[v])
+        for (int u : net.tensors[ti].vars)
+          if (u != v) nbr[v].push_back(u);
+      std::sort(nbr[v].begin(), nbr[v].end());
+      nbr[v].erase(std::unique(nbr[v].begin(), nbr[v].end()), nbr[v].end());
+    }
+    dec.assign(tree.nodes.size(), 0);
+  }
+
+  // rho reduction when the variables vs (all free at `n`) are fixed too.
+  int64_t drho(const Node& n, const std::vector<int32_t>& vs) {
+    for (int v : vs)
+      for (int id : tree.var_nodes[v]) {
+        if (dec[id]++ == 0) touched.push_back(id);
+      }
+    int64_t d = 0;
+    const int t = opt.log2_target;
+    for (int id : touched) {
+      const int s0 = n.sizes[id], s1 = s0 - dec[id];
+      d += std::max(0, s0 - t) - std::max(0, s1 - t);
+      dec[id] = 0;
+    }
+    touched.clear();
+    return d;
+  }
+
+  // Branching factor of the characteristic equation: gamma >= 1 with
+  // sum_i gamma^(-delta rho_i) = 1, solved for lambda = ln gamma by Newton's
+  // method (the sum is convex and decreasing in lambda; starting left of the
+  // root, the iterates increase monotonically to it).
+  static double gamma_of(const std::vector<std::pair<int64_t, int64_t>>& terms) {
+    int64_t total = 0;
+    for (auto& t : terms) {
+      if (t.first <= 0) return INFINITY;
+      total += t.second;
+    }
+    if (total == 0) return 0.0;
+    if (total == 1) return 1.0;
+    double lam = 0;
+    for (int it = 0; it < 60; ++it) {
+      double f = -1, df = 0;
+      for (auto& t : terms) {
+        const double e = (double)t.second * std::exp(-lam * (double)t.first);
+        f += e;
+        df -= (double)t.first * e;
+      }
+      const double step = f / df;
+      lam -= step;
+      if (std::fabs(step) <= 1e-12 * std::max(1.0, lam)) break;
+    }
+    return std::exp(lam);
+  }
+
+  struct Eval {
+    double gamma = INFINITY;
+    std::vector<int32_t> region;
+    std::vector<Cube> cubes;
+  };
+
+  Eval evaluate(const Node& n, const std::vector<int32_t>& R) {
+    Eval ev;
+    ev.region = R;
+    const int r = (int)R.size();
+    std::vector<int32_t> tt;
+    for (int v : R) tt.insert(tt.end(), var_tensors[v].begin(), var_tensors[v].end());
+    std::sort(tt.begin(), tt.end());
+    tt.erase(std::unique(tt.begin(), tt.end()), tt.end());
+    // per touching tensor: region positions of its vars; inside/cross; base max
+    std::vector<std::vector<int32_t>> rpos(tt.size());
+    std::vector<char> inside(tt.size(), 1);
+    std::vector<int64_t> base_max(tt.size());
+    uint32_t bmask = 0;
+    for (size_t i = 0; i < tt.size(); ++i) {
+      const BaseTensor& T = net.tensors[tt[i]];
+      rpos[i].assign(T.vars.size(), -1);
+      bool cross = false;
+      for (size_t j = 0; j < T.vars.size(); ++j) {
+        const int v = T.vars[j];
+        auto it = std::find(R.begin(), R.end(), v);
+        if (it != R.end()) rpos[i][j] = (int)(it - R.begin());
+        else if (!bit_get(n.fixed, v)) cross = true;
+      }
+      inside[i] = !cross;
+      if (cross)
+        for (size_t j = 0; j < T.vars.size(); ++j)
+          if (rpos[i][j] >= 0) bmask |= 1u << rpos[i][j];
+      base_max[i] = tensor_max(T, n.fixed, n.x);
+    }
+    const uint32_t nx = 1u << r;
+    // per touching tensor: table of its largest consistent entry over the
+    // states of its region variables (at most 2^|T| entries), so that every
+    // region configuration costs one table lookup per tensor
+    struct Tab {
+      std::vector<int32_t> pos;   // region positions of the tensor's region vars
+      std::vector<int64_t> val;   // indexed by those bits
+      bool inside;
+      int64_t base;
+    };
+    std::vector<Tab> tabs(tt.size());
+    for (size_t i = 0; i < tt.size(); ++i) {
+      const BaseTensor& T = net.tensors[tt[i]];
+      Tab& tb = tabs[i];
+      tb.inside = inside[i];
+      tb.base = base_max[i];
+      std::vector<int32_t> jr;  // tensor positions that are region vars
+      for (size_t j = 0; j < T.vars.size(); ++j)
+        if (rpos[i][j] >= 0) { jr.push_back((int)j); tb.pos.push_back(rpos[i][j]); }
+      tb.val.assign((size_t)1 << jr.size(), INT64_MIN);
+      for (uint32_t y = 0; y < (1u << jr.size()); ++y) {
+        uint32_t rx = 0;
+        for (size_t q = 0; q < jr.size(); ++q) rx |= ((y >> q) & 1u) << tb.pos[q];
+        tb.val[y] = tensor_max(T, n.fixed, n.x, rpos[i].data(), rx);
+      }
+    }
+    std::vector<int64_t> local(nx), bnd(nx);
+    std::vector<int64_t> gmaxv(nx, INT64_MIN);  // indexed by x & bmask
+    for (uint32_t x = 0; x < nx; ++x) {
+      int64_t lc = 0, b = n.bound;
+      bool feas = true;
+      for (const Tab& tb : tabs) {
+        uint32_t y = 0;
+        for (size_t q = 0; q < tb.pos.size(); ++q) y |= ((x >> tb.pos[q]) & 1u) << q;
+        const int64_t m = tb.val[y];
+        if (m == INT64_MIN) { feas = false; break; }
+        b += m - tb.base;
+        if (tb.inside) lc += m;
+      }
+      local[x] = feas ? lc : INT64_MIN;
+      bnd[x] = feas ? b : INT64_MIN;
+      if (feas && lc > gmaxv[x & bmask]) gmaxv[x & bmask] = lc;
+    }
+    const uint32_t full = nx - 1;
+    for (uint32_t x = 0; x < nx; ++x) {
+      if (local[x] == INT64_MIN) continue;
+      if (local[x] != gmaxv[x & bmask]) continue;      // boundary equivalence
+      if (bnd[x] < opt.incumbent) continue;              // global pruning (strict)
+      ev.cubes.push_back(Cube{full, x});
+    }
+    // delta rho per fixed subset of the region (cached)
+    std::unordered_map<uint32_t, int64_t> dcache;
+    auto dr = [&](uint32_t mask) {
+      auto it = dcache.find(mask);
+      if (it != dcache.end()) return it->second;
+      std::vector<int32_t> vs;
+      for (int j = 0; j < r; ++j)
+        if (mask >> j & 1) vs.push_back(R[j]);
+      const int64_t d = drho(n, vs);
+      dcache[mask] = d;
+      return d;
+    };
+    auto gam = [&](const std::vector<Cube>& cs) {
+      std::map<uint32_t, int64_t> cnt;
+      for (auto& c : cs) cnt[c.mask]++;
+      std::vector<std::pair<int64_t, int64_t>> terms;
+      for (auto& kv : cnt) terms.push_back({dr(kv.first), kv.second});
+      return gamma_of(terms);
+    };
+    ev.gamma = gam(ev.cubes);
+    // with nothing pruned, freeing variables only reproduces a smaller region
+    // (evaluated separately); otherwise free variables of the cover
+    if (ev.cubes.size() == nx) return ev;
+    // free variables of the cover while it lowers gamma (cubes stay disjoint
+    // and cover exactly the same configurations)
+    for (;;) {
+      int bestj = -1;
+      double bestg = ev.gamma;
+      std::vector<Cube> bestc;
+      for (int j = 0; j < r; ++j) {
+        const uint32_t bj = 1u << j;
+        std::unordered_map<uint64_t, char> have;
+        for (auto& c : ev.cubes) have[((uint64_t)c.mask << 32) | c.val] = 1;
+        std::vector<Cube> merged;
+        bool any = false;
+        for (auto& c : ev.cubes) {
+          if (!(c.mask & bj)) { merged.push_back(c); continue; }
+          const uint64_t partner = ((uint64_t)c.mask << 32) | (c.val ^ bj);
+          if (have.count(partner)) {
+            if (!(c.val & bj)) { merged.push_back(Cube{c.mask & ~bj, c.val}); any = true; }
+          } else {
+            merged.push_back(c);
+          }
+        }
+        if (!any) continue;
+        const double g = gam(merged);
+        if (g < bestg - 1e-12) { bestg = g; bestj = j; bestc = std::move(merged); }
+      }
+      if (bestj < 0) break;
+      ev.gamma = bestg;
+      ev.cubes = std::move(bestc);
+    }
+    return ev;
+  }
+
+  void emit(const Node& n, std::vector<LeafGroup>& leaves) {
+    auto it = group_of.find(n.fixed);
+    int gi;
+    if (it == group_of.end()) {
+      gi = (int)leaves.size();
+      LeafGroup g;
+      g.mask = n.fixed;
+      for (int v = 0; v < net.n; ++v)
+        if (bit_get(n.fixed, v)) g.vars.push_back(v);
+      leaves.push_back(std::move(g));
+      group_of[n.fixed] = gi;
+    } else {
+      gi = it->second;
+    }
+    LeafGroup& g = leaves[gi];
+    for (int v : g.vars) g.assign.push_back(n.x[v]);
+    g.count++;
+  }
+
+  void run(std::vector<LeafGroup>& leaves, SearchStats& st) {
+    Node root;
+    root.fixed.assign((net.n + 63) / 64, 0);
+    root.x.assign(net.n, 0);
+    root.sizes = node_sizes(tree, root.fixed);
+    root.rho = rho_of(tree, root.sizes, opt.log2_target);
+    root.bound = node_bound(net, root.fixed, root.x);
+    if (root.bound < opt.incumbent || root.bound == INT64_MIN) { st.pruned++; return; }
+    std::vector<Node> stack;
+    stack.push_back(std::move(root));
+    std::vector<double> heur(net.n), score(net.n);
+    while (!stack.empty()) {
+      if (opt.deadline > 0 && now_s() > opt.deadline)
+        throw Error(BBTN_E_TIMEOUT, "time limit reached during the search");
+      Node n = std::move(stack.back());
+      stack.pop_back();
+      st.nodes++;
+      if (n.rho == 0 || opt.log2_target <= 0) {
+        emit(n, leaves);
+        st.leaves++;
+        continue;
+      }
+      // overflow participation of every free variable
+      std::vector<int32_t> cand;
+      for (int v = 0; v < net.n; ++v) {
+        heur[v] = 0;
+        if (bit_get(n.fixed, v)) continue;
+        double s = 0;
+        for (int id : tree.var_nodes[v]) s += std::max(0, n.sizes[id] - opt.log2_target);
+        heur[v] = s;
+        if (s > 0) cand.push_back(v);
+      }
+      score = heur;
+      if (opt.scorer) opt.scorer(n.fixed, n.sizes, heur, score);
+      std::stable_sort(cand.begin(), cand.end(), [&](int a, int b) {
+        if (score[a] != score[b]) return score[a] > score[b];
+        return a < b;
+      });
+      if (cand.empty()) throw Error(BBTN_E_INTERNAL, "rho > 0 but no overflowing variable");
+      Eval best;
+      const int n_seeds = std::min<int>(2, (int)cand.size());
+      for (int si = 0; si < n_seeds; ++si) {
+        std::vector<int32_t> order{cand[si]};
+        while ((int)order.size() < opt.region_max) {
+          int pick = -1;
+          for (int v : order)
+            for (int u : nbr[v]) {
+              if (bit_get(n.fixed, u)) continue;
+              if (std::find(order.begin(), order.end(), u) != order.end()) continue;
+              if (pick < 0 || score[u] > score[pick] || (score[u] == score[pick] && u < pick)) pick = u;
+            }
+          if (pick < 0) break;
+          order.push_back(pick);
+        }
+        for (int r = 1; r <= (int)order.size(); ++r) {
+          std::vector<int32_t> R(order.begin(), order.begin() + r);
+          Eval ev = evaluate(n, R);
+          // lowest gamma; on a tie (within 1e-9 relative) the larger step,
+          // which reaches the same leaves through fewer search nodes
+          const double tol = 1e-9 * std::max(1.0, best.gamma);
+          if (ev.gamma < best.gamma - tol ||
+              (std::fabs(ev.gamma - best.gamma) <= tol && ev.cubes.size() > best.cubes.size())) {
+            best = std::move(ev);
+          }
+          if (best.gamma == 0.0) break;  // every configuration pruned
+        }
+        if (best.gamma == 0.0) break;
+      }
+      if (opt.record) opt.record(n.fixed, n.sizes, best.region, best.gamma, (int)best.cubes.size());
+      if (best.cubes.empty()) { st.pruned++; continue; }
+      if (!std::isfinite(best.gamma)) throw Error(BBTN_E_INTERNAL, "no branching rule reduces rho");
+      st.gamma_sum += best.gamma;
+      // children, first cube on top of the stack
+      for (int ci = (int)best.cubes.size() - 1; ci >= 0; --ci) {
+        const Cube& c = best.cubes[ci];
+        Node ch;
+        ch.fixed = n.fixed;
+        ch.x = n.x;
+        std::vector<int32_t> newly;
+        for (int j = 0; j < (int)best.region.size(); ++j)
+          if (c.mask >> j & 1) {
+            const int v = best.region[j];
+            bit_set(ch.fixed, v);
+            ch.x[v] = (uint8_t)((c.val >> j) & 1);
+            newly.push_back(v);
+          }
+        ch.bound = node_bound(net, ch.fixed, ch.x);
+        if (ch.bound == INT64_MIN || ch.bound < opt.incumbent) { st.pruned++; continue; }
+        ch.sizes = n.sizes;
+        for (int v : newly)
+          for (int id : tree.var_nodes[v]) ch.sizes[id]--;
+        ch.rho = rho_of(tree, ch.sizes, opt.log2_target);
+        stack.push_back(std::move(ch));
+      }
+    }
+  }
+};
+
+}  // namespace
+
+void bb_search(const Network& net, const Tree& tree, const SearchOptions& opt,
+               std::vector<LeafGroup>& leaves, SearchStats& stats) {
+  Searcher s(net, tree, opt);
+  s.run(leaves, stats);
+}
+
+// ------------------------------------------------------------ local search
+std::vector<uint8_t> local_search_spinglass(int32_t n, int32_t m, const int32_t* uv,
+                                            const int32_t* J, const int32_t* h, int sweeps,
+                                            uint64_t seed) {
+  std::vector<std::vector<std::pair<int, int>>> adj(n);
+  for (int e = 0; e < m; ++e) {
+    adj[uv[2 * e]].push_back({uv[2 * e + 1], J[e]});
+    adj[uv[2 * e + 1]].push_back({uv[2 * e], J[e]});
+  }
+  std::mt19937_64 rng(seed);
+  std::uniform_real_distribution<double> U(0, 1);
+  auto energy = [&](const std::vector<int>& s) {
+    int64_t E = 0;
+    for (int e = 0; e < m; ++e) E -= (int64_t)J[e] * s[uv[2 * e]] * s[uv[2 * e + 1]];
+    if (h) for (int i = 0; i < n; ++i) E -= (int64_t)h[i] * s[i];
+    return E;
+  };
+  std::vector<int> best_s(n, 1);
+  int64_t bestE = energy(best_s);
+  const int restarts = 3;
+  for (int rs = 0; rs < restarts; ++rs) {
+    std::vector<int> s(n);
+    for (int i = 0; i < n; ++i) s[i] = (rng() & 1) ? 1 : -1;
+    int64_t E = energy(s);
+    const double T0 = 2.0, T1 = 0.05;
+    for (int sw = 0; sw < sweeps + 20; ++sw) {
+      const double T = sw < sweeps ? T0 * std::pow(T1 / T0, (double)sw / std::max(1, sweeps - 1)) : 0.0;
+      for (int i = 0; i < n; ++i) {
+        int64_t f = h ? h[i] : 0;
+        for (auto& pr : adj[i]) f += (int64_t)pr.second * s[pr.first];
+        const int64_t dE = 2 * s[i] * f;
+        if (dE <= 0 || (T > 0 && U(rng) < std::exp(-(double)dE / T))) {
+          s[i] = -s[i];
+          E += dE;
+          if (E < bestE) { bestE = E; best_s = s; }
+        }
+      }
+    }
+  }
+  std::vector<uint8_t> x(n);
+  for (int i = 0; i < n; ++i) x[i] = best_s[i] > 0 ? 1 : 0;
+  return x;
+}
+
+std::vector<uint8_t> local_search_mwis(int32_t n, int32_t m, const int32_t* uv,
+                                       const int32_t* w, int restarts, uint64_t seed) {
+  std::vector<std::vector<int>> adj(n);
+  for (int e = 0; e < m; ++e) {
+    adj[uv[2 * e]].push_back(uv[2 * e + 1]);
+    adj[uv[2 * e + 1]].push_back(uv[2 * e]);
+  }
+  std::mt19937_64 rng(seed);
+  std::vector<uint8_t> best(n, 0);
+  int64_t bestW = -1;
+  for (int rs = 0; rs < std::max(1, restarts); ++rs) {
+    std::vector<double> key(n);
+    for (int i = 0; i < n; ++i) {
+      const double wi = w ? w[i] : 1;
+      key[i] = wi / (double)(adj[i].size() + 1) + 1e-6 * (double)(rng() % 1000000) / 1e6 * (rs > 0);
+    }
+    std::vector<int> ord(n);
+    for (int i = 0; i < n; ++i) ord[i] = i;
+    std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) { return key[a] > key[b]; });
+    std::vector<uint8_t> x(n, 0), blocked(n, 0);
+    int64_t W = 0;
+    for (int i : ord) {
+      if (blocked[i]) continue;
+      x[i] = 1;
+      W += w ? w[i] : 1;
+      for (int j : adj[i]) blocked[j] = 1;
+    }
+    if (W > bestW) { bestW = W; best = x; }
+  }
+  return best;
+}
+
+}  // namespace bbtn

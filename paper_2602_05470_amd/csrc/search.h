@@ -1,0 +1,77 @@
+// Branch-and-bound over the tensor network ("Branch-and-Bound Tensor
+// Network" section): a node fixes a set of variables; its sub-network's
+// problem size rho (Eq. 4) is the total overflow of the intermediates of the
+// contraction tree above T_target; a node with rho = 0 is a leaf whose
+// sub-network is contracted on the device.  Other nodes branch on a region R:
+// the feasible set F(R) keeps, for every boundary state, only the
+// locally-optimal interiors (ties kept) that also pass global pruning; the
+// branches D(R) are disjoint cubes covering F(R), chosen to minimise the
+// branching factor gamma of the characteristic equation.
+#pragma once
+#include <functional>
+#include <vector>
+#include "tree.h"
+
+namespace bbtn {
+
+struct LeafGroup {
+  std::vector<uint64_t> mask;     // fixed variables S
+  std::vector<int32_t> vars;      // S ascending
+  std::vector<uint8_t> assign;    // count * |S| states
+  int64_t count = 0;
+};
+
+struct SearchStats {
+  uint64_t nodes = 0, pruned = 0, leaves = 0;
+  double gamma_sum = 0;
+};
+
+// Orders candidate branching variables: returns one score per variable
+// (higher = branch earlier) for the free variables of a node.  Empty
+// function: the overflow-participation heuristic.
+using VarScorer = std::function<void(const std::vector<uint64_t>& fixed,
+                                     const std::vector<int16_t>& sizes,
+                                     const std::vector<double>& heuristic,
+                                     std::vector<double>& score)>;
+
+struct SearchOptions {
+  int log2_target = 10;
+  int region_max = 8;
+  int64_t incumbent = INT64_MIN;  // value of a known configuration (max form)
+  double deadline = 0;            // absolute wall time (s) or 0
+  VarScorer scorer;
+  // optional sink for per-node training records (features, outcome)
+  std::function<void(const std::vector<uint64_t>& fixed, const std::vector<int16_t>& sizes,
+                     const std::vector<int32_t>& region, double gamma, int n_children)>
+      record;
+};
+
+void bb_search(const Network& net, const Tree& tree, const SearchOptions& opt,
+               std::vector<LeafGroup>& leaves, SearchStats& stats);
+
+// Upper bound (max form) of a node: constant + sum over tensors of the
+// largest finite entry consistent with the fixed states.  INT64_MIN if a
+// tensor has no consistent finite entry.
+int64_t node_bound(const Network& net, const std::vector<uint64_t>& fixed,
+                   const std::vector<uint8_t>& x);
+
+// rho of Eq. 4 given per-internal-node free-variable counts.
+int64_t rho_of(const Tree& t, const std::vector<int16_t>& sizes, int log2_target);
+
+// Free-variable counts of the tree's internal nodes (indexed by node id)
+// for a fixed-variable mask.
+std::vector<int16_t> node_sizes(const Tree& t, const std::vector<uint64_t>& fixed);
+
+// Value (max form, including the folded constant) of a full assignment of
+// the network's variables, or INT64_MIN if infeasible.
+int64_t network_value(const Network& net, const std::vector<uint8_t>& x);
+
+// Local search for a good configuration of the original instance; returns
+// states per variable (0/1).
+std::vector<uint8_t> local_search_spinglass(int32_t n, int32_t m, const int32_t* uv,
+                                            const int32_t* J, const int32_t* h, int sweeps,
+                                            uint64_t seed);
+std::vector<uint8_t> local_search_mwis(int32_t n, int32_t m, const int32_t* uv,
+                                       const int32_t* w, int restarts, uint64_t seed);
+
+}  // namespace bbtn

@@ -1,0 +1,35 @@
+"""Writes the stored expected values used by the GPU tests.  Calls only the
+CPU oracle (exact transfer matrix) on the seeded inputs of `instances`.
+
+    python tests/golden/make_golden.py
+"""
+import os
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
+
+import instances as I  # noqa: E402
+from oracle import tm  # noqa: E402
+
+
+def main():
+    with open(os.path.join(HERE, "sg16.txt"), "w") as f:
+        f.write("# +-J spin glass 16x16 open lattice, zero field, seeds 0-19:\n")
+        f.write("# seed E0 degeneracy  (oracle: exact transfer matrix)\n")
+        for s in range(20):
+            e0, deg = tm.spin_glass_square(I.spin_glass_square(16, s))
+            f.write("%d %d %d\n" % (s, e0, deg))
+            f.flush()
+    with open(os.path.join(HERE, "ksg16.txt"), "w") as f:
+        f.write("# unweighted MIS on King's subgraph 16x16, fill 0.8, seeds 0-4:\n")
+        f.write("# seed n W* count  (oracle: exact transfer matrix)\n")
+        for s in range(5):
+            g = I.kings_subgraph(16, s)
+            w, c = tm.kings_subgraph(g)
+            f.write("%d %d %d %d\n" % (s, g["n"], w, c))
+            f.flush()
+
+
+if __name__ == "__main__":
+    main()

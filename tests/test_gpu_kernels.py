@@ -1,0 +1,169 @@
+"""Kernel parity on the GPU through the C ABI: every output element equals
+the oracle's definition (bit-exact: integer values and residues)."""
+import numpy as np
+import pytest
+
+import instances as I
+from oracle import device_ops as D
+from tests.gpu_util import torch_cuda, to_dev, from_dev, empty_dev
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    torch_cuda()
+    import paper_2602_05470_amd as B
+    c = B.Context(B.Options())
+    yield c
+    c.close()
+
+
+# shapes chosen to reach every tile configuration, ragged tails and split-K
+SHAPES = [
+    (1, 1, 1, 1), (1, 3, 5, 7), (2, 17, 33, 19), (1, 64, 64, 64), (3, 65, 130, 40),
+    (2, 40, 48, 33), (1, 4, 200, 24), (1, 200, 4, 24), (1, 1, 300, 50), (1, 300, 1, 50),
+    (2, 8, 20, 700), (1, 1, 1, 3000), (5, 2, 2, 2),
+]
+
+
+@pytest.mark.parametrize("shape", SHAPES)
+@pytest.mark.parametrize("k", [1, 3, 4])
+def test_tgemm_matches_oracle(ctx, shape, k):
+    torch = torch_cuda()
+    b, M, N, K = shape
+    primes = I.PRIMES_31[:k]
+    seed = hash((shape, k)) % 10000
+    Av, Ar = I.random_entries((b, M, K), k, seed=seed, vrange=3)
+    Bv, Br = I.random_entries((b, K, N), k, seed=seed + 1, vrange=3)
+    dA, dB = to_dev(torch, Av, Ar), to_dev(torch, Bv, Br)
+    dC = empty_dev(torch, k, b * M * N)
+    ctx.tgemm(k, primes, b, M, N, K, dA, dB, dC)
+    torch.cuda.synchronize()
+    gv, gr = from_dev(dC, k, b * M * N)
+    wv, wr = D.tgemm(Av, Ar, Bv, Br, primes)
+    assert np.array_equal(gv, wv.reshape(-1))
+    assert np.array_equal(gr, wr.reshape(k, -1))
+
+
+@pytest.mark.parametrize("K", [1, 3, 64, 4096])
+def test_tgemm_all_ties_max_residues(ctx, K):
+    """Every term ties and every residue is p - 1: the count is
+    K (p-1)^2 mod p, which exercises the 64-bit accumulator folds."""
+    torch = torch_cuda()
+    k = 4
+    primes = I.PRIMES_31[:k]
+    M = N = 5
+    Av = np.zeros((1, M, K), np.int32)
+    Bv = np.zeros((1, K, N), np.int32)
+    Ar = np.stack([np.full((1, M, K), p - 1, np.uint32) for p in primes])
+    Br = np.stack([np.full((1, K, N), p - 1, np.uint32) for p in primes])
+    dC = empty_dev(torch, k, M * N)
+    ctx.tgemm(k, primes, 1, M, N, K, to_dev(torch, Av, Ar), to_dev(torch, Bv, Br), dC)
+    gv, gr = from_dev(dC, k, M * N)
+    assert np.all(gv == 0)
+    for i, p in enumerate(primes):
+        assert np.all(gr[i] == (K * (p - 1) * (p - 1)) % p)
+
+
+def test_tgemm_all_minus_infinity(ctx):
+    torch = torch_cuda()
+    k = 2
+    primes = I.PRIMES_31[:k]
+    Av, Ar = I.random_entries((1, 9, 11), k, seed=3, neg_frac=1.0)
+    Bv, Br = I.random_entries((1, 11, 7), k, seed=4)
+    dC = empty_dev(torch, k, 63)
+    ctx.tgemm(k, primes, 1, 9, 7, 11, to_dev(torch, Av, Ar), to_dev(torch, Bv, Br), dC)
+    gv, gr = from_dev(dC, k, 63)
+    assert np.all(gv == I.NEG) and np.all(gr == 0)
+
+
+def test_tgemm_rejects_bad_prime(ctx):
+    torch = torch_cuda()
+    import paper_2602_05470_amd as B
+    Av, Ar = I.random_entries((1, 2, 2), 1, seed=0)
+    d = to_dev(torch, Av, Ar)
+    with pytest.raises(B.BBTNError):
+        ctx.tgemm(1, [7], 1, 2, 2, 2, d, d, empty_dev(torch, 1, 4))
+
+
+@pytest.mark.parametrize("case", [
+    dict(r_in=5, src=[4, 0, 2, 1, 3], L=1, fixed=None),
+    dict(r_in=6, src=[5, 4, 0], L=7, fixed="rand"),
+    dict(r_in=4, src=[0, 1, 2, 3], L=3, fixed=None, per_leaf=True),
+    dict(r_in=12, src=list(range(11, -1, -1)), L=2, fixed=None, per_leaf=True),
+    dict(r_in=3, src=[], L=4, fixed="rand"),
+])
+@pytest.mark.parametrize("k", [0, 3])
+def test_gather_matches_oracle(ctx, case, k):
+    torch = torch_cuda()
+    r_in, src, L = case["r_in"], case["src"], case["L"]
+    per_leaf = case.get("per_leaf", False)
+    n_in = (L if per_leaf else 1) << r_in
+    v, r = I.random_entries((n_in,), max(k, 1), seed=r_in + L)
+    r = r[:k] if k else np.zeros((0, n_in), np.uint32)
+    rng = np.random.default_rng(1)
+    free = [j for j in range(r_in) if j not in src]
+    fixed_vals = [{j: int(rng.integers(0, 2)) for j in free} for _ in range(L)]
+    fb = np.array([sum(b << j for j, b in fv.items()) for fv in fixed_vals], np.uint64)
+    dfb = torch.from_numpy(fb.view(np.int64)).to("cuda") if free else None
+    out = empty_dev(torch, k, L << len(src))
+    ctx.gather(k, r_in, len(src), src, L, (1 << r_in) if per_leaf else 0, dfb,
+               to_dev(torch, v, r), n_in, out)
+    gv, gr = from_dev(out, k, L << len(src))
+    for l in range(L):
+        off = (l << r_in) if per_leaf else 0
+        planes = [v[off:off + (1 << r_in)]] + [r[i][off:off + (1 << r_in)] for i in range(k)]
+        for pi, pl in enumerate(planes):
+            want = D.gather(pl, r_in, src, fixed_vals[l] if free else None)
+            got = (gv if pi == 0 else gr[pi - 1])[l << len(src):(l + 1) << len(src)]
+            assert np.array_equal(got.astype(np.int64), want.astype(np.int64))
+
+
+@pytest.mark.parametrize("outer,S", [(1, 1), (7, 3), (1, 5000), (300, 17), (2000, 600)])
+def test_reduce_matches_oracle(ctx, outer, S):
+    torch = torch_cuda()
+    k = 3
+    primes = I.PRIMES_31[:k]
+    v, r = I.random_entries((S, outer), k, seed=outer + S, vrange=2)
+    out = empty_dev(torch, k, outer)
+    ctx.reduce(k, primes, outer, S, outer, 1, to_dev(torch, v.reshape(-1), r.reshape(k, -1)),
+               S * outer, out)
+    gv, gr = from_dev(out, k, outer)
+    for o in range(outer):
+        mv, mr = D.merge(v[:, o], r[:, :, o], primes)
+        assert gv[o] == mv and list(gr[:, o]) == mr
+
+
+def test_bound_matches_oracle(ctx):
+    torch = torch_cuda()
+    rng = np.random.default_rng(7)
+    nb, T = 300, 5
+    lens = rng.integers(1, 9, size=nb * T).astype(np.int32)
+    offs = np.concatenate([[0], np.cumsum(lens)[:-1]]).astype(np.int64)
+    vals, _ = I.random_entries((int(lens.sum()),), 1, seed=9, vrange=5, neg_frac=0.3)
+    offset = rng.integers(-5, 5, size=nb).astype(np.int64)
+    inc = 3
+    dv = torch.from_numpy(vals).to("cuda")
+    bound = torch.zeros(nb, dtype=torch.int64, device="cuda")
+    keep = torch.full((nb,), -1, dtype=torch.int32, device="cuda")
+    nk = torch.zeros(1, dtype=torch.int32, device="cuda")
+    ctx.bound(nb, T, dv, torch.from_numpy(offs).to("cuda"), torch.from_numpy(lens).to("cuda"),
+              torch.from_numpy(offset).to("cuda"), inc, bound, keep, nk)
+    want_b, want_keep = [], []
+    for b in range(nb):
+        ms = [D.tensor_max(vals[offs[b * T + t]:offs[b * T + t] + lens[b * T + t]]) for t in range(T)]
+        ok = all(m > I.NEG_CUT for m in ms)
+        bd = int(offset[b]) + sum(m for m in ms if m > I.NEG_CUT)
+        want_b.append(bd)
+        if ok and bd >= inc:
+            want_keep.append(b)
+    got_b = bound.cpu().numpy()
+    for b in range(nb):
+        ms_ok = all(D.tensor_max(vals[offs[b * T + t]:offs[b * T + t] + lens[b * T + t]]) > I.NEG_CUT
+                    for t in range(T))
+        if ms_ok:
+            assert got_b[b] == want_b[b]
+    n = int(nk.item())
+    assert n == len(want_keep)
+    assert list(keep.cpu().numpy()[:n]) == want_keep
