@@ -138,8 +138,8 @@ bbtn_status bbtn_solve_mwis(bbtn_ctx* ctx, int32_t n, int32_t m,
                             bbtn_result* res);
 
 /* ------------------------------------------------------------------------
- * Kernel-level entry points (device pointers, caller-owned; run on `stream`
- * (hipStream_t) or the context's stream when NULL; asynchronous).
+ * Kernel-level entry points (device pointers, caller-owned; asynchronous on
+ * `stream`, a hipStream_t, where NULL is the null (default) stream).
  * primes: host array [k]; every p in (2^31 - 2^20, 2^31).
  * ---------------------------------------------------------------------- */
 
@@ -221,6 +221,64 @@ typedef struct {
 
 bbtn_status bbtn_profile(bbtn_ctx* ctx, int32_t enable);
 bbtn_status bbtn_get_kernel_stats(bbtn_ctx* ctx, int32_t kernel, bbtn_kernel_stats* out);
+
+/* ------------------------------------------------------------------------
+ * Learned branching scorer.  A perceptron 32 -> 128 -> 128 -> 1 with ReLU
+ * scores candidate branching variables; the planner uses the scores only to
+ * order the variables it grows regions from (seeds and growth order), so the
+ * branches it builds stay complete and orthogonal and results are unchanged.
+ * Parameter layout: bfloat16 weights W [W1 (128 x 32, row-major) | W2 (128 x
+ * 128) | w3 (128)] = 20608 values; float32 biases [b1 (128) | b2 (128) | b3].
+ * Inputs X: rows x 32 bfloat16 (standardised features); all accumulation and
+ * hidden activations are float32.
+ * ---------------------------------------------------------------------- */
+
+/* y[r] = w3 . relu(W2 relu(W1 x_r + b1) + b2) + b3.  h1, h2 (rows x 128
+ * float32, device) receive the hidden activations when non-NULL (both or
+ * neither).  Device pointers. */
+bbtn_status bbtn_mlp_forward(bbtn_ctx* ctx, int64_t rows, const uint16_t* X, const uint16_t* W,
+                             const float* bias, float* y, float* h1, float* h2, void* stream);
+
+/* Gradient of the mean squared error (1/rows) sum (y - t)^2 with respect to
+ * every parameter, given the forward pass's y, h1, h2.  grad (device, 20866
+ * float32): [W1 | W2 | w3 | b1 | b2 | b3] followed by the sum of squared
+ * errors.  Deterministic (per-block partial sums added in block order). */
+bbtn_status bbtn_mlp_backward(bbtn_ctx* ctx, int64_t rows, const uint16_t* X, const uint16_t* W,
+                              const float* y, const float* t, const float* h1, const float* h2,
+                              float* grad, void* stream);
+
+/* One Adam step (step >= 1, bias-corrected) on the float32 master copy
+ * master[20865] = [weights | biases] with moments m, v; refreshes the
+ * bfloat16 weights W and the float32 biases.  Device pointers. */
+bbtn_status bbtn_mlp_adam(bbtn_ctx* ctx, float* master, uint16_t* W, float* bias, float* m,
+                          float* v, const float* grad, float lr, float beta1, float beta2,
+                          float eps, int32_t step, void* stream);
+
+/* Load trained weights (file written by bbtn_scorer_train) into ctx; used
+ * when branching == 2. */
+bbtn_status bbtn_scorer_load(bbtn_ctx* ctx, const char* path);
+
+/* Training data from the search itself: run the planner on an instance
+ * (kind 0: spin glass with weights = J, h; kind 1: MWIS with weights = w)
+ * with T_target = 2^log2_target for up to max_nodes nodes; at each node,
+ * cand_per_node candidate seed variables give one row each: 32 features and
+ * the label log2(1 + sum over the children that survive pruning of
+ * 2^(time complexity of the child)).  Host arrays X[capacity*32], y[capacity];
+ * *rows receives the row count (pass X = y = NULL to query it).  Host-only:
+ * ctx may be NULL (region size 8) or a context (its region_max). */
+bbtn_status bbtn_scorer_collect(bbtn_ctx* ctx, int32_t kind, int32_t n, int32_t m,
+                                const int32_t* edge_uv, const int32_t* weights, const int32_t* h,
+                                int32_t log2_target, int32_t max_nodes, int32_t cand_per_node,
+                                float* X, float* y, int64_t capacity, int64_t* rows);
+
+/* Train the scorer on the GPU with the kernels above (minibatches of `batch`
+ * rows, Adam at learning rate lr, `epochs` passes, initialisation from seed).
+ * Features and labels are standardised; loss_out[epochs] (host, or NULL)
+ * receives the standardised mean squared error after every epoch.  The
+ * weights are written to save_path (or not, if NULL) and loaded into ctx. */
+bbtn_status bbtn_scorer_train(bbtn_ctx* ctx, const float* X, const float* y, int64_t rows,
+                              int32_t epochs, int32_t batch, float lr, uint64_t seed,
+                              float* loss_out, const char* save_path);
 
 #ifdef __cplusplus
 }

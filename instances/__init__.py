@@ -148,3 +148,22 @@ def random_entries(shape, k: int, seed: int, vrange: int = 8, neg_frac: float = 
         val[neg] = NEG
         res[:, neg] = 0
     return val, res
+
+
+def to_bf16_bits(x):
+    """float32 -> bfloat16 bit patterns, round to nearest even (inputs to the
+    scorer's kernels; finite values only)."""
+    u = np.asarray(x, dtype=np.float32).view(np.uint32).astype(np.uint64)
+    u = (u + 0x7FFF + ((u >> 16) & 1)) >> 16
+    return u.astype(np.uint16)
+
+
+def mlp_params(seed: int, n_in: int = 32, n_h: int = 128, scale: float = 1.0):
+    """Random MLP parameters (float32) for scorer kernel tests: weights
+    uniform in +-scale/sqrt(fan_in), biases uniform in +-0.1."""
+    rng = np.random.default_rng(seed)
+    def U(shape, fan):
+        return (rng.uniform(-1, 1, size=shape) * scale / np.sqrt(fan)).astype(np.float32)
+    return dict(W1=U((n_h, n_in), n_in), b1=rng.uniform(-.1, .1, n_h).astype(np.float32),
+                W2=U((n_h, n_h), n_h), b2=rng.uniform(-.1, .1, n_h).astype(np.float32),
+                w3=U((n_h,), n_h), b3=np.float32(rng.uniform(-.1, .1)))

@@ -55,7 +55,14 @@ _lib = None
 EXPORTS = ["bbtn_default_options", "bbtn_create", "bbtn_destroy", "bbtn_last_error",
            "bbtn_solve_spinglass", "bbtn_solve_mwis", "bbtn_tgemm", "bbtn_gather",
            "bbtn_reduce", "bbtn_bound", "bbtn_last_macs", "bbtn_profile",
-           "bbtn_get_kernel_stats"]
+           "bbtn_get_kernel_stats", "bbtn_mlp_forward", "bbtn_mlp_backward", "bbtn_mlp_adam",
+           "bbtn_scorer_load", "bbtn_scorer_collect", "bbtn_scorer_train"]
+
+# scorer parameter layout (see include/bbtn.h)
+MLP_IN, MLP_H = 32, 128
+MLP_NW = MLP_H * MLP_IN + MLP_H * MLP_H + MLP_H
+MLP_NB = 2 * MLP_H + 1
+MLP_NPARAM = MLP_NW + MLP_NB
 
 
 class _KStats(C.Structure):
@@ -101,6 +108,20 @@ def load(path: str = LIB_PATH):
     lib.bbtn_profile.restype = I32
     lib.bbtn_get_kernel_stats.argtypes = [P, I32, C.POINTER(_KStats)]
     lib.bbtn_get_kernel_stats.restype = I32
+    F = C.c_float
+    lib.bbtn_mlp_forward.argtypes = [P, I64, P, P, P, P, P, P, P]
+    lib.bbtn_mlp_forward.restype = I32
+    lib.bbtn_mlp_backward.argtypes = [P, I64, P, P, P, P, P, P, P, P]
+    lib.bbtn_mlp_backward.restype = I32
+    lib.bbtn_mlp_adam.argtypes = [P, P, P, P, P, P, P, F, F, F, F, I32, P]
+    lib.bbtn_mlp_adam.restype = I32
+    lib.bbtn_scorer_load.argtypes = [P, C.c_char_p]
+    lib.bbtn_scorer_load.restype = I32
+    lib.bbtn_scorer_collect.argtypes = [P, I32, I32, I32, P, P, P, I32, I32, I32, P, P, I64,
+                                        C.POINTER(C.c_int64)]
+    lib.bbtn_scorer_collect.restype = I32
+    lib.bbtn_scorer_train.argtypes = [P, P, P, I64, I32, I32, F, U64, P, C.c_char_p]
+    lib.bbtn_scorer_train.restype = I32
     _lib = lib
     return lib
 
@@ -158,7 +179,8 @@ def _ptr(a):
 
 def _stream(s):
     """hipStream_t for a kernel-level call: the given stream (torch stream or
-    int handle), else torch's current stream when torch is in use."""
+    int handle), else torch's current stream when torch is in use (its
+    default stream is handle 0, the null stream)."""
     if s is None:
         import sys
         torch = sys.modules.get("torch")
@@ -288,3 +310,73 @@ class Context:
                                         _dptr(tensor_len), _dptr(offset), int(incumbent),
                                         _dptr(bound), _dptr(keep_idx), _dptr(n_keep),
                                         _stream(stream)))
+
+    # ------------------------------------------------------------- scorer
+    def mlp_forward(self, rows, X, W, bias, y, h1=None, h2=None, stream=None):
+        """bbtn_mlp_forward on device tensors (X, W: int16/bfloat16 bits)."""
+        self._check(self.lib.bbtn_mlp_forward(self.h, rows, _dptr(X), _dptr(W), _dptr(bias),
+                                              _dptr(y), _dptr(h1), _dptr(h2), _stream(stream)))
+
+    def mlp_backward(self, rows, X, W, y, t, h1, h2, grad, stream=None):
+        """bbtn_mlp_backward: grad receives [dW | db | sum of squared errors]."""
+        self._check(self.lib.bbtn_mlp_backward(self.h, rows, _dptr(X), _dptr(W), _dptr(y),
+                                               _dptr(t), _dptr(h1), _dptr(h2), _dptr(grad),
+                                               _stream(stream)))
+
+    def mlp_adam(self, master, W, bias, m, v, grad, lr, beta1, beta2, eps, step, stream=None):
+        """bbtn_mlp_adam: one bias-corrected Adam step."""
+        self._check(self.lib.bbtn_mlp_adam(self.h, _dptr(master), _dptr(W), _dptr(bias), _dptr(m),
+                                           _dptr(v), _dptr(grad), lr, beta1, beta2, eps, step,
+                                           _stream(stream)))
+
+    def scorer_load(self, path):
+        """bbtn_scorer_load."""
+        self._check(self.lib.bbtn_scorer_load(self.h, path.encode()))
+
+    def scorer_collect(self, kind, n, edges, weights, h=None, log2_target=10, max_nodes=64,
+                       cand_per_node=8):
+        """bbtn_scorer_collect -> (X [rows, 32] float32, y [rows] float32)."""
+        edges = _i32(edges).reshape(-1, 2)
+        w = None if weights is None else _i32(weights)
+        hh = None if h is None else _i32(h)
+        rows = C.c_int64(0)
+        args = (self.h, kind, n, len(edges), _ptr(edges), _ptr(w), _ptr(hh), log2_target,
+                max_nodes, cand_per_node)
+        self._check(self.lib.bbtn_scorer_collect(*args, None, None, 0, C.byref(rows)))
+        X = np.zeros((rows.value, MLP_IN), np.float32)
+        y = np.zeros(rows.value, np.float32)
+        if rows.value:
+            self._check(self.lib.bbtn_scorer_collect(*args, _ptr(X), _ptr(y), rows.value,
+                                                     C.byref(rows)))
+        return X, y
+
+    def scorer_train(self, X, y, epochs=20, batch=1024, lr=1e-3, seed=0, save_path=None):
+        """bbtn_scorer_train -> per-epoch standardised MSE."""
+        X = np.ascontiguousarray(X, np.float32)
+        y = np.ascontiguousarray(y, np.float32)
+        loss = np.zeros(epochs, np.float32)
+        self._check(self.lib.bbtn_scorer_train(self.h, _ptr(X), _ptr(y), len(y), epochs, batch,
+                                               lr, seed, _ptr(loss),
+                                               save_path.encode() if save_path else None))
+        return loss
+
+
+def scorer_collect(kind, n, edges, weights, h=None, log2_target=10, max_nodes=64, cand_per_node=8):
+    """bbtn_scorer_collect without a device context (host-only search)."""
+    lib = load()
+    edges = _i32(edges).reshape(-1, 2)
+    w = None if weights is None else _i32(weights)
+    hh = None if h is None else _i32(h)
+    rows = C.c_int64(0)
+    args = (None, kind, n, len(edges), _ptr(edges), _ptr(w), _ptr(hh), log2_target, max_nodes,
+            cand_per_node)
+    s = lib.bbtn_scorer_collect(*args, None, None, 0, C.byref(rows))
+    if s != 0:
+        raise BBTNError(s, "bbtn_scorer_collect failed")
+    X = np.zeros((rows.value, MLP_IN), np.float32)
+    y = np.zeros(rows.value, np.float32)
+    if rows.value:
+        s = lib.bbtn_scorer_collect(*args, _ptr(X), _ptr(y), rows.value, C.byref(rows))
+        if s != 0:
+            raise BBTNError(s, "bbtn_scorer_collect failed")
+    return X, y

@@ -53,9 +53,9 @@ def _compile(src, force, hdr_m):
     if (not force and os.path.exists(obj)
             and os.path.getmtime(obj) >= max(os.path.getmtime(src), hdr_m)):
         return obj, None
-    cmd = [_hipcc()] + COMMON
+    cmd = [_hipcc()] + COMMON + HIP_ONLY
     if src.endswith(".hip"):
-        cmd += HIP_ONLY + ["-x", "hip"]
+        cmd += ["-x", "hip"]
     cmd += ["-c", src, "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:

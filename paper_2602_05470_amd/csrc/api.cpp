@@ -41,7 +41,9 @@ bbtn_status guard(bbtn_ctx* ctx, F&& f) {
   }
 }
 
-hipStream_t pick_stream(bbtn_ctx* ctx, void* s) { return s ? (hipStream_t)s : ctx->stream; }
+// Kernel-level entry points run on the caller's stream; NULL is the null
+// (default) stream, as everywhere in HIP.
+hipStream_t pick_stream(bbtn_ctx*, void* s) { return (hipStream_t)s; }
 
 // Leaves of the search in a flat order: (group, index in group).
 struct LeafRef {
@@ -584,6 +586,206 @@ bbtn_status bbtn_bound(bbtn_ctx* ctx, int64_t n_branch, int32_t tensors_per_bran
     ctx->misc.ensure((size_t)std::max<int64_t>(n_branch, 1) * 4);
     launch_bound(n_branch, tensors_per_branch, values, tensor_off, tensor_len, offset, incumbent,
                  bound, ctx->misc.as<int32_t>(), keep_idx, n_keep, pick_stream(ctx, stream));
+  });
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------------ scorer
+#include <random>
+
+#include "mlp.h"
+
+extern "C" {
+
+bbtn_status bbtn_mlp_forward(bbtn_ctx* ctx, int64_t rows, const uint16_t* X, const uint16_t* W,
+                             const float* bias, float* y, float* h1, float* h2, void* stream) {
+  if (!ctx) return BBTN_E_INVALID_ARG;
+  return guard(ctx, [&] {
+    BBTN_REQUIRE(rows >= 0 && (rows == 0 || (X && W && bias && y)), "bad arguments");
+    BBTN_REQUIRE((h1 == nullptr) == (h2 == nullptr), "h1 and h2 go together");
+    BBTN_HIP(hipSetDevice(ctx->opt.device));
+    launch_mlp_forward(rows, X, W, bias, y, h1, h2, pick_stream(ctx, stream));
+  });
+}
+
+bbtn_status bbtn_mlp_backward(bbtn_ctx* ctx, int64_t rows, const uint16_t* X, const uint16_t* W,
+                              const float* y, const float* t, const float* h1, const float* h2,
+                              float* grad, void* stream) {
+  if (!ctx) return BBTN_E_INVALID_ARG;
+  return guard(ctx, [&] {
+    BBTN_REQUIRE(rows >= 1 && X && W && y && t && h1 && h2 && grad, "bad arguments");
+    BBTN_HIP(hipSetDevice(ctx->opt.device));
+    ctx->partial.ensure((size_t)mlp_partial_floats(rows) * 4);
+    launch_mlp_backward(rows, X, W, y, t, h1, h2, ctx->partial.as<float>(), grad,
+                        pick_stream(ctx, stream));
+  });
+}
+
+bbtn_status bbtn_mlp_adam(bbtn_ctx* ctx, float* master, uint16_t* wbf, float* bias, float* m,
+                          float* v, const float* grad, float lr, float beta1, float beta2,
+                          float eps, int32_t step, void* stream) {
+  if (!ctx) return BBTN_E_INVALID_ARG;
+  return guard(ctx, [&] {
+    BBTN_REQUIRE(master && wbf && bias && m && v && grad && step >= 1, "bad arguments");
+    BBTN_HIP(hipSetDevice(ctx->opt.device));
+    launch_mlp_adam(master, wbf, bias, m, v, grad, lr, beta1, beta2, eps, step,
+                    pick_stream(ctx, stream));
+  });
+}
+
+bbtn_status bbtn_scorer_load(bbtn_ctx* ctx, const char* path) {
+  if (!ctx || !path) return BBTN_E_INVALID_ARG;
+  return guard(ctx, [&] {
+    BBTN_HIP(hipSetDevice(ctx->opt.device));
+    load_scorer(ctx, path);
+  });
+}
+
+bbtn_status bbtn_scorer_collect(bbtn_ctx* ctx, int32_t kind, int32_t n, int32_t m,
+                                const int32_t* edge_uv, const int32_t* weights, const int32_t* h,
+                                int32_t log2_target, int32_t max_nodes, int32_t cand_per_node,
+                                float* X, float* y, int64_t capacity, int64_t* rows) {
+  if (!rows) return BBTN_E_INVALID_ARG;
+  return guard(ctx, [&] {  // host-only: ctx may be NULL
+    check_graph(n, m, edge_uv);
+    BBTN_REQUIRE(kind == 0 || kind == 1, "kind must be 0 (spin glass) or 1 (MWIS)");
+    BBTN_REQUIRE(log2_target > 0 && max_nodes >= 1 && cand_per_node >= 1, "bad sizes");
+    Network net = kind == 0 ? build_spinglass(n, m, edge_uv, weights, h)
+                            : build_mwis(n, m, edge_uv, weights);
+    Tree tree = greedy_tree(net);
+    std::vector<uint8_t> x = kind == 0 ? local_search_spinglass(n, m, edge_uv, weights, h, 200, 12345)
+                                       : local_search_mwis(n, m, edge_uv, weights, 10, 12345);
+    std::vector<float> fx, fy;
+    const int rmax = ctx ? std::max(1, std::min(16, ctx->opt.region_max)) : 8;
+    collect_training(net, tree, log2_target, rmax,
+                     network_value(net, x), max_nodes, cand_per_node, fx, fy);
+    *rows = (int64_t)fy.size();
+    if (X && y) {
+      BBTN_REQUIRE(capacity >= (int64_t)fy.size(), "capacity too small");
+      std::memcpy(X, fx.data(), fx.size() * 4);
+      std::memcpy(y, fy.data(), fy.size() * 4);
+    }
+  });
+}
+
+bbtn_status bbtn_scorer_train(bbtn_ctx* ctx, const float* X, const float* y, int64_t rows,
+                              int32_t epochs, int32_t batch, float lr, uint64_t seed,
+                              float* loss_out, const char* save_path) {
+  if (!ctx) return BBTN_E_INVALID_ARG;
+  return guard(ctx, [&] {
+    BBTN_REQUIRE(X && y && rows >= 1 && epochs >= 1 && batch >= 1 && lr > 0, "bad arguments");
+    BBTN_HIP(hipSetDevice(ctx->opt.device));
+    hipStream_t st = ctx->stream;
+    ScorerModel mdl;
+    // standardisation
+    for (int q = 0; q < N_FEAT; ++q) {
+      double s = 0, s2 = 0;
+      for (int64_t r = 0; r < rows; ++r) { s += X[r * N_FEAT + q]; s2 += (double)X[r * N_FEAT + q] * X[r * N_FEAT + q]; }
+      const double mu = s / rows, var = std::max(0.0, s2 / rows - mu * mu);
+      mdl.fmean[q] = (float)mu;
+      mdl.fstd[q] = var > 1e-12 ? (float)std::sqrt(var) : 1.f;
+    }
+    {
+      double s = 0, s2 = 0;
+      for (int64_t r = 0; r < rows; ++r) { s += y[r]; s2 += (double)y[r] * y[r]; }
+      const double mu = s / rows, var = std::max(0.0, s2 / rows - mu * mu);
+      mdl.ymean = (float)mu;
+      mdl.ystd = var > 1e-12 ? (float)std::sqrt(var) : 1.f;
+    }
+    // shuffled, standardised data (bf16 inputs, f32 targets)
+    std::mt19937_64 rng(seed);
+    std::vector<int64_t> perm(rows);
+    for (int64_t r = 0; r < rows; ++r) perm[r] = r;
+    std::shuffle(perm.begin(), perm.end(), rng);
+    std::vector<uint16_t> xb((size_t)rows * N_FEAT);
+    std::vector<float> yt(rows);
+    for (int64_t i = 0; i < rows; ++i) {
+      const int64_t r = perm[i];
+      for (int q = 0; q < N_FEAT; ++q) {
+        float v = (X[r * N_FEAT + q] - mdl.fmean[q]) / mdl.fstd[q];
+        uint32_t u;
+        std::memcpy(&u, &v, 4);
+        xb[i * N_FEAT + q] = (uint16_t)((u + 0x7FFFu + ((u >> 16) & 1u)) >> 16);
+      }
+      yt[i] = (y[r] - mdl.ymean) / mdl.ystd;
+    }
+    // parameters: uniform +-1/sqrt(fan_in) weights, zero biases
+    std::vector<float> master(MLP_NPARAM, 0.f);
+    std::uniform_real_distribution<float> U(-1.f, 1.f);
+    for (int i = 0; i < MLP_H * MLP_IN; ++i) master[MLP_W1 + i] = U(rng) / std::sqrt((float)MLP_IN);
+    for (int i = 0; i < MLP_H * MLP_H; ++i) master[MLP_W2 + i] = U(rng) / std::sqrt((float)MLP_H);
+    for (int i = 0; i < MLP_H; ++i) master[MLP_W3 + i] = U(rng) / std::sqrt((float)MLP_H);
+    const int64_t B = std::min<int64_t>(batch, rows);
+    // device buffers
+    DevBuf dbuf;
+    auto al = [](size_t b) { return (b + 255) / 256 * 256; };
+    size_t off = 0;
+    const size_t o_x = off; off += al(xb.size() * 2);
+    const size_t o_y = off; off += al(yt.size() * 4);
+    const size_t o_p = off; off += al((size_t)rows * 4);
+    const size_t o_h1 = off; off += al((size_t)rows * MLP_H * 4);
+    const size_t o_h2 = off; off += al((size_t)rows * MLP_H * 4);
+    const size_t o_ms = off; off += al(MLP_NPARAM * 4);
+    const size_t o_m = off; off += al(MLP_NPARAM * 4);
+    const size_t o_v = off; off += al(MLP_NPARAM * 4);
+    const size_t o_g = off; off += al(MLP_NPART * 4);
+    const size_t o_w = off; off += al(MLP_NW * 2);
+    const size_t o_b = off; off += al(MLP_NB * 4);
+    dbuf.ensure(off);
+    char* d = dbuf.as<char>();
+    std::vector<uint16_t> wb(MLP_NW);
+    for (int i = 0; i < MLP_NW; ++i) {
+      uint32_t u;
+      std::memcpy(&u, &master[i], 4);
+      wb[i] = (uint16_t)((u + 0x7FFFu + ((u >> 16) & 1u)) >> 16);
+    }
+    std::vector<float> zeros(MLP_NPARAM, 0.f);
+    BBTN_HIP(hipMemcpyAsync(d + o_x, xb.data(), xb.size() * 2, hipMemcpyHostToDevice, st));
+    BBTN_HIP(hipMemcpyAsync(d + o_y, yt.data(), yt.size() * 4, hipMemcpyHostToDevice, st));
+    BBTN_HIP(hipMemcpyAsync(d + o_ms, master.data(), MLP_NPARAM * 4, hipMemcpyHostToDevice, st));
+    BBTN_HIP(hipMemcpyAsync(d + o_m, zeros.data(), MLP_NPARAM * 4, hipMemcpyHostToDevice, st));
+    BBTN_HIP(hipMemcpyAsync(d + o_v, zeros.data(), MLP_NPARAM * 4, hipMemcpyHostToDevice, st));
+    BBTN_HIP(hipMemcpyAsync(d + o_w, wb.data(), MLP_NW * 2, hipMemcpyHostToDevice, st));
+    BBTN_HIP(hipMemcpyAsync(d + o_b, master.data() + MLP_NW, MLP_NB * 4, hipMemcpyHostToDevice, st));
+    ctx->partial.ensure((size_t)mlp_partial_floats(B) * 4);
+    const uint16_t* dX = (const uint16_t*)(d + o_x);
+    const float* dY = (const float*)(d + o_y);
+    float* dP = (float*)(d + o_p);
+    float* dH1 = (float*)(d + o_h1);
+    float* dH2 = (float*)(d + o_h2);
+    int step = 0;
+    std::vector<float> pred(rows);
+    for (int e = 0; e < epochs; ++e) {
+      for (int64_t r0 = 0; r0 < rows; r0 += B) {
+        const int64_t nb = std::min<int64_t>(B, rows - r0);
+        launch_mlp_forward(nb, dX + r0 * N_FEAT, (const uint16_t*)(d + o_w),
+                           (const float*)(d + o_b), dP + r0, dH1 + r0 * MLP_H, dH2 + r0 * MLP_H, st);
+        launch_mlp_backward(nb, dX + r0 * N_FEAT, (const uint16_t*)(d + o_w), dP + r0, dY + r0,
+                            dH1 + r0 * MLP_H, dH2 + r0 * MLP_H, ctx->partial.as<float>(),
+                            (float*)(d + o_g), st);
+        launch_mlp_adam((float*)(d + o_ms), (uint16_t*)(d + o_w), (float*)(d + o_b),
+                        (float*)(d + o_m), (float*)(d + o_v), (const float*)(d + o_g), lr, 0.9f,
+                        0.999f, 1e-8f, ++step, st);
+      }
+      if (loss_out) {
+        launch_mlp_forward(rows, dX, (const uint16_t*)(d + o_w), (const float*)(d + o_b), dP,
+                           nullptr, nullptr, st);
+        BBTN_HIP(hipMemcpyAsync(pred.data(), dP, rows * 4, hipMemcpyDeviceToHost, st));
+        BBTN_HIP(hipStreamSynchronize(st));
+        double l = 0;
+        for (int64_t r = 0; r < rows; ++r) l += (double)(pred[r] - yt[r]) * (pred[r] - yt[r]);
+        loss_out[e] = (float)(l / rows);
+      }
+    }
+    mdl.params.resize(MLP_NPARAM);
+    BBTN_HIP(hipMemcpyAsync(mdl.params.data(), d + o_ms, MLP_NPARAM * 4, hipMemcpyDeviceToHost, st));
+    BBTN_HIP(hipStreamSynchronize(st));
+    dbuf.release();
+    if (save_path) {
+      if (!write_model(save_path, mdl)) throw Error(BBTN_E_INVALID_ARG, "cannot write scorer weights");
+      load_scorer(ctx, save_path);
+    }
   });
 }
 

@@ -60,7 +60,10 @@ struct bbtn_ctx {
   uint64_t last_macs = 0;
   std::map<bbtn::TuneKey, bbtn::TuneVal> tune;
   bool tune_loaded = false;
-  std::vector<std::vector<float>> scorer;  // learned scorer weights (host copy)
+  // learned scorer: [fmean 32][fstd 32][ymean][ystd][params] (host) and the
+  // device copy [bf16 weights][f32 biases][rows x 32 bf16 inputs][rows f32 out]
+  std::vector<float> scorer_model;
   bool scorer_loaded = false;
+  bbtn::DevBuf scorer_dev;
   bbtn::Prof prof;         // kernel timing (off unless enabled)
 };

@@ -53,6 +53,12 @@ TuneVal choose_tiles(bbtn_ctx* ctx, int k, int64_t batch, int64_t M, int64_t N, 
     int64_t sp = std::min<int64_t>(K / 64, (2048 + tiles - 1) / tiles);
     tv.splits = (int)std::max<int64_t>(1, std::min<int64_t>(sp, 256));
   }
+  // measured choice for products large enough to matter
+  if (ctx->opt.autotune_cache && (double)batch * M * N * K >= (double)(1 << 24)) {
+    tv = autotune_shape(ctx, k, batch, M, N, K, tv);
+    ctx->tune[key] = tv;
+    save_tune_cache(ctx, ctx->opt.autotune_cache);
+  }
   return tv;
 }
 

@@ -18,7 +18,14 @@ struct BaseDev {
 void upload_base(bbtn_ctx* ctx, const Network& net, const int* prime_idx, int k,
                  BaseDev& bd, DevBuf& buf);
 
-// Pick a tile configuration (and split-K factor) for one product.
+// Time the candidate tile configurations for one shape bucket.
+TuneVal autotune_shape(bbtn_ctx* ctx, int k, int64_t batch, int64_t M, int64_t N, int64_t K,
+                       const TuneVal& heuristic);
+void save_tune_cache(bbtn_ctx* ctx, const char* path);
+
+// Pick a tile configuration (and split-K factor) for one product: the
+// autotuner's cached choice, else (tuning when a cache path is set) a
+// measured one, else a shape heuristic.
 TuneVal choose_tiles(bbtn_ctx* ctx, int k, int64_t batch, int64_t M, int64_t N, int64_t K);
 
 // Run the program `g` for L branches.  assign[l * |S| + j] is the state of

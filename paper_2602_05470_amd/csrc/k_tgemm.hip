@@ -21,8 +21,8 @@
 namespace bbtn {
 
 const TileCfg kTileCfgs[N_TILE_CFGS] = {
-    {64, 64, 4, 4, 16},   // 0: large tiles, 256 threads
-    {32, 32, 2, 2, 16},   // 1: medium, 256 threads
+    {64, 64, 4, 4, 24},   // 0: large tiles, 256 threads (TK a multiple of 3: one fold per 3 steps)
+    {32, 32, 2, 2, 24},   // 1: medium, 256 threads
     {16, 16, 1, 1, 16},   // 2: small, 256 threads
     {8, 64, 1, 2, 16},    // 3: few rows, 256 threads
     {64, 8, 2, 1, 16},    // 4: few columns, 256 threads
@@ -144,6 +144,11 @@ tgemm_kernel(const GemmArgs a) {
     for (int r = 0; r < RM; ++r)
 #pragma unroll
       for (int c = 0; c < RN; ++c) any_finite |= (V[r][c] > NEG_CUT);
+    uint32_t vm1[RM][RN];
+#pragma unroll
+    for (int r = 0; r < RM; ++r)
+#pragma unroll
+      for (int c = 0; c < RN; ++c) vm1[r][c] = (uint32_t)V[r][c] - 1u;
     // ---- pass 2: counts of the q reaching V (skipped by tiles with no
     // finite output, e.g. fully constrained independent-set blocks)
     if (__syncthreads_or(any_finite)) {
@@ -153,7 +158,8 @@ tgemm_kernel(const GemmArgs a) {
           const int64_t m = m0 + i, q = k0 + j;
           const bool in = (m < a.M && q < kend);
           const int64_t o = m * a.K + q;
-          Av[j][i] = in ? (int32_t)Ab[o] : NEG;
+          // pass 2 stages negated values: the tie test below is one add3
+          Av[j][i] = in ? -(int32_t)Ab[o] : -NEG;
 #pragma unroll
           for (int p = 0; p < KR; ++p) Ac[p][j][i] = in ? Ab[(p + 1) * a.pA + o] : 0u;
         }
@@ -162,7 +168,7 @@ tgemm_kernel(const GemmArgs a) {
           const int64_t n = n0 + i, q = k0 + j;
           const bool in = (n < a.N && q < kend);
           const int64_t o = q * a.N + n;
-          Bv[j][i] = in ? (int32_t)Bb[o] : NEG;
+          Bv[j][i] = in ? -(int32_t)Bb[o] : -NEG;
 #pragma unroll
           for (int p = 0; p < KR; ++p) Bc[p][j][i] = in ? Bb[(p + 1) * a.pB + o] : 0u;
         }
@@ -182,14 +188,18 @@ tgemm_kernel(const GemmArgs a) {
 #pragma unroll
             for (int c = 0; c < RN; ++c) bc[p][c] = Bc[p][kk][tx * RN + c];
           }
+          // tie test without a compare: x = V - 1 - a - b is -1 exactly on a
+          // tie and >= 0 otherwise (a + b <= V), so x >> 31 is the tie mask.
+          // Sums that wrap involve stored zeros, whose residues are 0.
 #pragma unroll
           for (int r = 0; r < RM; ++r)
 #pragma unroll
             for (int c = 0; c < RN; ++c) {
-              const bool eq = (av[r] + bv[c] == V[r][c]);
+              const uint32_t x = (uint32_t)av[r] + (uint32_t)bv[c] + vm1[r][c];
+              const uint32_t msk = (uint32_t)((int32_t)x >> 31);
 #pragma unroll
               for (int p = 0; p < KR; ++p)
-                acc[p][r][c] += (uint64_t)(eq ? ac[p][r] : 0u) * bc[p][c];
+                acc[p][r][c] += (uint64_t)(ac[p][r] & msk) * bc[p][c];
             }
           // at most three products (< 2^62 each) between folds (< 2^54)
           if (kk % 3 == 2 || kk == TK - 1) {
@@ -236,8 +246,8 @@ static void launch_cfg(int cfg, dim3 grid, const GemmArgs& a, hipStream_t st) {
     hipLaunchKernelGGL((tgemm_kernel<KR, TM, TN, RM, RN, TK>), grid,          \
                        dim3((TM / RM) * (TN / RN)), 0, st, a);                \
     break;
-    BBTN_TG_CASE(0, 64, 64, 4, 4, 16)
-    BBTN_TG_CASE(1, 32, 32, 2, 2, 16)
+    BBTN_TG_CASE(0, 64, 64, 4, 4, 24)
+    BBTN_TG_CASE(1, 32, 32, 2, 2, 24)
     BBTN_TG_CASE(2, 16, 16, 1, 1, 16)
     BBTN_TG_CASE(3, 8, 64, 1, 2, 16)
     BBTN_TG_CASE(4, 64, 8, 2, 1, 16)

@@ -1,5 +1,7 @@
 #include "search.h"
 
+#include "scorer.h"
+
 #include <chrono>
 #include <cmath>
 #include <map>
@@ -163,6 +165,7 @@ struct Searcher {
     double gamma = INFINITY;
     std::vector<int32_t> region;
     std::vector<Cube> cubes;
+    std::unordered_map<uint32_t, int64_t> drho;  // rho reduction per fixed subset
   };
 
   Eval evaluate(const Node& n, const std::vector<int32_t>& R) {
@@ -220,6 +223,30 @@ struct Searcher {
         tb.val[y] = tensor_max(T, n.fixed, n.x, rpos[i].data(), rx);
       }
     }
+    // Nothing can be pruned when every region variable is on the boundary
+    // (boundary equivalence has one configuration per boundary state), no
+    // tensor has an infeasible entry under any region state, and even the
+    // smallest bound over region states reaches the incumbent.  Then F(R) is
+    // every configuration and the enumeration below is skipped.
+    {
+      bool may_prune = bmask != nx - 1;
+      int64_t minb = n.bound;
+      for (const Tab& tb : tabs) {
+        int64_t mn = INT64_MAX;
+        for (int64_t v : tb.val) mn = std::min(mn, v);
+        if (mn == INT64_MIN) { may_prune = true; break; }
+        minb += mn - tb.base;
+      }
+      if (!may_prune && minb >= opt.incumbent) {
+        ev.cubes.reserve(nx);
+        for (uint32_t x = 0; x < nx; ++x) ev.cubes.push_back(Cube{nx - 1, x});
+        std::vector<int32_t> vs(R.begin(), R.end());
+        const int64_t d = drho(n, vs);
+        ev.drho[nx - 1] = d;
+        ev.gamma = gamma_of({{d, (int64_t)nx}});
+        return ev;
+      }
+    }
     std::vector<int64_t> local(nx), bnd(nx);
     std::vector<int64_t> gmaxv(nx, INT64_MIN);  // indexed by x & bmask
     for (uint32_t x = 0; x < nx; ++x) {
@@ -254,6 +281,7 @@ struct Searcher {
         if (mask >> j & 1) vs.push_back(R[j]);
       const int64_t d = drho(n, vs);
       dcache[mask] = d;
+      ev.drho[mask] = d;
       return d;
     };
     auto gam = [&](const std::vector<Cube>& cs) {
@@ -299,6 +327,96 @@ struct Searcher {
     return ev;
   }
 
+  // lowest gamma; on a tie (within 1e-9 relative) the larger step, which
+  // reaches the same leaves through fewer search nodes
+  static bool better(const Eval& ev, const Eval& best) {
+    const double tol = 1e-9 * std::max(1.0, std::isfinite(best.gamma) ? best.gamma : 1.0);
+    return ev.gamma < best.gamma - tol ||
+           (std::fabs(ev.gamma - best.gamma) <= tol && ev.cubes.size() > best.cubes.size());
+  }
+
+  // Grow a region from `seed` by adjacency (highest score first, lowest id on
+  // ties) and keep the best branching rule over its prefixes.
+  Eval best_from_seed(const Node& n, int seed, const std::vector<double>& score) {
+    std::vector<int32_t> order{seed};
+    while ((int)order.size() < opt.region_max) {
+      int pick = -1;
+      for (int v : order)
+        for (int u : nbr[v]) {
+          if (bit_get(n.fixed, u)) continue;
+          if (std::find(order.begin(), order.end(), u) != order.end()) continue;
+          if (pick < 0 || score[u] > score[pick] || (score[u] == score[pick] && u < pick)) pick = u;
+        }
+      if (pick < 0) break;
+      order.push_back(pick);
+    }
+    Eval best;
+    for (int r = 1; r <= (int)order.size(); ++r) {
+      std::vector<int32_t> R(order.begin(), order.begin() + r);
+      Eval ev = evaluate(n, R);
+      if (better(ev, best)) best = std::move(ev);
+      if (best.gamma == 0.0) break;
+    }
+    return best;
+  }
+
+  void heuristic(const Node& n, std::vector<double>& heur, std::vector<int32_t>& cand) {
+    cand.clear();
+    for (int v = 0; v < net.n; ++v) {
+      heur[v] = 0;
+      if (bit_get(n.fixed, v)) continue;
+      double s = 0;
+      for (int id : tree.var_nodes[v]) s += std::max(0, n.sizes[id] - opt.log2_target);
+      heur[v] = s;
+      if (s > 0) cand.push_back(v);
+    }
+  }
+
+  // Children of a node under a branching rule: bounded, pruned if below the
+  // incumbent (strict).
+  void children(const Node& n, const Eval& best, std::vector<Node>& out, SearchStats& st) {
+    // tensors touched by the region and their largest entries at the node
+    std::vector<int32_t> tt;
+    for (int v : best.region) tt.insert(tt.end(), var_tensors[v].begin(), var_tensors[v].end());
+    std::sort(tt.begin(), tt.end());
+    tt.erase(std::unique(tt.begin(), tt.end()), tt.end());
+    std::vector<int64_t> base_max(tt.size());
+    for (size_t i = 0; i < tt.size(); ++i) base_max[i] = tensor_max(net.tensors[tt[i]], n.fixed, n.x);
+    for (int ci = (int)best.cubes.size() - 1; ci >= 0; --ci) {
+      const Cube& c = best.cubes[ci];
+      Node ch;
+      ch.fixed = n.fixed;
+      ch.x = n.x;
+      std::vector<int32_t> newly;
+      for (int j = 0; j < (int)best.region.size(); ++j)
+        if (c.mask >> j & 1) {
+          const int v = best.region[j];
+          bit_set(ch.fixed, v);
+          ch.x[v] = (uint8_t)((c.val >> j) & 1);
+          newly.push_back(v);
+        }
+      // bound: only tensors holding a newly fixed variable change
+      int64_t b = n.bound;
+      for (size_t i = 0; i < tt.size() && b != INT64_MIN; ++i) {
+        const BaseTensor& T = net.tensors[tt[i]];
+        bool hit = false;
+        for (int v : T.vars)
+          if (std::find(newly.begin(), newly.end(), v) != newly.end()) { hit = true; break; }
+        if (!hit) continue;
+        const int64_t m = tensor_max(T, ch.fixed, ch.x);
+        b = (m == INT64_MIN) ? INT64_MIN : b + (m - base_max[i]);
+      }
+      ch.bound = b;
+      if (ch.bound == INT64_MIN || ch.bound < opt.incumbent) { st.pruned++; continue; }
+      ch.sizes = n.sizes;
+      for (int v : newly)
+        for (int id : tree.var_nodes[v]) ch.sizes[id]--;
+      auto it = best.drho.find(c.mask);
+      ch.rho = it != best.drho.end() ? n.rho - it->second : rho_of(tree, ch.sizes, opt.log2_target);
+      out.push_back(std::move(ch));
+    }
+  }
+
   void emit(const Node& n, std::vector<LeafGroup>& leaves) {
     auto it = group_of.find(n.fixed);
     int gi;
@@ -342,14 +460,7 @@ struct Searcher {
       }
       // overflow participation of every free variable
       std::vector<int32_t> cand;
-      for (int v = 0; v < net.n; ++v) {
-        heur[v] = 0;
-        if (bit_get(n.fixed, v)) continue;
-        double s = 0;
-        for (int id : tree.var_nodes[v]) s += std::max(0, n.sizes[id] - opt.log2_target);
-        heur[v] = s;
-        if (s > 0) cand.push_back(v);
-      }
+      heuristic(n, heur, cand);
       score = heur;
       if (opt.scorer) opt.scorer(n.fixed, n.sizes, heur, score);
       std::stable_sort(cand.begin(), cand.end(), [&](int a, int b) {
@@ -360,63 +471,94 @@ struct Searcher {
       Eval best;
       const int n_seeds = std::min<int>(2, (int)cand.size());
       for (int si = 0; si < n_seeds; ++si) {
-        std::vector<int32_t> order{cand[si]};
-        while ((int)order.size() < opt.region_max) {
-          int pick = -1;
-          for (int v : order)
-            for (int u : nbr[v]) {
-              if (bit_get(n.fixed, u)) continue;
-              if (std::find(order.begin(), order.end(), u) != order.end()) continue;
-              if (pick < 0 || score[u] > score[pick] || (score[u] == score[pick] && u < pick)) pick = u;
-            }
-          if (pick < 0) break;
-          order.push_back(pick);
-        }
-        for (int r = 1; r <= (int)order.size(); ++r) {
-          std::vector<int32_t> R(order.begin(), order.begin() + r);
-          Eval ev = evaluate(n, R);
-          // lowest gamma; on a tie (within 1e-9 relative) the larger step,
-          // which reaches the same leaves through fewer search nodes
-          const double tol = 1e-9 * std::max(1.0, best.gamma);
-          if (ev.gamma < best.gamma - tol ||
-              (std::fabs(ev.gamma - best.gamma) <= tol && ev.cubes.size() > best.cubes.size())) {
-            best = std::move(ev);
-          }
-          if (best.gamma == 0.0) break;  // every configuration pruned
-        }
-        if (best.gamma == 0.0) break;
+        Eval ev = best_from_seed(n, cand[si], score);
+        if (better(ev, best)) best = std::move(ev);
+        if (best.gamma == 0.0) break;  // every configuration pruned
       }
-      if (opt.record) opt.record(n.fixed, n.sizes, best.region, best.gamma, (int)best.cubes.size());
       if (best.cubes.empty()) { st.pruned++; continue; }
       if (!std::isfinite(best.gamma)) throw Error(BBTN_E_INTERNAL, "no branching rule reduces rho");
       st.gamma_sum += best.gamma;
       // children, first cube on top of the stack
-      for (int ci = (int)best.cubes.size() - 1; ci >= 0; --ci) {
-        const Cube& c = best.cubes[ci];
-        Node ch;
-        ch.fixed = n.fixed;
-        ch.x = n.x;
-        std::vector<int32_t> newly;
-        for (int j = 0; j < (int)best.region.size(); ++j)
-          if (c.mask >> j & 1) {
-            const int v = best.region[j];
-            bit_set(ch.fixed, v);
-            ch.x[v] = (uint8_t)((c.val >> j) & 1);
-            newly.push_back(v);
-          }
-        ch.bound = node_bound(net, ch.fixed, ch.x);
-        if (ch.bound == INT64_MIN || ch.bound < opt.incumbent) { st.pruned++; continue; }
-        ch.sizes = n.sizes;
-        for (int v : newly)
-          for (int id : tree.var_nodes[v]) ch.sizes[id]--;
-        ch.rho = rho_of(tree, ch.sizes, opt.log2_target);
-        stack.push_back(std::move(ch));
-      }
+      children(n, best, stack, st);
     }
   }
 };
 
 }  // namespace
+
+void collect_training(const Network& net, const Tree& tree, int log2_target, int region_max,
+                      int64_t incumbent, int max_nodes, int cand_per_node,
+                      std::vector<float>& X, std::vector<float>& y) {
+  SearchOptions opt;
+  opt.log2_target = log2_target;
+  opt.region_max = region_max;
+  opt.incumbent = incumbent;
+  Searcher s(net, tree, opt);
+  FeatureCtx fc(net, tree, log2_target);
+  Node root;
+  root.fixed.assign((net.n + 63) / 64, 0);
+  root.x.assign(net.n, 0);
+  root.sizes = node_sizes(tree, root.fixed);
+  root.rho = rho_of(tree, root.sizes, log2_target);
+  root.bound = node_bound(net, root.fixed, root.x);
+  if (root.bound == INT64_MIN || root.bound < incumbent || root.rho == 0) return;
+  std::vector<Node> stack;
+  stack.push_back(std::move(root));
+  std::vector<double> heur(net.n);
+  std::vector<int32_t> cand;
+  SearchStats st;
+  uint64_t rng = 0x9E3779B97F4A7C15ull ^ (uint64_t)net.n;
+  auto next = [&]() {
+    rng ^= rng << 13; rng ^= rng >> 7; rng ^= rng << 17;
+    return rng;
+  };
+  int done = 0;
+  float f[N_FEAT];
+  while (!stack.empty() && done < max_nodes) {
+    Node n = std::move(stack.back());
+    stack.pop_back();
+    if (n.rho == 0) continue;
+    s.heuristic(n, heur, cand);
+    if (cand.empty()) continue;
+    std::stable_sort(cand.begin(), cand.end(), [&](int a, int b) {
+      if (heur[a] != heur[b]) return heur[a] > heur[b];
+      return a < b;
+    });
+    // candidates: the best half by the heuristic and a random other half
+    std::vector<int32_t> pick;
+    for (int i = 0; i < (int)cand.size() && (int)pick.size() < cand_per_node / 2; ++i) pick.push_back(cand[i]);
+    for (int tries = 0; tries < 4 * cand_per_node && (int)pick.size() < cand_per_node; ++tries) {
+      const int v = cand[next() % cand.size()];
+      if (std::find(pick.begin(), pick.end(), v) == pick.end()) pick.push_back(v);
+    }
+    Searcher::Eval chosen;
+    for (int v : pick) {
+      Searcher::Eval ev = s.best_from_seed(n, v, heur);
+      // label: log2 (1 + sum over surviving children of 2^tc(child))
+      std::map<uint32_t, double> tc_of;
+      double total = 0;
+      for (auto& c : ev.cubes) {
+        auto it = tc_of.find(c.mask);
+        if (it == tc_of.end()) {
+          std::vector<uint64_t> fx = n.fixed;
+          for (int j = 0; j < (int)ev.region.size(); ++j)
+            if (c.mask >> j & 1) bit_set(fx, ev.region[j]);
+          it = tc_of.emplace(c.mask, complexity(tree, fx).tc_log2).first;
+        }
+        total += std::exp2(it->second);
+      }
+      fc.features(v, n.fixed, n.sizes, heur, n.rho, f);
+      X.insert(X.end(), f, f + N_FEAT);
+      y.push_back((float)std::log2(1.0 + total));
+      if (v == cand[0] || (v == cand[std::min<size_t>(1, cand.size() - 1)] && Searcher::better(ev, chosen)))
+        if (Searcher::better(ev, chosen)) chosen = std::move(ev);
+    }
+    ++done;
+    // continue the search with the heuristic's choice
+    if (chosen.cubes.empty() || !std::isfinite(chosen.gamma)) continue;
+    s.children(n, chosen, stack, st);
+  }
+}
 
 void bb_search(const Network& net, const Tree& tree, const SearchOptions& opt,
                std::vector<LeafGroup>& leaves, SearchStats& stats) {

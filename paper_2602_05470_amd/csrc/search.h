@@ -40,10 +40,6 @@ struct SearchOptions {
   int64_t incumbent = INT64_MIN;  // value of a known configuration (max form)
   double deadline = 0;            // absolute wall time (s) or 0
   VarScorer scorer;
-  // optional sink for per-node training records (features, outcome)
-  std::function<void(const std::vector<uint64_t>& fixed, const std::vector<int16_t>& sizes,
-                     const std::vector<int32_t>& region, double gamma, int n_children)>
-      record;
 };
 
 void bb_search(const Network& net, const Tree& tree, const SearchOptions& opt,

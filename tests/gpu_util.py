@@ -14,7 +14,7 @@ def to_dev(torch, val, res):
     """(int32 values [E], uint32 residues [k, E]) -> int32 device buffer of
     (1 + k) * E words: value plane, then residue planes."""
     val = np.ascontiguousarray(val, dtype=np.int32).reshape(-1)
-    res = np.ascontiguousarray(res, dtype=np.uint32).reshape(res.shape[0], -1)
+    res = np.ascontiguousarray(res, dtype=np.uint32).reshape(res.shape[0], val.size)
     host = np.concatenate([val.view(np.int32), res.view(np.int32).reshape(-1)])
     return torch.from_numpy(host).to("cuda")
 

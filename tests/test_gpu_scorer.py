@@ -1,0 +1,150 @@
+"""Learned-scorer kernels on the GPU against the float64 oracle: forward
+scores within 1e-3 relative, gradients within 1e-3 relative (per parameter
+block, L2), Adam step on the float32 master copy, deterministic training,
+and exactness of solves that use a trained scorer."""
+import os
+
+import numpy as np
+import pytest
+
+import instances as I
+from oracle import mlp as O, tm
+from tests.gpu_util import torch_cuda
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def B():
+    torch_cuda()
+    import paper_2602_05470_amd as B
+    return B
+
+
+def _pack(B, P):
+    W = np.concatenate([P["W1"].reshape(-1), P["W2"].reshape(-1), P["w3"].reshape(-1)])
+    b = np.concatenate([P["b1"], P["b2"], [P["b3"]]]).astype(np.float32)
+    return I.to_bf16_bits(W), b
+
+
+def _decode(B, Wbits, b):
+    Wd = O.decode_bf16(Wbits)
+    W1 = Wd[:128 * 32].reshape(128, 32)
+    W2 = Wd[128 * 32:128 * 32 + 128 * 128].reshape(128, 128)
+    w3 = Wd[128 * 32 + 128 * 128:]
+    return W1, b[:128].astype(np.float64), W2, b[128:256].astype(np.float64), w3, float(b[256])
+
+
+@pytest.mark.parametrize("rows", [1, 63, 64, 200, 1000])
+def test_forward_matches_oracle(B, rows):
+    torch = torch_cuda()
+    P = I.mlp_params(rows)
+    Wbits, b = _pack(B, P)
+    X = np.random.default_rng(rows).normal(size=(rows, 32)).astype(np.float32)
+    Xbits = I.to_bf16_bits(X)
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    y = torch.zeros(rows, dtype=torch.float32, device="cuda")
+    h1 = torch.zeros(rows * 128, dtype=torch.float32, device="cuda")
+    h2 = torch.zeros(rows * 128, dtype=torch.float32, device="cuda")
+    with B.Context() as ctx:
+        ctx.mlp_forward(rows, dev(Xbits.view(np.int16)), dev(Wbits.view(np.int16)), dev(b), y, h1, h2)
+        torch.cuda.synchronize()
+    want, wh1, wh2 = O.forward(O.decode_bf16(Xbits), *_decode(B, Wbits, b))
+    got = y.cpu().numpy().astype(np.float64)
+    assert np.all(np.abs(got - want) <= 1e-3 * np.maximum(1.0, np.abs(want)))
+    assert np.allclose(h1.cpu().numpy().reshape(rows, 128), wh1, rtol=1e-4, atol=1e-5)
+    assert np.allclose(h2.cpu().numpy().reshape(rows, 128), wh2, rtol=1e-4, atol=1e-5)
+
+
+@pytest.mark.parametrize("rows", [5, 64, 300])
+def test_backward_matches_oracle(B, rows):
+    torch = torch_cuda()
+    P = I.mlp_params(100 + rows)
+    Wbits, b = _pack(B, P)
+    rng = np.random.default_rng(rows)
+    X = rng.normal(size=(rows, 32)).astype(np.float32)
+    t = rng.normal(size=rows).astype(np.float32)
+    Xbits = I.to_bf16_bits(X)
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    y = torch.zeros(rows, dtype=torch.float32, device="cuda")
+    h1 = torch.zeros(rows * 128, dtype=torch.float32, device="cuda")
+    h2 = torch.zeros(rows * 128, dtype=torch.float32, device="cuda")
+    g = torch.zeros(B.MLP_NPARAM + 1, dtype=torch.float32, device="cuda")
+    dX, dW, db, dt = dev(Xbits.view(np.int16)), dev(Wbits.view(np.int16)), dev(b), dev(t)
+    with B.Context() as ctx:
+        ctx.mlp_forward(rows, dX, dW, db, y, h1, h2)
+        ctx.mlp_backward(rows, dX, dW, y, dt, h1, h2, g)
+        torch.cuda.synchronize()
+    params = _decode(B, Wbits, b)
+    loss, want = O.loss_and_grads(O.decode_bf16(Xbits), t.astype(np.float64), *params)
+    got = g.cpu().numpy().astype(np.float64)
+    nw1, nw2 = 128 * 32, 128 * 128
+    blocks = {"W1": got[:nw1], "W2": got[nw1:nw1 + nw2], "w3": got[nw1 + nw2:nw1 + nw2 + 128],
+              "b1": got[B.MLP_NW:B.MLP_NW + 128], "b2": got[B.MLP_NW + 128:B.MLP_NW + 256],
+              "b3": got[B.MLP_NW + 256:B.MLP_NW + 257]}
+    for name, arr in blocks.items():
+        w = np.atleast_1d(want[name]).reshape(-1)
+        err = np.linalg.norm(arr - w) / max(np.linalg.norm(w), 1e-12)
+        assert err <= 1e-3, (name, err)
+    assert abs(got[-1] / rows - loss) <= 1e-3 * max(1.0, loss)
+
+
+def test_adam_step_matches_oracle(B):
+    torch = torch_cuda()
+    n = B.MLP_NPARAM
+    rng = np.random.default_rng(1)
+    master = rng.normal(size=n).astype(np.float32)
+    m = rng.normal(size=n).astype(np.float32) * 0.01
+    v = np.abs(rng.normal(size=n)).astype(np.float32) * 0.01
+    g = rng.normal(size=n + 1).astype(np.float32)
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    dmaster, dm, dv = dev(master), dev(m), dev(v)
+    W = torch.zeros(B.MLP_NW, dtype=torch.int16, device="cuda")
+    bias = torch.zeros(B.MLP_NB, dtype=torch.float32, device="cuda")
+    with B.Context() as ctx:
+        ctx.mlp_adam(dmaster, W, bias, dm, dv, dev(g), 1e-2, 0.9, 0.999, 1e-8, 3)
+        torch.cuda.synchronize()
+    p, mm, vv = O.adam_step(master.astype(np.float64), g[:n].astype(np.float64),
+                            m.astype(np.float64), v.astype(np.float64), lr=1e-2, t=3)
+    gm = dmaster.cpu().numpy().astype(np.float64)
+    assert np.allclose(gm, p, rtol=1e-5, atol=1e-6)
+    assert np.allclose(dm.cpu().numpy(), mm, rtol=1e-5, atol=1e-7)
+    wbits = W.cpu().numpy().view(np.uint16)
+    assert np.array_equal(wbits, O.encode_bf16(dmaster.cpu().numpy()[:B.MLP_NW]))
+    assert np.array_equal(bias.cpu().numpy(), dmaster.cpu().numpy()[B.MLP_NW:])
+
+
+def test_training_reduces_loss_and_is_deterministic(B, tmp_path):
+    rng = np.random.default_rng(0)
+    X = rng.normal(size=(3000, 32)).astype(np.float32)
+    y = (np.sin(X[:, 0]) + 0.5 * X[:, 1] * X[:, 2] + 0.1 * X[:, 3]).astype(np.float32)
+    with B.Context() as ctx:
+        l1 = ctx.scorer_train(X, y, epochs=15, batch=256, lr=2e-3, seed=7,
+                              save_path=str(tmp_path / "a.bin"))
+        l2 = ctx.scorer_train(X, y, epochs=15, batch=256, lr=2e-3, seed=7,
+                              save_path=str(tmp_path / "b.bin"))
+    assert l1[-1] < 0.7 * l1[0]
+    assert np.array_equal(l1, l2)
+    assert open(tmp_path / "a.bin", "rb").read() == open(tmp_path / "b.bin", "rb").read()
+
+
+def test_collect_and_scorer_keeps_results_exact(B, tmp_path):
+    X, y = [], []
+    with B.Context(B.Options(region_max=6)) as ctx:
+        for s in range(3):
+            g = I.spin_glass_square(10, 500 + s)
+            Xi, yi = ctx.scorer_collect(0, g["n"], g["edges"], g["J"], log2_target=6,
+                                        max_nodes=20, cand_per_node=6)
+            X.append(Xi)
+            y.append(yi)
+        X, y = np.concatenate(X), np.concatenate(y)
+        assert len(y) > 20 and np.all(np.isfinite(X)) and np.all(np.isfinite(y))
+        path = str(tmp_path / "w.bin")
+        ctx.scorer_train(X, y, epochs=5, batch=128, lr=1e-3, seed=1, save_path=path)
+    g = I.spin_glass_square(12, 3)
+    want = tm.spin_glass_square(g)
+    for branching in (1, 2):
+        with B.Context(B.Options(log2_target=7, branching=branching,
+                                 scorer_weights=path if branching == 2 else None)) as ctx:
+            r = ctx.solve_spinglass(g["n"], g["edges"], g["J"])
+        assert (r.value, r.count) == want

@@ -331,3 +331,47 @@ def test_crt_round_trip():
         M *= p
     for x in [0, 1, 2, M - 1, M // 3] + [int(rng.integers(0, 2**62)) * int(rng.integers(0, 2**60)) % M for _ in range(50)]:
         assert crt.crt([x % p for p in primes], primes) == x
+
+
+# --------------------------------------------------------------- MLP oracle
+def test_mlp_gradients_by_finite_differences():
+    from oracle import mlp
+    rng = np.random.default_rng(3)
+    P = I.mlp_params(5)
+    P = {k: np.asarray(v, np.float64) for k, v in P.items()}
+    X = rng.normal(size=(7, 32))
+    t = rng.normal(size=7)
+    names = ["W1", "b1", "W2", "b2", "w3", "b3"]
+    loss, g = mlp.loss_and_grads(X, t, *[P[n] for n in names])
+    eps = 1e-6
+    for n in names:
+        arr = np.atleast_1d(P[n]).astype(np.float64)
+        flat = arr.reshape(-1)
+        for idx in rng.choice(flat.size, size=min(6, flat.size), replace=False):
+            up = flat.copy(); up[idx] += eps
+            dn = flat.copy(); dn[idx] -= eps
+            def L(vals):
+                Q = dict(P)
+                Q[n] = vals.reshape(arr.shape) if np.ndim(P[n]) else float(vals[0])
+                return mlp.loss_and_grads(X, t, *[Q[m] for m in names])[0]
+            fd = (L(up) - L(dn)) / (2 * eps)
+            an = np.atleast_1d(g[n]).reshape(-1)[idx]
+            assert abs(fd - an) <= 1e-6 * max(1.0, abs(fd)), (n, idx, fd, an)
+
+
+def test_adam_first_step_closed_form():
+    from oracle import mlp
+    # with m = v = 0 at t = 1 the bias-corrected step is lr * g / (|g| + eps)
+    p, m, v = mlp.adam_step(np.array([1.0, -2.0]), np.array([0.5, -3.0]), np.zeros(2),
+                            np.zeros(2), lr=0.1, t=1)
+    assert np.allclose(p, [1.0 - 0.1 * 0.5 / (0.5 + 1e-8), -2.0 + 0.1 * 3.0 / (3.0 + 1e-8)])
+
+
+def test_bf16_decode_is_exact():
+    from oracle import mlp
+    x = np.array([1.0, -2.5, 3.140625, 1e-3, 65504.0], np.float32)
+    bits = I.to_bf16_bits(x)
+    back = mlp.decode_bf16(bits)
+    # bf16 keeps 8 significant bits: relative rounding error below 2^-8
+    assert np.all(np.abs(back - x) <= np.abs(x) * 2.0 ** -8)
+    assert back[0] == 1.0 and back[1] == -2.5 and back[2] == 3.140625
