@@ -79,6 +79,9 @@ typedef struct {
   int32_t region_max;        /* largest branching region |R| (<= 16)            */
   int32_t local_search;      /* > 0: seed the incumbent of global pruning with
                                 this many local-search sweeps                   */
+  int32_t graphs;            /* 1: a step program that runs repeatedly (chunks,
+                                one branch at a time) is captured once into a
+                                hipGraph and replayed; 0: plain launches        */
   const char* scorer_weights;/* path of learned-scorer weights, or NULL         */
   const char* autotune_cache;/* path of the tile autotuner cache, or NULL       */
   double time_limit_s;       /* <= 0: none                                      */
@@ -263,7 +266,8 @@ bbtn_status bbtn_scorer_load(bbtn_ctx* ctx, const char* path);
  * with T_target = 2^log2_target for up to max_nodes nodes; at each node,
  * cand_per_node candidate seed variables give one row each: 32 features and
  * the label log2(1 + sum over the children that survive pruning of
- * 2^(time complexity of the child)).  Host arrays X[capacity*32], y[capacity];
+ * 2^(time complexity of the child)), minus the smallest such label among the
+ * node's candidates (the scorer ranks the candidates of one node).  Host arrays X[capacity*32], y[capacity];
  * *rows receives the row count (pass X = y = NULL to query it).  Host-only:
  * ctx may be NULL (region size 8) or a context (its region_max). */
 bbtn_status bbtn_scorer_collect(bbtn_ctx* ctx, int32_t kind, int32_t n, int32_t m,

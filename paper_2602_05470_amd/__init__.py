@@ -36,6 +36,7 @@ class _Options(C.Structure):
                 ("max_primes", C.c_int32), ("log2_target", C.c_int32),
                 ("branching", C.c_int32), ("batched", C.c_int32),
                 ("region_max", C.c_int32), ("local_search", C.c_int32),
+                ("graphs", C.c_int32),
                 ("scorer_weights", C.c_char_p), ("autotune_cache", C.c_char_p),
                 ("time_limit_s", C.c_double), ("stream", C.c_void_p)]
 
@@ -137,6 +138,7 @@ class Options:
     batched: int = 1
     region_max: int = 8
     local_search: int = 200
+    graphs: int = 1
     scorer_weights: str | None = None
     autotune_cache: str | None = None
     time_limit_s: float = 0.0
@@ -146,7 +148,7 @@ class Options:
         o = _Options()
         load().bbtn_default_options(C.byref(o))
         for f in ("device", "residues_per_pass", "max_primes", "log2_target", "branching",
-                  "batched", "region_max", "local_search", "time_limit_s"):
+                  "batched", "region_max", "local_search", "graphs", "time_limit_s"):
             setattr(o, f, getattr(self, f))
         o.scorer_weights = self.scorer_weights.encode() if self.scorer_weights else None
         o.autotune_cache = self.autotune_cache.encode() if self.autotune_cache else None

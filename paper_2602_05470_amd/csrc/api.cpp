@@ -125,7 +125,8 @@ void run_pass(bbtn_ctx* ctx, const Network& net, const std::vector<LeafGroup>& g
       const int64_t L = std::min<int64_t>(chunk, (int64_t)(sel[gi].size() - c0));
       ctx->leafout.ensure((size_t)(1 + k) * L * 4);
       const DevTensor o{ctx->leafout.as<uint32_t>(), L};
-      run_group(ctx, net, g, bd, mod, &asg[gi][c0 * S], L, o, st);
+      run_group(ctx, net, g, bd, mod, &asg[gi][c0 * S], L, o, st,
+                /*reuse=*/sel[gi].size() > (size_t)chunk);
       std::vector<uint32_t> h((size_t)(1 + k) * L);
       BBTN_HIP(hipMemcpyAsync(h.data(), o.ptr, h.size() * 4, hipMemcpyDeviceToHost, st));
       BBTN_HIP(hipStreamSynchronize(st));
@@ -150,7 +151,15 @@ void recover_config(bbtn_ctx* ctx, const Network& net, const Tree& tree, const L
     ctx->leafout.ensure(64);
     const DevTensor o{ctx->leafout.as<uint32_t>(), 1};
     const uint64_t macs0 = ctx->last_macs;
-    run_group(ctx, net, g, bd, mod, &G.assign[leaf * G.vars.size()], 1, o, st);
+    if (ctx->opt.batched && persist_fits(g, 0)) {
+      // one persistent launch (one workgroup: its scratch starts at the
+      // workspace base, where the traceback reads)
+      std::vector<uint32_t> tmp;
+      std::vector<PersistJob> jobs{PersistJob{&g, &G.assign[leaf * G.vars.size()], 1, &tmp}};
+      run_persistent(ctx, net, jobs, bd, mod, st);
+    } else {
+      run_group(ctx, net, g, bd, mod, &G.assign[leaf * G.vars.size()], 1, o, st);
+    }
     ctx->last_macs = macs0;  // bookkeeping counts the counting passes only
     // traceback program
     std::vector<TraceStep> ts;
@@ -210,6 +219,11 @@ void solve_network(bbtn_ctx* ctx, Network& net, const std::vector<uint8_t>& ls_x
   const double t0 = now_s();
   const bbtn_options& opt = ctx->opt;
   ctx->last_macs = 0;
+  ctx->clear_graphs();  // captured programs refer to the previous solve's plans
+  struct GraphScope {
+    bbtn_ctx* c;
+    ~GraphScope() { c->clear_graphs(); }
+  } graph_scope{ctx};
   for (int i = 0; i < 8; ++i) res->seconds[i] = 0;
   const double deadline = opt.time_limit_s > 0 ? t0 + opt.time_limit_s : 0;
   Tree tree = greedy_tree(net);
@@ -397,6 +411,7 @@ void bbtn_default_options(bbtn_options* o) {
   o->batched = 1;
   o->region_max = 8;
   o->local_search = 200;
+  o->graphs = 1;
   o->scorer_weights = nullptr;
   o->autotune_cache = nullptr;
   o->time_limit_s = 0;
@@ -446,6 +461,7 @@ void bbtn_destroy(bbtn_ctx* ctx) {
   ctx->leafout.release();
   ctx->misc.release();
   ctx->persist.release();
+  ctx->clear_graphs();
   if (ctx->own) (void)hipStreamDestroy(ctx->own);
   delete ctx;
 }

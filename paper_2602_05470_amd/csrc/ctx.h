@@ -35,6 +35,11 @@ struct DevBuf {
   T* as() const { return (T*)p; }
 };
 
+// Captured step programs: keyed by the program, its batch, residues and
+// every device pointer the launches bake in.
+using GraphKey = std::tuple<const void*, int64_t, int, void*, void*, void*, void*, void*, void*,
+                            uint32_t>;
+
 // Autotuner key: residues, log2 of (batch, M, N, K) buckets.
 using TuneKey = std::tuple<int, int, int, int, int>;
 struct TuneVal {
@@ -66,4 +71,9 @@ struct bbtn_ctx {
   bool scorer_loaded = false;
   bbtn::DevBuf scorer_dev;
   bbtn::Prof prof;         // kernel timing (off unless enabled)
+  std::map<bbtn::GraphKey, hipGraphExec_t> graphs;
+  void clear_graphs() {
+    for (auto& kv : graphs) (void)hipGraphExecDestroy(kv.second);
+    graphs.clear();
+  }
 };

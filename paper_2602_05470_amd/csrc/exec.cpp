@@ -90,7 +90,7 @@ void leaf_constants(const Network& net, const GroupPlan& g, const int* prime_idx
 
 void run_group(bbtn_ctx* ctx, const Network& net, const GroupPlan& g, const BaseDev& bd,
                const Moduli& mod, const uint8_t* assign, int64_t L, DevTensor out,
-               hipStream_t st) {
+               hipStream_t st, bool reuse) {
   const int k = bd.k;
   const int W = 1 + k;  // words per entry
   const size_t S = g.fixed_vars.size();
@@ -130,52 +130,91 @@ void run_group(bbtn_ctx* ctx, const Network& net, const GroupPlan& g, const Base
   BBTN_HIP(hipStreamSynchronize(st));  // host staging vectors die with this scope
   const DevTensor lconst{ctx->leafconst.as<uint32_t>(), L};
 
-  for (const Step& s : g.steps) {
-    DevTensor opnd[2];
-    const Operand* ops[2] = {&s.a, &s.b};
-    const int ranks[2] = {(int)s.a_vars.size(), (int)s.b_vars.size()};
-    for (int w = 0; w < 2; ++w) {
-      const Operand& op = *ops[w];
-      if (op.base) {
-        const GatherPlan gp = make_gather_plan(op.r_in, ranks[w], op.src_bits.data());
-        const DevTensor src{bd.t.ptr + bd.off[op.id], bd.total};
-        const int ph = ctx->prof.begin(st);
-        launch_gather(k, gp, L, 0, ctx->fixbits.as<uint64_t>() + (size_t)op.base_op * L, src,
-                      buf(op.temp), st);
-        ctx->prof.end(ph, st, K_GATHER, 0, 2.0 * W * 4 * (double)(L << ranks[w]));
-        opnd[w] = buf(op.temp);
-      } else if (!op.direct) {
-        const GatherPlan gp = make_gather_plan(op.r_in, ranks[w], op.src_bits.data());
-        const int ph = ctx->prof.begin(st);
-        launch_gather(k, gp, L, 1ll << op.r_in, nullptr, buf(op.id), buf(op.temp), st);
-        ctx->prof.end(ph, st, K_GATHER, 0, 2.0 * W * 4 * (double)(L << ranks[w]));
-        opnd[w] = buf(op.temp);
-      } else {
-        opnd[w] = buf(op.id);
-      }
-    }
+  // tile choices (possibly autotuned, which allocates) and split-K space are
+  // settled before any capture
+  std::vector<TuneVal> tvs(g.steps.size());
+  int64_t part_entries = 0;
+  for (size_t si = 0; si < g.steps.size(); ++si) {
+    const Step& s = g.steps[si];
     const int64_t M = 1ll << s.rm, N = 1ll << s.rn, K = 1ll << s.rk;
-    const int64_t batch = L << s.rb;
-    GemmShape sh{batch, M, N, K, M * K, K * N, M * N};
-    const TuneVal tv = choose_tiles(ctx, k, batch, M, N, K);
-    DevTensor part{};
-    if (tv.splits > 1) {
-      const int64_t ent = (int64_t)tv.splits * batch * M * N;
-      ctx->partial.ensure((size_t)W * ent * 4);
-      part = DevTensor{ctx->partial.as<uint32_t>(), ent};
-    }
-    const int ph = ctx->prof.begin(st);
-    launch_tgemm(k, mod, sh, opnd[0], opnd[1], buf(s.out), tv.cfg, tv.splits, part, st);
-    ctx->prof.end(ph, st, K_TGEMM, (double)L * s.macs() * (2 + 2 * k),
-                  (double)W * 4 * (double)batch * (double)(M * K + K * N + M * N));
-    ctx->last_macs += (uint64_t)(L * s.macs());
+    tvs[si] = choose_tiles(ctx, k, L << s.rb, M, N, K);
+    if (tvs[si].splits > 1) part_entries = std::max<int64_t>(part_entries, (int64_t)tvs[si].splits * (L << s.rb) * M * N);
   }
-  if (g.root_buf >= 0) {
-    launch_otimes(k, mod, L, buf(g.root_buf), lconst, out, st);
+  if (part_entries > 0) ctx->partial.ensure((size_t)W * part_entries * 4);
+  auto issue = [&]() {
+    for (size_t si = 0; si < g.steps.size(); ++si) {
+      const Step& s = g.steps[si];
+      DevTensor opnd[2];
+      const Operand* ops[2] = {&s.a, &s.b};
+      const int ranks[2] = {(int)s.a_vars.size(), (int)s.b_vars.size()};
+      for (int w = 0; w < 2; ++w) {
+        const Operand& op = *ops[w];
+        if (op.base) {
+          const GatherPlan gp = make_gather_plan(op.r_in, ranks[w], op.src_bits.data());
+          const DevTensor src{bd.t.ptr + bd.off[op.id], bd.total};
+          const int ph = ctx->prof.begin(st);
+          launch_gather(k, gp, L, 0, ctx->fixbits.as<uint64_t>() + (size_t)op.base_op * L, src,
+                        buf(op.temp), st);
+          ctx->prof.end(ph, st, K_GATHER, 0, 2.0 * W * 4 * (double)(L << ranks[w]));
+          opnd[w] = buf(op.temp);
+        } else if (!op.direct) {
+          const GatherPlan gp = make_gather_plan(op.r_in, ranks[w], op.src_bits.data());
+          const int ph = ctx->prof.begin(st);
+          launch_gather(k, gp, L, 1ll << op.r_in, nullptr, buf(op.id), buf(op.temp), st);
+          ctx->prof.end(ph, st, K_GATHER, 0, 2.0 * W * 4 * (double)(L << ranks[w]));
+          opnd[w] = buf(op.temp);
+        } else {
+          opnd[w] = buf(op.id);
+        }
+      }
+      const int64_t M = 1ll << s.rm, N = 1ll << s.rn, K = 1ll << s.rk;
+      const int64_t batch = L << s.rb;
+      GemmShape sh{batch, M, N, K, M * K, K * N, M * N};
+      const TuneVal tv = tvs[si];
+      DevTensor part{};
+      if (tv.splits > 1) part = DevTensor{ctx->partial.as<uint32_t>(), (int64_t)tv.splits * batch * M * N};
+      const int ph = ctx->prof.begin(st);
+      launch_tgemm(k, mod, sh, opnd[0], opnd[1], buf(s.out), tv.cfg, tv.splits, part, st);
+      ctx->prof.end(ph, st, K_TGEMM, (double)L * s.macs() * (2 + 2 * k),
+                    (double)W * 4 * (double)batch * (double)(M * K + K * N + M * N));
+    }
+    if (g.root_buf >= 0) {
+      launch_otimes(k, mod, L, buf(g.root_buf), lconst, out, st);
+    } else {
+      // the whole sub-network folded into constants: copy them
+      const GatherPlan id = make_gather_plan(0, 0, nullptr);
+      launch_gather(k, id, L, 1, nullptr, lconst, out, st);
+    }
+  };
+  for (const Step& s : g.steps) ctx->last_macs += (uint64_t)(L * s.macs());
+  // A program that runs more than once with the same shapes (chunks of a
+  // group, or one branch at a time) is captured into a hipGraph on first use
+  // and replayed: its device inputs (fixed bits, constants) sit in the same
+  // buffers, refreshed before every replay.
+  if (reuse && ctx->opt.graphs && !ctx->prof.on && g.steps.size() >= 2) {
+    const GraphKey key{(const void*)&g, L, k, ctx->work.p, ctx->partial.p, ctx->fixbits.p,
+                       ctx->leafconst.p, (void*)out.ptr, (void*)bd.t.ptr, mod.p[0]};
+    auto it = ctx->graphs.find(key);
+    if (it == ctx->graphs.end()) {
+      hipGraph_t graph;
+      BBTN_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+      try {
+        issue();
+      } catch (...) {
+        hipGraph_t dead;
+        (void)hipStreamEndCapture(st, &dead);
+        if (dead) (void)hipGraphDestroy(dead);
+        throw;
+      }
+      BBTN_HIP(hipStreamEndCapture(st, &graph));
+      hipGraphExec_t exec;
+      BBTN_HIP(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
+      (void)hipGraphDestroy(graph);
+      it = ctx->graphs.emplace(key, exec).first;
+    }
+    BBTN_HIP(hipGraphLaunch(it->second, st));
   } else {
-    // the whole sub-network folded into constants: copy them
-    const GatherPlan id = make_gather_plan(0, 0, nullptr);
-    launch_gather(k, id, L, 1, nullptr, lconst, out, st);
+    issue();
   }
 }
 

@@ -31,10 +31,11 @@ TuneVal choose_tiles(bbtn_ctx* ctx, int k, int64_t batch, int64_t M, int64_t N, 
 // Run the program `g` for L branches.  assign[l * |S| + j] is the state of
 // the j-th fixed variable (ascending ids) of branch l.  Writes, for every
 // branch, root (.) folded constant into `out` (tensor buffer of L entries).
-// With keep_all the workspace keeps every operand (values only, k = 0).
+// With reuse (the same program will run again with the same shapes) the
+// launches are captured into a hipGraph once and replayed.
 void run_group(bbtn_ctx* ctx, const Network& net, const GroupPlan& g, const BaseDev& bd,
                const Moduli& mod, const uint8_t* assign, int64_t L, DevTensor out,
-               hipStream_t st);
+               hipStream_t st, bool reuse = false);
 
 // Per-branch folded constants on the host: value and k residues.
 void leaf_constants(const Network& net, const GroupPlan& g, const int* prime_idx, int k,

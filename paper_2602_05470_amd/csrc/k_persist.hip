@@ -10,6 +10,8 @@
 //      pairwise, counting tropical algebra), with the K range split over
 //      several threads when the output is small, and writes C to scratch.
 // The root scalar (.) the branch's folded constant is the branch's result.
+// A program built to keep every intermediate also writes each staged operand
+// to scratch (configuration recovery reads them afterwards).
 // Counts use the same lazy 64-bit accumulation as the tiled product.
 #include "persist_dev.h"
 
@@ -94,7 +96,11 @@ persist_kernel(const PersistArgs a) {
             s |= (((uint64_t)e >> run.out_lo) & ((1ull << run.len) - 1)) << run.in_lo;
           }
 #pragma unroll
-          for (int p = 0; p < W; ++p) dst[p * cap + e] = src[p * sstride + s];
+          for (int p = 0; p < W; ++p) {
+            const uint32_t x = src[p * sstride + s];
+            dst[p * cap + e] = x;
+            if (op.mat_off >= 0) scr[p * a.scratch_entries + op.mat_off + e] = x;
+          }
         }
       }
       __syncthreads();

@@ -78,6 +78,8 @@ void run_persistent(bbtn_ctx* ctx, const Network& net, const std::vector<Persist
         po.src_off = op.base ? bd.off[op.id] : g.buf_off[op.id];
         po.n_runs = gpn.n_runs;
         for (int r = 0; r < gpn.n_runs; ++r) po.runs[r] = gpn.runs[r];
+        // programs that keep everything materialise gathered operands
+        po.mat_off = (op.temp >= 0 && g.keep_all) ? g.buf_off[op.temp] : -1;
         po.fix_off = (int32_t)fixes.size();
         po.n_fix = 0;
         if (op.base)

@@ -19,6 +19,7 @@ struct POperand {
   int32_t n_runs, n_fix;
   int32_t fix_off;   // into the PFix array
   int32_t pad;
+  int64_t mat_off;   // >= 0: also write the staged operand to scratch here
   GatherRun runs[P_MAX_RUNS];
 };
 

@@ -66,6 +66,7 @@ GroupPlan build_plan(const Network& net, const Tree& tree,
                      const std::vector<uint64_t>& fixed, bool keep_all) {
   GroupPlan g;
   g.fixed = fixed;
+  g.keep_all = keep_all;
   for (int v = 0; v < net.n; ++v)
     if (bit_get(fixed, v)) g.fixed_vars.push_back(v);
   enum { FOLDED, BASE, STEP };

@@ -46,6 +46,7 @@ struct GroupPlan {
   int32_t root_buf = -1;            // buffer of the final scalar, -1 if none
   std::vector<std::pair<int32_t, int32_t>> base_ops;  // (step, 0=A / 1=B)
   int32_t max_rank = 0;             // largest tensor rank in the program
+  bool keep_all = false;            // every buffer kept, operands materialised
   double macs = 0;                  // per branch
 };
 

@@ -532,6 +532,7 @@ void collect_training(const Network& net, const Tree& tree, int log2_target, int
       if (std::find(pick.begin(), pick.end(), v) == pick.end()) pick.push_back(v);
     }
     Searcher::Eval chosen;
+    const size_t row0 = y.size();
     for (int v : pick) {
       Searcher::Eval ev = s.best_from_seed(n, v, heur);
       // label: log2 (1 + sum over surviving children of 2^tc(child))
@@ -553,6 +554,11 @@ void collect_training(const Network& net, const Tree& tree, int log2_target, int
       if (v == cand[0] || (v == cand[std::min<size_t>(1, cand.size() - 1)] && Searcher::better(ev, chosen)))
         if (Searcher::better(ev, chosen)) chosen = std::move(ev);
     }
+    // labels relative to the node's cheapest candidate: the scorer only has
+    // to rank the candidates of one node
+    float lo = INFINITY;
+    for (size_t i = row0; i < y.size(); ++i) lo = std::min(lo, y[i]);
+    for (size_t i = row0; i < y.size(); ++i) y[i] -= lo;
     ++done;
     // continue the search with the heuristic's choice
     if (chosen.cubes.empty() || !std::isfinite(chosen.gamma)) continue;

@@ -132,3 +132,19 @@ def test_invalid_arguments(B):
             ctx.solve_spinglass(3, [(1, 1)], [1])
         with pytest.raises(B.BBTNError):
             ctx.solve_mwis(3, [(0, 1)], [1, 0, 1])
+
+
+@pytest.mark.parametrize("seed", [0, 7])
+def test_per_branch_graph_replay_equals_eager(B, seed):
+    """One branch at a time: with graphs the step program of the group is
+    captured once and replayed for every branch (inputs refreshed eagerly,
+    stream synchronised between replays); every replay feeds the count."""
+    g = I.spin_glass_square(16, seed)
+    want = {s: (e, d) for s, e, d in _golden("sg16.txt")}[seed]
+    res = {}
+    for graphs in (0, 1):
+        with B.Context(B.Options(log2_target=10, batched=0, graphs=graphs)) as ctx:
+            r = ctx.solve_spinglass(g["n"], g["edges"], g["J"])
+        _check_sg(r, g, want)
+        res[graphs] = (r.value, r.count, r.leaves, bytes(r.config))
+    assert res[0] == res[1]
