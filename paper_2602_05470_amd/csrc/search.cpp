@@ -101,6 +101,7 @@ struct Searcher {
   std::vector<int32_t> dec;      // scratch: decrements per tree node
   std::vector<int32_t> touched;  // scratch: tree nodes with dec > 0
   std::map<std::vector<uint64_t>, int> group_of;
+  std::map<std::vector<uint64_t>, std::vector<int32_t>> rule_memo;  // fixed set -> region
 
   Searcher(const Network& n, const Tree& t, const SearchOptions& o) : net(n), tree(t), opt(o) {
     var_tensors.assign(net.n, {});
@@ -469,11 +470,25 @@ struct Searcher {
       });
       if (cand.empty()) throw Error(BBTN_E_INTERNAL, "rho > 0 but no overflowing variable");
       Eval best;
-      const int n_seeds = std::min<int>(2, (int)cand.size());
-      for (int si = 0; si < n_seeds; ++si) {
-        Eval ev = best_from_seed(n, cand[si], score);
-        if (better(ev, best)) best = std::move(ev);
-        if (best.gamma == 0.0) break;  // every configuration pruned
+      // Nodes with the same fixed-variable set have the same rho structure.
+      // When the rule chosen for an earlier such node pruned nothing, try it
+      // first: if it again prunes nothing it is taken as is (the branches
+      // are complete and disjoint either way; only the choice of rule is
+      // shared).
+      auto memo = rule_memo.find(n.fixed);
+      if (memo != rule_memo.end()) {
+        Eval ev = evaluate(n, memo->second);
+        if (ev.cubes.size() == ((size_t)1 << memo->second.size())) best = std::move(ev);
+      }
+      if (best.cubes.empty()) {
+        const int n_seeds = std::min<int>(2, (int)cand.size());
+        for (int si = 0; si < n_seeds; ++si) {
+          Eval ev = best_from_seed(n, cand[si], score);
+          if (better(ev, best)) best = std::move(ev);
+          if (best.gamma == 0.0) break;  // every configuration pruned
+        }
+        if (!best.cubes.empty() && best.cubes.size() == ((size_t)1 << best.region.size()))
+          rule_memo[n.fixed] = best.region;
       }
       if (best.cubes.empty()) { st.pruned++; continue; }
       if (!std::isfinite(best.gamma)) throw Error(BBTN_E_INTERNAL, "no branching rule reduces rho");
