@@ -454,6 +454,7 @@ void bbtn_destroy(bbtn_ctx* ctx) {
   (void)hipSetDevice(ctx->opt.device);
   if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
   ctx->work.release();
+  ctx->shared_ws.release();
   ctx->partial.release();
   ctx->base.release();
   ctx->fixbits.release();

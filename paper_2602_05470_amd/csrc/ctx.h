@@ -38,7 +38,7 @@ struct DevBuf {
 // Captured step programs: keyed by the program, its batch, residues and
 // every device pointer the launches bake in.
 using GraphKey = std::tuple<const void*, int64_t, int, void*, void*, void*, void*, void*, void*,
-                            uint32_t>;
+                            uint32_t, void*>;
 
 // Autotuner key: residues, log2 of (batch, M, N, K) buckets.
 using TuneKey = std::tuple<int, int, int, int, int>;
@@ -55,6 +55,7 @@ struct bbtn_ctx {
   hipStream_t own = nullptr;
   hipStream_t stream = nullptr;
   bbtn::DevBuf work;      // step-program workspace
+  bbtn::DevBuf shared_ws; // shared subtrees of the step-program workspace
   bbtn::DevBuf partial;   // split-K partials
   bbtn::DevBuf base;      // base tensors of the current pass
   bbtn::DevBuf fixbits;   // per-branch fixed bits of base operands

@@ -94,11 +94,19 @@ void run_group(bbtn_ctx* ctx, const Network& net, const GroupPlan& g, const Base
   const int k = bd.k;
   const int W = 1 + k;  // words per entry
   const size_t S = g.fixed_vars.size();
-  // workspace
+  // workspaces: branch buffers scale with L; shared subtrees (scratch and
+  // roots) are computed once
   ctx->work.ensure((size_t)W * L * std::max<int64_t>(g.peak, 1) * 4);
+  ctx->shared_ws.ensure((size_t)W * std::max<int64_t>(g.subtree_peak + g.shared_total, 1) * 4);
   uint32_t* ws = ctx->work.as<uint32_t>();
+  uint32_t* sw = ctx->shared_ws.as<uint32_t>();
   auto buf = [&](int id) {
-    return DevTensor{ws + (size_t)W * L * g.buf_off[id], L * g.buf_entries[id]};
+    switch (g.buf_region[id]) {
+      case R_SUBTREE: return DevTensor{sw + (size_t)W * g.buf_off[id], g.buf_entries[id]};
+      case R_SHARED:
+        return DevTensor{sw + (size_t)W * (g.subtree_peak + g.buf_off[id]), g.buf_entries[id]};
+      default: return DevTensor{ws + (size_t)W * L * g.buf_off[id], L * g.buf_entries[id]};
+    }
   };
   // fixed bits of every base operand for every branch
   std::vector<int> pos_of(net.n, -1);
@@ -136,14 +144,22 @@ void run_group(bbtn_ctx* ctx, const Network& net, const GroupPlan& g, const Base
   int64_t part_entries = 0;
   for (size_t si = 0; si < g.steps.size(); ++si) {
     const Step& s = g.steps[si];
+    const int64_t Ls = s.shared ? 1 : L;
     const int64_t M = 1ll << s.rm, N = 1ll << s.rn, K = 1ll << s.rk;
-    tvs[si] = choose_tiles(ctx, k, L << s.rb, M, N, K);
-    if (tvs[si].splits > 1) part_entries = std::max<int64_t>(part_entries, (int64_t)tvs[si].splits * (L << s.rb) * M * N);
+    tvs[si] = choose_tiles(ctx, k, Ls << s.rb, M, N, K);
+    if (tvs[si].splits > 1) part_entries = std::max<int64_t>(part_entries, (int64_t)tvs[si].splits * (Ls << s.rb) * M * N);
   }
   if (part_entries > 0) ctx->partial.ensure((size_t)W * part_entries * 4);
+  // shared steps first (once), then the branch steps
+  std::vector<size_t> order;
+  for (size_t si = 0; si < g.steps.size(); ++si)
+    if (g.steps[si].shared) order.push_back(si);
+  for (size_t si = 0; si < g.steps.size(); ++si)
+    if (!g.steps[si].shared) order.push_back(si);
   auto issue = [&]() {
-    for (size_t si = 0; si < g.steps.size(); ++si) {
+    for (size_t si : order) {
       const Step& s = g.steps[si];
+      const int64_t Ls = s.shared ? 1 : L;
       DevTensor opnd[2];
       const Operand* ops[2] = {&s.a, &s.b};
       const int ranks[2] = {(int)s.a_vars.size(), (int)s.b_vars.size()};
@@ -152,30 +168,33 @@ void run_group(bbtn_ctx* ctx, const Network& net, const GroupPlan& g, const Base
         if (op.base) {
           const GatherPlan gp = make_gather_plan(op.r_in, ranks[w], op.src_bits.data());
           const DevTensor src{bd.t.ptr + bd.off[op.id], bd.total};
+          const uint64_t* fbits =
+              s.shared ? nullptr : ctx->fixbits.as<uint64_t>() + (size_t)op.base_op * L;
           const int ph = ctx->prof.begin(st);
-          launch_gather(k, gp, L, 0, ctx->fixbits.as<uint64_t>() + (size_t)op.base_op * L, src,
-                        buf(op.temp), st);
-          ctx->prof.end(ph, st, K_GATHER, 0, 2.0 * W * 4 * (double)(L << ranks[w]));
+          launch_gather(k, gp, Ls, 0, fbits, src, buf(op.temp), st);
+          ctx->prof.end(ph, st, K_GATHER, 0, 2.0 * W * 4 * (double)(Ls << ranks[w]));
           opnd[w] = buf(op.temp);
         } else if (!op.direct) {
           const GatherPlan gp = make_gather_plan(op.r_in, ranks[w], op.src_bits.data());
+          // a shared root is read by every branch: no branch stride
+          const int64_t stride = g.buf_region[op.id] == R_SHARED ? 0 : (1ll << op.r_in);
           const int ph = ctx->prof.begin(st);
-          launch_gather(k, gp, L, 1ll << op.r_in, nullptr, buf(op.id), buf(op.temp), st);
-          ctx->prof.end(ph, st, K_GATHER, 0, 2.0 * W * 4 * (double)(L << ranks[w]));
+          launch_gather(k, gp, Ls, stride, nullptr, buf(op.id), buf(op.temp), st);
+          ctx->prof.end(ph, st, K_GATHER, 0, 2.0 * W * 4 * (double)(Ls << ranks[w]));
           opnd[w] = buf(op.temp);
         } else {
           opnd[w] = buf(op.id);
         }
       }
       const int64_t M = 1ll << s.rm, N = 1ll << s.rn, K = 1ll << s.rk;
-      const int64_t batch = L << s.rb;
+      const int64_t batch = Ls << s.rb;
       GemmShape sh{batch, M, N, K, M * K, K * N, M * N};
       const TuneVal tv = tvs[si];
       DevTensor part{};
       if (tv.splits > 1) part = DevTensor{ctx->partial.as<uint32_t>(), (int64_t)tv.splits * batch * M * N};
       const int ph = ctx->prof.begin(st);
       launch_tgemm(k, mod, sh, opnd[0], opnd[1], buf(s.out), tv.cfg, tv.splits, part, st);
-      ctx->prof.end(ph, st, K_TGEMM, (double)L * s.macs() * (2 + 2 * k),
+      ctx->prof.end(ph, st, K_TGEMM, (double)Ls * s.macs() * (2 + 2 * k),
                     (double)W * 4 * (double)batch * (double)(M * K + K * N + M * N));
     }
     if (g.root_buf >= 0) {
@@ -186,14 +205,15 @@ void run_group(bbtn_ctx* ctx, const Network& net, const GroupPlan& g, const Base
       launch_gather(k, id, L, 1, nullptr, lconst, out, st);
     }
   };
-  for (const Step& s : g.steps) ctx->last_macs += (uint64_t)(L * s.macs());
+  for (const Step& s : g.steps) ctx->last_macs += (uint64_t)((s.shared ? 1 : L) * s.macs());
   // A program that runs more than once with the same shapes (chunks of a
   // group, or one branch at a time) is captured into a hipGraph on first use
   // and replayed: its device inputs (fixed bits, constants) sit in the same
   // buffers, refreshed before every replay.
   if (reuse && ctx->opt.graphs && !ctx->prof.on && g.steps.size() >= 2) {
     const GraphKey key{(const void*)&g, L, k, ctx->work.p, ctx->partial.p, ctx->fixbits.p,
-                       ctx->leafconst.p, (void*)out.ptr, (void*)bd.t.ptr, mod.p[0]};
+                       ctx->leafconst.p, (void*)out.ptr, (void*)bd.t.ptr, mod.p[0],
+                       ctx->shared_ws.p};
     auto it = ctx->graphs.find(key);
     if (it == ctx->graphs.end()) {
       hipGraph_t graph;

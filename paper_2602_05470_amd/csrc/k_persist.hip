@@ -71,11 +71,10 @@ persist_kernel(const PersistArgs a) {
     __syncthreads();
     if (task >= a.n_tasks) break;
     const PTask tk = a.tasks[task];
-    const PGroup gp = a.groups[tk.group];
     const uint8_t* asg = a.assign + tk.assign_off;
 
-    for (int32_t si = 0; si < gp.n_steps; ++si) {
-      const PStep st = a.steps[gp.step_off + si];
+    for (int32_t si = 0; si < tk.n_steps; ++si) {
+      const PStep st = a.steps[tk.step_off + si];
       // ---- stage operands
 #pragma unroll
       for (int w = 0; w < 2; ++w) {
@@ -86,8 +85,12 @@ persist_kernel(const PersistArgs a) {
           const PFix fx = a.fixes[op.fix_off + f];
           fixed |= (uint64_t)(asg[fx.idx] & 1) << fx.pos;
         }
-        const uint32_t* src = op.base ? a.base + op.src_off : scr + op.src_off;
-        const int64_t sstride = op.base ? a.base_total : a.scratch_entries;
+        const uint32_t* src = op.kind == PK_BASE     ? a.base + op.src_off
+                              : op.kind == PK_SHARED ? a.shared + op.src_off
+                                                     : scr + op.src_off;
+        const int64_t sstride = op.kind == PK_BASE     ? a.base_total
+                                : op.kind == PK_SHARED ? a.shared_entries
+                                                       : a.scratch_entries;
         const int64_t n = 1ll << op.rank;
         for (int64_t e = tid; e < n; e += NTHR) {
           uint64_t s = fixed;
@@ -169,26 +172,28 @@ persist_kernel(const PersistArgs a) {
         }
         if (j == 0 && o < nC) {
           const bool fin = V > NEG_CUT;
-          uint32_t* c = scr + st.c_off;
+          const bool sh = st.c_kind == PK_SHARED;
+          uint32_t* c = (sh ? a.shared : scr) + st.c_off;
+          const int64_t cs = sh ? a.shared_entries : a.scratch_entries;
           c[o] = (uint32_t)(fin ? V : NEG);
 #pragma unroll
-          for (int p = 0; p < KR; ++p) c[(p + 1) * a.scratch_entries + o] = fin ? res[p] : 0u;
+          for (int p = 0; p < KR; ++p) c[(p + 1) * cs + o] = fin ? res[p] : 0u;
         }
       }
       __syncthreads();
     }
     // ---- branch result = root (.) folded constant
-    if (tid == 0) {
+    if (tid == 0 && tk.out_idx >= 0) {
       const int64_t l = tk.out_idx;
       const int32_t cv = (int32_t)a.lconst[l];
       int32_t rv = 0;
-      const uint32_t* root = scr + gp.root_off;
-      if (gp.root_off >= 0) rv = (int32_t)root[0];
+      const uint32_t* root = scr + tk.root_off;
+      if (tk.root_off >= 0) rv = (int32_t)root[0];
       const bool fin = cv > NEG_CUT && rv > NEG_CUT;
       a.out[l] = (uint32_t)(fin ? cv + rv : NEG);
 #pragma unroll
       for (int p = 0; p < KR; ++p) {
-        const uint32_t rr = gp.root_off >= 0 ? root[(p + 1) * a.scratch_entries] : 1u;
+        const uint32_t rr = tk.root_off >= 0 ? root[(p + 1) * a.scratch_entries] : 1u;
         const uint64_t x = (uint64_t)rr * a.lconst[(p + 1) * a.n_out + l];
         a.out[(p + 1) * a.n_out + l] = fin ? pmod(x, a.mod.p[p], a.mod.c[p]) : 0u;
       }

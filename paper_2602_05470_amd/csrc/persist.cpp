@@ -45,25 +45,24 @@ void run_persistent(bbtn_ctx* ctx, const Network& net, const std::vector<Persist
   const int k = bd.k;
   const int W = 1 + k;
   std::vector<PStep> steps;
-  std::vector<PGroup> groups;
   std::vector<PFix> fixes;
-  std::vector<PTask> tasks;
+  std::vector<PTask> shared_tasks, tasks;
   std::vector<uint8_t> assign;
-  int64_t n_out = 0, scratch = 1, max_rank = 0;
+  int64_t n_out = 0, scratch = 1, max_rank = 0, shared_total = 0;
   std::vector<int64_t> out_base(jobs.size());
   for (size_t ji = 0; ji < jobs.size(); ++ji) {
     const GroupPlan& g = *jobs[ji].plan;
-    PGroup pg{};
-    pg.step_off = (int32_t)steps.size();
-    pg.n_steps = (int32_t)g.steps.size();
-    pg.root_off = g.root_buf >= 0 ? g.buf_off[g.root_buf] : -1;
-    scratch = std::max<int64_t>(scratch, g.peak);
+    const int64_t shared_base = shared_total;
+    shared_total += g.shared_total;
+    scratch = std::max<int64_t>(scratch, std::max(g.peak, g.subtree_peak));
     std::vector<int> pos_of(net.n, -1);
     for (size_t j = 0; j < g.fixed_vars.size(); ++j) pos_of[g.fixed_vars[j]] = (int)j;
-    for (const Step& s : g.steps) {
+    auto emit_step = [&](const Step& s) {
       PStep ps{};
       ps.rb = s.rb; ps.rm = s.rm; ps.rn = s.rn; ps.rk = s.rk;
-      ps.c_off = g.buf_off[s.out];
+      const bool out_shared = g.buf_region[s.out] == R_SHARED;
+      ps.c_kind = out_shared ? PK_SHARED : PK_SCRATCH;
+      ps.c_off = g.buf_off[s.out] + (out_shared ? shared_base : 0);
       const Operand* ops[2] = {&s.a, &s.b};
       POperand* pops[2] = {&ps.a, &ps.b};
       for (int w = 0; w < 2; ++w) {
@@ -73,9 +72,17 @@ void run_persistent(bbtn_ctx* ctx, const Network& net, const std::vector<Persist
         max_rank = std::max<int64_t>(max_rank, rank);
         const GatherPlan gpn = make_gather_plan(op.r_in, rank, op.src_bits.data());
         if (gpn.n_runs > P_MAX_RUNS) throw Error(BBTN_E_INTERNAL, "persistent: too many runs");
-        po.base = op.base ? 1 : 0;
+        if (op.base) {
+          po.kind = PK_BASE;
+          po.src_off = bd.off[op.id];
+        } else if (g.buf_region[op.id] == R_SHARED) {
+          po.kind = PK_SHARED;
+          po.src_off = shared_base + g.buf_off[op.id];
+        } else {
+          po.kind = PK_SCRATCH;
+          po.src_off = g.buf_off[op.id];
+        }
         po.rank = rank;
-        po.src_off = op.base ? bd.off[op.id] : g.buf_off[op.id];
         po.n_runs = gpn.n_runs;
         for (int r = 0; r < gpn.n_runs; ++r) po.runs[r] = gpn.runs[r];
         // programs that keep everything materialise gathered operands
@@ -89,15 +96,32 @@ void run_persistent(bbtn_ctx* ctx, const Network& net, const std::vector<Persist
           }
       }
       steps.push_back(ps);
+    };
+    // shared subtrees: one task each, run before any branch
+    for (auto& rg : g.shared_ranges) {
+      PTask t{};
+      t.step_off = (int32_t)steps.size();
+      for (int i = rg.first; i < rg.second; ++i) emit_step(g.steps[i]);
+      t.n_steps = (int32_t)steps.size() - t.step_off;
+      t.assign_off = 0;
+      t.out_idx = -1;
+      t.root_off = -1;
+      shared_tasks.push_back(t);
     }
-    groups.push_back(pg);
+    // the branch program
+    const int32_t prog = (int32_t)steps.size();
+    for (const Step& s : g.steps)
+      if (!s.shared) emit_step(s);
+    const int32_t n_prog = (int32_t)steps.size() - prog;
     const size_t S = g.fixed_vars.size();
     out_base[ji] = n_out;
     for (int64_t l = 0; l < jobs[ji].L; ++l) {
       PTask t{};
-      t.group = (int32_t)ji;
+      t.step_off = prog;
+      t.n_steps = n_prog;
       t.assign_off = (int64_t)assign.size() + (int64_t)(l * S);
       t.out_idx = n_out + l;
+      t.root_off = g.root_buf >= 0 ? g.buf_off[g.root_buf] : -1;
       tasks.push_back(t);
     }
     assign.insert(assign.end(), jobs[ji].assign, jobs[ji].assign + jobs[ji].L * S);
@@ -121,17 +145,18 @@ void run_persistent(bbtn_ctx* ctx, const Network& net, const std::vector<Persist
   // one device buffer for the program and per-branch data
   size_t off = 0;
   const size_t o_steps = off; off = align_up(off + steps.size() * sizeof(PStep));
-  const size_t o_groups = off; off = align_up(off + groups.size() * sizeof(PGroup));
   const size_t o_fixes = off; off = align_up(off + std::max<size_t>(fixes.size(), 1) * sizeof(PFix));
+  const size_t o_stasks = off; off = align_up(off + std::max<size_t>(shared_tasks.size(), 1) * sizeof(PTask));
   const size_t o_tasks = off; off = align_up(off + tasks.size() * sizeof(PTask));
   const size_t o_assign = off; off = align_up(off + std::max<size_t>(assign.size(), 1));
   const size_t o_lconst = off; off = align_up(off + lconst.size() * 4);
   const size_t o_out = off; off = align_up(off + lconst.size() * 4);
-  const size_t o_queue = off; off = align_up(off + 8);
+  const size_t o_queue = off; off = align_up(off + 16);
+  const size_t o_shared = off; off = align_up(off + (size_t)W * std::max<int64_t>(shared_total, 1) * 4);
   std::vector<uint8_t> host(o_out, 0);
   std::memcpy(&host[o_steps], steps.data(), steps.size() * sizeof(PStep));
-  std::memcpy(&host[o_groups], groups.data(), groups.size() * sizeof(PGroup));
   if (!fixes.empty()) std::memcpy(&host[o_fixes], fixes.data(), fixes.size() * sizeof(PFix));
+  if (!shared_tasks.empty()) std::memcpy(&host[o_stasks], shared_tasks.data(), shared_tasks.size() * sizeof(PTask));
   std::memcpy(&host[o_tasks], tasks.data(), tasks.size() * sizeof(PTask));
   if (!assign.empty()) std::memcpy(&host[o_assign], assign.data(), assign.size());
   std::memcpy(&host[o_lconst], lconst.data(), lconst.size() * 4);
@@ -142,14 +167,12 @@ void run_persistent(bbtn_ctx* ctx, const Network& net, const std::vector<Persist
   const int64_t lds_entries = 1ll << max_rank;
   const size_t lds = persist_lds_bytes(k, lds_entries);
   const int per_cu = std::max(1, std::min(2, (int)((160u << 10) / std::max<size_t>(lds, 1))));
-  const int n_blocks = (int)std::min<int64_t>((int64_t)device_cus() * per_cu, (int64_t)tasks.size());
-  ctx->work.ensure((size_t)n_blocks * W * scratch * 4);
+  const int64_t max_blocks = (int64_t)device_cus() * per_cu;
+  const int64_t most = std::max<int64_t>((int64_t)tasks.size(), (int64_t)shared_tasks.size());
+  ctx->work.ensure((size_t)std::min(max_blocks, most) * W * scratch * 4);
   PersistArgs a{};
   a.steps = (const PStep*)(dev + o_steps);
-  a.groups = (const PGroup*)(dev + o_groups);
   a.fixes = (const PFix*)(dev + o_fixes);
-  a.tasks = (const PTask*)(dev + o_tasks);
-  a.n_tasks = (int64_t)tasks.size();
   a.assign = dev + o_assign;
   a.base = bd.t.ptr;
   a.base_total = bd.total;
@@ -158,20 +181,32 @@ void run_persistent(bbtn_ctx* ctx, const Network& net, const std::vector<Persist
   a.n_out = n_out;
   a.scratch = ctx->work.as<uint32_t>();
   a.scratch_entries = scratch;
+  a.shared = (uint32_t*)(dev + o_shared);
+  a.shared_entries = std::max<int64_t>(shared_total, 1);
   a.lds_entries = lds_entries;
-  a.queue = (unsigned long long*)(dev + o_queue);
   a.mod = mod;
   double ops = 0, bytes = 0;
   for (auto& j : jobs) {
-    ops += (double)j.L * j.plan->macs * (2 + 2 * k);
+    ops += ((double)j.L * j.plan->macs + j.plan->shared_macs) * (2 + 2 * k);
     double e = 0;
     for (const Step& s : j.plan->steps)
-      e += std::ldexp(1.0, (int)s.a_vars.size()) + std::ldexp(1.0, (int)s.b_vars.size()) +
-           std::ldexp(1.0, (int)s.c_vars.size());
-    bytes += (double)j.L * e * W * 4;
+      e += (s.shared ? 1.0 : (double)j.L) *
+           (std::ldexp(1.0, (int)s.a_vars.size()) + std::ldexp(1.0, (int)s.b_vars.size()) +
+            std::ldexp(1.0, (int)s.c_vars.size()));
+    bytes += e * W * 4;
   }
   const int ph = ctx->prof.begin(st);
-  launch_persist(k, a, n_blocks, st);
+  if (!shared_tasks.empty()) {
+    // shared subtrees first, then the branches (stream order separates them)
+    a.tasks = (const PTask*)(dev + o_stasks);
+    a.n_tasks = (int64_t)shared_tasks.size();
+    a.queue = (unsigned long long*)(dev + o_queue);
+    launch_persist(k, a, (int)std::min<int64_t>(max_blocks, a.n_tasks), st);
+  }
+  a.tasks = (const PTask*)(dev + o_tasks);
+  a.n_tasks = (int64_t)tasks.size();
+  a.queue = (unsigned long long*)(dev + o_queue + 8);
+  launch_persist(k, a, (int)std::min<int64_t>(max_blocks, a.n_tasks), st);
   ctx->prof.end(ph, st, K_PERSIST, ops, bytes);
   std::vector<uint32_t> outh(lconst.size());
   BBTN_HIP(hipMemcpyAsync(outh.data(), dev + o_out, outh.size() * 4, hipMemcpyDeviceToHost, st));
@@ -185,7 +220,7 @@ void run_persistent(bbtn_ctx* ctx, const Network& net, const std::vector<Persist
       std::memcpy(&o[(size_t)p * L], &outh[(size_t)p * n_out + out_base[ji]], L * 4);
   }
   uint64_t macs = 0;
-  for (auto& j : jobs) macs += (uint64_t)(j.L * j.plan->macs);
+  for (auto& j : jobs) macs += (uint64_t)(j.L * j.plan->macs + j.plan->shared_macs);
   ctx->last_macs += macs;
 }
 

@@ -11,9 +11,12 @@ struct PFix {
   int32_t idx;  // index of the variable in the group's fixed-variable list
 };
 
+// where an operand is read from / an output is written to
+enum PKind { PK_SCRATCH = 0, PK_BASE = 1, PK_SHARED = 2 };
+
 struct POperand {
-  int32_t base;      // 1: base tensor (src_off = entry offset in the base buffer)
-                     // 0: intermediate (src_off = entry offset in scratch)
+  int32_t kind;      // PKind: workgroup scratch, base tensors or shared region
+                     // (src_off = entry offset there)
   int32_t rank;      // rank of the operand in the step's layout
   int64_t src_off;
   int32_t n_runs, n_fix;
@@ -25,25 +28,24 @@ struct POperand {
 
 struct PStep {
   int32_t rb, rm, rn, rk;
-  int64_t c_off;     // scratch entry offset of the output
+  int64_t c_off;     // entry offset of the output (scratch or shared region)
+  int32_t c_kind;    // PK_SCRATCH or PK_SHARED
+  int32_t pad2;
   POperand a, b;
 };
 
-struct PGroup {
-  int32_t step_off, n_steps;
-  int64_t root_off;  // scratch entry offset of the root scalar, -1 if none
-};
-
+// A task runs steps [step_off, step_off + n_steps).  Branch tasks
+// (out_idx >= 0) then write root (.) folded constant to out[out_idx]; shared
+// subtree tasks (out_idx < 0) only fill the shared region.
 struct PTask {
-  int32_t group;
-  int32_t pad;
+  int32_t step_off, n_steps;
   int64_t assign_off;  // byte offset of the branch's fixed states
-  int64_t out_idx;     // output slot
+  int64_t out_idx;     // output slot, or -1
+  int64_t root_off;    // scratch entry offset of the root scalar, -1 if none
 };
 
 struct PersistArgs {
   const PStep* steps;
-  const PGroup* groups;
   const PFix* fixes;
   const PTask* tasks;
   int64_t n_tasks;
@@ -55,6 +57,8 @@ struct PersistArgs {
   int64_t n_out;
   uint32_t* scratch;       // per workgroup: (1 + k) planes of scratch_entries
   int64_t scratch_entries;
+  uint32_t* shared;        // (1 + k) planes of shared_entries
+  int64_t shared_entries;
   int64_t lds_entries;
   unsigned long long* queue;
   Moduli mod;

@@ -73,8 +73,15 @@ GroupPlan build_plan(const Network& net, const Tree& tree,
   const int NN = (int)tree.nodes.size();
   std::vector<int> status(NN, FOLDED), rep(NN, -1), buf_of(NN, -1);
   std::vector<std::vector<int32_t>> layout(NN);  // stored layout of STEP outputs
-  auto new_buf = [&](int64_t entries) {
+  // subtrees without a fixed variable are the same in every branch
+  std::vector<char> hasfix(NN, 0);
+  for (int i = 0; i < tree.n_base; ++i)
+    for (int v : tree.nodes[i].vars) hasfix[i] |= bit_get(fixed, v);
+  for (int id : tree.dfs_post) hasfix[id] = hasfix[tree.nodes[id].left] | hasfix[tree.nodes[id].right];
+  const bool sharing = !keep_all && !g.fixed_vars.empty();
+  auto new_buf = [&](int64_t entries, int region) {
     g.buf_entries.push_back(entries);
+    g.buf_region.push_back(region);
     return (int32_t)g.buf_entries.size() - 1;
   };
   // buffer lifetimes in step indices: [def, last use]
@@ -94,7 +101,7 @@ GroupPlan build_plan(const Network& net, const Tree& tree,
       rep[i] = i;
     }
   }
-  for (int id : tree.postorder) {
+  for (int id : tree.dfs_post) {  // subtrees are contiguous in this order
     const TNode& n = tree.nodes[id];
     const int sl = status[n.left], sr = status[n.right];
     if (sl == FOLDED && sr == FOLDED) { status[id] = FOLDED; continue; }
@@ -121,6 +128,7 @@ GroupPlan build_plan(const Network& net, const Tree& tree,
       throw Error(BBTN_E_INTERNAL, "plan: variable private to one operand");
     Step s;
     s.node = id;
+    s.shared = sharing && !hasfix[id];
     s.rb = (int)batch.size();
     s.rm = (int)M.size();
     s.rn = (int)N.size();
@@ -129,6 +137,7 @@ GroupPlan build_plan(const Network& net, const Tree& tree,
     s.b_vars = cat3(N, K, batch);
     s.c_vars = cat3(N, M, batch);
     const int si = (int)g.steps.size();
+    const int own_region = s.shared ? R_SUBTREE : R_BRANCH;
     auto make_op = [&](int r, const std::vector<int32_t>& want, int which) {
       Operand op;
       if (status[r] == BASE) {
@@ -147,12 +156,15 @@ GroupPlan build_plan(const Network& net, const Tree& tree,
         op.base = false;
         op.id = buf_of[r];
         op.r_in = (int)have.size();
-        op.direct = (have == want);
+        // a branch step reading a shared subtree's root: that root lives in
+        // the shared region and is gathered per branch (no branch stride)
+        if (!s.shared && g.buf_region[op.id] != R_BRANCH) g.buf_region[op.id] = R_SHARED;
+        op.direct = (have == want) && g.buf_region[op.id] != R_SHARED;
         for (int v : want)
           op.src_bits.push_back((int)(std::find(have.begin(), have.end(), v) - have.begin()));
       }
       if (!op.direct) {
-        op.temp = new_buf(1ll << want.size());
+        op.temp = new_buf(1ll << want.size(), own_region);
         def(op.temp, si);
       }
       if (!op.base) use(op.id, si);
@@ -160,13 +172,14 @@ GroupPlan build_plan(const Network& net, const Tree& tree,
     };
     s.a = make_op(ra, s.a_vars, 0);
     s.b = make_op(rb_, s.b_vars, 1);
-    s.out = new_buf(1ll << C.size());
+    s.out = new_buf(1ll << C.size(), own_region);
     def(s.out, si);
     buf_of[id] = s.out;
     layout[id] = s.c_vars;
     g.max_rank = std::max({g.max_rank, (int)s.a_vars.size(), (int)s.b_vars.size(),
                            (int)s.c_vars.size()});
-    g.macs += s.macs();
+    if (s.shared) g.shared_macs += s.macs();
+    else { g.macs += s.macs(); g.n_branch_steps++; }
     g.steps.push_back(std::move(s));
   }
   if (tree.root >= 0 && status[tree.root] == STEP) {
@@ -175,17 +188,35 @@ GroupPlan build_plan(const Network& net, const Tree& tree,
   } else if (tree.root >= 0 && status[tree.root] == BASE) {
     throw Error(BBTN_E_INTERNAL, "plan: root is a base tensor with free variables");
   }
-  // offsets: first fit over lifetimes (or disjoint when keeping everything)
+  // maximal shared subtrees: runs of consecutive shared steps ending at a
+  // step whose output is read by a branch step
+  for (int i = 0; i < (int)g.steps.size();) {
+    if (!g.steps[i].shared) { ++i; continue; }
+    int j = i;
+    while (j < (int)g.steps.size() && g.steps[j].shared) {
+      const bool root = g.buf_region[g.steps[j].out] == R_SHARED;
+      ++j;
+      if (root) break;
+    }
+    g.shared_ranges.push_back({i, j});
+    i = j;
+  }
+  // offsets: first fit over lifetimes per region (or disjoint when keeping
+  // everything); shared-region buffers never overlap
   const int nb = (int)g.buf_entries.size();
   g.buf_off.assign(nb, 0);
   if (keep_all) {
     int64_t off = 0;
     for (int i = 0; i < nb; ++i) { g.buf_off[i] = off; off += g.buf_entries[i]; }
     g.peak = off;
-  } else {
-    // process buffers in definition order; live intervals in an ordered map
-    std::vector<int> order(nb);
-    for (int i = 0; i < nb; ++i) order[i] = i;
+    return g;
+  }
+  for (int i = 0; i < nb; ++i)
+    if (g.buf_region[i] == R_SHARED) { g.buf_off[i] = g.shared_total; g.shared_total += g.buf_entries[i]; }
+  for (int region : {R_BRANCH, R_SUBTREE}) {
+    std::vector<int> order;
+    for (int i = 0; i < nb; ++i)
+      if (g.buf_region[i] == region) order.push_back(i);
     std::stable_sort(order.begin(), order.end(),
                      [&](int x, int y) { return life[x].first < life[y].first; });
     std::vector<int> active;  // placed buffers still alive
@@ -206,7 +237,7 @@ GroupPlan build_plan(const Network& net, const Tree& tree,
       peak = std::max(peak, off + g.buf_entries[i]);
       active.push_back(i);
     }
-    g.peak = peak;
+    (region == R_BRANCH ? g.peak : g.subtree_peak) = peak;
   }
   return g;
 }

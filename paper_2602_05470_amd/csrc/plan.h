@@ -10,6 +10,13 @@
 
 namespace bbtn {
 
+// Where a buffer lives.  Subtrees of the contraction tree that hold no fixed
+// variable are the same for every branch: their steps ("shared" steps) run
+// once per pass.  Their intermediates live in a per-subtree scratch and the
+// root of each such subtree in a shared region that every branch reads; the
+// remaining ("branch") steps run per branch in the branch workspace.
+enum Region { R_BRANCH = 0, R_SUBTREE = 1, R_SHARED = 2 };
+
 // One operand of a step: a base tensor sliced per branch, or an
 // intermediate buffer; gathered into the step's required layout unless it
 // is already stored that way.
@@ -28,6 +35,7 @@ struct Operand {
 //   A: [K][M][batch], B: [N][K][batch], C: [N][M][batch].
 struct Step {
   int32_t node = -1;
+  bool shared = false;              // runs once per pass (no fixed variable below)
   int32_t rb = 0, rm = 0, rn = 0, rk = 0;
   Operand a, b;
   int32_t out = -1;                 // buffer id of C
@@ -39,19 +47,27 @@ struct GroupPlan {
   std::vector<uint64_t> fixed;      // bitmask of fixed variables S
   std::vector<int32_t> fixed_vars;  // S, ascending
   std::vector<Step> steps;          // children before parents
-  std::vector<int64_t> buf_entries; // per-branch entries of every buffer
-  std::vector<int64_t> buf_off;     // per-branch entry offset of every buffer
-  int64_t peak = 0;                 // per-branch entries of the workspace
+  std::vector<int64_t> buf_entries; // entries of every buffer (per branch for R_BRANCH)
+  std::vector<int64_t> buf_off;     // entry offset of every buffer within its region
+  std::vector<int32_t> buf_region;  // Region of every buffer
+  int64_t peak = 0;                 // per-branch entries of the branch workspace
+  int64_t subtree_peak = 0;         // entries of the subtree scratch
+  int64_t shared_total = 0;         // entries of the shared region
+  // maximal shared subtrees as [begin, end) ranges of `steps`
+  std::vector<std::pair<int32_t, int32_t>> shared_ranges;
   std::vector<int32_t> folded;      // base tensors with every variable fixed
   int32_t root_buf = -1;            // buffer of the final scalar, -1 if none
   std::vector<std::pair<int32_t, int32_t>> base_ops;  // (step, 0=A / 1=B)
   int32_t max_rank = 0;             // largest tensor rank in the program
   bool keep_all = false;            // every buffer kept, operands materialised
-  double macs = 0;                  // per branch
+  double macs = 0;                  // per branch (branch steps)
+  double shared_macs = 0;           // per pass (shared steps)
+  int32_t n_branch_steps = 0;
 };
 
 // keep_all: never reuse buffers and materialise every operand in its
-// required layout (values-only recontraction for configuration recovery).
+// required layout (values-only recontraction for configuration recovery);
+// keep_all plans share nothing.
 GroupPlan build_plan(const Network& net, const Tree& tree,
                      const std::vector<uint64_t>& fixed, bool keep_all);
 

@@ -101,6 +101,18 @@ Tree greedy_tree(const Network& net) {
     for (size_t i = 1; i < rest.size(); ++i) acc = merge(acc, rest[i]);
     t.root = acc;
   }
+  // depth-first post-order from the root (iterative)
+  if (t.root >= 0) {
+    std::vector<std::pair<int32_t, int>> st{{t.root, 0}};
+    while (!st.empty()) {
+      auto& top = st.back();
+      const TNode& nd = t.nodes[top.first];
+      if (nd.left < 0) { st.pop_back(); continue; }  // base tensor
+      if (top.second == 0) { top.second = 1; st.push_back({nd.left, 0}); }
+      else if (top.second == 1) { top.second = 2; st.push_back({nd.right, 0}); }
+      else { t.dfs_post.push_back(top.first); st.pop_back(); }
+    }
+  }
   t.var_nodes.assign(net.n, {});
   for (int id : t.postorder)
     for (int v : t.nodes[id].vars) t.var_nodes[v].push_back(id);

@@ -18,7 +18,9 @@ struct Tree {
   std::vector<TNode> nodes;       // leaves first (node i = base tensor i)
   int32_t root = -1;
   int32_t n_base = 0;
-  std::vector<int32_t> postorder; // internal nodes, children before parents
+  std::vector<int32_t> postorder; // internal nodes in merge order (children first)
+  std::vector<int32_t> dfs_post;  // internal nodes in depth-first post-order:
+                                  // every subtree is a contiguous range
   // var -> internal nodes whose tensor holds it
   std::vector<std::vector<int32_t>> var_nodes;
 };
