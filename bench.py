@@ -100,6 +100,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-micro", action="store_true")
+    ap.add_argument("--no-per-branch", action="store_true")
+    ap.add_argument("--micro-only", action="store_true",
+                    help="only the counting-product micro-benchmark and a copy of known size "
+                         "(for hardware-counter runs)")
     ap.add_argument("--batched", type=int, default=1)
     args = ap.parse_args()
     if args.gpus != 1:
@@ -110,6 +114,18 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     import paper_2602_05470_amd as B
     import instances as I
+    if args.micro_only:
+        ctx = B.Context(B.Options())
+        res = tgemm_micro(B, ctx, torch)
+        # a plain device copy of known size (512 MiB read + 512 MiB written):
+        # the reference that scales the hardware byte counters
+        x = torch.ones(128 << 20, dtype=torch.int32, device="cuda")
+        y = torch.empty_like(x)
+        y.copy_(x)
+        torch.cuda.synchronize()
+        ctx.close()
+        print(json.dumps({"tgemm_micro": res, "copy_bytes_each_way": 512 << 20}), flush=True)
+        return
     want = golden_sg16()
     insts = [I.spin_glass_square(16, s) for s in range(20)]
     opts = B.Options(log2_target=10, residues_per_pass=3, branching=1, batched=args.batched)
@@ -122,10 +138,12 @@ def main():
     t0 = time.perf_counter()
     exact = 0
     leaves = 0
+    phases = [0.0] * 8
     for i in range(args.steps):
         g = insts[i % 20]
         r = ctx.solve_spinglass(g["n"], g["edges"], g["J"])
         leaves += r.leaves
+        phases = [a + b for a, b in zip(phases, r.seconds)]
         ok = (r.value, r.count) == want[i % 20] and r.certified
         exact += ok
         print("step %d seed %d E0=%d deg=%d leaves=%d %s" % (i, i % 20, r.value, r.count, r.leaves,
@@ -167,6 +185,26 @@ def main():
                         "GB_s": round(s["bytes"] / max(s["seconds"], 1e-12) / 1e9, 2)}
                     for n, s in stats.items()},
     }
+    names = ["total", "build+plan", "search", "contraction", "crt+certification", "configuration"]
+    line["phases_ms"] = {nm: round(1e3 * phases[i] / args.steps, 3) for i, nm in enumerate(names)}
+    if not args.no_per_branch:
+        # the same path without batching: one branch at a time (step programs
+        # replayed from a hipGraph), on the first instances
+        pb = B.Context(B.Options(log2_target=10, residues_per_pass=3, branching=1, batched=0))
+        g = insts[0]
+        pb.solve_spinglass(g["n"], g["edges"], g["J"])
+        n_pb = 3
+        t2 = time.perf_counter()
+        ok = 0
+        for i in range(n_pb):
+            g = insts[i]
+            r = pb.solve_spinglass(g["n"], g["edges"], g["J"])
+            ok += (r.value, r.count) == want[i] and r.certified
+        t3 = time.perf_counter()
+        pb.close()
+        line["per_branch"] = {"value": round(3600.0 * ok / (t3 - t2), 1), "unit": "instances/hour",
+                              "instances": n_pb, "exact": ok,
+                              "note": "batched=0: branches contracted one at a time"}
     if not args.no_micro:
         line["tgemm_micro"] = tgemm_micro(B, ctx, torch)
     if not args.no_cpu_baseline:

@@ -265,9 +265,11 @@ bbtn_status bbtn_scorer_load(bbtn_ctx* ctx, const char* path);
  * (kind 0: spin glass with weights = J, h; kind 1: MWIS with weights = w)
  * with T_target = 2^log2_target for up to max_nodes nodes; at each node,
  * cand_per_node candidate seed variables give one row each: 32 features and
- * the label log2(1 + sum over the children that survive pruning of
- * 2^(time complexity of the child)), minus the smallest such label among the
- * node's candidates (the scorer ranks the candidates of one node).  Host arrays X[capacity*32], y[capacity];
+ * the label log2(gamma) of the best branching rule the planner grows from
+ * that seed (the characteristic equation's branching factor, which reflects
+ * both the problem-size reduction and the configurations pruned), minus the
+ * smallest such label among the node's candidates (the scorer ranks the
+ * candidates of one node).  Host arrays X[capacity*32], y[capacity];
  * *rows receives the row count (pass X = y = NULL to query it).  Host-only:
  * ctx may be NULL (region size 8) or a context (its region_max). */
 bbtn_status bbtn_scorer_collect(bbtn_ctx* ctx, int32_t kind, int32_t n, int32_t m,

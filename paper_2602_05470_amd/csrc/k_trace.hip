@@ -5,49 +5,47 @@
 // already known (set by the step that consumed the output), so the step's
 // summed variables take the state q that reaches the maximum of
 // A[b, m, q] + B[b, q, n] (lowest q on ties).  One workgroup; a parallel
-// argmax over q per step.  Latency-bound.
+// argmax over q per step.  Latency-bound.  Up to 48K variables.
 #include "kernels.h"
 #include "trace.h"
 
 namespace bbtn {
 
-__global__ void __launch_bounds__(256)
+// One wavefront walks the steps; the variable states live in LDS so that a
+// state written by lane 0 is read by the other lanes of the same wave (LDS
+// operations of a wave complete in order) without a workgroup barrier.
+constexpr int TRACE_LDS_VARS = 48 * 1024;
+
+__global__ void __launch_bounds__(64)
 trace_kernel(const TraceStep* steps, int32_t n_steps, const int32_t* vars,
-             const int32_t* ws, int8_t* assign, int32_t* status) {
-  __shared__ int64_t sbase[2];
-  __shared__ int32_t sv[4];
-  __shared__ int64_t sq[4];
+             const int32_t* ws, int8_t* assign, int32_t n_vars, int32_t* status) {
+  __shared__ int8_t sa[TRACE_LDS_VARS];
+  const int lane = threadIdx.x;
+  for (int v = lane; v < n_vars; v += 64) sa[v] = assign[v];
+  __syncthreads();
+  int bad = 0;
   for (int32_t s = n_steps - 1; s >= 0; --s) {
     const TraceStep st = steps[s];
     const int32_t* av = vars + st.var_off;                 // [K][M][batch]
     const int32_t* bv = av + (st.rk + st.rm + st.rb);      // [N][K][batch]
-    if (threadIdx.x == 0) {
-      int64_t ab = 0, bb = 0;
-      int bad = 0;
-      for (int j = st.rk; j < st.rk + st.rm + st.rb; ++j) {
-        const int8_t x = assign[av[j]];
-        bad |= x < 0;
-        ab |= (int64_t)(x & 1) << j;
-      }
-      for (int j = 0; j < st.rn + st.rk + st.rb; ++j) {
-        if (j >= st.rn && j < st.rn + st.rk) continue;
-        const int8_t x = assign[bv[j]];
-        bad |= x < 0;
-        bb |= (int64_t)(x & 1) << j;
-      }
-      if (bad) atomicOr(status, 1);
-      sbase[0] = ab;
-      sbase[1] = bb;
+    // every lane forms the operand bases from the known states
+    int64_t ab = 0, bb = 0;
+    for (int j = st.rk; j < st.rk + st.rm + st.rb; ++j) {
+      const int8_t x = sa[av[j]];
+      bad |= x < 0;
+      ab |= (int64_t)(x & 1) << j;
     }
-    __syncthreads();
-    const int64_t ab = sbase[0], bb = sbase[1];
+    for (int j = 0; j < st.rn + st.rk + st.rb; ++j) {
+      if (j >= st.rn && j < st.rn + st.rk) continue;
+      const int8_t x = sa[bv[j]];
+      bad |= x < 0;
+      bb |= (int64_t)(x & 1) << j;
+    }
     int32_t best = INT32_MIN;
     int64_t bq = INT64_MAX;
     const int64_t nq = 1ll << st.rk;
-    for (int64_t q = threadIdx.x; q < nq; q += blockDim.x) {
-      const int32_t x = ws[st.a_off + ab + q];
-      const int32_t y = ws[st.b_off + bb + (q << st.rn)];
-      const int32_t v = x + y;
+    for (int64_t q = lane; q < nq; q += 64) {
+      const int32_t v = ws[st.a_off + ab + q] + ws[st.b_off + bb + (q << st.rn)];
       if (v > NEG_CUT && (v > best || (v == best && q < bq))) { best = v; bq = q; }
     }
 #pragma unroll
@@ -56,27 +54,26 @@ trace_kernel(const TraceStep* steps, int32_t n_steps, const int32_t* vars,
       const int64_t oq = __shfl_xor(bq, d, 64);
       if (ov > best || (ov == best && oq < bq)) { best = ov; bq = oq; }
     }
-    const int lane = threadIdx.x % 64, wave = threadIdx.x / 64;
-    if (lane == 0) { sv[wave] = best; sq[wave] = bq; }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      for (int w = 1; w < (int)(blockDim.x / 64); ++w)
-        if (sv[w] > best || (sv[w] == best && sq[w] < bq)) { best = sv[w]; bq = sq[w]; }
-      if (best == INT32_MIN) {
-        atomicOr(status, 2);
-        bq = 0;
-      }
-      for (int j = 0; j < st.rk; ++j) assign[av[j]] = (int8_t)((bq >> j) & 1);
+    if (best == INT32_MIN) {
+      bad |= 2;
+      bq = 0;
     }
-    __syncthreads();
+    for (int j = lane; j < st.rk; j += 64) sa[av[j]] = (int8_t)((bq >> j) & 1);
+    __syncthreads();  // a single wave: keeps the LDS writes ordered before the next reads
   }
+  for (int v = lane; v < n_vars; v += 64) assign[v] = sa[v];
+  // fold every lane's flags into one status word
+#pragma unroll
+  for (int d = 32; d > 0; d >>= 1) bad |= __shfl_xor(bad, d, 64);
+  if (lane == 0 && bad) *status = bad;
 }
 
 void launch_trace(const TraceStep* steps, int32_t n_steps, const int32_t* vars, const int32_t* ws,
-                  int8_t* assign, int32_t* status, hipStream_t st) {
+                  int8_t* assign, int32_t n_vars, int32_t* status, hipStream_t st) {
   if (n_steps <= 0) return;
-  hipLaunchKernelGGL(trace_kernel, dim3(1), dim3(256), 0, st, steps, n_steps, vars, ws, assign,
-                     status);
+  BBTN_REQUIRE(n_vars <= TRACE_LDS_VARS, "configuration traceback: too many variables");
+  hipLaunchKernelGGL(trace_kernel, dim3(1), dim3(64), 0, st, steps, n_steps, vars, ws, assign,
+                     n_vars, status);
   BBTN_HIP(hipGetLastError());
 }
 

@@ -169,7 +169,8 @@ void load_scorer(bbtn_ctx* ctx, const char* path) {
 }
 
 // Scores every free variable of a node with the MLP on the device: the score
-// is minus the predicted (standardised) log-cost, so cheaper seeds come first.
+// is minus the predicted (standardised) log branching factor, so seeds with
+// the smallest predicted gamma come first.
 VarScorer make_var_scorer(bbtn_ctx* ctx, const Network& net, const Tree& tree, int log2_target) {
   auto fc = std::make_shared<FeatureCtx>(net, tree, log2_target);
   const int64_t t = log2_target;

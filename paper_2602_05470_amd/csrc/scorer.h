@@ -42,9 +42,10 @@ VarScorer make_var_scorer(bbtn_ctx* ctx, const Network& net, const Tree& tree, i
 void load_tune_cache(bbtn_ctx* ctx, const char* path);
 
 // Run the search on a network and record, for sampled nodes and candidate
-// seeds, (features, label): the label is log2 of the summed time complexity of
-// the children that survive pruning (one level deep), minus the smallest
-// label among the node's candidates.
+// seeds, (features, label): the label is log2 of the branching factor gamma
+// of the best rule grown from the seed (the characteristic equation, which
+// folds the problem-size reduction and the pruning of F(R) together), minus
+// the smallest label among the node's candidates.
 void collect_training(const Network& net, const Tree& tree, int log2_target, int region_max,
                       int64_t incumbent, int max_nodes, int cand_per_node,
                       std::vector<float>& X, std::vector<float>& y);

@@ -462,12 +462,6 @@ struct Searcher {
       // overflow participation of every free variable
       std::vector<int32_t> cand;
       heuristic(n, heur, cand);
-      score = heur;
-      if (opt.scorer) opt.scorer(n.fixed, n.sizes, heur, score);
-      std::stable_sort(cand.begin(), cand.end(), [&](int a, int b) {
-        if (score[a] != score[b]) return score[a] > score[b];
-        return a < b;
-      });
       if (cand.empty()) throw Error(BBTN_E_INTERNAL, "rho > 0 but no overflowing variable");
       Eval best;
       // Nodes with the same fixed-variable set have the same rho structure.
@@ -481,6 +475,13 @@ struct Searcher {
         if (ev.cubes.size() == ((size_t)1 << memo->second.size())) best = std::move(ev);
       }
       if (best.cubes.empty()) {
+        // rank the seeds: the learned scorer when loaded, else the heuristic
+        score = heur;
+        if (opt.scorer) opt.scorer(n.fixed, n.sizes, heur, score);
+        std::stable_sort(cand.begin(), cand.end(), [&](int a, int b) {
+          if (score[a] != score[b]) return score[a] > score[b];
+          return a < b;
+        });
         const int n_seeds = std::min<int>(2, (int)cand.size());
         for (int si = 0; si < n_seeds; ++si) {
           Eval ev = best_from_seed(n, cand[si], score);
@@ -550,30 +551,23 @@ void collect_training(const Network& net, const Tree& tree, int log2_target, int
     const size_t row0 = y.size();
     for (int v : pick) {
       Searcher::Eval ev = s.best_from_seed(n, v, heur);
-      // label: log2 (1 + sum over surviving children of 2^tc(child))
-      std::map<uint32_t, double> tc_of;
-      double total = 0;
-      for (auto& c : ev.cubes) {
-        auto it = tc_of.find(c.mask);
-        if (it == tc_of.end()) {
-          std::vector<uint64_t> fx = n.fixed;
-          for (int j = 0; j < (int)ev.region.size(); ++j)
-            if (c.mask >> j & 1) bit_set(fx, ev.region[j]);
-          it = tc_of.emplace(c.mask, complexity(tree, fx).tc_log2).first;
-        }
-        total += std::exp2(it->second);
-      }
+      // label: the branching factor (characteristic equation) of the best
+      // rule the planner builds from this seed, in log2; it folds together
+      // the problem-size reduction and the pruning of F(R).  A seed whose
+      // rules reduce nothing gets the largest label seen at the node.
+      const double lg = ev.gamma == 0.0 ? 0.0 : std::log2(std::max(1.0, ev.gamma));
       fc.features(v, n.fixed, n.sizes, heur, n.rho, f);
       X.insert(X.end(), f, f + N_FEAT);
-      y.push_back((float)std::log2(1.0 + total));
+      y.push_back(std::isfinite(lg) ? (float)lg : -1.f);
       if (v == cand[0] || (v == cand[std::min<size_t>(1, cand.size() - 1)] && Searcher::better(ev, chosen)))
         if (Searcher::better(ev, chosen)) chosen = std::move(ev);
     }
-    // labels relative to the node's cheapest candidate: the scorer only has
-    // to rank the candidates of one node
-    float lo = INFINITY;
-    for (size_t i = row0; i < y.size(); ++i) lo = std::min(lo, y[i]);
-    for (size_t i = row0; i < y.size(); ++i) y[i] -= lo;
+    // labels relative to the node's best candidate: the scorer only has to
+    // rank the candidates of one node
+    float lo = INFINITY, hi = 0.f;
+    for (size_t i = row0; i < y.size(); ++i)
+      if (y[i] >= 0) { lo = std::min(lo, y[i]); hi = std::max(hi, y[i]); }
+    for (size_t i = row0; i < y.size(); ++i) y[i] = y[i] >= 0 ? y[i] - lo : hi - lo + 1.f;
     ++done;
     // continue the search with the heuristic's choice
     if (chosen.cubes.empty() || !std::isfinite(chosen.gamma)) continue;

@@ -12,6 +12,6 @@ struct TraceStep {
 };
 
 void launch_trace(const TraceStep* steps, int32_t n_steps, const int32_t* vars, const int32_t* ws,
-                  int8_t* assign, int32_t* status, hipStream_t st);
+                  int8_t* assign, int32_t n_vars, int32_t* status, hipStream_t st);
 
 }  // namespace bbtn

@@ -3,9 +3,9 @@
 Data: for seeded +-J lattices (16 x 16 at T_target = 2^10 and 24 x 24 at
 2^16 by default), the planner records, at each of the first `max_nodes`
 search nodes and for several candidate seed variables, 32 features and the
-label log2(1 + sum over the surviving children of 2^tc(child)) (the
-branching's cost one level deep, after pruning), taken relative to the node's
-cheapest candidate.  Collection is host code
+label log2(gamma) of the best branching rule grown from that seed (the
+characteristic equation's branching factor, after pruning), taken relative to
+the node's best candidate.  Collection is host code
 (run in threads; the library releases the GIL).  Training runs on the GPU
 with the library's own forward/backward/Adam kernels.
 

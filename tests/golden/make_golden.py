@@ -10,10 +10,40 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
 
 import instances as I  # noqa: E402
-from oracle import tm  # noqa: E402
+from oracle import tm, tm_c  # noqa: E402
+
+
+def larger():
+    """Exact pins for larger parity cases (C transfer matrix, multiword
+    counts)."""
+    with open(os.path.join(HERE, "sg20.txt"), "w") as f:
+        f.write("# +-J spin glass 20x20 open lattice, zero field, seeds 0-4:\n")
+        f.write("# seed E0 degeneracy  (oracle: exact transfer matrix, C)\n")
+        for s in range(5):
+            g = I.spin_glass_square(20, s)
+            e0, deg = tm_c.spin_glass_lattice(20, 20, g["edges"], g["J"])
+            f.write("%d %d %d\n" % (s, e0, deg))
+            f.flush()
+    with open(os.path.join(HERE, "ksg20.txt"), "w") as f:
+        f.write("# unweighted MIS on King's subgraph 20x20, fill 0.8, seeds 0-4:\n")
+        f.write("# seed n W* count  (oracle: exact transfer matrix, C)\n")
+        for s in range(5):
+            g = I.kings_subgraph(20, s)
+            w, c = tm_c.kings_subgraph(g)
+            f.write("%d %d %d %d\n" % (s, g["n"], w, c))
+            f.flush()
+    with open(os.path.join(HERE, "sg24.txt"), "w") as f:
+        f.write("# +-J spin glass 24x24 open lattice, zero field, seeds 0-1:\n")
+        f.write("# seed E0 degeneracy  (oracle: exact transfer matrix, C)\n")
+        for s in range(2):
+            g = I.spin_glass_square(24, s)
+            e0, deg = tm_c.spin_glass_lattice(24, 24, g["edges"], g["J"])
+            f.write("%d %d %d\n" % (s, e0, deg))
+            f.flush()
 
 
 def main():
+    larger()
     with open(os.path.join(HERE, "sg16.txt"), "w") as f:
         f.write("# +-J spin glass 16x16 open lattice, zero field, seeds 0-19:\n")
         f.write("# seed E0 degeneracy  (oracle: exact transfer matrix)\n")

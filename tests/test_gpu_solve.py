@@ -148,3 +148,35 @@ def test_per_branch_graph_replay_equals_eager(B, seed):
         _check_sg(r, g, want)
         res[graphs] = (r.value, r.count, r.leaves, bytes(r.config))
     assert res[0] == res[1]
+
+
+@pytest.mark.parametrize("seed", range(5))
+def test_sg20_bbtn_vs_c_transfer_matrix(B, seed):
+    """20x20 +-J (65536 branches at T_target = 2^12), counts past 2^57."""
+    want = {s: (e, d) for s, e, d in _golden("sg20.txt")}[seed]
+    g = I.spin_glass_square(20, seed)
+    with B.Context(B.Options(log2_target=12, residues_per_pass=3)) as ctx:
+        r = ctx.solve_spinglass(g["n"], g["edges"], g["J"])
+    _check_sg(r, g, want)
+
+
+@pytest.mark.parametrize("seed", range(5))
+def test_ksg20_bbtn_vs_c_transfer_matrix(B, seed):
+    s, n, w, c = _golden("ksg20.txt")[seed]
+    g = I.kings_subgraph(20, seed)
+    assert g["n"] == n
+    with B.Context(B.Options(log2_target=12, residues_per_pass=4)) as ctx:
+        r = ctx.solve_mwis(g["n"], g["edges"], g["w"])
+    assert (r.value, r.count) == (w, c) and r.certified
+    assert config.independent_set_weight(r.config, g["edges"], g["w"]) == w
+
+
+@pytest.mark.parametrize("seed", range(2))
+def test_sg24_large_leaves_four_residues(B, seed):
+    """24x24 at T_target = 2^16: branch tensors too large for LDS go through
+    the step-by-step batched executor; 4 residues per pass."""
+    want = {s: (e, d) for s, e, d in _golden("sg24.txt")}[seed]
+    g = I.spin_glass_square(24, seed)
+    with B.Context(B.Options(log2_target=16, residues_per_pass=4)) as ctx:
+        r = ctx.solve_spinglass(g["n"], g["edges"], g["J"])
+    _check_sg(r, g, want)

@@ -375,3 +375,31 @@ def test_bf16_decode_is_exact():
     # bf16 keeps 8 significant bits: relative rounding error below 2^-8
     assert np.all(np.abs(back - x) <= np.abs(x) * 2.0 ** -8)
     assert back[0] == 1.0 and back[1] == -2.5 and back[2] == 3.140625
+
+
+# ------------------------------------------------- C transfer-matrix oracle
+def test_c_tm_matches_python_tm_and_brute_force():
+    from oracle import tm_c
+    for s in range(3):
+        g = I.spin_glass_square(4, s)
+        assert tm_c.spin_glass_lattice(4, 4, g["edges"], g["J"]) == brute.spin_glass(g["n"], g["edges"], g["J"])[:2]
+        g = I.spin_glass_square(9, s)
+        assert tm_c.spin_glass_lattice(9, 9, g["edges"], g["J"]) == tm.spin_glass_square(g)
+        g = I.spin_glass_rect(5, 7, s)
+        h = np.random.default_rng(s).integers(-2, 3, size=g["n"]).astype(np.int32)
+        assert tm_c.spin_glass_lattice(5, 7, g["edges"], g["J"], h) == tm.spin_glass_lattice(5, 7, g["edges"], g["J"], h)
+        g = I.kings_subgraph(9, s)
+        assert tm_c.kings_subgraph(g) == tm.kings_subgraph(g)
+        g = I.kings_subgraph(5, s, weights="1..10")
+        assert tm_c.kings_subgraph(g) == brute.mwis(g["n"], g["edges"], g["w"])[:2]
+
+
+def test_c_tm_multiword_counts():
+    """Counts beyond 64 bits: with every coupling zero each configuration has
+    energy 0, so the degeneracy is exactly 2^n (n = 90 > 64 here)."""
+    from oracle import tm_c
+    g = I.spin_glass_rect(30, 3, 0)           # frontier of 3 sites
+    J = np.zeros_like(g["J"])
+    assert tm_c.spin_glass_lattice(30, 3, g["edges"], J) == (0, 2 ** 90)
+    g = I.full_kings_graph(3)
+    assert tm_c.kings_subgraph(g) == (4, 1)
