@@ -137,7 +137,7 @@ class Options:
     branching: int = 1
     batched: int = 1
     region_max: int = 8
-    local_search: int = 200
+    local_search: int = 100
     graphs: int = 1
     scorer_weights: str | None = None
     autotune_cache: str | None = None

@@ -410,7 +410,7 @@ void bbtn_default_options(bbtn_options* o) {
   o->branching = 1;
   o->batched = 1;
   o->region_max = 8;
-  o->local_search = 200;
+  o->local_search = 100;
   o->graphs = 1;
   o->scorer_weights = nullptr;
   o->autotune_cache = nullptr;

@@ -585,13 +585,16 @@ void bb_search(const Network& net, const Tree& tree, const SearchOptions& opt,
 std::vector<uint8_t> local_search_spinglass(int32_t n, int32_t m, const int32_t* uv,
                                             const int32_t* J, const int32_t* h, int sweeps,
                                             uint64_t seed) {
+  // simulated annealing (single-spin Metropolis updates, geometric
+  // temperature schedule), then zero-temperature sweeps; one restart per 100
+  // sweeps.  Acceptance probabilities come from a per-sweep table of
+  // exp(-dE/T) for small dE.
   std::vector<std::vector<std::pair<int, int>>> adj(n);
   for (int e = 0; e < m; ++e) {
     adj[uv[2 * e]].push_back({uv[2 * e + 1], J[e]});
     adj[uv[2 * e + 1]].push_back({uv[2 * e], J[e]});
   }
   std::mt19937_64 rng(seed);
-  std::uniform_real_distribution<double> U(0, 1);
   auto energy = [&](const std::vector<int>& s) {
     int64_t E = 0;
     for (int e = 0; e < m; ++e) E -= (int64_t)J[e] * s[uv[2 * e]] * s[uv[2 * e + 1]];
@@ -600,19 +603,28 @@ std::vector<uint8_t> local_search_spinglass(int32_t n, int32_t m, const int32_t*
   };
   std::vector<int> best_s(n, 1);
   int64_t bestE = energy(best_s);
-  const int restarts = 3;
+  const int restarts = std::max(1, sweeps / 100);
+  const int per = std::max(1, std::min(sweeps, 100));
+  constexpr int TAB = 64;
+  double acc[TAB];
   for (int rs = 0; rs < restarts; ++rs) {
     std::vector<int> s(n);
     for (int i = 0; i < n; ++i) s[i] = (rng() & 1) ? 1 : -1;
     int64_t E = energy(s);
     const double T0 = 2.0, T1 = 0.05;
-    for (int sw = 0; sw < sweeps + 20; ++sw) {
-      const double T = sw < sweeps ? T0 * std::pow(T1 / T0, (double)sw / std::max(1, sweeps - 1)) : 0.0;
+    for (int sw = 0; sw < per + 10; ++sw) {
+      const double T = sw < per ? T0 * std::pow(T1 / T0, (double)sw / std::max(1, per - 1)) : 0.0;
+      for (int d = 0; d < TAB; ++d) acc[d] = T > 0 ? std::exp(-(double)d / T) : 0.0;
       for (int i = 0; i < n; ++i) {
         int64_t f = h ? h[i] : 0;
         for (auto& pr : adj[i]) f += (int64_t)pr.second * s[pr.first];
         const int64_t dE = 2 * s[i] * f;
-        if (dE <= 0 || (T > 0 && U(rng) < std::exp(-(double)dE / T))) {
+        bool flip = dE <= 0;
+        if (!flip && T > 0) {
+          const double p = dE < TAB ? acc[dE] : std::exp(-(double)dE / T);
+          flip = (double)(rng() >> 11) * 0x1.0p-53 < p;
+        }
+        if (flip) {
           s[i] = -s[i];
           E += dE;
           if (E < bestE) { bestE = E; best_s = s; }
