@@ -20,6 +20,18 @@
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+/* number of threads the parallel loops use */
+int tm_threads(void) {
+#ifdef _OPENMP
+  return omp_get_max_threads();
+#else
+  return 1;
+#endif
+}
 
 typedef struct {
   int64_t *v;     /* [S] values (min form)          */

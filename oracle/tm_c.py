@@ -23,8 +23,15 @@ def _load():
         lib.ksg_tm.argtypes = [C.c_int, C.c_void_p, C.c_void_p, C.POINTER(C.c_int64), C.c_void_p,
                                C.c_int]
         lib.ksg_tm.restype = C.c_int
+        lib.tm_threads.argtypes = []
+        lib.tm_threads.restype = C.c_int
         _lib = lib
     return _lib
+
+
+def threads():
+    """Threads the C oracle's parallel loops use (OpenMP)."""
+    return int(_load().tm_threads())
 
 
 def _count(words):

@@ -48,97 +48,120 @@ __device__ __forceinline__ void combine(int32_t& v, uint32_t* r, int32_t v2, con
   }
 }
 
-constexpr int NTHR = 256;
+constexpr int NTHR = PERSIST_THREADS;
 
+// source index of entry e of a staged operand: the fixed bits plus every run
+// of contiguous bits moved from e into place (runs and count are uniform)
+__device__ __forceinline__ uint32_t gather_index(uint32_t e, uint32_t fixed, int nr,
+                                                 const uint32_t (&rr)[P_MAX_RUNS]) {
+  uint32_t s = fixed;
+#pragma unroll
+  for (int r = 0; r < P_MAX_RUNS; ++r) {
+    if (r < nr) {
+      const uint32_t x = rr[r];
+      const uint32_t ol = x & 255u, il = (x >> 8) & 255u, len = x >> 16;
+      s |= ((e >> ol) & ((1u << len) - 1u)) << il;
+    }
+  }
+  return s;
+}
+
+// One wavefront per workgroup and per task.  The task index is made
+// wave-uniform, and every descriptor is read through a pointer at a uniform
+// address, so descriptors stay in scalar registers.
 template <int KR>
 __global__ void __launch_bounds__(NTHR)
 persist_kernel(const PersistArgs a) {
   constexpr int W = 1 + KR;
   extern __shared__ uint32_t lds[];
-  const int64_t cap = a.lds_entries;  // entries per operand buffer
-  uint32_t* la = lds;                 // W planes of cap entries
+  const int cap = (int)a.lds_entries;  // entries per operand buffer
+  uint32_t* la = lds;                  // W planes of cap entries
   uint32_t* lb = lds + W * cap;
   int32_t* pv = (int32_t*)(lb + W * cap);  // NTHR partial values
   uint32_t* pr = (uint32_t*)(pv + NTHR);   // KR x NTHR partial residues
-  __shared__ int64_t s_task;
   uint32_t* scr = a.scratch + (int64_t)blockIdx.x * W * a.scratch_entries;
   const int tid = threadIdx.x;
 
   for (;;) {
-    if (tid == 0) s_task = atomicAdd(a.queue, 1ull);
-    __syncthreads();
-    const int64_t task = s_task;
-    __syncthreads();
+    uint32_t got = 0;
+    if (tid == 0) got = (uint32_t)atomicAdd(a.queue, 1ull);
+    const int64_t task = (int64_t)__builtin_amdgcn_readfirstlane(__shfl(got, 0));
     if (task >= a.n_tasks) break;
-    const PTask tk = a.tasks[task];
-    const uint8_t* asg = a.assign + tk.assign_off;
+    const PTask* tk = a.tasks + task;
+    const uint8_t* asg = a.assign + tk->assign_off;
+    const int32_t n_steps = tk->n_steps;
+    const PStep* sp = a.steps + tk->step_off;
 
-    for (int32_t si = 0; si < tk.n_steps; ++si) {
-      const PStep st = a.steps[tk.step_off + si];
+    for (int32_t si = 0; si < n_steps; ++si, ++sp) {
       // ---- stage operands
 #pragma unroll
       for (int w = 0; w < 2; ++w) {
-        const POperand& op = w == 0 ? st.a : st.b;
+        const POperand* op = w == 0 ? &sp->a : &sp->b;
         uint32_t* dst = w == 0 ? la : lb;
-        uint64_t fixed = 0;
-        for (int f = 0; f < op.n_fix; ++f) {
-          const PFix fx = a.fixes[op.fix_off + f];
-          fixed |= (uint64_t)(asg[fx.idx] & 1) << fx.pos;
+        uint32_t fixed = 0;
+        const int nf = op->n_fix;
+        for (int f = 0; f < nf; ++f) {
+          const PFix fx = a.fixes[op->fix_off + f];
+          fixed |= (uint32_t)(asg[fx.idx] & 1) << fx.pos;
         }
-        const uint32_t* src = op.kind == PK_BASE     ? a.base + op.src_off
-                              : op.kind == PK_SHARED ? a.shared + op.src_off
-                                                     : scr + op.src_off;
-        const int64_t sstride = op.kind == PK_BASE     ? a.base_total
-                                : op.kind == PK_SHARED ? a.shared_entries
-                                                       : a.scratch_entries;
-        const int64_t n = 1ll << op.rank;
-        for (int64_t e = tid; e < n; e += NTHR) {
-          uint64_t s = fixed;
-          for (int r = 0; r < op.n_runs; ++r) {
-            const GatherRun run = op.runs[r];
-            s |= (((uint64_t)e >> run.out_lo) & ((1ull << run.len) - 1)) << run.in_lo;
-          }
+        const int kind = op->kind;
+        const uint32_t* src = kind == PK_BASE     ? a.base + op->src_off
+                              : kind == PK_SHARED ? a.shared + op->src_off
+                                                  : scr + op->src_off;
+        const int64_t sstride = kind == PK_BASE     ? a.base_total
+                                : kind == PK_SHARED ? a.shared_entries
+                                                    : a.scratch_entries;
+        const int nr = op->n_runs;
+        uint32_t rr[P_MAX_RUNS];
+#pragma unroll
+        for (int r = 0; r < P_MAX_RUNS; ++r) rr[r] = op->runs[r];
+        const int n = 1 << op->rank;
+        const int64_t mat = op->mat_off;
+        for (int e = tid; e < n; e += NTHR) {
+          const uint32_t s = gather_index((uint32_t)e, fixed, nr, rr);
 #pragma unroll
           for (int p = 0; p < W; ++p) {
             const uint32_t x = src[p * sstride + s];
             dst[p * cap + e] = x;
-            if (op.mat_off >= 0) scr[p * a.scratch_entries + op.mat_off + e] = x;
+            if (mat >= 0) scr[p * a.scratch_entries + mat + e] = x;
           }
         }
       }
       __syncthreads();
       // ---- product
-      const int rn = st.rn, rm = st.rm, rk = st.rk;
-      const int64_t nC = 1ll << (st.rb + rm + rn);
-      const int64_t K = 1ll << rk;
+      const int rn = sp->rn, rm = sp->rm, rk = sp->rk;
+      const int nC = 1 << (sp->rb + rm + rn);
+      const int K = 1 << rk;
       // threads per output: split K when outputs are few
       int tpo = 1;
       while (tpo * 2 <= NTHR / nC && tpo * 2 <= K) tpo *= 2;
-      const int64_t kper = K / tpo;
-      const int64_t per_round = NTHR / tpo;
-      for (int64_t o0 = 0; o0 < nC; o0 += per_round) {
-        const int64_t o = o0 + tid / tpo;
+      const int kper = K / tpo;
+      const int per_round = NTHR / tpo;
+      const int c_kind = sp->c_kind;
+      const int64_t c_off = sp->c_off;
+      for (int o0 = 0; o0 < nC; o0 += per_round) {
+        const int o = o0 + tid / tpo;
         const int j = tid % tpo;
         int32_t V = INT32_MIN;
         uint32_t res[KR > 0 ? KR : 1];
         if (o < nC) {
-          const int64_t n = o & ((1ll << rn) - 1);
-          const int64_t m = (o >> rn) & ((1ll << rm) - 1);
-          const int64_t b = o >> (rn + rm);
-          const int64_t abase = (m << rk) | (b << (rk + rm));
-          const int64_t bbase = n | (b << (rn + rk));
-          const int64_t q0 = j * kper, q1 = q0 + kper;
+          const int nn = o & ((1 << rn) - 1);
+          const int m = (o >> rn) & ((1 << rm) - 1);
+          const int b = o >> (rn + rm);
+          const int abase = (m << rk) | (b << (rk + rm));
+          const int bbase = nn | (b << (rn + rk));
+          const int q0 = j * kper, q1 = q0 + kper;
           const int32_t* Av = (const int32_t*)la;
           const int32_t* Bv = (const int32_t*)lb;
-          for (int64_t q = q0; q < q1; ++q) V = max(V, Av[abase + q] + Bv[bbase + (q << rn)]);
+          for (int q = q0; q < q1; ++q) V = max(V, Av[abase + q] + Bv[bbase + (q << rn)]);
           if constexpr (KR > 0) {
             uint64_t acc[KR];
 #pragma unroll
             for (int p = 0; p < KR; ++p) acc[p] = 0;
             if (V > NEG_CUT) {
               int cnt = 0;
-              for (int64_t q = q0; q < q1; ++q) {
-                const int64_t ia = abase + q, ib = bbase + (q << rn);
+              for (int q = q0; q < q1; ++q) {
+                const int ia = abase + q, ib = bbase + (q << rn);
                 if (Av[ia] + Bv[ib] == V) {
 #pragma unroll
                   for (int p = 0; p < KR; ++p)
@@ -172,8 +195,8 @@ persist_kernel(const PersistArgs a) {
         }
         if (j == 0 && o < nC) {
           const bool fin = V > NEG_CUT;
-          const bool sh = st.c_kind == PK_SHARED;
-          uint32_t* c = (sh ? a.shared : scr) + st.c_off;
+          const bool sh = c_kind == PK_SHARED;
+          uint32_t* c = (sh ? a.shared : scr) + c_off;
           const int64_t cs = sh ? a.shared_entries : a.scratch_entries;
           c[o] = (uint32_t)(fin ? V : NEG);
 #pragma unroll
@@ -183,17 +206,18 @@ persist_kernel(const PersistArgs a) {
       __syncthreads();
     }
     // ---- branch result = root (.) folded constant
-    if (tid == 0 && tk.out_idx >= 0) {
-      const int64_t l = tk.out_idx;
+    const int64_t l = tk->out_idx;
+    const int64_t root_off = tk->root_off;
+    if (tid == 0 && l >= 0) {
       const int32_t cv = (int32_t)a.lconst[l];
       int32_t rv = 0;
-      const uint32_t* root = scr + tk.root_off;
-      if (tk.root_off >= 0) rv = (int32_t)root[0];
+      const uint32_t* root = scr + root_off;
+      if (root_off >= 0) rv = (int32_t)root[0];
       const bool fin = cv > NEG_CUT && rv > NEG_CUT;
       a.out[l] = (uint32_t)(fin ? cv + rv : NEG);
 #pragma unroll
       for (int p = 0; p < KR; ++p) {
-        const uint32_t rr = tk.root_off >= 0 ? root[(p + 1) * a.scratch_entries] : 1u;
+        const uint32_t rr = root_off >= 0 ? root[(p + 1) * a.scratch_entries] : 1u;
         const uint64_t x = (uint64_t)rr * a.lconst[(p + 1) * a.n_out + l];
         a.out[(p + 1) * a.n_out + l] = fin ? pmod(x, a.mod.p[p], a.mod.c[p]) : 0u;
       }

@@ -173,7 +173,7 @@ tgemm_kernel(const GemmArgs a) {
           for (int p = 0; p < KR; ++p) Bc[p][j][i] = in ? Bb[(p + 1) * a.pB + o] : 0u;
         }
         __syncthreads();
-#pragma unroll
+#pragma unroll 3
         for (int kk = 0; kk < TK; ++kk) {
           int32_t av[RM], bv[RN];
           uint32_t ac[KR][RM], bc[KR][RN];

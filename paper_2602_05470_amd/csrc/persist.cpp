@@ -7,8 +7,7 @@
 namespace bbtn {
 
 int persist_max_rank(int k) {
-  // two operand buffers of (1 + k) planes within 64 KiB of LDS, so that two
-  // workgroups share a CU
+  // two operand buffers of (1 + k) planes within 64 KiB of LDS
   int r = 0;
   while (persist_lds_bytes(k, 1ll << (r + 1)) <= (64u << 10)) ++r;
   return r;
@@ -84,7 +83,7 @@ void run_persistent(bbtn_ctx* ctx, const Network& net, const std::vector<Persist
         }
         po.rank = rank;
         po.n_runs = gpn.n_runs;
-        for (int r = 0; r < gpn.n_runs; ++r) po.runs[r] = gpn.runs[r];
+        for (int r = 0; r < gpn.n_runs; ++r) po.runs[r] = pack_run(gpn.runs[r]);
         // programs that keep everything materialise gathered operands
         po.mat_off = (op.temp >= 0 && g.keep_all) ? g.buf_off[op.temp] : -1;
         po.fix_off = (int32_t)fixes.size();
@@ -163,10 +162,11 @@ void run_persistent(bbtn_ctx* ctx, const Network& net, const std::vector<Persist
   ctx->persist.ensure(off);
   uint8_t* dev = ctx->persist.as<uint8_t>();
   BBTN_HIP(hipMemcpyAsync(dev, host.data(), host.size(), hipMemcpyHostToDevice, st));
-  // launch shape: up to 2 workgroups per CU (LDS-limited), never more than tasks
+  // launch shape: as many one-wave workgroups per CU as LDS allows (at most
+  // 16), never more than tasks
   const int64_t lds_entries = 1ll << max_rank;
   const size_t lds = persist_lds_bytes(k, lds_entries);
-  const int per_cu = std::max(1, std::min(2, (int)((160u << 10) / std::max<size_t>(lds, 1))));
+  const int per_cu = std::max(1, std::min(16, (int)((160u << 10) / std::max<size_t>(lds, 1))));
   const int64_t max_blocks = (int64_t)device_cus() * per_cu;
   const int64_t most = std::max<int64_t>((int64_t)tasks.size(), (int64_t)shared_tasks.size());
   ctx->work.ensure((size_t)std::min(max_blocks, most) * W * scratch * 4);

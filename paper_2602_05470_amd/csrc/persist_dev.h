@@ -23,8 +23,13 @@ struct POperand {
   int32_t fix_off;   // into the PFix array
   int32_t pad;
   int64_t mat_off;   // >= 0: also write the staged operand to scratch here
-  GatherRun runs[P_MAX_RUNS];
+  // runs of contiguous bits, packed as out_lo | in_lo << 8 | len << 16
+  uint32_t runs[P_MAX_RUNS];
 };
+
+inline uint32_t pack_run(const GatherRun& r) {
+  return (uint32_t)r.out_lo | (uint32_t)r.in_lo << 8 | (uint32_t)r.len << 16;
+}
 
 struct PStep {
   int32_t rb, rm, rn, rk;
@@ -60,9 +65,12 @@ struct PersistArgs {
   uint32_t* shared;        // (1 + k) planes of shared_entries
   int64_t shared_entries;
   int64_t lds_entries;
-  unsigned long long* queue;
+  unsigned long long* queue;  // task counter, zeroed before the launch
   Moduli mod;
 };
+
+// one wavefront per workgroup
+constexpr int PERSIST_THREADS = 64;
 
 size_t persist_lds_bytes(int k, int64_t lds_entries);
 void launch_persist(int k, const PersistArgs& a, int n_blocks, hipStream_t st);
