@@ -28,6 +28,8 @@ const TileCfg kTileCfgs[N_TILE_CFGS] = {
     {64, 8, 2, 1, 16},    // 4: few columns, 256 threads
     {1, 256, 1, 1, 16},   // 5: one row (vector-matrix), 256 threads
     {256, 1, 1, 1, 16},   // 6: one column (matrix-vector), 256 threads
+    {64, 32, 4, 2, 24},   // 7: tall, 256 threads (fewer accumulators than 0)
+    {32, 64, 2, 4, 24},   // 8: wide, 256 threads
 };
 
 struct GemmArgs {
@@ -76,10 +78,19 @@ tgemm_kernel(const GemmArgs a) {
   constexpr int TY = TM / RM;
   constexpr int NT = TX * TY;
   constexpr int KP = KR > 0 ? KR : 1;
-  __shared__ int32_t Av[TK][TM];
-  __shared__ int32_t Bv[TK][TN];
-  __shared__ uint32_t Ac[KP][TK][TM];
-  __shared__ uint32_t Bc[KP][TK][TN];
+  // A is staged transposed (k-major): consecutive threads write consecutive
+  // k of one row, so rows of TM words would put them all in one LDS bank;
+  // four words of padding spread them (rows stay 16-byte aligned)
+  constexpr int TMP = TM >= 8 ? TM + 4 : TM;
+  // one LDS region per operand: rows [0, TK) hold values, rows
+  // [(1 + p) TK, (2 + p) TK) residue plane p; the values pass uses all
+  // (1 + KP) TK rows as one deeper slice
+  __shared__ uint32_t As[(1 + KP) * TK][TMP];
+  __shared__ uint32_t Bs[(1 + KP) * TK][TN];
+  auto Av = [&](int kk, int i) -> int32_t& { return *(int32_t*)&As[kk][i]; };
+  auto Bv = [&](int kk, int i) -> int32_t& { return *(int32_t*)&Bs[kk][i]; };
+  auto Ac = [&](int p, int kk, int i) -> uint32_t& { return As[(1 + p) * TK + kk][i]; };
+  auto Bc = [&](int p, int kk, int i) -> uint32_t& { return Bs[(1 + p) * TK + kk][i]; };
 
   int64_t t = xcd_remap(blockIdx.x, gridDim.x);
   const int64_t tn_i = t % a.tiles_n;
@@ -102,32 +113,35 @@ tgemm_kernel(const GemmArgs a) {
 #pragma unroll
     for (int c = 0; c < RN; ++c) V[r][c] = INT32_MIN;
 
-  // ---- pass 1: values
-  for (int64_t k0 = kbeg; k0 < kend; k0 += TK) {
-    for (int idx = tid; idx < TM * TK; idx += NT) {
-      const int i = idx / TK, j = idx % TK;
-      const int64_t m = m0 + i, q = k0 + j;
-      Av[j][i] = (m < a.M && q < kend) ? (int32_t)Ab[m * a.K + q] : NEG;
-    }
-    for (int idx = tid; idx < TK * TN; idx += NT) {
-      const int j = idx / TN, i = idx % TN;
-      const int64_t n = n0 + i, q = k0 + j;
-      Bv[j][i] = (n < a.N && q < kend) ? (int32_t)Bb[q * a.N + n] : NEG;
-    }
-    __syncthreads();
+  // ---- pass 1: values, in slices (1 + KP) times deeper than pass 2's
+  {
+    constexpr int TK1 = (1 + KP) * TK;
+    for (int64_t k0 = kbeg; k0 < kend; k0 += TK1) {
+      for (int idx = tid; idx < TM * TK1; idx += NT) {
+        const int i = idx / TK1, j = idx % TK1;
+        const int64_t m = m0 + i, q = k0 + j;
+        Av(j, i) = (m < a.M && q < kend) ? (int32_t)Ab[m * a.K + q] : NEG;
+      }
+      for (int idx = tid; idx < TK1 * TN; idx += NT) {
+        const int j = idx / TN, i = idx % TN;
+        const int64_t n = n0 + i, q = k0 + j;
+        Bv(j, i) = (n < a.N && q < kend) ? (int32_t)Bb[q * a.N + n] : NEG;
+      }
+      __syncthreads();
 #pragma unroll 4
-    for (int kk = 0; kk < TK; ++kk) {
-      int32_t av[RM], bv[RN];
+      for (int kk = 0; kk < TK1; ++kk) {
+        int32_t av[RM], bv[RN];
 #pragma unroll
-      for (int r = 0; r < RM; ++r) av[r] = Av[kk][ty * RM + r];
+        for (int r = 0; r < RM; ++r) av[r] = Av(kk, ty * RM + r);
 #pragma unroll
-      for (int c = 0; c < RN; ++c) bv[c] = Bv[kk][tx * RN + c];
+        for (int c = 0; c < RN; ++c) bv[c] = Bv(kk, tx * RN + c);
 #pragma unroll
-      for (int r = 0; r < RM; ++r)
+        for (int r = 0; r < RM; ++r)
 #pragma unroll
-        for (int c = 0; c < RN; ++c) V[r][c] = max(V[r][c], av[r] + bv[c]);
+          for (int c = 0; c < RN; ++c) V[r][c] = max(V[r][c], av[r] + bv[c]);
+      }
+      __syncthreads();
     }
-    __syncthreads();
   }
 
   uint64_t acc[KP][RM][RN];
@@ -159,18 +173,18 @@ tgemm_kernel(const GemmArgs a) {
           const bool in = (m < a.M && q < kend);
           const int64_t o = m * a.K + q;
           // pass 2 stages negated values: the tie test below is one add3
-          Av[j][i] = in ? -(int32_t)Ab[o] : -NEG;
+          Av(j, i) = in ? -(int32_t)Ab[o] : -NEG;
 #pragma unroll
-          for (int p = 0; p < KR; ++p) Ac[p][j][i] = in ? Ab[(p + 1) * a.pA + o] : 0u;
+          for (int p = 0; p < KR; ++p) Ac(p, j, i) = in ? Ab[(p + 1) * a.pA + o] : 0u;
         }
         for (int idx = tid; idx < TK * TN; idx += NT) {
           const int j = idx / TN, i = idx % TN;
           const int64_t n = n0 + i, q = k0 + j;
           const bool in = (n < a.N && q < kend);
           const int64_t o = q * a.N + n;
-          Bv[j][i] = in ? -(int32_t)Bb[o] : -NEG;
+          Bv(j, i) = in ? -(int32_t)Bb[o] : -NEG;
 #pragma unroll
-          for (int p = 0; p < KR; ++p) Bc[p][j][i] = in ? Bb[(p + 1) * a.pB + o] : 0u;
+          for (int p = 0; p < KR; ++p) Bc(p, j, i) = in ? Bb[(p + 1) * a.pB + o] : 0u;
         }
         __syncthreads();
 #pragma unroll 3
@@ -178,15 +192,15 @@ tgemm_kernel(const GemmArgs a) {
           int32_t av[RM], bv[RN];
           uint32_t ac[KR][RM], bc[KR][RN];
 #pragma unroll
-          for (int r = 0; r < RM; ++r) av[r] = Av[kk][ty * RM + r];
+          for (int r = 0; r < RM; ++r) av[r] = Av(kk, ty * RM + r);
 #pragma unroll
-          for (int c = 0; c < RN; ++c) bv[c] = Bv[kk][tx * RN + c];
+          for (int c = 0; c < RN; ++c) bv[c] = Bv(kk, tx * RN + c);
 #pragma unroll
           for (int p = 0; p < KR; ++p) {
 #pragma unroll
-            for (int r = 0; r < RM; ++r) ac[p][r] = Ac[p][kk][ty * RM + r];
+            for (int r = 0; r < RM; ++r) ac[p][r] = Ac(p, kk, ty * RM + r);
 #pragma unroll
-            for (int c = 0; c < RN; ++c) bc[p][c] = Bc[p][kk][tx * RN + c];
+            for (int c = 0; c < RN; ++c) bc[p][c] = Bc(p, kk, tx * RN + c);
           }
           // tie test without a compare: x = V - 1 - a - b is -1 exactly on a
           // tie and >= 0 otherwise (a + b <= V), so x >> 31 is the tie mask.
@@ -253,6 +267,8 @@ static void launch_cfg(int cfg, dim3 grid, const GemmArgs& a, hipStream_t st) {
     BBTN_TG_CASE(4, 64, 8, 2, 1, 16)
     BBTN_TG_CASE(5, 1, 256, 1, 1, 16)
     BBTN_TG_CASE(6, 256, 1, 1, 1, 16)
+    BBTN_TG_CASE(7, 64, 32, 4, 2, 24)
+    BBTN_TG_CASE(8, 32, 64, 2, 4, 24)
 #undef BBTN_TG_CASE
     default:
       throw Error(BBTN_E_INTERNAL, "bad tile config");

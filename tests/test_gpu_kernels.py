@@ -46,6 +46,43 @@ def test_tgemm_matches_oracle(ctx, shape, k):
     assert np.array_equal(gr, wr.reshape(k, -1))
 
 
+def _bucket(x):
+    b = 0
+    while (1 << (b + 1)) <= x:
+        b += 1
+    return b
+
+
+N_TILE_CFGS = 9
+
+
+@pytest.mark.parametrize("cfg", range(N_TILE_CFGS))
+@pytest.mark.parametrize("splits", [1, 4])
+@pytest.mark.parametrize("k", [3, 4])
+def test_tgemm_every_tile_config(tmp_path, cfg, splits, k):
+    """Force each tile configuration (and split-K) through a tile-cache file;
+    ragged shape spanning several tiles in every dimension."""
+    torch = torch_cuda()
+    import paper_2602_05470_amd as B
+    b, M, N, K = 2, 70, 75, 100
+    cache = tmp_path / "tiles.txt"
+    cache.write_text("%d %d %d %d %d %d %d\n" % (k, _bucket(b), _bucket(M), _bucket(N), _bucket(K),
+                                                cfg, splits))
+    primes = I.PRIMES_31[:k]
+    seed = 31 * cfg + splits + k
+    Av, Ar = I.random_entries((b, M, K), k, seed=seed, vrange=3)
+    Bv, Br = I.random_entries((b, K, N), k, seed=seed + 1, vrange=3)
+    dA, dB = to_dev(torch, Av, Ar), to_dev(torch, Bv, Br)
+    dC = empty_dev(torch, k, b * M * N)
+    with B.Context(B.Options(autotune_cache=str(cache))) as c:
+        c.tgemm(k, primes, b, M, N, K, dA, dB, dC)
+        torch.cuda.synchronize()
+    gv, gr = from_dev(dC, k, b * M * N)
+    wv, wr = D.tgemm(Av, Ar, Bv, Br, primes)
+    assert np.array_equal(gv, wv.reshape(-1))
+    assert np.array_equal(gr, wr.reshape(k, -1))
+
+
 @pytest.mark.parametrize("K", [1, 3, 64, 4096])
 def test_tgemm_all_ties_max_residues(ctx, K):
     """Every term ties and every residue is p - 1: the count is
