@@ -226,7 +226,21 @@ void solve_network(bbtn_ctx* ctx, Network& net, const std::vector<uint8_t>& ls_x
   } graph_scope{ctx};
   for (int i = 0; i < 8; ++i) res->seconds[i] = 0;
   const double deadline = opt.time_limit_s > 0 ? t0 + opt.time_limit_s : 0;
-  Tree tree = greedy_tree(net);
+  Tree tree;
+  {
+    std::vector<std::vector<int32_t>> shape;
+    shape.reserve(net.tensors.size() + 1);
+    shape.push_back({net.n});
+    for (const auto& T : net.tensors) shape.push_back(T.vars);
+    auto it = ctx->tree_cache.find(shape);
+    if (it != ctx->tree_cache.end()) {
+      tree = it->second;
+    } else {
+      tree = greedy_tree(net);
+      if (ctx->tree_cache.size() >= 8) ctx->tree_cache.clear();
+      ctx->tree_cache.emplace(std::move(shape), tree);
+    }
+  }
   // search
   const double t1 = now_s();
   std::vector<LeafGroup> groups;

@@ -5,6 +5,7 @@
 #include <tuple>
 #include "common.h"
 #include "prof.h"
+#include "tree.h"
 
 namespace bbtn {
 
@@ -73,6 +74,9 @@ struct bbtn_ctx {
   bbtn::DevBuf scorer_dev;
   bbtn::Prof prof;         // kernel timing (off unless enabled)
   std::map<bbtn::GraphKey, hipGraphExec_t> graphs;
+  // contraction trees by network structure (the variable lists of the
+  // simplified tensors, which do not depend on couplings or weights)
+  std::map<std::vector<std::vector<int32_t>>, bbtn::Tree> tree_cache;
   void clear_graphs() {
     for (auto& kv : graphs) (void)hipGraphExecDestroy(kv.second);
     graphs.clear();

@@ -459,10 +459,6 @@ struct Searcher {
         st.leaves++;
         continue;
       }
-      // overflow participation of every free variable
-      std::vector<int32_t> cand;
-      heuristic(n, heur, cand);
-      if (cand.empty()) throw Error(BBTN_E_INTERNAL, "rho > 0 but no overflowing variable");
       Eval best;
       // Nodes with the same fixed-variable set have the same rho structure.
       // When the rule chosen for an earlier such node pruned nothing, try it
@@ -475,6 +471,10 @@ struct Searcher {
         if (ev.cubes.size() == ((size_t)1 << memo->second.size())) best = std::move(ev);
       }
       if (best.cubes.empty()) {
+        // overflow participation of every free variable
+        std::vector<int32_t> cand;
+        heuristic(n, heur, cand);
+        if (cand.empty()) throw Error(BBTN_E_INTERNAL, "rho > 0 but no overflowing variable");
         // rank the seeds: the learned scorer when loaded, else the heuristic
         score = heur;
         if (opt.scorer) opt.scorer(n.fixed, n.sizes, heur, score);
