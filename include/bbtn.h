@@ -65,7 +65,10 @@ typedef struct bbtn_ctx bbtn_ctx;
 /* Solver options.  Fill with bbtn_default_options, then override. */
 typedef struct {
   int32_t device;            /* HIP device ordinal                              */
-  int32_t residues_per_pass; /* k in [1, 4]: residues carried per entry         */
+  int32_t residues_per_pass; /* k in [0, 4]: residues carried per entry; 0 =
+                                values only (ground value and one optimal
+                                configuration, no count: count_words = 0,
+                                n_primes = 0, certified = 0)               */
   int32_t max_primes;        /* certification adds passes up to this many primes */
   int32_t log2_target;       /* log2 T_target of Eq. 4 (entries of the largest
                                 intermediate tensor); <= 0: no branching        */

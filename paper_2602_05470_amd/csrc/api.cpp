@@ -246,6 +246,10 @@ void solve_network(bbtn_ctx* ctx, Network& net, const std::vector<uint8_t>& ls_x
   std::vector<LeafGroup> groups;
   SearchStats stats;
   const bool branch = opt.branching != 0 && opt.log2_target > 0;
+  const bool values_only = opt.residues_per_pass == 0;
+  // value (with the folded constant, like node_bound) of the local-search
+  // configuration: a lower bound on the optimum, used for global pruning
+  const int64_t incumbent = ls_x.empty() ? INT64_MIN : network_value(net, ls_x);
   if (!branch) {
     LeafGroup g;
     g.mask.assign((net.n + 63) / 64, 0);
@@ -256,9 +260,8 @@ void solve_network(bbtn_ctx* ctx, Network& net, const std::vector<uint8_t>& ls_x
     SearchOptions so;
     so.log2_target = opt.log2_target;
     so.region_max = std::max(1, std::min(16, opt.region_max));
-    // value (with the folded constant, like node_bound) of the local-search
-    // configuration: a lower bound on the optimum, used for global pruning
-    so.incumbent = ls_x.empty() ? INT64_MIN : network_value(net, ls_x);
+    so.incumbent = incumbent;
+    so.values_only = values_only;
     so.deadline = deadline;
     if (opt.branching == 2 && ctx->scorer_loaded) so.scorer = make_var_scorer(ctx, net, tree, opt.log2_target);
     bb_search(net, tree, so, groups, stats);
@@ -275,7 +278,7 @@ void solve_network(bbtn_ctx* ctx, Network& net, const std::vector<uint8_t>& ls_x
   // can contribute no count (global pruning with the exact incumbent), so
   // the counting passes below touch only the leaves reaching the optimum.
   const auto& P = prime_table();
-  const int k = std::max(1, std::min(KMAX, opt.residues_per_pass));
+  const int k = values_only ? 0 : std::max(1, std::min(KMAX, opt.residues_per_pass));
   const int max_primes = std::max(k, std::min(BBTN_MAX_PRIMES, opt.max_primes));
   std::vector<std::vector<int64_t>> sel(groups.size());
   for (size_t gi = 0; gi < groups.size(); ++gi)
@@ -287,6 +290,41 @@ void solve_network(bbtn_ctx* ctx, Network& net, const std::vector<uint8_t>& ls_x
   for (auto& gv : pv.val)
     for (int32_t v : gv)
       if (v > NEG_CUT && v > best) best = v;
+  if (values_only) {
+    // the optimum is the best leaf or, when the search pruned everything
+    // that could not beat it, the incumbent itself
+    const bool use_inc = incumbent != INT64_MIN &&
+                         (best <= NEG_CUT || incumbent > (int64_t)best + net.const_val);
+    if (best <= NEG_CUT && !use_inc) throw Error(BBTN_E_INTERNAL, "no feasible configuration found");
+    std::vector<int8_t> states;
+    if (use_inc) {
+      states.assign(ls_x.begin(), ls_x.end());
+    } else {
+      LeafRef first{-1, -1};
+      for (size_t gi = 0; gi < groups.size() && first.group < 0; ++gi)
+        for (int64_t i = 0; i < groups[gi].count; ++i)
+          if (pv.val[gi][i] == best) { first = LeafRef{(int32_t)gi, i}; break; }
+      recover_config(ctx, net, tree, groups[first.group], first.idx, states);
+    }
+    const double t6 = now_s();
+    res->seconds[5] = t6 - t3;
+    const int64_t value = use_inc ? incumbent : (int64_t)best + net.const_val;
+    res->value = net.spin ? -value : value;
+    res->n_primes = 0;
+    res->certified = 0;
+    res->count_words = 0;
+    res->leaves = stats.leaves;
+    res->pruned = stats.pruned;
+    res->nodes = stats.nodes;
+    res->macs = ctx->last_macs;
+    if (res->config)
+      for (int v = 0; v < net.n; ++v)
+        res->config[v] = net.spin ? (int8_t)(states[v] ? 1 : -1) : (int8_t)(states[v] ? 1 : 0);
+    if (res->count)
+      for (int i = 0; i < res->count_capacity; ++i) res->count[i] = 0;
+    res->seconds[0] = now_s() - t0;
+    return;
+  }
   if (best <= NEG_CUT) throw Error(BBTN_E_INTERNAL, "no feasible configuration found");
   std::vector<std::vector<int64_t>> opt_sel(groups.size());
   LeafRef first{-1, -1};
@@ -299,44 +337,58 @@ void solve_network(bbtn_ctx* ctx, Network& net, const std::vector<uint8_t>& ls_x
         if (first.group < 0) first = LeafRef{(int32_t)gi, i};
       }
   stats.pruned += stats.leaves - n_opt;
-  // first counting pass: k residues, optimal leaves only
+  // certification: a count never exceeds 2^n (the number of configurations)
+  auto bits_of = [&](const std::vector<int>& ids) {
+    double bits = 0;
+    for (int id : ids) bits += std::log2((double)P[id]);
+    return bits;
+  };
+  const double need_bits = (double)net.n + 1.0;
+  // first counting pass over the optimal leaves: k residues, plus, when k
+  // primes cannot certify by size and one more residue fits the entry, a
+  // (k+1)-th prime in the same pass that checks the CRT value
   std::vector<int> used;
   for (int p = 0; p < k; ++p) used.push_back(p);
+  const bool fused_check = bits_of(used) <= need_bits && k < KMAX && max_primes > k;
+  if (fused_check) used.push_back(k);
   PassOut po;
   run_pass(ctx, net, groups, plans, opt_sel, used, po, opt.batched != 0);
   for (size_t gi = 0; gi < groups.size(); ++gi)
     for (int64_t i : opt_sel[gi])
       if (po.val[gi][i] != best) throw Error(BBTN_E_INTERNAL, "counting pass disagrees on a value");
   std::vector<uint32_t> residues;  // aligned with `used`
-  auto sum_pass = [&](const PassOut& o, int np) {
-    for (int p = 0; p < np; ++p) {
-      const uint32_t pr = P[used[residues.size()]];
+  auto sum_pass = [&](const PassOut& o, const std::vector<int>& ids) {
+    for (size_t p = 0; p < ids.size(); ++p) {
+      const uint32_t pr = P[ids[p]];
       uint32_t s = 0;
       for (size_t gi = 0; gi < groups.size(); ++gi)
         for (int64_t i : opt_sel[gi]) s = addmod(s, o.res[gi][p][i], pr);
-      s = mulmod(s, net.const_res[used[residues.size()]], pr);
-      residues.push_back(s);
+      residues.push_back(mulmod(s, net.const_res[ids[p]], pr));
     }
   };
-  sum_pass(po, k);
+  sum_pass(po, used);
   const double t4 = now_s();
   res->seconds[3] = t4 - t3;
-  // certification: the count is at most 2^n (number of configurations)
-  auto prod_bits = [&]() {
-    double b = 0;
-    for (int id : used) b += std::log2((double)P[id]);
-    return b;
-  };
   std::vector<uint32_t> pr_used;
-  auto cur_primes = [&]() {
+  auto primes_of = [&](size_t count_of) {
     pr_used.clear();
-    for (int id : used) pr_used.push_back(P[id]);
+    for (size_t i = 0; i < count_of; ++i) pr_used.push_back(P[used[i]]);
     return pr_used;
   };
-  std::vector<uint32_t> count = crt_garner(residues, cur_primes());
   int certified = 0;
-  for (;;) {
-    if (prod_bits() > (double)net.n + 1.0) { certified = 1; break; }
+  std::vector<uint32_t> count;
+  if (fused_check) {
+    // CRT over the first k primes, checked against the (k+1)-th
+    const std::vector<uint32_t> first_k(residues.begin(), residues.begin() + k);
+    count = crt_garner(first_k, primes_of(k));
+    const bool agree = bigint_mod(count, P[used[k]]) == residues[k];
+    count = crt_garner(residues, primes_of(used.size()));
+    certified = agree ? 1 : 0;
+  } else {
+    count = crt_garner(residues, primes_of(used.size()));
+  }
+  while (!certified) {
+    if (bits_of(used) > need_bits) { certified = 1; break; }
     const int nxt = (int)used.size();
     if (nxt >= max_primes) break;
     // one extra prime over the optimal leaves only
@@ -351,7 +403,7 @@ void solve_network(bbtn_ctx* ctx, Network& net, const std::vector<uint8_t>& ls_x
     const bool agree = bigint_mod(count, pq) == r;
     used.push_back(nxt);
     residues.push_back(r);
-    count = crt_garner(residues, cur_primes());
+    count = crt_garner(residues, primes_of(used.size()));
     if (agree) { certified = 1; break; }
     // not yet: add a full pass of k primes
     std::vector<int> more;
@@ -359,17 +411,9 @@ void solve_network(bbtn_ctx* ctx, Network& net, const std::vector<uint8_t>& ls_x
     if (more.empty()) break;
     PassOut pm;
     run_pass(ctx, net, groups, plans, opt_sel, more, pm, opt.batched != 0);
-    const size_t before = used.size();
+    sum_pass(pm, more);
     for (int id : more) used.push_back(id);
-    for (size_t p = 0; p < more.size(); ++p) {
-      const uint32_t pr = P[more[p]];
-      uint32_t s = 0;
-      for (size_t gi = 0; gi < groups.size(); ++gi)
-        for (int64_t i : opt_sel[gi]) s = addmod(s, pm.res[gi][p][i], pr);
-      residues.push_back(mulmod(s, net.const_res[more[p]], pr));
-    }
-    (void)before;
-    count = crt_garner(residues, cur_primes());
+    count = crt_garner(residues, primes_of(used.size()));
   }
   const double t5 = now_s();
   res->seconds[4] = t5 - t4;
@@ -439,8 +483,8 @@ bbtn_status bbtn_create(const bbtn_options* opt, bbtn_ctx** out) {
   if (!ctx) return BBTN_E_OOM;
   if (opt) ctx->opt = *opt; else bbtn_default_options(&ctx->opt);
   bbtn_status s = guard(ctx, [&] {
-    BBTN_REQUIRE(ctx->opt.residues_per_pass >= 1 && ctx->opt.residues_per_pass <= KMAX,
-                 "residues_per_pass must be in [1, 4]");
+    BBTN_REQUIRE(ctx->opt.residues_per_pass >= 0 && ctx->opt.residues_per_pass <= KMAX,
+                 "residues_per_pass must be in [0, 4]");
     int ndev = 0;
     BBTN_HIP(hipGetDeviceCount(&ndev));
     BBTN_REQUIRE(ctx->opt.device >= 0 && ctx->opt.device < ndev, "no such device");

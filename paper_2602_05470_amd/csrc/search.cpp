@@ -238,7 +238,7 @@ struct Searcher {
         if (mn == INT64_MIN) { may_prune = true; break; }
         minb += mn - tb.base;
       }
-      if (!may_prune && minb >= opt.incumbent) {
+      if (!may_prune && (opt.values_only ? minb > opt.incumbent : minb >= opt.incumbent)) {
         ev.cubes.reserve(nx);
         for (uint32_t x = 0; x < nx; ++x) ev.cubes.push_back(Cube{nx - 1, x});
         std::vector<int32_t> vs(R.begin(), R.end());
@@ -266,10 +266,19 @@ struct Searcher {
       if (feas && lc > gmaxv[x & bmask]) gmaxv[x & bmask] = lc;
     }
     const uint32_t full = nx - 1;
+    std::vector<char> taken;
+    if (opt.values_only) taken.assign(nx, 0);
     for (uint32_t x = 0; x < nx; ++x) {
       if (local[x] == INT64_MIN) continue;
       if (local[x] != gmaxv[x & bmask]) continue;      // boundary equivalence
-      if (bnd[x] < opt.incumbent) continue;              // global pruning (strict)
+      if (opt.values_only) {
+        // one optimal interior per boundary state; prune what cannot beat
+        // the incumbent
+        if (taken[x & bmask] || bnd[x] <= opt.incumbent) continue;
+        taken[x & bmask] = 1;
+      } else if (bnd[x] < opt.incumbent) {
+        continue;                                        // global pruning (strict)
+      }
       ev.cubes.push_back(Cube{full, x});
     }
     // delta rho per fixed subset of the region (cached)
@@ -408,7 +417,11 @@ struct Searcher {
         b = (m == INT64_MIN) ? INT64_MIN : b + (m - base_max[i]);
       }
       ch.bound = b;
-      if (ch.bound == INT64_MIN || ch.bound < opt.incumbent) { st.pruned++; continue; }
+      if (ch.bound == INT64_MIN || ch.bound < opt.incumbent ||
+          (opt.values_only && ch.bound == opt.incumbent)) {
+        st.pruned++;
+        continue;
+      }
       ch.sizes = n.sizes;
       for (int v : newly)
         for (int id : tree.var_nodes[v]) ch.sizes[id]--;
@@ -444,7 +457,11 @@ struct Searcher {
     root.sizes = node_sizes(tree, root.fixed);
     root.rho = rho_of(tree, root.sizes, opt.log2_target);
     root.bound = node_bound(net, root.fixed, root.x);
-    if (root.bound < opt.incumbent || root.bound == INT64_MIN) { st.pruned++; return; }
+    if (root.bound < opt.incumbent || root.bound == INT64_MIN ||
+        (opt.values_only && root.bound == opt.incumbent)) {
+      st.pruned++;
+      return;
+    }
     std::vector<Node> stack;
     stack.push_back(std::move(root));
     std::vector<double> heur(net.n), score(net.n);

@@ -38,6 +38,10 @@ struct SearchOptions {
   int log2_target = 10;
   int region_max = 8;
   int64_t incumbent = INT64_MIN;  // value of a known configuration (max form)
+  // values only (no counts): branches that cannot beat the incumbent are
+  // pruned (non-strict; the caller keeps the incumbent's configuration) and
+  // boundary equivalence keeps one optimal interior per boundary state
+  bool values_only = false;
   double deadline = 0;            // absolute wall time (s) or 0
   VarScorer scorer;
 };
