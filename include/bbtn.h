@@ -264,6 +264,25 @@ bbtn_status bbtn_mlp_adam(bbtn_ctx* ctx, float* master, uint16_t* W, float* bias
  * when branching == 2. */
 bbtn_status bbtn_scorer_load(bbtn_ctx* ctx, const char* path);
 
+/* The planner alone, on the host (ctx may be NULL; no device is used): build
+ * the network of a spin-glass (kind 0: weights = J, h) or MWIS (kind 1:
+ * weights = w, h unused) instance, order it greedily, take the local-search
+ * incumbent (local_search sweeps; 0 = no incumbent) and run the
+ * branch-and-bound search with T_target = 2^log2_target and regions of at
+ * most region_max variables ("Branch-and-Bound Tensor Network" section).
+ * values_only != 0 selects the values-only pruning of residues_per_pass = 0.
+ * Leaf l is written to leaves[l*n .. l*n + n): -1 for a free variable, else
+ * its fixed state (s, with s = 1 meaning sigma = +1; or x).  *n_leaves
+ * receives the leaf count; pass leaves = NULL to query it.  *incumbent
+ * receives the incumbent's value in the problem's convention (energy or
+ * weight), or INT64_MIN when there is none.  Errors: BBTN_E_INVALID_ARG,
+ * BBTN_E_BUFFER_TOO_SMALL (capacity < *n_leaves with leaves != NULL). */
+bbtn_status bbtn_plan_leaves(bbtn_ctx* ctx, int32_t kind, int32_t n, int32_t m,
+                             const int32_t* edge_uv, const int32_t* weights, const int32_t* h,
+                             int32_t log2_target, int32_t region_max, int32_t local_search,
+                             int32_t values_only, int8_t* leaves, int64_t capacity,
+                             int64_t* n_leaves, int64_t* incumbent);
+
 /* Training data from the search itself: run the planner on an instance
  * (kind 0: spin glass with weights = J, h; kind 1: MWIS with weights = w)
  * with T_target = 2^log2_target for up to max_nodes nodes; at each node,

@@ -57,7 +57,7 @@ EXPORTS = ["bbtn_default_options", "bbtn_create", "bbtn_destroy", "bbtn_last_err
            "bbtn_solve_spinglass", "bbtn_solve_mwis", "bbtn_tgemm", "bbtn_gather",
            "bbtn_reduce", "bbtn_bound", "bbtn_last_macs", "bbtn_profile",
            "bbtn_get_kernel_stats", "bbtn_mlp_forward", "bbtn_mlp_backward", "bbtn_mlp_adam",
-           "bbtn_scorer_load", "bbtn_scorer_collect", "bbtn_scorer_train"]
+           "bbtn_scorer_load", "bbtn_scorer_collect", "bbtn_scorer_train", "bbtn_plan_leaves"]
 
 # scorer parameter layout (see include/bbtn.h)
 MLP_IN, MLP_H = 32, 128
@@ -118,6 +118,9 @@ def load(path: str = LIB_PATH):
     lib.bbtn_mlp_adam.restype = I32
     lib.bbtn_scorer_load.argtypes = [P, C.c_char_p]
     lib.bbtn_scorer_load.restype = I32
+    lib.bbtn_plan_leaves.argtypes = [P, I32, I32, I32, P, P, P, I32, I32, I32, I32, P, I64,
+                                     C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
+    lib.bbtn_plan_leaves.restype = I32
     lib.bbtn_scorer_collect.argtypes = [P, I32, I32, I32, P, P, P, I32, I32, I32, P, P, I64,
                                         C.POINTER(C.c_int64)]
     lib.bbtn_scorer_collect.restype = I32
@@ -361,6 +364,32 @@ class Context:
                                                lr, seed, _ptr(loss),
                                                save_path.encode() if save_path else None))
         return loss
+
+
+def plan_leaves(kind, n, edges, weights, h=None, log2_target=10, region_max=8, local_search=100,
+                values_only=False):
+    """bbtn_plan_leaves without a device context: the leaves of the
+    branch-and-bound search as an int8 array [leaves, n] (-1 = free, else the
+    fixed state), and the local-search incumbent's value (None if none)."""
+    lib = load()
+    edges = _i32(edges).reshape(-1, 2)
+    w = None if weights is None else _i32(weights)
+    hh = None if h is None else _i32(h)
+    nl = C.c_int64(0)
+    inc = C.c_int64(0)
+    args = (None, kind, n, len(edges), _ptr(edges), _ptr(w), _ptr(hh), log2_target, region_max,
+            local_search, int(bool(values_only)))
+    s = lib.bbtn_plan_leaves(*args, None, 0, C.byref(nl), C.byref(inc))
+    if s != 0:
+        raise BBTNError(s, "bbtn_plan_leaves failed")
+    out = np.zeros((nl.value, n), np.int8)
+    if nl.value:
+        s = lib.bbtn_plan_leaves(*args, out.ctypes.data_as(C.c_void_p), nl.value, C.byref(nl),
+                                 C.byref(inc))
+        if s != 0:
+            raise BBTNError(s, "bbtn_plan_leaves failed")
+    incumbent = None if inc.value == -(1 << 63) else int(inc.value)
+    return out, incumbent
 
 
 def scorer_collect(kind, n, edges, weights, h=None, log2_target=10, max_nodes=64, cand_per_node=8):

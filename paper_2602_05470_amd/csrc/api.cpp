@@ -717,6 +717,50 @@ bbtn_status bbtn_scorer_load(bbtn_ctx* ctx, const char* path) {
   });
 }
 
+bbtn_status bbtn_plan_leaves(bbtn_ctx* ctx, int32_t kind, int32_t n, int32_t m,
+                             const int32_t* edge_uv, const int32_t* weights, const int32_t* h,
+                             int32_t log2_target, int32_t region_max, int32_t local_search,
+                             int32_t values_only, int8_t* leaves, int64_t capacity,
+                             int64_t* n_leaves, int64_t* incumbent) {
+  if (!n_leaves || !incumbent) return BBTN_E_INVALID_ARG;
+  return guard(ctx, [&] {  // host-only: ctx may be NULL
+    check_graph(n, m, edge_uv);
+    BBTN_REQUIRE(kind == 0 || kind == 1, "kind must be 0 (spin glass) or 1 (MWIS)");
+    BBTN_REQUIRE(log2_target > 0 && region_max >= 1 && local_search >= 0, "bad options");
+    if (kind == 0) BBTN_REQUIRE(weights != nullptr, "J is NULL");
+    Network net = kind == 0 ? build_spinglass(n, m, edge_uv, weights, h)
+                            : build_mwis(n, m, edge_uv, weights);
+    Tree tree = greedy_tree(net);
+    std::vector<uint8_t> x;
+    if (local_search > 0)
+      x = kind == 0 ? local_search_spinglass(n, m, edge_uv, weights, h, local_search, 12345)
+                    : local_search_mwis(n, m, edge_uv, weights, std::max(1, local_search / 20), 12345);
+    SearchOptions so;
+    so.log2_target = log2_target;
+    so.region_max = std::min(16, region_max);
+    so.incumbent = x.empty() ? INT64_MIN : network_value(net, x);
+    so.values_only = values_only != 0;
+    std::vector<LeafGroup> groups;
+    SearchStats stats;
+    bb_search(net, tree, so, groups, stats);
+    int64_t total = 0;
+    for (const auto& g : groups) total += g.count;
+    *n_leaves = total;
+    *incumbent = so.incumbent == INT64_MIN ? INT64_MIN
+                 : (net.spin ? -so.incumbent : so.incumbent);
+    if (!leaves) return;
+    if (capacity < total) throw Error(BBTN_E_BUFFER_TOO_SMALL, "leaf buffer too small");
+    int64_t row = 0;
+    for (const auto& g : groups)
+      for (int64_t l = 0; l < g.count; ++l, ++row) {
+        int8_t* out = leaves + row * n;
+        std::memset(out, -1, (size_t)n);
+        for (size_t j = 0; j < g.vars.size(); ++j)
+          out[g.vars[j]] = (int8_t)g.assign[(size_t)l * g.vars.size() + j];
+      }
+  });
+}
+
 bbtn_status bbtn_scorer_collect(bbtn_ctx* ctx, int32_t kind, int32_t n, int32_t m,
                                 const int32_t* edge_uv, const int32_t* weights, const int32_t* h,
                                 int32_t log2_target, int32_t max_nodes, int32_t cand_per_node,

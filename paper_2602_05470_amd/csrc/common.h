@@ -28,6 +28,15 @@ struct Error : std::runtime_error {
                                              hipGetErrorString(e_));           \
   } while (0)
 
+// after a kernel launch: a launch error names the kernel
+#define BBTN_LAUNCHED(what)                                                    \
+  do {                                                                         \
+    hipError_t e_ = hipGetLastError();                                         \
+    if (e_ != hipSuccess)                                                      \
+      throw ::bbtn::Error(BBTN_E_DEVICE, std::string("launch of ") + (what) +  \
+                                             ": " + hipGetErrorString(e_));    \
+  } while (0)
+
 #define BBTN_REQUIRE(cond, msg)                                                \
   do {                                                                         \
     if (!(cond)) throw ::bbtn::Error(BBTN_E_INVALID_ARG, msg);                 \

@@ -68,7 +68,7 @@ void launch_gather(int k, const GatherPlan& gp, int64_t L, int64_t in_stride,
     case 4: hipLaunchKernelGGL(gather_kernel<5>, grid, block, 0, st, g); break;
     default: throw Error(BBTN_E_INVALID_ARG, "k must be in [0, 4]");
   }
-  BBTN_HIP(hipGetLastError());
+  BBTN_LAUNCHED("gather");
 }
 
 }  // namespace bbtn

@@ -166,7 +166,7 @@ void launch_mlp_forward(int64_t R, const uint16_t* X, const uint16_t* W, const f
   const int64_t nb = (R + RB - 1) / RB;
   hipLaunchKernelGGL(mlp_forward_kernel, dim3((unsigned)nb), dim3(MLP_H), 0, st, R, X, W, bias,
                      y, h1, h2);
-  BBTN_HIP(hipGetLastError());
+  BBTN_LAUNCHED("mlp forward");
 }
 
 void launch_mlp_backward(int64_t R, const uint16_t* X, const uint16_t* W, const float* y,
@@ -176,10 +176,10 @@ void launch_mlp_backward(int64_t R, const uint16_t* X, const uint16_t* W, const 
   const int64_t nb = (R + RB - 1) / RB;
   hipLaunchKernelGGL(mlp_backward_kernel, dim3((unsigned)nb), dim3(MLP_H), 0, st, R, X, W, y, t,
                      h1, h2, part);
-  BBTN_HIP(hipGetLastError());
+  BBTN_LAUNCHED("mlp backward");
   hipLaunchKernelGGL(mlp_reduce_kernel, dim3((MLP_NPART + 255) / 256), dim3(256), 0, st, nb, part,
                      grad);
-  BBTN_HIP(hipGetLastError());
+  BBTN_LAUNCHED("mlp backward reduce");
 }
 
 int64_t mlp_partial_floats(int64_t R) { return ((R + RB - 1) / RB) * (int64_t)MLP_NPART; }
@@ -190,7 +190,7 @@ void launch_mlp_adam(float* master, uint16_t* wbf, float* bias, float* m, float*
   const float c1 = 1.f - powf(b1, (float)step), c2 = 1.f - powf(b2, (float)step);
   hipLaunchKernelGGL(mlp_adam_kernel, dim3((MLP_NPARAM + 255) / 256), dim3(256), 0, st, master,
                      wbf, bias, m, v, g, lr, b1, b2, eps, c1, c2);
-  BBTN_HIP(hipGetLastError());
+  BBTN_LAUNCHED("adam");
 }
 
 }  // namespace bbtn

@@ -237,7 +237,7 @@ size_t persist_lds_bytes(int k, int64_t lds_entries) {
 void launch_persist(int k, const PersistArgs& a, int n_blocks, hipStream_t st) {
   const size_t lds = persist_lds_bytes(k, a.lds_entries);
   hipLaunchKernelGGL(zero_kernel, dim3(1), dim3(1), 0, st, a.queue);
-  BBTN_HIP(hipGetLastError());
+  BBTN_LAUNCHED("persist queue reset");
   switch (k) {
 #define BBTN_PK(K)                                                                 \
   case K:                                                                          \
@@ -254,7 +254,7 @@ void launch_persist(int k, const PersistArgs& a, int n_blocks, hipStream_t st) {
     default:
       throw Error(BBTN_E_INVALID_ARG, "k must be in [0, 4]");
   }
-  BBTN_HIP(hipGetLastError());
+  BBTN_LAUNCHED("persist");
 }
 
 }  // namespace bbtn

@@ -240,7 +240,7 @@ void launch_reduce(int k, const Moduli& mod, int64_t outer, int64_t S,
     case 4: reduce_dispatch<4>(a, st); break;
     default: throw Error(BBTN_E_INVALID_ARG, "k must be in [0, 4]");
   }
-  BBTN_HIP(hipGetLastError());
+  BBTN_LAUNCHED("reduce");
 }
 
 void launch_bound(int64_t n_branch, int32_t T, const int32_t* values,
@@ -251,11 +251,11 @@ void launch_bound(int64_t n_branch, int32_t T, const int32_t* values,
     const int64_t blocks = std::min<int64_t>(n_branch, 65536);
     hipLaunchKernelGGL(bound_kernel, dim3((unsigned)blocks), dim3(256), 0, st, n_branch, T,
                        values, off, len, offset, incumbent, bound, flags);
-    BBTN_HIP(hipGetLastError());
+    BBTN_LAUNCHED("bound");
   }
   hipLaunchKernelGGL(compact_kernel, dim3(1), dim3(1024), 0, st, n_branch, flags, keep_idx,
                      n_keep);
-  BBTN_HIP(hipGetLastError());
+  BBTN_LAUNCHED("compact");
 }
 
 }  // namespace bbtn
@@ -293,7 +293,7 @@ void launch_otimes(int k, const Moduli& mod, int64_t L, DevTensor a, DevTensor b
     case 4: hipLaunchKernelGGL(otimes_kernel<4>, dim3(blocks), dim3(256), 0, st, L, a.ptr, a.pstride, b.ptr, b.pstride, out.ptr, out.pstride, mod); break;
     default: throw Error(BBTN_E_INVALID_ARG, "k must be in [0, 4]");
   }
-  BBTN_HIP(hipGetLastError());
+  BBTN_LAUNCHED("reduce");
 }
 
 }  // namespace bbtn

@@ -26,8 +26,8 @@ const TileCfg kTileCfgs[N_TILE_CFGS] = {
     {16, 16, 1, 1, 16},   // 2: small, 256 threads
     {8, 64, 1, 2, 16},    // 3: few rows, 256 threads
     {64, 8, 2, 1, 16},    // 4: few columns, 256 threads
-    {1, 256, 1, 1, 16},   // 5: one row (vector-matrix), 256 threads
-    {256, 1, 1, 1, 16},   // 6: one column (matrix-vector), 256 threads
+    {1, 256, 1, 1, 12},   // 5: one row (vector-matrix), 256 threads
+    {256, 1, 1, 1, 12},   // 6: one column (matrix-vector), 256 threads
     {64, 32, 4, 2, 24},   // 7: tall, 256 threads (fewer accumulators than 0)
     {32, 64, 2, 4, 24},   // 8: wide, 256 threads
 };
@@ -87,6 +87,7 @@ tgemm_kernel(const GemmArgs a) {
   // (1 + KP) TK rows as one deeper slice
   __shared__ uint32_t As[(1 + KP) * TK][TMP];
   __shared__ uint32_t Bs[(1 + KP) * TK][TN];
+  static_assert(sizeof(As) + sizeof(Bs) <= 65536, "tile exceeds 64 KiB of static LDS");
   auto Av = [&](int kk, int i) -> int32_t& { return *(int32_t*)&As[kk][i]; };
   auto Bv = [&](int kk, int i) -> int32_t& { return *(int32_t*)&Bs[kk][i]; };
   auto Ac = [&](int p, int kk, int i) -> uint32_t& { return As[(1 + p) * TK + kk][i]; };
@@ -265,8 +266,8 @@ static void launch_cfg(int cfg, dim3 grid, const GemmArgs& a, hipStream_t st) {
     BBTN_TG_CASE(2, 16, 16, 1, 1, 16)
     BBTN_TG_CASE(3, 8, 64, 1, 2, 16)
     BBTN_TG_CASE(4, 64, 8, 2, 1, 16)
-    BBTN_TG_CASE(5, 1, 256, 1, 1, 16)
-    BBTN_TG_CASE(6, 256, 1, 1, 1, 16)
+    BBTN_TG_CASE(5, 1, 256, 1, 1, 12)
+    BBTN_TG_CASE(6, 256, 1, 1, 1, 12)
     BBTN_TG_CASE(7, 64, 32, 4, 2, 24)
     BBTN_TG_CASE(8, 32, 64, 2, 4, 24)
 #undef BBTN_TG_CASE
@@ -291,7 +292,8 @@ static void launch_core(int k, const GemmArgs& a0, int cfg, hipStream_t st) {
     case 4: launch_cfg<4>(cfg, grid, a, st); break;
     default: throw Error(BBTN_E_INVALID_ARG, "k must be in [0, 4]");
   }
-  BBTN_HIP(hipGetLastError());
+  BBTN_LAUNCHED("tgemm (tile config " + std::to_string(cfg) + ", k " + std::to_string(k) +
+                ", grid " + std::to_string(total) + ")");
 }
 
 void launch_tgemm(int k, const Moduli& mod, const GemmShape& s, DevTensor A,

@@ -74,7 +74,7 @@ void launch_trace(const TraceStep* steps, int32_t n_steps, const int32_t* vars, 
   BBTN_REQUIRE(n_vars <= TRACE_LDS_VARS, "configuration traceback: too many variables");
   hipLaunchKernelGGL(trace_kernel, dim3(1), dim3(64), 0, st, steps, n_steps, vars, ws, assign,
                      n_vars, status);
-  BBTN_HIP(hipGetLastError());
+  BBTN_LAUNCHED("trace");
 }
 
 }  // namespace bbtn

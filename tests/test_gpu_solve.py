@@ -180,3 +180,19 @@ def test_sg24_large_leaves_four_residues(B, seed):
     with B.Context(B.Options(log2_target=16, residues_per_pass=4)) as ctx:
         r = ctx.solve_spinglass(g["n"], g["edges"], g["J"])
     _check_sg(r, g, want)
+
+
+def test_one_context_many_instances(B):
+    """One context solving different couplings on repeated topologies (the
+    contraction-tree cache) and switching between problem kinds."""
+    sg = {s: (e, d) for s, e, d in _golden("sg16.txt")}
+    ksg = {s: (w, c) for s, _, w, c in _golden("ksg16.txt")}
+    with B.Context(B.Options(log2_target=10)) as ctx:
+        for seed in (0, 1, 2):
+            g = I.spin_glass_square(16, seed)
+            _check_sg(ctx.solve_spinglass(g["n"], g["edges"], g["J"]), g, sg[seed])
+            k = I.kings_subgraph(16, seed)
+            r = ctx.solve_mwis(k["n"], k["edges"], k["w"])
+            assert (r.value, r.count) == ksg[seed] and r.certified
+        g = I.spin_glass_square(16, 5)
+        _check_sg(ctx.solve_spinglass(g["n"], g["edges"], g["J"]), g, sg[5])
