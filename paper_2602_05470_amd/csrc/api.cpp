@@ -190,7 +190,8 @@ void recover_config(bbtn_ctx* ctx, const Network& net, const Tree& tree, const L
     BBTN_HIP(hipMemcpyAsync(dasg, states.data(), net.n, hipMemcpyHostToDevice, st));
     const int32_t zero = 0;
     BBTN_HIP(hipMemcpyAsync(dstat, &zero, 4, hipMemcpyHostToDevice, st));
-    launch_trace(dts, (int32_t)ts.size(), dvars, ctx->work.as<int32_t>(), dasg, net.n, dstat, st);
+    launch_trace(dts, (int32_t)ts.size(), dvars, (int32_t)vars.size(), ctx->work.as<int32_t>(),
+                 dasg, net.n, dstat, st);
     int32_t stat = 0;
     BBTN_HIP(hipMemcpyAsync(states.data(), dasg, net.n, hipMemcpyDeviceToHost, st));
     BBTN_HIP(hipMemcpyAsync(&stat, dstat, 4, hipMemcpyDeviceToHost, st));

@@ -48,8 +48,6 @@ __device__ __forceinline__ void combine(int32_t& v, uint32_t* r, int32_t v2, con
   }
 }
 
-constexpr int NTHR = PERSIST_THREADS;
-
 // source index of entry e of a staged operand: the fixed bits plus every run
 // of contiguous bits moved from e into place (runs and count are uniform)
 __device__ __forceinline__ uint32_t gather_index(uint32_t e, uint32_t fixed, int nr,
@@ -66,10 +64,12 @@ __device__ __forceinline__ uint32_t gather_index(uint32_t e, uint32_t fixed, int
   return s;
 }
 
-// One wavefront per workgroup and per task.  The task index is made
-// wave-uniform, and every descriptor is read through a pointer at a uniform
-// address, so descriptors stay in scalar registers.
-template <int KR>
+// One workgroup per task: one wavefront when tasks are many, 256 or 1024
+// threads when they are few (the steps of a task are then wide enough to use
+// them).  The task index is made uniform, and every descriptor is read
+// through a pointer at a uniform address, so descriptors stay in scalar
+// registers.
+template <int KR, int NTHR>
 __global__ void __launch_bounds__(NTHR)
 persist_kernel(const PersistArgs a) {
   constexpr int W = 1 + KR;
@@ -82,10 +82,19 @@ persist_kernel(const PersistArgs a) {
   uint32_t* scr = a.scratch + (int64_t)blockIdx.x * W * a.scratch_entries;
   const int tid = threadIdx.x;
 
+  __shared__ uint32_t s_task;
   for (;;) {
     uint32_t got = 0;
     if (tid == 0) got = (uint32_t)atomicAdd(a.queue, 1ull);
-    const int64_t task = (int64_t)__builtin_amdgcn_readfirstlane(__shfl(got, 0));
+    if constexpr (NTHR == 64) {
+      got = __shfl(got, 0);
+    } else {
+      if (tid == 0) s_task = got;
+      __syncthreads();
+      got = s_task;
+      __syncthreads();
+    }
+    const int64_t task = (int64_t)__builtin_amdgcn_readfirstlane(got);
     if (task >= a.n_tasks) break;
     const PTask* tk = a.tasks + task;
     const uint8_t* asg = a.assign + tk->assign_off;
@@ -230,20 +239,18 @@ __global__ void zero_kernel(unsigned long long* q) { *q = 0; }
 
 }  // namespace
 
-size_t persist_lds_bytes(int k, int64_t lds_entries) {
-  return (size_t)2 * (1 + k) * lds_entries * 4 + (size_t)NTHR * 4 * (1 + k);
+size_t persist_lds_bytes(int k, int64_t lds_entries, int threads) {
+  return (size_t)2 * (1 + k) * lds_entries * 4 + (size_t)threads * 4 * (1 + k);
 }
 
-void launch_persist(int k, const PersistArgs& a, int n_blocks, hipStream_t st) {
-  const size_t lds = persist_lds_bytes(k, a.lds_entries);
-  hipLaunchKernelGGL(zero_kernel, dim3(1), dim3(1), 0, st, a.queue);
-  BBTN_LAUNCHED("persist queue reset");
+template <int NT>
+static void launch_nt(int k, const PersistArgs& a, int n_blocks, size_t lds, hipStream_t st) {
   switch (k) {
 #define BBTN_PK(K)                                                                 \
   case K:                                                                          \
-    BBTN_HIP(hipFuncSetAttribute((const void*)persist_kernel<K>,                    \
+    BBTN_HIP(hipFuncSetAttribute((const void*)persist_kernel<K, NT>,                \
                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds)); \
-    hipLaunchKernelGGL(persist_kernel<K>, dim3(n_blocks), dim3(NTHR), lds, st, a); \
+    hipLaunchKernelGGL((persist_kernel<K, NT>), dim3(n_blocks), dim3(NT), lds, st, a); \
     break;
     BBTN_PK(0)
     BBTN_PK(1)
@@ -253,6 +260,18 @@ void launch_persist(int k, const PersistArgs& a, int n_blocks, hipStream_t st) {
 #undef BBTN_PK
     default:
       throw Error(BBTN_E_INVALID_ARG, "k must be in [0, 4]");
+  }
+}
+
+void launch_persist(int k, const PersistArgs& a, int n_blocks, int threads, hipStream_t st) {
+  const size_t lds = persist_lds_bytes(k, a.lds_entries, threads);
+  hipLaunchKernelGGL(zero_kernel, dim3(1), dim3(1), 0, st, a.queue);
+  BBTN_LAUNCHED("persist queue reset");
+  switch (threads) {
+    case 64: launch_nt<64>(k, a, n_blocks, lds, st); break;
+    case 256: launch_nt<256>(k, a, n_blocks, lds, st); break;
+    case 1024: launch_nt<1024>(k, a, n_blocks, lds, st); break;
+    default: throw Error(BBTN_E_INTERNAL, "persistent executor: bad workgroup size");
   }
   BBTN_LAUNCHED("persist");
 }

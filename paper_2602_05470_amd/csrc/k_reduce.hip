@@ -293,7 +293,7 @@ void launch_otimes(int k, const Moduli& mod, int64_t L, DevTensor a, DevTensor b
     case 4: hipLaunchKernelGGL(otimes_kernel<4>, dim3(blocks), dim3(256), 0, st, L, a.ptr, a.pstride, b.ptr, b.pstride, out.ptr, out.pstride, mod); break;
     default: throw Error(BBTN_E_INVALID_ARG, "k must be in [0, 4]");
   }
-  BBTN_LAUNCHED("reduce");
+  BBTN_LAUNCHED("otimes");
 }
 
 }  // namespace bbtn

@@ -43,6 +43,7 @@ struct GemmArgs {
   int64_t kchunk;            // K range per split
   int64_t splits;
   int64_t tiles_m, tiles_n;
+  int64_t total;             // tiles * splits * batch (work items of the grid)
   Moduli mod;
 };
 
@@ -71,9 +72,9 @@ __device__ __forceinline__ int64_t xcd_remap(int64_t w, int64_t G) {
                    : rem * (per + 1) + (xcd - rem) * per + local;
 }
 
+// One output tile (tile index w of a.total, before the XCD remap).
 template <int KR, int TM, int TN, int RM, int RN, int TK>
-__global__ void __launch_bounds__((TM / RM) * (TN / RN))
-tgemm_kernel(const GemmArgs a) {
+__device__ __forceinline__ void tgemm_tile(const GemmArgs& a, int64_t w) {
   constexpr int TX = TN / RN;
   constexpr int TY = TM / RM;
   constexpr int NT = TX * TY;
@@ -93,7 +94,7 @@ tgemm_kernel(const GemmArgs a) {
   auto Ac = [&](int p, int kk, int i) -> uint32_t& { return As[(1 + p) * TK + kk][i]; };
   auto Bc = [&](int p, int kk, int i) -> uint32_t& { return Bs[(1 + p) * TK + kk][i]; };
 
-  int64_t t = xcd_remap(blockIdx.x, gridDim.x);
+  int64_t t = xcd_remap(w, a.total);
   const int64_t tn_i = t % a.tiles_n;
   t /= a.tiles_n;
   const int64_t tm_i = t % a.tiles_m;
@@ -253,13 +254,35 @@ tgemm_kernel(const GemmArgs a) {
   }
 }
 
+template <int KR, int TM, int TN, int RM, int RN, int TK>
+__global__ void __launch_bounds__((TM / RM) * (TN / RN))
+tgemm_kernel(const GemmArgs a) {
+  tgemm_tile<KR, TM, TN, RM, RN, TK>(a, blockIdx.x);
+}
+
+// Grids beyond 2^20 tiles: each workgroup walks the tiles with the grid's
+// stride (a dispatch must stay below 2^32 work-items).  The stride is a
+// multiple of 8, so every tile a workgroup takes maps to the same XCD.
+template <int KR, int TM, int TN, int RM, int RN, int TK>
+__global__ void __launch_bounds__((TM / RM) * (TN / RN))
+tgemm_kernel_strided(const GemmArgs a) {
+  for (int64_t w = blockIdx.x; w < a.total; w += gridDim.x) {
+    tgemm_tile<KR, TM, TN, RM, RN, TK>(a, w);
+    __syncthreads();  // LDS is restaged for the next tile
+  }
+}
+
 template <int KR>
 static void launch_cfg(int cfg, dim3 grid, const GemmArgs& a, hipStream_t st) {
   switch (cfg) {
 #define BBTN_TG_CASE(I, TM, TN, RM, RN, TK)                                   \
   case I:                                                                     \
-    hipLaunchKernelGGL((tgemm_kernel<KR, TM, TN, RM, RN, TK>), grid,          \
-                       dim3((TM / RM) * (TN / RN)), 0, st, a);                \
+    if (a.total == (int64_t)grid.x)                                           \
+      hipLaunchKernelGGL((tgemm_kernel<KR, TM, TN, RM, RN, TK>), grid,        \
+                         dim3((TM / RM) * (TN / RN)), 0, st, a);              \
+    else                                                                      \
+      hipLaunchKernelGGL((tgemm_kernel_strided<KR, TM, TN, RM, RN, TK>), grid, \
+                         dim3((TM / RM) * (TN / RN)), 0, st, a);              \
     break;
     BBTN_TG_CASE(0, 64, 64, 4, 4, 24)
     BBTN_TG_CASE(1, 32, 32, 2, 2, 24)
@@ -282,8 +305,11 @@ static void launch_core(int k, const GemmArgs& a0, int cfg, hipStream_t st) {
   a.tiles_m = (a.M + tc.tm - 1) / tc.tm;
   a.tiles_n = (a.N + tc.tn - 1) / tc.tn;
   const int64_t total = a.tiles_m * a.tiles_n * a.splits * a.batch;
-  BBTN_REQUIRE(total > 0 && total < (1ll << 31), "tgemm grid out of range");
-  dim3 grid((unsigned)total);
+  BBTN_REQUIRE(total > 0, "empty tgemm grid");
+  a.total = total;
+  // at most 2^20 workgroups of <= 256 threads, a multiple of 8 when capped
+  const int64_t cap = 1ll << 20;
+  dim3 grid((unsigned)(total <= cap ? total : cap));
   switch (k) {
     case 0: launch_cfg<0>(cfg, grid, a, st); break;
     case 1: launch_cfg<1>(cfg, grid, a, st); break;

@@ -13,20 +13,39 @@ namespace bbtn {
 
 // One wavefront walks the steps; the variable states live in LDS so that a
 // state written by lane 0 is read by the other lanes of the same wave (LDS
-// operations of a wave complete in order) without a workgroup barrier.
+// operations of a wave complete in order) without a workgroup barrier.  When
+// they fit, the step descriptors and variable lists are first copied into
+// LDS too (one coalesced prologue), so that a step costs one round trip to
+// memory (the operand values) instead of one per variable.
 constexpr int TRACE_LDS_VARS = 48 * 1024;
+constexpr size_t TRACE_STAGE_BYTES = 104 * 1024;
 
+template <bool STAGED>
 __global__ void __launch_bounds__(64)
-trace_kernel(const TraceStep* steps, int32_t n_steps, const int32_t* vars,
+trace_kernel(const TraceStep* steps, int32_t n_steps, const int32_t* vars, int32_t n_var_words,
              const int32_t* ws, int8_t* assign, int32_t n_vars, int32_t* status) {
   __shared__ int8_t sa[TRACE_LDS_VARS];
+  extern __shared__ int64_t stage64[];  // STAGED: [steps][vars]
   const int lane = threadIdx.x;
   for (int v = lane; v < n_vars; v += 64) sa[v] = assign[v];
+  const TraceStep* S = steps;
+  const int32_t* VV = vars;
+  if constexpr (STAGED) {
+    TraceStep* ls = (TraceStep*)stage64;
+    int32_t* lv = (int32_t*)(ls + n_steps);
+    const int32_t* gs = (const int32_t*)steps;
+    int32_t* ds = (int32_t*)ls;
+    const int sw = n_steps * (int)(sizeof(TraceStep) / 4);
+    for (int i = lane; i < sw; i += 64) ds[i] = gs[i];
+    for (int i = lane; i < n_var_words; i += 64) lv[i] = vars[i];
+    S = ls;
+    VV = lv;
+  }
   __syncthreads();
   int bad = 0;
   for (int32_t s = n_steps - 1; s >= 0; --s) {
-    const TraceStep st = steps[s];
-    const int32_t* av = vars + st.var_off;                 // [K][M][batch]
+    const TraceStep st = S[s];
+    const int32_t* av = VV + st.var_off;                   // [K][M][batch]
     const int32_t* bv = av + (st.rk + st.rm + st.rb);      // [N][K][batch]
     // every lane forms the operand bases from the known states
     int64_t ab = 0, bb = 0;
@@ -68,12 +87,21 @@ trace_kernel(const TraceStep* steps, int32_t n_steps, const int32_t* vars,
   if (lane == 0 && bad) *status = bad;
 }
 
-void launch_trace(const TraceStep* steps, int32_t n_steps, const int32_t* vars, const int32_t* ws,
-                  int8_t* assign, int32_t n_vars, int32_t* status, hipStream_t st) {
+void launch_trace(const TraceStep* steps, int32_t n_steps, const int32_t* vars,
+                  int32_t n_var_words, const int32_t* ws, int8_t* assign, int32_t n_vars,
+                  int32_t* status, hipStream_t st) {
   if (n_steps <= 0) return;
   BBTN_REQUIRE(n_vars <= TRACE_LDS_VARS, "configuration traceback: too many variables");
-  hipLaunchKernelGGL(trace_kernel, dim3(1), dim3(64), 0, st, steps, n_steps, vars, ws, assign,
-                     n_vars, status);
+  const size_t stage = (size_t)n_steps * sizeof(TraceStep) + (size_t)n_var_words * 4;
+  if (stage <= TRACE_STAGE_BYTES) {
+    BBTN_HIP(hipFuncSetAttribute((const void*)trace_kernel<true>,
+                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)stage));
+    hipLaunchKernelGGL(trace_kernel<true>, dim3(1), dim3(64), stage, st, steps, n_steps, vars,
+                       n_var_words, ws, assign, n_vars, status);
+  } else {
+    hipLaunchKernelGGL(trace_kernel<false>, dim3(1), dim3(64), 0, st, steps, n_steps, vars,
+                       n_var_words, ws, assign, n_vars, status);
+  }
   BBTN_LAUNCHED("trace");
 }
 

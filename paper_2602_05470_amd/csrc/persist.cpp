@@ -9,7 +9,7 @@ namespace bbtn {
 int persist_max_rank(int k) {
   // two operand buffers of (1 + k) planes within 64 KiB of LDS
   int r = 0;
-  while (persist_lds_bytes(k, 1ll << (r + 1)) <= (64u << 10)) ++r;
+  while (persist_lds_bytes(k, 1ll << (r + 1), 64) <= (64u << 10)) ++r;
   return r;
 }
 
@@ -162,14 +162,27 @@ void run_persistent(bbtn_ctx* ctx, const Network& net, const std::vector<Persist
   ctx->persist.ensure(off);
   uint8_t* dev = ctx->persist.as<uint8_t>();
   BBTN_HIP(hipMemcpyAsync(dev, host.data(), host.size(), hipMemcpyHostToDevice, st));
-  // launch shape: as many one-wave workgroups per CU as LDS allows (at most
-  // 16), never more than tasks
+  // launch shape per launch: one-wave workgroups when tasks are plentiful,
+  // wider ones when they are few; as many per CU as LDS and the wave limit
+  // allow, never more than tasks
   const int64_t lds_entries = 1ll << max_rank;
-  const size_t lds = persist_lds_bytes(k, lds_entries);
-  const int per_cu = std::max(1, std::min(16, (int)((160u << 10) / std::max<size_t>(lds, 1))));
-  const int64_t max_blocks = (int64_t)device_cus() * per_cu;
-  const int64_t most = std::max<int64_t>((int64_t)tasks.size(), (int64_t)shared_tasks.size());
-  ctx->work.ensure((size_t)std::min(max_blocks, most) * W * scratch * 4);
+  struct Shape {
+    int threads;
+    int64_t blocks;
+  };
+  auto shape_for = [&](int64_t n_tasks) {
+    const int64_t cus = device_cus();
+    const int threads = n_tasks >= 2 * cus ? 64 : (n_tasks >= cus / 4 ? 256 : 1024);
+    const size_t lds = persist_lds_bytes(k, lds_entries, threads);
+    const int by_lds = (int)((160u << 10) / std::max<size_t>(lds, 1));
+    const int by_waves = 32 / (threads / 64);
+    const int per_cu = std::max(1, std::min({16, by_lds, by_waves}));
+    return Shape{threads, std::min<int64_t>(cus * per_cu, n_tasks)};
+  };
+  const Shape sh_shared = shape_for((int64_t)shared_tasks.size());
+  const Shape sh_branch = shape_for((int64_t)tasks.size());
+  const int64_t most = std::max<int64_t>(shared_tasks.empty() ? 0 : sh_shared.blocks, sh_branch.blocks);
+  ctx->work.ensure((size_t)most * W * scratch * 4);
   PersistArgs a{};
   a.steps = (const PStep*)(dev + o_steps);
   a.fixes = (const PFix*)(dev + o_fixes);
@@ -201,12 +214,12 @@ void run_persistent(bbtn_ctx* ctx, const Network& net, const std::vector<Persist
     a.tasks = (const PTask*)(dev + o_stasks);
     a.n_tasks = (int64_t)shared_tasks.size();
     a.queue = (unsigned long long*)(dev + o_queue);
-    launch_persist(k, a, (int)std::min<int64_t>(max_blocks, a.n_tasks), st);
+    launch_persist(k, a, (int)sh_shared.blocks, sh_shared.threads, st);
   }
   a.tasks = (const PTask*)(dev + o_tasks);
   a.n_tasks = (int64_t)tasks.size();
   a.queue = (unsigned long long*)(dev + o_queue + 8);
-  launch_persist(k, a, (int)std::min<int64_t>(max_blocks, a.n_tasks), st);
+  launch_persist(k, a, (int)sh_branch.blocks, sh_branch.threads, st);
   ctx->prof.end(ph, st, K_PERSIST, ops, bytes);
   std::vector<uint32_t> outh(lconst.size());
   BBTN_HIP(hipMemcpyAsync(outh.data(), dev + o_out, outh.size() * 4, hipMemcpyDeviceToHost, st));

@@ -69,10 +69,8 @@ struct PersistArgs {
   Moduli mod;
 };
 
-// one wavefront per workgroup
-constexpr int PERSIST_THREADS = 64;
-
-size_t persist_lds_bytes(int k, int64_t lds_entries);
-void launch_persist(int k, const PersistArgs& a, int n_blocks, hipStream_t st);
+// workgroup sizes: 64 (one wavefront), 256 or 1024 threads
+size_t persist_lds_bytes(int k, int64_t lds_entries, int threads);
+void launch_persist(int k, const PersistArgs& a, int n_blocks, int threads, hipStream_t st);
 
 }  // namespace bbtn

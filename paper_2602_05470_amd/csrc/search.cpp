@@ -492,16 +492,29 @@ struct Searcher {
         std::vector<int32_t> cand;
         heuristic(n, heur, cand);
         if (cand.empty()) throw Error(BBTN_E_INTERNAL, "rho > 0 but no overflowing variable");
-        // rank the seeds: the learned scorer when loaded, else the heuristic
-        score = heur;
-        if (opt.scorer) opt.scorer(n.fixed, n.sizes, heur, score);
+        // seeds: the heuristic's two best candidates; with the learned
+        // scorer, its best candidate and the heuristic's best (the scorer
+        // ranks seeds only; regions always grow in the heuristic's order,
+        // the order its training labels were measured with)
         std::stable_sort(cand.begin(), cand.end(), [&](int a, int b) {
-          if (score[a] != score[b]) return score[a] > score[b];
+          if (heur[a] != heur[b]) return heur[a] > heur[b];
           return a < b;
         });
-        const int n_seeds = std::min<int>(2, (int)cand.size());
-        for (int si = 0; si < n_seeds; ++si) {
-          Eval ev = best_from_seed(n, cand[si], score);
+        std::vector<int32_t> seeds;
+        if (opt.scorer) {
+          score = heur;
+          opt.scorer(n.fixed, n.sizes, heur, score);
+          std::vector<int32_t> by_score(cand);
+          std::stable_sort(by_score.begin(), by_score.end(),
+                           [&](int a, int b) { return score[a] > score[b]; });
+          seeds.push_back(by_score[0]);
+          if (cand[0] != by_score[0]) seeds.push_back(cand[0]);
+          else if (by_score.size() > 1) seeds.push_back(by_score[1]);
+        } else {
+          for (int si = 0; si < std::min<int>(2, (int)cand.size()); ++si) seeds.push_back(cand[si]);
+        }
+        for (int sd : seeds) {
+          Eval ev = best_from_seed(n, sd, heur);
           if (better(ev, best)) best = std::move(ev);
           if (best.gamma == 0.0) break;  // every configuration pruned
         }
