@@ -6,6 +6,7 @@
 #include <cmath>
 #include <cstring>
 #include <fstream>
+#include <future>
 
 #include "crt.h"
 #include "ctx.h"
@@ -215,6 +216,24 @@ void recover_config(bbtn_ctx* ctx, const Network& net, const Tree& tree, const L
     if (states[v] < 0) states[v] = 0;  // variable in no tensor at all
 }
 
+// The context that recovers configurations concurrently with the counting
+// passes: created on first use with the same device and executor options,
+// its own stream and workspaces, and a copy of the tile choices.
+bbtn_ctx* aux_context(bbtn_ctx* ctx) {
+  if (!ctx->aux) {
+    bbtn_options o = ctx->opt;
+    o.stream = nullptr;
+    o.scorer_weights = nullptr;
+    o.autotune_cache = nullptr;
+    bbtn_ctx* a = nullptr;
+    const bbtn_status s = bbtn_create(&o, &a);
+    if (s != BBTN_OK) throw Error(s, "cannot create the configuration-recovery context");
+    ctx->aux = a;
+  }
+  ctx->aux->tune = ctx->tune;
+  return ctx->aux;
+}
+
 void solve_network(bbtn_ctx* ctx, Network& net, const std::vector<uint8_t>& ls_x,
                    bbtn_result* res) {
   const double t0 = now_s();
@@ -338,6 +357,14 @@ void solve_network(bbtn_ctx* ctx, Network& net, const std::vector<uint8_t>& ls_x
         if (first.group < 0) first = LeafRef{(int32_t)gi, i};
       }
   stats.pruned += stats.leaves - n_opt;
+  // one optimal configuration, recovered on the second context while this
+  // one runs the counting passes (they share no device buffers)
+  std::vector<int8_t> states;
+  bbtn_ctx* aux = aux_context(ctx);
+  std::future<void> cfg_job = std::async(std::launch::async, [&, aux] {
+    BBTN_HIP(hipSetDevice(aux->opt.device));
+    recover_config(aux, net, tree, groups[first.group], first.idx, states);
+  });
   // certification: a count never exceeds 2^n (the number of configurations)
   auto bits_of = [&](const std::vector<int>& ids) {
     double bits = 0;
@@ -418,9 +445,8 @@ void solve_network(bbtn_ctx* ctx, Network& net, const std::vector<uint8_t>& ls_x
   }
   const double t5 = now_s();
   res->seconds[4] = t5 - t4;
-  // configuration
-  std::vector<int8_t> states;
-  recover_config(ctx, net, tree, groups[first.group], first.idx, states);
+  // configuration (waits for the recovery; rethrows its error)
+  cfg_job.get();
   const double t6 = now_s();
   res->seconds[5] = t6 - t5;
   // fill the result
@@ -523,6 +549,7 @@ void bbtn_destroy(bbtn_ctx* ctx) {
   ctx->persist.release();
   ctx->clear_graphs();
   if (ctx->own) (void)hipStreamDestroy(ctx->own);
+  bbtn_destroy(ctx->aux);
   delete ctx;
 }
 

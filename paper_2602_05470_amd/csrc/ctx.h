@@ -77,6 +77,9 @@ struct bbtn_ctx {
   // contraction trees by network structure (the variable lists of the
   // simplified tensors, which do not depend on couplings or weights)
   std::map<std::vector<std::vector<int32_t>>, bbtn::Tree> tree_cache;
+  // second context (own stream and workspaces) that recovers the optimal
+  // configuration while this one runs the counting passes
+  bbtn_ctx* aux = nullptr;
   void clear_graphs() {
     for (auto& kv : graphs) (void)hipGraphExecDestroy(kv.second);
     graphs.clear();

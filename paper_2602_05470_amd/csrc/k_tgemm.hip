@@ -30,6 +30,9 @@ const TileCfg kTileCfgs[N_TILE_CFGS] = {
     {256, 1, 1, 1, 12},   // 6: one column (matrix-vector), 256 threads
     {64, 32, 4, 2, 24},   // 7: tall, 256 threads (fewer accumulators than 0)
     {32, 64, 2, 4, 24},   // 8: wide, 256 threads
+    {64, 64, 4, 4, 24},   // 9: as 0, operands staged four words at a time
+    {64, 32, 4, 2, 24},   // 10: as 7, four-word staging
+    {32, 64, 2, 4, 24},   // 11: as 8, four-word staging
 };
 
 struct GemmArgs {
@@ -44,6 +47,7 @@ struct GemmArgs {
   int64_t splits;
   int64_t tiles_m, tiles_n;
   int64_t total;             // tiles * splits * batch (work items of the grid)
+  int32_t vec_a, vec_b;      // operands staged four words at a time (aligned rows)
   Moduli mod;
 };
 
@@ -73,7 +77,7 @@ __device__ __forceinline__ int64_t xcd_remap(int64_t w, int64_t G) {
 }
 
 // One output tile (tile index w of a.total, before the XCD remap).
-template <int KR, int TM, int TN, int RM, int RN, int TK>
+template <int KR, int TM, int TN, int RM, int RN, int TK, bool VEC>
 __device__ __forceinline__ void tgemm_tile(const GemmArgs& a, int64_t w) {
   constexpr int TX = TN / RN;
   constexpr int TY = TM / RM;
@@ -86,8 +90,8 @@ __device__ __forceinline__ void tgemm_tile(const GemmArgs& a, int64_t w) {
   // one LDS region per operand: rows [0, TK) hold values, rows
   // [(1 + p) TK, (2 + p) TK) residue plane p; the values pass uses all
   // (1 + KP) TK rows as one deeper slice
-  __shared__ uint32_t As[(1 + KP) * TK][TMP];
-  __shared__ uint32_t Bs[(1 + KP) * TK][TN];
+  __shared__ __attribute__((aligned(16))) uint32_t As[(1 + KP) * TK][TMP];
+  __shared__ __attribute__((aligned(16))) uint32_t Bs[(1 + KP) * TK][TN];
   static_assert(sizeof(As) + sizeof(Bs) <= 65536, "tile exceeds 64 KiB of static LDS");
   auto Av = [&](int kk, int i) -> int32_t& { return *(int32_t*)&As[kk][i]; };
   auto Bv = [&](int kk, int i) -> int32_t& { return *(int32_t*)&Bs[kk][i]; };
@@ -119,15 +123,49 @@ __device__ __forceinline__ void tgemm_tile(const GemmArgs& a, int64_t w) {
   {
     constexpr int TK1 = (1 + KP) * TK;
     for (int64_t k0 = kbeg; k0 < kend; k0 += TK1) {
-      for (int idx = tid; idx < TM * TK1; idx += NT) {
-        const int i = idx / TK1, j = idx % TK1;
-        const int64_t m = m0 + i, q = k0 + j;
-        Av(j, i) = (m < a.M && q < kend) ? (int32_t)Ab[m * a.K + q] : NEG;
+      if (VEC && a.vec_a) {
+        // four consecutive k of one row per load (rows and slices are
+        // multiples of four words, so a load is wholly in range or out)
+        constexpr int KV = TK1 / 4;
+#pragma unroll 1
+        for (int idx = tid; idx < TM * KV; idx += NT) {
+          const int i = idx / KV, j = (idx % KV) * 4;
+          const int64_t m = m0 + i, q = k0 + j;
+          uint4 v = make_uint4((uint32_t)NEG, (uint32_t)NEG, (uint32_t)NEG, (uint32_t)NEG);
+          if (m < a.M && q < kend) v = *(const uint4*)(Ab + m * a.K + q);
+          As[j][i] = v.x;
+          As[j + 1][i] = v.y;
+          As[j + 2][i] = v.z;
+          As[j + 3][i] = v.w;
+        }
+      } else {
+        for (int idx = tid; idx < TM * TK1; idx += NT) {
+          const int i = idx / TK1, j = idx % TK1;
+          const int64_t m = m0 + i, q = k0 + j;
+          Av(j, i) = (m < a.M && q < kend) ? (int32_t)Ab[m * a.K + q] : NEG;
+        }
       }
-      for (int idx = tid; idx < TK1 * TN; idx += NT) {
-        const int j = idx / TN, i = idx % TN;
-        const int64_t n = n0 + i, q = k0 + j;
-        Bv(j, i) = (n < a.N && q < kend) ? (int32_t)Bb[q * a.N + n] : NEG;
+      bool vb = false;
+      if constexpr (VEC && TN % 4 == 0) {
+        if (a.vec_b) {
+          vb = true;
+          constexpr int NV = TN / 4;
+#pragma unroll 1
+          for (int idx = tid; idx < TK1 * NV; idx += NT) {
+            const int j = idx / NV, i = (idx % NV) * 4;
+            const int64_t n = n0 + i, q = k0 + j;
+            uint4 v = make_uint4((uint32_t)NEG, (uint32_t)NEG, (uint32_t)NEG, (uint32_t)NEG);
+            if (n < a.N && q < kend) v = *(const uint4*)(Bb + q * a.N + n);
+            *(uint4*)&Bs[j][i] = v;
+          }
+        }
+      }
+      if (!vb) {
+        for (int idx = tid; idx < TK1 * TN; idx += NT) {
+          const int j = idx / TN, i = idx % TN;
+          const int64_t n = n0 + i, q = k0 + j;
+          Bv(j, i) = (n < a.N && q < kend) ? (int32_t)Bb[q * a.N + n] : NEG;
+        }
       }
       __syncthreads();
 #pragma unroll 4
@@ -169,24 +207,76 @@ __device__ __forceinline__ void tgemm_tile(const GemmArgs& a, int64_t w) {
     // finite output, e.g. fully constrained independent-set blocks)
     if (__syncthreads_or(any_finite)) {
       for (int64_t k0 = kbeg; k0 < kend; k0 += TK) {
-        for (int idx = tid; idx < TM * TK; idx += NT) {
-          const int i = idx / TK, j = idx % TK;
-          const int64_t m = m0 + i, q = k0 + j;
-          const bool in = (m < a.M && q < kend);
-          const int64_t o = m * a.K + q;
-          // pass 2 stages negated values: the tie test below is one add3
-          Av(j, i) = in ? -(int32_t)Ab[o] : -NEG;
+        // pass 2 stages negated values: the tie test below is one add3
+        if (VEC && a.vec_a) {
+          constexpr int KV = TK / 4;
+  #pragma unroll 1
+        for (int idx = tid; idx < TM * KV; idx += NT) {
+            const int i = idx / KV, j = (idx % KV) * 4;
+            const int64_t m = m0 + i, q = k0 + j;
+            const bool in = (m < a.M && q < kend);
+            const int64_t o = m * a.K + q;
+            uint4 v = make_uint4((uint32_t)NEG, (uint32_t)NEG, (uint32_t)NEG, (uint32_t)NEG);
+            if (in) v = *(const uint4*)(Ab + o);
+            Av(j, i) = -(int32_t)v.x;
+            Av(j + 1, i) = -(int32_t)v.y;
+            Av(j + 2, i) = -(int32_t)v.z;
+            Av(j + 3, i) = -(int32_t)v.w;
 #pragma unroll
-          for (int p = 0; p < KR; ++p) Ac(p, j, i) = in ? Ab[(p + 1) * a.pA + o] : 0u;
+            for (int p = 0; p < KR; ++p) {
+              uint4 r = make_uint4(0u, 0u, 0u, 0u);
+              if (in) r = *(const uint4*)(Ab + (p + 1) * a.pA + o);
+              Ac(p, j, i) = r.x;
+              Ac(p, j + 1, i) = r.y;
+              Ac(p, j + 2, i) = r.z;
+              Ac(p, j + 3, i) = r.w;
+            }
+          }
+        } else {
+          for (int idx = tid; idx < TM * TK; idx += NT) {
+            const int i = idx / TK, j = idx % TK;
+            const int64_t m = m0 + i, q = k0 + j;
+            const bool in = (m < a.M && q < kend);
+            const int64_t o = m * a.K + q;
+            Av(j, i) = in ? -(int32_t)Ab[o] : -NEG;
+#pragma unroll
+            for (int p = 0; p < KR; ++p) Ac(p, j, i) = in ? Ab[(p + 1) * a.pA + o] : 0u;
+          }
         }
-        for (int idx = tid; idx < TK * TN; idx += NT) {
-          const int j = idx / TN, i = idx % TN;
-          const int64_t n = n0 + i, q = k0 + j;
-          const bool in = (n < a.N && q < kend);
-          const int64_t o = q * a.N + n;
-          Bv(j, i) = in ? -(int32_t)Bb[o] : -NEG;
+        bool vb = false;
+        if constexpr (VEC && TN % 4 == 0) {
+          if (a.vec_b) {
+            vb = true;
+            constexpr int NV = TN / 4;
+#pragma unroll 1
+            for (int idx = tid; idx < TK * NV; idx += NT) {
+              const int j = idx / NV, i = (idx % NV) * 4;
+              const int64_t n = n0 + i, q = k0 + j;
+              const bool in = (n < a.N && q < kend);
+              const int64_t o = q * a.N + n;
+              uint4 v = make_uint4((uint32_t)NEG, (uint32_t)NEG, (uint32_t)NEG, (uint32_t)NEG);
+              if (in) v = *(const uint4*)(Bb + o);
+              *(uint4*)&Bs[j][i] = make_uint4((uint32_t)(-(int32_t)v.x), (uint32_t)(-(int32_t)v.y),
+                                              (uint32_t)(-(int32_t)v.z), (uint32_t)(-(int32_t)v.w));
 #pragma unroll
-          for (int p = 0; p < KR; ++p) Bc(p, j, i) = in ? Bb[(p + 1) * a.pB + o] : 0u;
+              for (int p = 0; p < KR; ++p) {
+                uint4 r = make_uint4(0u, 0u, 0u, 0u);
+                if (in) r = *(const uint4*)(Bb + (p + 1) * a.pB + o);
+                *(uint4*)&Bs[(1 + p) * TK + j][i] = r;
+              }
+            }
+          }
+        }
+        if (!vb) {
+          for (int idx = tid; idx < TK * TN; idx += NT) {
+            const int j = idx / TN, i = idx % TN;
+            const int64_t n = n0 + i, q = k0 + j;
+            const bool in = (n < a.N && q < kend);
+            const int64_t o = q * a.N + n;
+            Bv(j, i) = in ? -(int32_t)Bb[o] : -NEG;
+#pragma unroll
+            for (int p = 0; p < KR; ++p) Bc(p, j, i) = in ? Bb[(p + 1) * a.pB + o] : 0u;
+          }
         }
         __syncthreads();
 #pragma unroll 3
@@ -254,20 +344,20 @@ __device__ __forceinline__ void tgemm_tile(const GemmArgs& a, int64_t w) {
   }
 }
 
-template <int KR, int TM, int TN, int RM, int RN, int TK>
+template <int KR, int TM, int TN, int RM, int RN, int TK, bool VEC>
 __global__ void __launch_bounds__((TM / RM) * (TN / RN))
 tgemm_kernel(const GemmArgs a) {
-  tgemm_tile<KR, TM, TN, RM, RN, TK>(a, blockIdx.x);
+  tgemm_tile<KR, TM, TN, RM, RN, TK, VEC>(a, blockIdx.x);
 }
 
 // Grids beyond 2^20 tiles: each workgroup walks the tiles with the grid's
 // stride (a dispatch must stay below 2^32 work-items).  The stride is a
 // multiple of 8, so every tile a workgroup takes maps to the same XCD.
-template <int KR, int TM, int TN, int RM, int RN, int TK>
+template <int KR, int TM, int TN, int RM, int RN, int TK, bool VEC>
 __global__ void __launch_bounds__((TM / RM) * (TN / RN))
 tgemm_kernel_strided(const GemmArgs a) {
   for (int64_t w = blockIdx.x; w < a.total; w += gridDim.x) {
-    tgemm_tile<KR, TM, TN, RM, RN, TK>(a, w);
+    tgemm_tile<KR, TM, TN, RM, RN, TK, VEC>(a, w);
     __syncthreads();  // LDS is restaged for the next tile
   }
 }
@@ -275,24 +365,27 @@ tgemm_kernel_strided(const GemmArgs a) {
 template <int KR>
 static void launch_cfg(int cfg, dim3 grid, const GemmArgs& a, hipStream_t st) {
   switch (cfg) {
-#define BBTN_TG_CASE(I, TM, TN, RM, RN, TK)                                   \
-  case I:                                                                     \
-    if (a.total == (int64_t)grid.x)                                           \
-      hipLaunchKernelGGL((tgemm_kernel<KR, TM, TN, RM, RN, TK>), grid,        \
-                         dim3((TM / RM) * (TN / RN)), 0, st, a);              \
-    else                                                                      \
-      hipLaunchKernelGGL((tgemm_kernel_strided<KR, TM, TN, RM, RN, TK>), grid, \
-                         dim3((TM / RM) * (TN / RN)), 0, st, a);              \
+#define BBTN_TG_CASE(I, TM, TN, RM, RN, TK, VEC)                                  \
+  case I:                                                                          \
+    if (a.total == (int64_t)grid.x)                                                \
+      hipLaunchKernelGGL((tgemm_kernel<KR, TM, TN, RM, RN, TK, VEC>), grid,         \
+                         dim3((TM / RM) * (TN / RN)), 0, st, a);                   \
+    else                                                                           \
+      hipLaunchKernelGGL((tgemm_kernel_strided<KR, TM, TN, RM, RN, TK, VEC>), grid, \
+                         dim3((TM / RM) * (TN / RN)), 0, st, a);                   \
     break;
-    BBTN_TG_CASE(0, 64, 64, 4, 4, 24)
-    BBTN_TG_CASE(1, 32, 32, 2, 2, 24)
-    BBTN_TG_CASE(2, 16, 16, 1, 1, 16)
-    BBTN_TG_CASE(3, 8, 64, 1, 2, 16)
-    BBTN_TG_CASE(4, 64, 8, 2, 1, 16)
-    BBTN_TG_CASE(5, 1, 256, 1, 1, 12)
-    BBTN_TG_CASE(6, 256, 1, 1, 1, 12)
-    BBTN_TG_CASE(7, 64, 32, 4, 2, 24)
-    BBTN_TG_CASE(8, 32, 64, 2, 4, 24)
+    BBTN_TG_CASE(0, 64, 64, 4, 4, 24, false)
+    BBTN_TG_CASE(1, 32, 32, 2, 2, 24, false)
+    BBTN_TG_CASE(2, 16, 16, 1, 1, 16, false)
+    BBTN_TG_CASE(3, 8, 64, 1, 2, 16, false)
+    BBTN_TG_CASE(4, 64, 8, 2, 1, 16, false)
+    BBTN_TG_CASE(5, 1, 256, 1, 1, 12, false)
+    BBTN_TG_CASE(6, 256, 1, 1, 1, 12, false)
+    BBTN_TG_CASE(7, 64, 32, 4, 2, 24, false)
+    BBTN_TG_CASE(8, 32, 64, 2, 4, 24, false)
+    BBTN_TG_CASE(9, 64, 64, 4, 4, 24, true)
+    BBTN_TG_CASE(10, 64, 32, 4, 2, 24, true)
+    BBTN_TG_CASE(11, 32, 64, 2, 4, 24, true)
 #undef BBTN_TG_CASE
     default:
       throw Error(BBTN_E_INTERNAL, "bad tile config");
@@ -307,6 +400,13 @@ static void launch_core(int k, const GemmArgs& a0, int cfg, hipStream_t st) {
   const int64_t total = a.tiles_m * a.tiles_n * a.splits * a.batch;
   BBTN_REQUIRE(total > 0, "empty tgemm grid");
   a.total = total;
+  // four-word staging needs 16-byte aligned rows, planes and batches, and K
+  // slices that are whole multiples of four
+  auto al16 = [](const void* p) { return ((uintptr_t)p & 15u) == 0; };
+  a.vec_a = a.K % 4 == 0 && a.kchunk % 4 == 0 && al16(a.A) && (k == 0 || a.pA % 4 == 0) &&
+            (a.batch == 1 || a.sAb % 4 == 0);
+  a.vec_b = a.N % 4 == 0 && al16(a.B) && (k == 0 || a.pB % 4 == 0) &&
+            (a.batch == 1 || a.sBb % 4 == 0);
   // at most 2^20 workgroups of <= 256 threads, a multiple of 8 when capped
   const int64_t cap = 1ll << 20;
   dim3 grid((unsigned)(total <= cap ? total : cap));

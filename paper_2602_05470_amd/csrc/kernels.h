@@ -10,7 +10,7 @@ namespace bbtn {
 struct TileCfg {
   int tm, tn, rm, rn, tk;
 };
-constexpr int N_TILE_CFGS = 9;
+constexpr int N_TILE_CFGS = 12;
 extern const TileCfg kTileCfgs[N_TILE_CFGS];
 
 struct GemmShape {

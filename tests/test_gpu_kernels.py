@@ -53,18 +53,20 @@ def _bucket(x):
     return b
 
 
-N_TILE_CFGS = 9
+N_TILE_CFGS = 12
 
 
 @pytest.mark.parametrize("cfg", range(N_TILE_CFGS))
 @pytest.mark.parametrize("splits", [1, 4])
 @pytest.mark.parametrize("k", [3, 4])
-def test_tgemm_every_tile_config(tmp_path, cfg, splits, k):
+@pytest.mark.parametrize("shape", [(2, 70, 75, 100), (3, 33, 68, 48)])
+def test_tgemm_every_tile_config(tmp_path, cfg, splits, k, shape):
     """Force each tile configuration (and split-K) through a tile-cache file;
-    ragged shape spanning several tiles in every dimension."""
+    ragged shapes spanning several tiles in every dimension (the second has
+    rows of whole multiples of four words, for the four-word staging)."""
     torch = torch_cuda()
     import paper_2602_05470_amd as B
-    b, M, N, K = 2, 70, 75, 100
+    b, M, N, K = shape
     cache = tmp_path / "tiles.txt"
     cache.write_text("%d %d %d %d %d %d %d\n" % (k, _bucket(b), _bucket(M), _bucket(N), _bucket(K),
                                                 cfg, splits))
