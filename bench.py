@@ -4,10 +4,12 @@ Workload (the configuration the headline metric is quoted on): +-J spin glass
 on a 16 x 16 open-boundary lattice, couplings +-1 from numpy seeds 0-19, zero
 field; plain BBTN with T_target = 2^10 (greedy contraction order, branching on
 separator spins), counts as residues modulo 3 primes per pass, CRT-certified.
-One step = one full solve of one instance (seed = step index mod 20) through
-the C ABI: network build, search, values-only pass, counting passes, CRT and
-certification, configuration recovery.  Every result is checked against the
-oracle's stored exact values; only exact, certified results are counted.
+One step = one call through the C ABI that fully solves --batch-size
+instances (default 20: seeds 0-19, bbtn_solve_batch): network build, search,
+values-only pass, counting pass, CRT and certification, configuration
+recovery; --workers contexts run steps concurrently.  Every result is
+checked against the oracle's stored exact values; only exact, certified
+results are counted.
 
 The JSON line also carries
   roofline:     the dominant kernel's semiring operations per second (events
@@ -105,7 +107,7 @@ def tgemm_micro(B, ctx, torch):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-micro", action="store_true")
@@ -114,9 +116,12 @@ def main():
                     help="only the counting-product micro-benchmark and a copy of known size "
                          "(for hardware-counter runs)")
     ap.add_argument("--batched", type=int, default=1)
-    ap.add_argument("--workers", type=int, default=4,
+    ap.add_argument("--workers", type=int, default=2,
                     help="concurrent solver contexts (threads, one stream each): one "
-                         "instance's host planning overlaps another's contraction")
+                         "call's host planning overlaps another's contraction")
+    ap.add_argument("--batch-size", type=int, default=20,
+                    help="instances per call (bbtn_solve_batch when > 1): their branch "
+                         "sub-networks share every device launch")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on exactly one GPU: this build's path is single-GPU "
@@ -142,13 +147,24 @@ def main():
     insts = [I.spin_glass_square(16, s) for s in range(20)]
     opts = B.Options(log2_target=10, residues_per_pass=3, branching=1, batched=args.batched)
     T = max(1, args.workers)
+    Bsz = max(1, args.batch_size)
     ctxs = [B.Context(opts) for _ in range(T)]
-    # warm-up: every worker context solves `warmup` instances (workspace
-    # growth, code loading) before the clock starts
+
+    def solve_step(c, i):
+        """Step i: instances i*Bsz .. i*Bsz+Bsz-1 (seeds mod 20), one call."""
+        seeds = [(i * Bsz + j) % 20 for j in range(Bsz)]
+        if Bsz == 1:
+            g = insts[seeds[0]]
+            return seeds, [c.solve_spinglass(g["n"], g["edges"], g["J"])]
+        rs, _ = c.solve_batch(0, [(insts[s]["n"], insts[s]["edges"], insts[s]["J"], None)
+                                  for s in seeds])
+        return seeds, rs
+
+    # warm-up: every worker context runs `warmup` steps (workspace growth,
+    # code loading) before the clock starts
     for c in ctxs:
         for i in range(args.warmup):
-            g = insts[i % 20]
-            c.solve_spinglass(g["n"], g["edges"], g["J"])
+            solve_step(c, i)
         c.profile(True)
     torch.cuda.synchronize()
     lock = threading.Lock()
@@ -162,8 +178,7 @@ def main():
                 nxt[0] += 1
             if i >= args.steps:
                 return
-            g = insts[i % 20]
-            results[i] = c.solve_spinglass(g["n"], g["edges"], g["J"])
+            results[i] = solve_step(c, i)
 
     t0 = time.perf_counter()
     if T == 1:
@@ -178,14 +193,17 @@ def main():
     t1 = time.perf_counter()
     exact = 0
     leaves = 0
+    n_inst = 0
     phases = [0.0] * 8
-    for i, r in enumerate(results):
-        leaves += r.leaves
-        phases = [a + b for a, b in zip(phases, r.seconds)]
-        ok = (r.value, r.count) == want[i % 20] and r.certified
-        exact += ok
-        print("step %d seed %d E0=%d deg=%d leaves=%d %s" % (i, i % 20, r.value, r.count, r.leaves,
-              "exact" if ok else "MISMATCH"), file=sys.stderr, flush=True)
+    for i, (seeds, rs) in enumerate(results):
+        for s, r in zip(seeds, rs):
+            n_inst += 1
+            leaves += r.leaves
+            phases = [a + b for a, b in zip(phases, r.seconds)]
+            ok = (r.value, r.count) == want[s] and r.certified
+            exact += ok
+            print("step %d seed %d E0=%d deg=%d leaves=%d %s" % (i, s, r.value, r.count, r.leaves,
+                  "exact" if ok else "MISMATCH"), file=sys.stderr, flush=True)
     stats = {}
     for name in ("tgemm", "persist", "gather"):
         agg = {"launches": 0, "seconds": 0.0, "ops": 0.0, "bytes": 0.0}
@@ -216,9 +234,10 @@ def main():
         "data": "synthetic",
         "config": {"workload": "+-J spin glass 16x16 open lattice, seeds 0-19, zero field, "
                                "plain BBTN T_target=2^10, 3 primes per pass; one step = one "
-                               "instance, solved by one of %d concurrent contexts" % T,
-                   "exact": exact, "leaves_per_instance": round(leaves / args.steps, 1),
-                   "batched": args.batched, "workers": T},
+                               "call solving %d instance(s), %d concurrent contexts" % (Bsz, T),
+                   "instances": n_inst, "exact": exact,
+                   "leaves_per_instance": round(leaves / max(n_inst, 1), 1),
+                   "batched": args.batched, "batch_size": Bsz, "workers": T},
         "roofline": {"bound": "alu", "kernel": dom,
                      "achieved": round(achieved / 1e12, 4), "peak": round(VALU_PEAK_OPS / 1e12, 2),
                      "unit": "TOP/s", "frac": round(achieved / VALU_PEAK_OPS, 5),
@@ -232,7 +251,8 @@ def main():
                     for n, s in stats.items()},
     }
     names = ["total", "build+plan", "search", "contraction", "crt+certification", "configuration"]
-    line["phases_ms"] = {nm: round(1e3 * phases[i] / args.steps, 3) for i, nm in enumerate(names)}
+    line["phases_ms"] = {nm: round(1e3 * phases[i] / max(n_inst, 1), 3)
+                         for i, nm in enumerate(names)}
     if not args.no_per_branch:
         # the same path without batching: one branch at a time (step programs
         # replayed from a hipGraph), on the first instances

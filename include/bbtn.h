@@ -264,6 +264,26 @@ bbtn_status bbtn_mlp_adam(bbtn_ctx* ctx, float* master, uint16_t* W, float* bias
  * when branching == 2. */
 bbtn_status bbtn_scorer_load(bbtn_ctx* ctx, const char* path);
 
+/* Several independent instances of one problem in one call (ensembles of
+ * seeded instances, "Applications" section).  The instances are built,
+ * ordered and searched on parallel host threads; then the branch
+ * sub-networks of all instances share each device launch: one persistent
+ * launch for the values pass, one for the counting pass, one for
+ * configuration recovery and one traceback launch.
+ * kind 0: spin glass, weights[i] = J of instance i (m[i] entries), h[i] =
+ * its field or NULL (h itself may be NULL: no fields); kind 1: MWIS,
+ * weights[i] = w (n[i] entries) or NULL for unit weights, h unused.
+ * edge_uv[i]: 2 m[i] vertex ids.  results[i] as for the single-instance
+ * calls (caller-owned count and config buffers); status[i] (caller-owned,
+ * n_inst entries) receives each instance's status.  Returns BBTN_OK when
+ * every instance succeeded, else the first failing instance's status (the
+ * others' results are still filled); a device failure fails every
+ * instance. */
+bbtn_status bbtn_solve_batch(bbtn_ctx* ctx, int32_t kind, int32_t n_inst, const int32_t* n,
+                             const int32_t* m, const int32_t* const* edge_uv,
+                             const int32_t* const* weights, const int32_t* const* h,
+                             bbtn_result* results, bbtn_status* status);
+
 /* The planner alone, on the host (ctx may be NULL; no device is used): build
  * the network of a spin-glass (kind 0: weights = J, h) or MWIS (kind 1:
  * weights = w, h unused) instance, order it greedily, take the local-search

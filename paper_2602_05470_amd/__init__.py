@@ -57,7 +57,8 @@ EXPORTS = ["bbtn_default_options", "bbtn_create", "bbtn_destroy", "bbtn_last_err
            "bbtn_solve_spinglass", "bbtn_solve_mwis", "bbtn_tgemm", "bbtn_gather",
            "bbtn_reduce", "bbtn_bound", "bbtn_last_macs", "bbtn_profile",
            "bbtn_get_kernel_stats", "bbtn_mlp_forward", "bbtn_mlp_backward", "bbtn_mlp_adam",
-           "bbtn_scorer_load", "bbtn_scorer_collect", "bbtn_scorer_train", "bbtn_plan_leaves"]
+           "bbtn_scorer_load", "bbtn_scorer_collect", "bbtn_scorer_train", "bbtn_plan_leaves",
+           "bbtn_solve_batch"]
 
 # scorer parameter layout (see include/bbtn.h)
 MLP_IN, MLP_H = 32, 128
@@ -97,6 +98,8 @@ def load(path: str = LIB_PATH):
     lib.bbtn_solve_spinglass.restype = I32
     lib.bbtn_solve_mwis.argtypes = [P, I32, I32, P, P, C.POINTER(_Result)]
     lib.bbtn_solve_mwis.restype = I32
+    lib.bbtn_solve_batch.argtypes = [P, I32, I32, P, P, P, P, P, P, P]
+    lib.bbtn_solve_batch.restype = I32
     lib.bbtn_tgemm.argtypes = [P, I32, P, I64, I64, I64, I64, P, P, P, P]
     lib.bbtn_tgemm.restype = I32
     lib.bbtn_gather.argtypes = [P, I32, I32, I32, P, I64, I64, P, P, I64, P, P]
@@ -275,6 +278,53 @@ class Context:
                       residues=[int(r.residues[i]) for i in range(r.n_primes)],
                       config=cfg, leaves=int(r.leaves), pruned=int(r.pruned),
                       nodes=int(r.nodes), macs=int(r.macs), seconds=list(r.seconds))
+
+    def solve_batch(self, kind, instances, raise_failed=True):
+        """bbtn_solve_batch: instances is a list of (n, edges, weights, h)
+        (kind 0: spin glass, weights = J; kind 1: MWIS, weights = w or None,
+        h ignored).  Returns (results, statuses)."""
+        N = len(instances)
+        n_arr = (C.c_int32 * max(N, 1))()
+        m_arr = (C.c_int32 * max(N, 1))()
+        uv_arr = (C.c_void_p * max(N, 1))()
+        w_arr = (C.c_void_p * max(N, 1))()
+        h_arr = (C.c_void_p * max(N, 1))()
+        res = (_Result * max(N, 1))()
+        st = (C.c_int32 * max(N, 1))()
+        keep, cnts, cfgs = [], [], []
+        for i, (n, edges, w, h) in enumerate(instances):
+            e = _i32(edges).reshape(-1, 2)
+            ww = None if w is None else _i32(w)
+            hh = None if (h is None or kind != 0) else _i32(h)
+            keep += [e, ww, hh]
+            n_arr[i], m_arr[i] = n, len(e)
+            uv_arr[i] = e.ctypes.data
+            w_arr[i] = None if ww is None else ww.ctypes.data
+            h_arr[i] = None if hh is None else hh.ctypes.data
+            cap = (n + 64) // 32 + 2
+            cnt = (C.c_uint32 * cap)()
+            cfg = np.zeros(n, dtype=np.int8)
+            cnts.append(cnt)
+            cfgs.append(cfg)
+            res[i].count = C.cast(cnt, C.POINTER(C.c_uint32))
+            res[i].count_capacity = cap
+            res[i].config = cfg.ctypes.data_as(C.POINTER(C.c_int8))
+        s = self.lib.bbtn_solve_batch(self.h, kind, N, n_arr, m_arr, uv_arr, w_arr, h_arr, res, st)
+        statuses = [int(st[i]) for i in range(N)]
+        if s != 0 and raise_failed:
+            self._check(s)
+        out = []
+        for i in range(N):
+            r = res[i]
+            count = 0
+            for j in reversed(range(r.count_words)):
+                count = (count << 32) | int(cnts[i][j])
+            out.append(Result(value=int(r.value), count=count, certified=bool(r.certified),
+                              primes=[int(r.primes[j]) for j in range(r.n_primes)],
+                              residues=[int(r.residues[j]) for j in range(r.n_primes)],
+                              config=cfgs[i], leaves=int(r.leaves), pruned=int(r.pruned),
+                              nodes=int(r.nodes), macs=int(r.macs), seconds=list(r.seconds)))
+        return out, statuses
 
     def solve_spinglass(self, n, edges, J, h=None, **kw) -> Result:
         """bbtn_solve_spinglass: E0 = min H (Eq. 1), exact degeneracy, one

@@ -14,15 +14,12 @@
 #include "persist.h"
 #include "scorer.h"
 #include "search.h"
+#include "solve.h"
 #include "trace.h"
 
 using namespace bbtn;
 
 namespace {
-
-double now_s() {
-  return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
-}
 
 template <class F>
 bbtn_status guard(bbtn_ctx* ctx, F&& f) {
@@ -46,433 +43,15 @@ bbtn_status guard(bbtn_ctx* ctx, F&& f) {
 // (default) stream, as everywhere in HIP.
 hipStream_t pick_stream(bbtn_ctx*, void* s) { return (hipStream_t)s; }
 
-// Leaves of the search in a flat order: (group, index in group).
-struct LeafRef {
-  int32_t group;
-  int64_t idx;
-};
-
-// Per-branch results of one pass: value and k residues per leaf.
-struct PassOut {
-  std::vector<std::vector<int32_t>> val;             // [group][leaf]
-  std::vector<std::vector<std::vector<uint32_t>>> res;  // [group][p][leaf]
-};
-
-int64_t leaves_per_chunk(bbtn_ctx* ctx, const GroupPlan& g, int k) {
-  size_t freeb = 0, totalb = 0;
-  if (hipMemGetInfo(&freeb, &totalb) != hipSuccess) freeb = (size_t)8 << 30;
-  const double budget = 0.45 * (double)(freeb + ctx->work.bytes);
-  const double per = (double)(1 + k) * 4.0 * (double)std::max<int64_t>(g.peak, 1) * 1.05 +
-                     (double)(1 + k) * 12.0 + 8.0 * (double)(g.base_ops.size() + 1);
-  int64_t L = (int64_t)(budget / per);
-  return std::max<int64_t>(1, std::min<int64_t>(L, 1 << 20));
-}
-
-// Run pass with primes pidx[0..k) over the selected leaves of every group.
-// sel[g] lists leaf indices (ascending) to run for group g.
-void run_pass(bbtn_ctx* ctx, const Network& net, const std::vector<LeafGroup>& groups,
-              std::vector<GroupPlan>& plans, const std::vector<std::vector<int64_t>>& sel,
-              const std::vector<int>& pidx, PassOut& out, bool batched) {
-  const int k = (int)pidx.size();
-  hipStream_t st = ctx->stream;
-  std::vector<uint32_t> primes(k);
-  for (int p = 0; p < k; ++p) primes[p] = prime_table()[pidx[p]];
-  const Moduli mod = make_moduli(k, primes.data());
-  BaseDev bd;
-  upload_base(ctx, net, pidx.data(), k, bd, ctx->base);
-  out.val.assign(groups.size(), {});
-  out.res.assign(groups.size(), {});
-  // the selected branches of every group, packed per group
-  std::vector<std::vector<uint8_t>> asg(groups.size());
-  for (size_t gi = 0; gi < groups.size(); ++gi) {
-    const LeafGroup& G = groups[gi];
-    out.val[gi].assign(G.count, NEG);
-    out.res[gi].assign(k, std::vector<uint32_t>(G.count, 0));
-    const size_t S = G.vars.size();
-    asg[gi].resize(sel[gi].size() * S);
-    for (size_t i = 0; i < sel[gi].size(); ++i)
-      std::memcpy(&asg[gi][i * S], &G.assign[sel[gi][i] * S], S);
-  }
-  auto scatter = [&](size_t gi, size_t c0, int64_t L, const uint32_t* h) {
-    for (int64_t i = 0; i < L; ++i) {
-      const int64_t leaf = sel[gi][c0 + i];
-      out.val[gi][leaf] = (int32_t)h[i];
-      for (int p = 0; p < k; ++p) out.res[gi][p][leaf] = h[(size_t)(p + 1) * L + i];
-    }
-  };
-  // groups whose operands fit in LDS: one persistent launch for all of them
-  std::vector<PersistJob> jobs;
-  std::vector<size_t> job_group;
-  std::vector<std::vector<uint32_t>> job_out(groups.size());
-  for (size_t gi = 0; gi < groups.size(); ++gi) {
-    if (!batched || sel[gi].empty() || !persist_fits(plans[gi], k)) continue;
-    jobs.push_back(PersistJob{&plans[gi], asg[gi].data(), (int64_t)sel[gi].size(), &job_out[gi]});
-    job_group.push_back(gi);
-  }
-  if (!jobs.empty()) {
-    run_persistent(ctx, net, jobs, bd, mod, st);
-    for (size_t j = 0; j < jobs.size(); ++j)
-      scatter(job_group[j], 0, jobs[j].L, job_out[job_group[j]].data());
-  }
-  // the rest: step by step, batched over the group's branches (chunked by
-  // memory), or one branch at a time when batching is off
-  for (size_t gi = 0; gi < groups.size(); ++gi) {
-    if (sel[gi].empty()) continue;
-    if (batched && persist_fits(plans[gi], k)) continue;
-    const GroupPlan& g = plans[gi];
-    const size_t S = groups[gi].vars.size();
-    const int64_t chunk = batched ? leaves_per_chunk(ctx, g, k) : 1;
-    for (size_t c0 = 0; c0 < sel[gi].size(); c0 += chunk) {
-      const int64_t L = std::min<int64_t>(chunk, (int64_t)(sel[gi].size() - c0));
-      ctx->leafout.ensure((size_t)(1 + k) * L * 4);
-      const DevTensor o{ctx->leafout.as<uint32_t>(), L};
-      run_group(ctx, net, g, bd, mod, &asg[gi][c0 * S], L, o, st,
-                /*reuse=*/sel[gi].size() > (size_t)chunk);
-      std::vector<uint32_t> h((size_t)(1 + k) * L);
-      BBTN_HIP(hipMemcpyAsync(h.data(), o.ptr, h.size() * 4, hipMemcpyDeviceToHost, st));
-      BBTN_HIP(hipStreamSynchronize(st));
-      ctx->prof.resolve();
-      scatter(gi, c0, L, h.data());
-    }
-  }
-}
-
-// Recover an optimal configuration from the winning leaf.
-void recover_config(bbtn_ctx* ctx, const Network& net, const Tree& tree, const LeafGroup& G,
-                    int64_t leaf, std::vector<int8_t>& states) {
-  hipStream_t st = ctx->stream;
-  states.assign(net.n, -1);
-  for (size_t j = 0; j < G.vars.size(); ++j) states[G.vars[j]] = (int8_t)G.assign[leaf * G.vars.size() + j];
-  GroupPlan g = build_plan(net, tree, G.mask, /*keep_all=*/true);
-  if (!g.steps.empty()) {
-    const int pidx0 = 0;
-    BaseDev bd;
-    upload_base(ctx, net, &pidx0, 0, bd, ctx->base);
-    const Moduli mod = make_moduli(0, nullptr);
-    ctx->leafout.ensure(64);
-    const DevTensor o{ctx->leafout.as<uint32_t>(), 1};
-    const uint64_t macs0 = ctx->last_macs;
-    if (ctx->opt.batched && persist_fits(g, 0)) {
-      // one persistent launch (one workgroup: its scratch starts at the
-      // workspace base, where the traceback reads)
-      std::vector<uint32_t> tmp;
-      std::vector<PersistJob> jobs{PersistJob{&g, &G.assign[leaf * G.vars.size()], 1, &tmp}};
-      run_persistent(ctx, net, jobs, bd, mod, st);
-    } else {
-      run_group(ctx, net, g, bd, mod, &G.assign[leaf * G.vars.size()], 1, o, st);
-    }
-    ctx->last_macs = macs0;  // bookkeeping counts the counting passes only
-    // traceback program
-    std::vector<TraceStep> ts;
-    std::vector<int32_t> vars;
-    for (const Step& s : g.steps) {
-      TraceStep t{};
-      t.rb = s.rb; t.rm = s.rm; t.rn = s.rn; t.rk = s.rk;
-      t.a_off = g.buf_off[s.a.direct ? s.a.id : s.a.temp];
-      t.b_off = g.buf_off[s.b.direct ? s.b.id : s.b.temp];
-      t.var_off = (int32_t)vars.size();
-      vars.insert(vars.end(), s.a_vars.begin(), s.a_vars.end());
-      vars.insert(vars.end(), s.b_vars.begin(), s.b_vars.end());
-      ts.push_back(t);
-    }
-    auto al = [](size_t b) { return (b + 255) / 256 * 256; };
-    const size_t bytes_ts = ts.size() * sizeof(TraceStep);
-    const size_t off_v = al(bytes_ts);
-    const size_t off_a = off_v + al(std::max<size_t>(vars.size(), 1) * 4);
-    const size_t off_s = off_a + al((size_t)net.n);
-    ctx->misc.ensure(off_s + 256);
-    char* base = ctx->misc.as<char>();
-    TraceStep* dts = (TraceStep*)base;
-    int32_t* dvars = (int32_t*)(base + off_v);
-    int8_t* dasg = (int8_t*)(base + off_a);
-    int32_t* dstat = (int32_t*)(base + off_s);
-    BBTN_HIP(hipMemcpyAsync(dts, ts.data(), bytes_ts, hipMemcpyHostToDevice, st));
-    BBTN_HIP(hipMemcpyAsync(dvars, vars.data(), vars.size() * 4, hipMemcpyHostToDevice, st));
-    BBTN_HIP(hipMemcpyAsync(dasg, states.data(), net.n, hipMemcpyHostToDevice, st));
-    const int32_t zero = 0;
-    BBTN_HIP(hipMemcpyAsync(dstat, &zero, 4, hipMemcpyHostToDevice, st));
-    launch_trace(dts, (int32_t)ts.size(), dvars, (int32_t)vars.size(), ctx->work.as<int32_t>(),
-                 dasg, net.n, dstat, st);
-    int32_t stat = 0;
-    BBTN_HIP(hipMemcpyAsync(states.data(), dasg, net.n, hipMemcpyDeviceToHost, st));
-    BBTN_HIP(hipMemcpyAsync(&stat, dstat, 4, hipMemcpyDeviceToHost, st));
-    BBTN_HIP(hipStreamSynchronize(st));
-    if (stat) throw Error(BBTN_E_INTERNAL, "configuration traceback failed");
-  }
-  // variables eliminated while simplifying, in reverse order
-  for (size_t i = net.peel.size(); i-- > 0;) {
-    const PeelRec& r = net.peel[i];
-    int64_t base = 0;
-    int pos = -1;
-    for (size_t j = 0; j < r.tvars.size(); ++j) {
-      if (r.tvars[j] == r.var) { pos = (int)j; continue; }
-      base |= (int64_t)(states[r.tvars[j]] & 1) << j;
-    }
-    const int32_t v0 = r.tval[base], v1 = r.tval[base | (1ll << pos)];
-    const bool f0 = v0 > NEG_CUT, f1 = v1 > NEG_CUT;
-    states[r.var] = (f1 && (!f0 || v1 > v0)) ? 1 : 0;
-  }
-  for (int v = 0; v < net.n; ++v)
-    if (states[v] < 0) states[v] = 0;  // variable in no tensor at all
-}
-
-// The context that recovers configurations concurrently with the counting
-// passes: created on first use with the same device and executor options,
-// its own stream and workspaces, and a copy of the tile choices.
-bbtn_ctx* aux_context(bbtn_ctx* ctx) {
-  if (!ctx->aux) {
-    bbtn_options o = ctx->opt;
-    o.stream = nullptr;
-    o.scorer_weights = nullptr;
-    o.autotune_cache = nullptr;
-    bbtn_ctx* a = nullptr;
-    const bbtn_status s = bbtn_create(&o, &a);
-    if (s != BBTN_OK) throw Error(s, "cannot create the configuration-recovery context");
-    ctx->aux = a;
-  }
-  ctx->aux->tune = ctx->tune;
-  return ctx->aux;
-}
-
-void solve_network(bbtn_ctx* ctx, Network& net, const std::vector<uint8_t>& ls_x,
-                   bbtn_result* res) {
-  const double t0 = now_s();
-  const bbtn_options& opt = ctx->opt;
-  ctx->last_macs = 0;
-  ctx->clear_graphs();  // captured programs refer to the previous solve's plans
-  struct GraphScope {
-    bbtn_ctx* c;
-    ~GraphScope() { c->clear_graphs(); }
-  } graph_scope{ctx};
-  for (int i = 0; i < 8; ++i) res->seconds[i] = 0;
-  const double deadline = opt.time_limit_s > 0 ? t0 + opt.time_limit_s : 0;
-  Tree tree;
-  {
-    std::vector<std::vector<int32_t>> shape;
-    shape.reserve(net.tensors.size() + 1);
-    shape.push_back({net.n});
-    for (const auto& T : net.tensors) shape.push_back(T.vars);
-    auto it = ctx->tree_cache.find(shape);
-    if (it != ctx->tree_cache.end()) {
-      tree = it->second;
-    } else {
-      tree = greedy_tree(net);
-      if (ctx->tree_cache.size() >= 8) ctx->tree_cache.clear();
-      ctx->tree_cache.emplace(std::move(shape), tree);
-    }
-  }
-  // search
-  const double t1 = now_s();
-  std::vector<LeafGroup> groups;
-  SearchStats stats;
-  const bool branch = opt.branching != 0 && opt.log2_target > 0;
-  const bool values_only = opt.residues_per_pass == 0;
-  // value (with the folded constant, like node_bound) of the local-search
-  // configuration: a lower bound on the optimum, used for global pruning
-  const int64_t incumbent = ls_x.empty() ? INT64_MIN : network_value(net, ls_x);
-  if (!branch) {
-    LeafGroup g;
-    g.mask.assign((net.n + 63) / 64, 0);
-    g.count = 1;
-    groups.push_back(g);
-    stats.leaves = 1;
-  } else {
-    SearchOptions so;
-    so.log2_target = opt.log2_target;
-    so.region_max = std::max(1, std::min(16, opt.region_max));
-    so.incumbent = incumbent;
-    so.values_only = values_only;
-    so.deadline = deadline;
-    if (opt.branching == 2 && ctx->scorer_loaded) so.scorer = make_var_scorer(ctx, net, tree, opt.log2_target);
-    bb_search(net, tree, so, groups, stats);
-  }
-  const double t2 = now_s();
-  // plans
-  std::vector<GroupPlan> plans;
-  for (auto& G : groups) plans.push_back(build_plan(net, tree, G.mask, false));
-  const double t3 = now_s();
-  res->seconds[1] = (t1 - t0) + (t3 - t2);
-  res->seconds[2] = t2 - t1;
-  // Values-only pass over every leaf (the max-plus part of the algebra):
-  // its exact values give the optimum, and a leaf whose value is below it
-  // can contribute no count (global pruning with the exact incumbent), so
-  // the counting passes below touch only the leaves reaching the optimum.
-  const auto& P = prime_table();
-  const int k = values_only ? 0 : std::max(1, std::min(KMAX, opt.residues_per_pass));
-  const int max_primes = std::max(k, std::min(BBTN_MAX_PRIMES, opt.max_primes));
-  std::vector<std::vector<int64_t>> sel(groups.size());
-  for (size_t gi = 0; gi < groups.size(); ++gi)
-    for (int64_t i = 0; i < groups[gi].count; ++i) sel[gi].push_back(i);
-  PassOut pv;
-  run_pass(ctx, net, groups, plans, sel, {}, pv, opt.batched != 0);
-  if (deadline > 0 && now_s() > deadline) throw Error(BBTN_E_TIMEOUT, "time limit reached");
-  int32_t best = NEG;
-  for (auto& gv : pv.val)
-    for (int32_t v : gv)
-      if (v > NEG_CUT && v > best) best = v;
-  if (values_only) {
-    // the optimum is the best leaf or, when the search pruned everything
-    // that could not beat it, the incumbent itself
-    const bool use_inc = incumbent != INT64_MIN &&
-                         (best <= NEG_CUT || incumbent > (int64_t)best + net.const_val);
-    if (best <= NEG_CUT && !use_inc) throw Error(BBTN_E_INTERNAL, "no feasible configuration found");
-    std::vector<int8_t> states;
-    if (use_inc) {
-      states.assign(ls_x.begin(), ls_x.end());
-    } else {
-      LeafRef first{-1, -1};
-      for (size_t gi = 0; gi < groups.size() && first.group < 0; ++gi)
-        for (int64_t i = 0; i < groups[gi].count; ++i)
-          if (pv.val[gi][i] == best) { first = LeafRef{(int32_t)gi, i}; break; }
-      recover_config(ctx, net, tree, groups[first.group], first.idx, states);
-    }
-    const double t6 = now_s();
-    res->seconds[5] = t6 - t3;
-    const int64_t value = use_inc ? incumbent : (int64_t)best + net.const_val;
-    res->value = net.spin ? -value : value;
-    res->n_primes = 0;
-    res->certified = 0;
-    res->count_words = 0;
-    res->leaves = stats.leaves;
-    res->pruned = stats.pruned;
-    res->nodes = stats.nodes;
-    res->macs = ctx->last_macs;
-    if (res->config)
-      for (int v = 0; v < net.n; ++v)
-        res->config[v] = net.spin ? (int8_t)(states[v] ? 1 : -1) : (int8_t)(states[v] ? 1 : 0);
-    if (res->count)
-      for (int i = 0; i < res->count_capacity; ++i) res->count[i] = 0;
-    res->seconds[0] = now_s() - t0;
-    return;
-  }
-  if (best <= NEG_CUT) throw Error(BBTN_E_INTERNAL, "no feasible configuration found");
-  std::vector<std::vector<int64_t>> opt_sel(groups.size());
-  LeafRef first{-1, -1};
-  uint64_t n_opt = 0;
-  for (size_t gi = 0; gi < groups.size(); ++gi)
-    for (int64_t i = 0; i < groups[gi].count; ++i)
-      if (pv.val[gi][i] == best) {
-        opt_sel[gi].push_back(i);
-        ++n_opt;
-        if (first.group < 0) first = LeafRef{(int32_t)gi, i};
-      }
-  stats.pruned += stats.leaves - n_opt;
-  // one optimal configuration, recovered on the second context while this
-  // one runs the counting passes (they share no device buffers)
-  std::vector<int8_t> states;
-  bbtn_ctx* aux = aux_context(ctx);
-  std::future<void> cfg_job = std::async(std::launch::async, [&, aux] {
-    BBTN_HIP(hipSetDevice(aux->opt.device));
-    recover_config(aux, net, tree, groups[first.group], first.idx, states);
-  });
-  // certification: a count never exceeds 2^n (the number of configurations)
-  auto bits_of = [&](const std::vector<int>& ids) {
-    double bits = 0;
-    for (int id : ids) bits += std::log2((double)P[id]);
-    return bits;
-  };
-  const double need_bits = (double)net.n + 1.0;
-  // first counting pass over the optimal leaves: k residues, plus, when k
-  // primes cannot certify by size and one more residue fits the entry, a
-  // (k+1)-th prime in the same pass that checks the CRT value
-  std::vector<int> used;
-  for (int p = 0; p < k; ++p) used.push_back(p);
-  const bool fused_check = bits_of(used) <= need_bits && k < KMAX && max_primes > k;
-  if (fused_check) used.push_back(k);
-  PassOut po;
-  run_pass(ctx, net, groups, plans, opt_sel, used, po, opt.batched != 0);
-  for (size_t gi = 0; gi < groups.size(); ++gi)
-    for (int64_t i : opt_sel[gi])
-      if (po.val[gi][i] != best) throw Error(BBTN_E_INTERNAL, "counting pass disagrees on a value");
-  std::vector<uint32_t> residues;  // aligned with `used`
-  auto sum_pass = [&](const PassOut& o, const std::vector<int>& ids) {
-    for (size_t p = 0; p < ids.size(); ++p) {
-      const uint32_t pr = P[ids[p]];
-      uint32_t s = 0;
-      for (size_t gi = 0; gi < groups.size(); ++gi)
-        for (int64_t i : opt_sel[gi]) s = addmod(s, o.res[gi][p][i], pr);
-      residues.push_back(mulmod(s, net.const_res[ids[p]], pr));
-    }
-  };
-  sum_pass(po, used);
-  const double t4 = now_s();
-  res->seconds[3] = t4 - t3;
-  std::vector<uint32_t> pr_used;
-  auto primes_of = [&](size_t count_of) {
-    pr_used.clear();
-    for (size_t i = 0; i < count_of; ++i) pr_used.push_back(P[used[i]]);
-    return pr_used;
-  };
-  int certified = 0;
-  std::vector<uint32_t> count;
-  if (fused_check) {
-    // CRT over the first k primes, checked against the (k+1)-th
-    const std::vector<uint32_t> first_k(residues.begin(), residues.begin() + k);
-    count = crt_garner(first_k, primes_of(k));
-    const bool agree = bigint_mod(count, P[used[k]]) == residues[k];
-    count = crt_garner(residues, primes_of(used.size()));
-    certified = agree ? 1 : 0;
-  } else {
-    count = crt_garner(residues, primes_of(used.size()));
-  }
-  while (!certified) {
-    if (bits_of(used) > need_bits) { certified = 1; break; }
-    const int nxt = (int)used.size();
-    if (nxt >= max_primes) break;
-    // one extra prime over the optimal leaves only
-    std::vector<int> one{nxt};
-    PassOut pc;
-    run_pass(ctx, net, groups, plans, opt_sel, one, pc, opt.batched != 0);
-    const uint32_t pq = P[nxt];
-    uint32_t r = 0;
-    for (size_t gi = 0; gi < groups.size(); ++gi)
-      for (int64_t i : opt_sel[gi]) r = addmod(r, pc.res[gi][0][i], pq);
-    r = mulmod(r, net.const_res[nxt], pq);
-    const bool agree = bigint_mod(count, pq) == r;
-    used.push_back(nxt);
-    residues.push_back(r);
-    count = crt_garner(residues, primes_of(used.size()));
-    if (agree) { certified = 1; break; }
-    // not yet: add a full pass of k primes
-    std::vector<int> more;
-    for (int p = 0; p < k && (int)used.size() + p < max_primes; ++p) more.push_back((int)used.size() + p);
-    if (more.empty()) break;
-    PassOut pm;
-    run_pass(ctx, net, groups, plans, opt_sel, more, pm, opt.batched != 0);
-    sum_pass(pm, more);
-    for (int id : more) used.push_back(id);
-    count = crt_garner(residues, primes_of(used.size()));
-  }
-  const double t5 = now_s();
-  res->seconds[4] = t5 - t4;
-  // configuration (waits for the recovery; rethrows its error)
-  cfg_job.get();
-  const double t6 = now_s();
-  res->seconds[5] = t6 - t5;
-  // fill the result
-  const int64_t value = (int64_t)best + net.const_val;
-  res->value = net.spin ? -value : value;
-  res->n_primes = (int32_t)used.size();
-  for (size_t i = 0; i < used.size(); ++i) {
-    res->primes[i] = P[used[i]];
-    res->residues[i] = residues[i];
-  }
-  res->certified = certified;
-  res->count_words = (int32_t)count.size();
-  res->leaves = stats.leaves;
-  res->pruned = stats.pruned;
-  res->nodes = stats.nodes;
-  res->macs = ctx->last_macs;
-  if (res->config)
-    for (int v = 0; v < net.n; ++v)
-      res->config[v] = net.spin ? (int8_t)(states[v] ? 1 : -1) : (int8_t)(states[v] ? 1 : 0);
-  res->seconds[0] = now_s() - t0;
-  if (res->count) {
-    if (res->count_capacity < res->count_words)
-      throw Error(BBTN_E_BUFFER_TOO_SMALL, "count buffer too small");
-    for (int i = 0; i < res->count_capacity; ++i) res->count[i] = i < (int)count.size() ? count[i] : 0;
-  }
-  if (!certified) throw Error(BBTN_E_COUNT_UNCERTIFIED, "count not certified within max_primes");
+// One instance through the shared pipeline; its own failure becomes this
+// call's status.
+void solve_network(bbtn_ctx* ctx, Network&& net, std::vector<uint8_t>&& ls_x, bbtn_result* res) {
+  std::vector<Instance> one(1);
+  one[0].net = std::move(net);
+  one[0].ls_x = std::move(ls_x);
+  one[0].res = res;
+  solve_instances(ctx, one);
+  if (one[0].status != BBTN_OK) throw Error(one[0].status, one[0].err);
 }
 
 void check_graph(int32_t n, int32_t m, const int32_t* uv) {
@@ -591,7 +170,50 @@ bbtn_status bbtn_solve_spinglass(bbtn_ctx* ctx, int32_t n, int32_t m, const int3
     std::vector<uint8_t> x;
     if (ctx->opt.local_search > 0)
       x = local_search_spinglass(n, m, edge_uv, J, h, ctx->opt.local_search, 12345);
-    solve_network(ctx, net, x, res);
+    solve_network(ctx, std::move(net), std::move(x), res);
+  });
+}
+
+bbtn_status bbtn_solve_batch(bbtn_ctx* ctx, int32_t kind, int32_t n_inst, const int32_t* n,
+                             const int32_t* m, const int32_t* const* edge_uv,
+                             const int32_t* const* weights, const int32_t* const* h,
+                             bbtn_result* results, bbtn_status* status) {
+  if (!ctx || !results || !status || n_inst < 0) return BBTN_E_INVALID_ARG;
+  if (n_inst > 0 && (!n || !m || !edge_uv || !weights)) return BBTN_E_INVALID_ARG;
+  return guard(ctx, [&] {
+    BBTN_REQUIRE(kind == 0 || kind == 1, "kind must be 0 (spin glass) or 1 (MWIS)");
+    BBTN_HIP(hipSetDevice(ctx->opt.device));
+    std::vector<Instance> insts(n_inst);
+    const int ls = ctx->opt.local_search;
+    for (int32_t i = 0; i < n_inst; ++i) {
+      insts[i].res = &results[i];
+      const int32_t ni = n[i], mi = m[i];
+      const int32_t* uv = edge_uv[i];
+      const int32_t* w = weights[i];
+      const int32_t* hi = h ? h[i] : nullptr;
+      insts[i].build = [kind, ni, mi, uv, w, hi, ls](Instance& in) {
+        check_graph(ni, mi, uv);
+        if (kind == 0) {
+          BBTN_REQUIRE(mi == 0 || w != nullptr, "J is NULL");
+          in.net = build_spinglass(ni, mi, uv, w, hi);
+          if (ls > 0) in.ls_x = local_search_spinglass(ni, mi, uv, w, hi, ls, 12345);
+        } else {
+          in.net = build_mwis(ni, mi, uv, w);
+          if (ls > 0) in.ls_x = local_search_mwis(ni, mi, uv, w, std::max(1, ls / 20), 12345);
+        }
+      };
+    }
+    solve_instances(ctx, insts);
+    bbtn_status first = BBTN_OK;
+    std::string msg;
+    for (int32_t i = 0; i < n_inst; ++i) {
+      status[i] = insts[i].status;
+      if (first == BBTN_OK && insts[i].status != BBTN_OK) {
+        first = insts[i].status;
+        msg = "instance " + std::to_string(i) + ": " + insts[i].err;
+      }
+    }
+    if (first != BBTN_OK) throw Error(first, msg);
   });
 }
 
@@ -605,7 +227,7 @@ bbtn_status bbtn_solve_mwis(bbtn_ctx* ctx, int32_t n, int32_t m, const int32_t* 
     std::vector<uint8_t> x;
     if (ctx->opt.local_search > 0)
       x = local_search_mwis(n, m, edge_uv, w, std::max(1, ctx->opt.local_search / 20), 12345);
-    solve_network(ctx, net, x, res);
+    solve_network(ctx, std::move(net), std::move(x), res);
   });
 }
 

@@ -1,6 +1,7 @@
 // The opaque context behind bbtn_ctx: device, stream, workspace, caches.
 #pragma once
 #include <map>
+#include <mutex>
 #include <string>
 #include <tuple>
 #include "common.h"
@@ -77,6 +78,7 @@ struct bbtn_ctx {
   // contraction trees by network structure (the variable lists of the
   // simplified tensors, which do not depend on couplings or weights)
   std::map<std::vector<std::vector<int32_t>>, bbtn::Tree> tree_cache;
+  std::mutex tree_mu;  // planning threads share the cache
   // second context (own stream and workspaces) that recovers the optimal
   // configuration while this one runs the counting passes
   bbtn_ctx* aux = nullptr;

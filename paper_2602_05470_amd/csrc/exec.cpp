@@ -29,6 +29,37 @@ void upload_base(bbtn_ctx* ctx, const Network& net, const int* prime_idx, int k,
   bd.t = DevTensor{buf.as<uint32_t>(), bd.total};
 }
 
+void upload_bases(bbtn_ctx* ctx, const std::vector<const Network*>& nets, const int* prime_idx,
+                  int k, BaseDev& bd, std::vector<std::vector<int64_t>>& offs, DevBuf& buf) {
+  bd.k = k;
+  bd.off.clear();
+  offs.assign(nets.size(), {});
+  int64_t total = 0;
+  for (size_t i = 0; i < nets.size(); ++i) {
+    offs[i].resize(nets[i]->tensors.size());
+    for (size_t t = 0; t < nets[i]->tensors.size(); ++t) {
+      offs[i][t] = total;
+      total += nets[i]->tensors[t].size();
+    }
+  }
+  bd.total = std::max<int64_t>(total, 1);
+  std::vector<uint32_t> host((size_t)(1 + k) * bd.total, 0);
+  for (size_t i = 0; i < nets.size(); ++i)
+    for (size_t t = 0; t < nets[i]->tensors.size(); ++t) {
+      const BaseTensor& T = nets[i]->tensors[t];
+      for (int64_t e = 0; e < T.size(); ++e) {
+        host[offs[i][t] + e] = (uint32_t)T.val[e];
+        for (int p = 0; p < k; ++p)
+          host[(size_t)(p + 1) * bd.total + offs[i][t] + e] =
+              T.res[(size_t)prime_idx[p] * T.size() + e];
+      }
+    }
+  buf.ensure(host.size() * 4);
+  BBTN_HIP(hipMemcpyAsync(buf.p, host.data(), host.size() * 4, hipMemcpyHostToDevice, ctx->stream));
+  BBTN_HIP(hipStreamSynchronize(ctx->stream));
+  bd.t = DevTensor{buf.as<uint32_t>(), bd.total};
+}
+
 static int ilog2_bucket(int64_t x) {
   int b = 0;
   while ((1ll << (b + 1)) <= x) ++b;
@@ -43,6 +74,7 @@ TuneVal choose_tiles(bbtn_ctx* ctx, int k, int64_t batch, int64_t M, int64_t N, 
   TuneVal tv{2, 1};
   if (M == 1 && N >= 64) tv.cfg = 5;
   else if (N == 1 && M >= 64) tv.cfg = 6;
+  else if (k >= 1 && M >= 32 && N >= 64) tv.cfg = 8;  // measured best for counting products
   else if (M >= 64 && N >= 64) tv.cfg = 0;
   else if (M >= 32 && N >= 32) tv.cfg = 1;
   else if (M <= 8 && N >= 64) tv.cfg = 3;

@@ -17,6 +17,10 @@ struct BaseDev {
 };
 void upload_base(bbtn_ctx* ctx, const Network& net, const int* prime_idx, int k,
                  BaseDev& bd, DevBuf& buf);
+// Base tensors of several networks in one buffer: tensor t of network i at
+// offs[i][t]; bd.off stays empty.
+void upload_bases(bbtn_ctx* ctx, const std::vector<const Network*>& nets, const int* prime_idx,
+                  int k, BaseDev& bd, std::vector<std::vector<int64_t>>& offs, DevBuf& buf);
 
 // Time the candidate tile configurations for one shape bucket.
 TuneVal autotune_shape(bbtn_ctx* ctx, int k, int64_t batch, int64_t M, int64_t N, int64_t K,

@@ -79,7 +79,7 @@ persist_kernel(const PersistArgs a) {
   uint32_t* lb = lds + W * cap;
   int32_t* pv = (int32_t*)(lb + W * cap);  // NTHR partial values
   uint32_t* pr = (uint32_t*)(pv + NTHR);   // KR x NTHR partial residues
-  uint32_t* scr = a.scratch + (int64_t)blockIdx.x * W * a.scratch_entries;
+  uint32_t* const scr_block = a.scratch + (int64_t)blockIdx.x * W * a.scratch_entries;
   const int tid = threadIdx.x;
 
   __shared__ uint32_t s_task;
@@ -96,6 +96,8 @@ persist_kernel(const PersistArgs a) {
     }
     const int64_t task = (int64_t)__builtin_amdgcn_readfirstlane(got);
     if (task >= a.n_tasks) break;
+    uint32_t* const scr =
+        a.per_task_scratch ? a.scratch + task * W * a.scratch_entries : scr_block;
     const PTask* tk = a.tasks + task;
     const uint8_t* asg = a.assign + tk->assign_off;
     const int32_t n_steps = tk->n_steps;

@@ -22,8 +22,16 @@ constexpr size_t TRACE_STAGE_BYTES = 104 * 1024;
 
 template <bool STAGED>
 __global__ void __launch_bounds__(64)
-trace_kernel(const TraceStep* steps, int32_t n_steps, const int32_t* vars, int32_t n_var_words,
-             const int32_t* ws, int8_t* assign, int32_t n_vars, int32_t* status) {
+trace_kernel(const TraceJob* jobs) {
+  const TraceJob* jb = jobs + blockIdx.x;
+  const TraceStep* steps = jb->steps;
+  const int32_t n_steps = jb->n_steps;
+  const int32_t* vars = jb->vars;
+  const int32_t n_var_words = jb->n_var_words;
+  const int32_t* ws = jb->ws;
+  int8_t* assign = jb->assign;
+  const int32_t n_vars = jb->n_vars;
+  int32_t* status = jb->status;
   __shared__ int8_t sa[TRACE_LDS_VARS];
   extern __shared__ int64_t stage64[];  // STAGED: [steps][vars]
   const int lane = threadIdx.x;
@@ -87,20 +95,17 @@ trace_kernel(const TraceStep* steps, int32_t n_steps, const int32_t* vars, int32
   if (lane == 0 && bad) *status = bad;
 }
 
-void launch_trace(const TraceStep* steps, int32_t n_steps, const int32_t* vars,
-                  int32_t n_var_words, const int32_t* ws, int8_t* assign, int32_t n_vars,
-                  int32_t* status, hipStream_t st) {
-  if (n_steps <= 0) return;
-  BBTN_REQUIRE(n_vars <= TRACE_LDS_VARS, "configuration traceback: too many variables");
-  const size_t stage = (size_t)n_steps * sizeof(TraceStep) + (size_t)n_var_words * 4;
+void launch_trace(const TraceJob* jobs, int32_t n_jobs, int32_t max_steps, int32_t max_var_words,
+                  int32_t max_vars, hipStream_t st) {
+  if (n_jobs <= 0 || max_steps <= 0) return;
+  BBTN_REQUIRE(max_vars <= TRACE_LDS_VARS, "configuration traceback: too many variables");
+  const size_t stage = (size_t)max_steps * sizeof(TraceStep) + (size_t)max_var_words * 4;
   if (stage <= TRACE_STAGE_BYTES) {
     BBTN_HIP(hipFuncSetAttribute((const void*)trace_kernel<true>,
                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)stage));
-    hipLaunchKernelGGL(trace_kernel<true>, dim3(1), dim3(64), stage, st, steps, n_steps, vars,
-                       n_var_words, ws, assign, n_vars, status);
+    hipLaunchKernelGGL(trace_kernel<true>, dim3(n_jobs), dim3(64), stage, st, jobs);
   } else {
-    hipLaunchKernelGGL(trace_kernel<false>, dim3(1), dim3(64), 0, st, steps, n_steps, vars,
-                       n_var_words, ws, assign, n_vars, status);
+    hipLaunchKernelGGL(trace_kernel<false>, dim3(n_jobs), dim3(64), 0, st, jobs);
   }
   BBTN_LAUNCHED("trace");
 }

@@ -39,8 +39,9 @@ int device_cus() {
 }
 }  // namespace
 
-void run_persistent(bbtn_ctx* ctx, const Network& net, const std::vector<PersistJob>& jobs,
-                    const BaseDev& bd, const Moduli& mod, hipStream_t st) {
+void run_persistent(bbtn_ctx* ctx, const std::vector<PersistJob>& jobs, const BaseDev& bd,
+                    const Moduli& mod, hipStream_t st, bool per_task_scratch,
+                    int64_t* scratch_entries) {
   const int k = bd.k;
   const int W = 1 + k;
   std::vector<PStep> steps;
@@ -54,6 +55,7 @@ void run_persistent(bbtn_ctx* ctx, const Network& net, const std::vector<Persist
     const int64_t shared_base = shared_total;
     shared_total += g.shared_total;
     scratch = std::max<int64_t>(scratch, std::max(g.peak, g.subtree_peak));
+    const Network& net = *jobs[ji].net;
     std::vector<int> pos_of(net.n, -1);
     for (size_t j = 0; j < g.fixed_vars.size(); ++j) pos_of[g.fixed_vars[j]] = (int)j;
     auto emit_step = [&](const Step& s) {
@@ -73,7 +75,7 @@ void run_persistent(bbtn_ctx* ctx, const Network& net, const std::vector<Persist
         if (gpn.n_runs > P_MAX_RUNS) throw Error(BBTN_E_INTERNAL, "persistent: too many runs");
         if (op.base) {
           po.kind = PK_BASE;
-          po.src_off = bd.off[op.id];
+          po.src_off = jobs[ji].base_off[op.id];
         } else if (g.buf_region[op.id] == R_SHARED) {
           po.kind = PK_SHARED;
           po.src_off = shared_base + g.buf_off[op.id];
@@ -136,7 +138,7 @@ void run_persistent(bbtn_ctx* ctx, const Network& net, const std::vector<Persist
   std::vector<uint32_t> lconst((size_t)W * n_out);
   for (size_t ji = 0; ji < jobs.size(); ++ji) {
     std::vector<uint32_t> lc;
-    leaf_constants(net, *jobs[ji].plan, pidx.data(), k, jobs[ji].assign, jobs[ji].L, lc);
+    leaf_constants(*jobs[ji].net, *jobs[ji].plan, pidx.data(), k, jobs[ji].assign, jobs[ji].L, lc);
     for (int p = 0; p < W; ++p)
       std::memcpy(&lconst[(size_t)p * n_out + out_base[ji]], &lc[(size_t)p * jobs[ji].L],
                   jobs[ji].L * 4);
@@ -181,8 +183,13 @@ void run_persistent(bbtn_ctx* ctx, const Network& net, const std::vector<Persist
   };
   const Shape sh_shared = shape_for((int64_t)shared_tasks.size());
   const Shape sh_branch = shape_for((int64_t)tasks.size());
-  const int64_t most = std::max<int64_t>(shared_tasks.empty() ? 0 : sh_shared.blocks, sh_branch.blocks);
+  int64_t most = std::max<int64_t>(shared_tasks.empty() ? 0 : sh_shared.blocks, sh_branch.blocks);
+  if (per_task_scratch) {
+    BBTN_REQUIRE(shared_tasks.empty(), "per-task scratch takes programs without shared steps");
+    most = (int64_t)tasks.size();
+  }
   ctx->work.ensure((size_t)most * W * scratch * 4);
+  if (scratch_entries) *scratch_entries = scratch;
   PersistArgs a{};
   a.steps = (const PStep*)(dev + o_steps);
   a.fixes = (const PFix*)(dev + o_fixes);
@@ -197,6 +204,7 @@ void run_persistent(bbtn_ctx* ctx, const Network& net, const std::vector<Persist
   a.shared = (uint32_t*)(dev + o_shared);
   a.shared_entries = std::max<int64_t>(shared_total, 1);
   a.lds_entries = lds_entries;
+  a.per_task_scratch = per_task_scratch ? 1 : 0;
   a.mod = mod;
   double ops = 0, bytes = 0;
   for (auto& j : jobs) {

@@ -65,6 +65,8 @@ struct PersistArgs {
   uint32_t* shared;        // (1 + k) planes of shared_entries
   int64_t shared_entries;
   int64_t lds_entries;
+  int32_t per_task_scratch;   // scratch of task i at i * (1 + k) * scratch_entries
+  int32_t pad;
   unsigned long long* queue;  // task counter, zeroed before the launch
   Moduli mod;
 };

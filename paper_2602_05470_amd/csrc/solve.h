@@ -1,0 +1,30 @@
+// The solve pipeline over one or several instances: build and plan each
+// instance on the host (in parallel threads), then run the values pass, the
+// counting pass and configuration recovery of all instances through shared
+// device launches.
+#pragma once
+#include <functional>
+#include <string>
+#include <vector>
+#include "ctx.h"
+#include "network.h"
+
+namespace bbtn {
+
+struct Instance {
+  // when set, fills net and ls_x on a planning thread (errors become this
+  // instance's status)
+  std::function<void(Instance&)> build;
+  Network net;
+  std::vector<uint8_t> ls_x;     // local-search configuration (may be empty)
+  bbtn_result* res = nullptr;    // caller's result
+  bbtn_status status = BBTN_OK;  // outcome of this instance
+  std::string err;
+};
+
+// Solve every instance.  An instance's own failure (time limit, count not
+// certified, buffer too small, no feasible configuration) is recorded in its
+// status; a device failure throws and ends the call for every instance.
+void solve_instances(bbtn_ctx* ctx, std::vector<Instance>& insts);
+
+}  // namespace bbtn

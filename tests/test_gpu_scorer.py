@@ -148,3 +148,30 @@ def test_collect_and_scorer_keeps_results_exact(B, tmp_path):
                                  scorer_weights=path if branching == 2 else None)) as ctx:
             r = ctx.solve_spinglass(g["n"], g["edges"], g["J"])
         assert (r.value, r.count) == want
+
+
+def test_shipped_scorer_gain_on_kings_subgraphs(B):
+    """The scorer shipped with the package for King's subgraphs (trained by
+    train_scorer --problem ksg on seeds 10000-10249 at 16 x 16 and
+    20000-20249 at 20 x 20) against the plain planner on held-out 16 x 16
+    instances, seeds 100-105, T_target = 2^8: identical exact results, and
+    fewer multiply-accumulates contracted in total (it picks branching seeds
+    whose rules have smaller branching factors)."""
+    import os
+    weights = os.path.join(os.path.dirname(B.__file__), "scorer_ksg.bin")
+    tot = {1: 0, 2: 0}
+    leaves = {1: 0, 2: 0}
+    for s in range(100, 106):
+        g = I.kings_subgraph(16, s)
+        got = {}
+        for branching in (1, 2):
+            with B.Context(B.Options(log2_target=8, branching=branching,
+                                     scorer_weights=weights if branching == 2 else None)) as ctx:
+                r = ctx.solve_mwis(g["n"], g["edges"], g["w"])
+            got[branching] = (r.value, r.count, r.certified)
+            tot[branching] += r.macs
+            leaves[branching] += r.leaves
+        assert got[1] == got[2] and got[1][2]
+    print("multiply-accumulates plain %d scorer %d (ratio %.3f); leaves %d vs %d"
+          % (tot[1], tot[2], tot[2] / tot[1], leaves[1], leaves[2]))
+    assert tot[2] < tot[1]
