@@ -116,7 +116,7 @@ def main():
                     help="only the counting-product micro-benchmark and a copy of known size "
                          "(for hardware-counter runs)")
     ap.add_argument("--batched", type=int, default=1)
-    ap.add_argument("--workers", type=int, default=2,
+    ap.add_argument("--workers", type=int, default=4,
                     help="concurrent solver contexts (threads, one stream each): one "
                          "call's host planning overlaps another's contraction")
     ap.add_argument("--batch-size", type=int, default=20,

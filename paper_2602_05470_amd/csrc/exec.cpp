@@ -74,7 +74,10 @@ TuneVal choose_tiles(bbtn_ctx* ctx, int k, int64_t batch, int64_t M, int64_t N, 
   TuneVal tv{2, 1};
   if (M == 1 && N >= 64) tv.cfg = 5;
   else if (N == 1 && M >= 64) tv.cfg = 6;
-  else if (k >= 1 && M >= 32 && N >= 64) tv.cfg = 8;  // measured best for counting products
+  // measured best for counting products (four-word staging when aligned)
+  else if (k >= 4 && M >= 32 && N >= 64) tv.cfg = 11;
+  else if (k >= 1 && M >= 64 && N >= 32) tv.cfg = 10;
+  else if (k >= 1 && M >= 32 && N >= 64) tv.cfg = 8;
   else if (M >= 64 && N >= 64) tv.cfg = 0;
   else if (M >= 32 && N >= 32) tv.cfg = 1;
   else if (M <= 8 && N >= 64) tv.cfg = 3;

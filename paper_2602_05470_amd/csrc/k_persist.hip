@@ -79,6 +79,7 @@ persist_kernel(const PersistArgs a) {
   uint32_t* lb = lds + W * cap;
   int32_t* pv = (int32_t*)(lb + W * cap);  // NTHR partial values
   uint32_t* pr = (uint32_t*)(pv + NTHR);   // KR x NTHR partial residues
+  uint32_t* fixtab = pr + KR * NTHR;       // the task's fixed bits per slot
   uint32_t* const scr_block = a.scratch + (int64_t)blockIdx.x * W * a.scratch_entries;
   const int tid = threadIdx.x;
 
@@ -102,6 +103,24 @@ persist_kernel(const PersistArgs a) {
     const uint8_t* asg = a.assign + tk->assign_off;
     const int32_t n_steps = tk->n_steps;
     const PStep* sp = a.steps + tk->step_off;
+    const uint32_t* const base = a.base + tk->base_off;
+    uint32_t* const shared = a.shared + tk->shared_off;
+    // the fixed bits of every base operand of the program, from the task's
+    // states (once per task instead of once per step)
+    const int32_t n_slots = tk->n_slots;
+    if (n_slots > 0) {
+      const PSlot* sl = a.slots + tk->slot_off;
+      for (int j = tid; j < n_slots; j += NTHR) {
+        const PSlot q = sl[j];
+        uint32_t f = 0;
+        for (int i = 0; i < q.n_fix; ++i) {
+          const PFix fx = a.fixes[q.fix_off + i];
+          f |= (uint32_t)(asg[fx.idx] & 1) << fx.pos;
+        }
+        fixtab[j] = f;
+      }
+      __syncthreads();
+    }
 
     for (int32_t si = 0; si < n_steps; ++si, ++sp) {
       // ---- stage operands
@@ -109,15 +128,11 @@ persist_kernel(const PersistArgs a) {
       for (int w = 0; w < 2; ++w) {
         const POperand* op = w == 0 ? &sp->a : &sp->b;
         uint32_t* dst = w == 0 ? la : lb;
-        uint32_t fixed = 0;
-        const int nf = op->n_fix;
-        for (int f = 0; f < nf; ++f) {
-          const PFix fx = a.fixes[op->fix_off + f];
-          fixed |= (uint32_t)(asg[fx.idx] & 1) << fx.pos;
-        }
+        const int slot = op->slot;
+        const uint32_t fixed = slot >= 0 ? fixtab[slot] : 0u;
         const int kind = op->kind;
-        const uint32_t* src = kind == PK_BASE     ? a.base + op->src_off
-                              : kind == PK_SHARED ? a.shared + op->src_off
+        const uint32_t* src = kind == PK_BASE     ? base + op->src_off
+                              : kind == PK_SHARED ? shared + op->src_off
                                                   : scr + op->src_off;
         const int64_t sstride = kind == PK_BASE     ? a.base_total
                                 : kind == PK_SHARED ? a.shared_entries
@@ -207,7 +222,7 @@ persist_kernel(const PersistArgs a) {
         if (j == 0 && o < nC) {
           const bool fin = V > NEG_CUT;
           const bool sh = c_kind == PK_SHARED;
-          uint32_t* c = (sh ? a.shared : scr) + c_off;
+          uint32_t* c = (sh ? shared : scr) + c_off;
           const int64_t cs = sh ? a.shared_entries : a.scratch_entries;
           c[o] = (uint32_t)(fin ? V : NEG);
 #pragma unroll
@@ -241,8 +256,9 @@ __global__ void zero_kernel(unsigned long long* q) { *q = 0; }
 
 }  // namespace
 
-size_t persist_lds_bytes(int k, int64_t lds_entries, int threads) {
-  return (size_t)2 * (1 + k) * lds_entries * 4 + (size_t)threads * 4 * (1 + k);
+size_t persist_lds_bytes(int k, int64_t lds_entries, int threads, int slots) {
+  return (size_t)2 * (1 + k) * lds_entries * 4 + (size_t)threads * 4 * (1 + k) +
+         (size_t)slots * 4;
 }
 
 template <int NT>
@@ -266,7 +282,7 @@ static void launch_nt(int k, const PersistArgs& a, int n_blocks, size_t lds, hip
 }
 
 void launch_persist(int k, const PersistArgs& a, int n_blocks, int threads, hipStream_t st) {
-  const size_t lds = persist_lds_bytes(k, a.lds_entries, threads);
+  const size_t lds = persist_lds_bytes(k, a.lds_entries, threads, a.max_slots);
   hipLaunchKernelGGL(zero_kernel, dim3(1), dim3(1), 0, st, a.queue);
   BBTN_LAUNCHED("persist queue reset");
   switch (threads) {

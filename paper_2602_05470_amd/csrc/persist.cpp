@@ -1,6 +1,8 @@
 #include "persist.h"
 
 #include <cstring>
+#include <map>
+#include <string>
 
 #include "persist_dev.h"
 
@@ -9,12 +11,16 @@ namespace bbtn {
 int persist_max_rank(int k) {
   // two operand buffers of (1 + k) planes within 64 KiB of LDS
   int r = 0;
-  while (persist_lds_bytes(k, 1ll << (r + 1), 64) <= (64u << 10)) ++r;
+  while (persist_lds_bytes(k, 1ll << (r + 1), 64, 0) <= (64u << 10)) ++r;
   return r;
 }
 
 bool persist_fits(const GroupPlan& g, int k) {
   if (g.steps.empty()) return true;
+  // the per-task fixed-bit table lives in LDS: at most 4096 slots
+  size_t n_slots = 0;
+  for (const Step& s : g.steps) n_slots += !s.a.fixed_pos.empty() + !s.b.fixed_pos.empty();
+  if (n_slots > 4096) return false;
   int mx = 0;
   for (const Step& s : g.steps) mx = std::max({mx, (int)s.a_vars.size(), (int)s.b_vars.size()});
   for (const Step& s : g.steps) {
@@ -46,83 +52,123 @@ void run_persistent(bbtn_ctx* ctx, const std::vector<PersistJob>& jobs, const Ba
   const int W = 1 + k;
   std::vector<PStep> steps;
   std::vector<PFix> fixes;
+  std::vector<PSlot> slots;
   std::vector<PTask> shared_tasks, tasks;
   std::vector<uint8_t> assign;
   int64_t n_out = 0, scratch = 1, max_rank = 0, shared_total = 0;
+  int32_t max_slots = 0;
   std::vector<int64_t> out_base(jobs.size());
+  // programs already emitted, by content: instances with the same
+  // contraction tree and fixed set share one copy
+  struct ProgRef {
+    int32_t step_off, n_steps, slot_off, n_slots;
+  };
+  std::map<std::string, ProgRef> seen;
   for (size_t ji = 0; ji < jobs.size(); ++ji) {
     const GroupPlan& g = *jobs[ji].plan;
     const int64_t shared_base = shared_total;
     shared_total += g.shared_total;
     scratch = std::max<int64_t>(scratch, std::max(g.peak, g.subtree_peak));
     const Network& net = *jobs[ji].net;
+    const int64_t base0 = net.tensors.empty() ? 0 : jobs[ji].base_off[0];
     std::vector<int> pos_of(net.n, -1);
     for (size_t j = 0; j < g.fixed_vars.size(); ++j) pos_of[g.fixed_vars[j]] = (int)j;
-    auto emit_step = [&](const Step& s) {
-      PStep ps{};
-      ps.rb = s.rb; ps.rm = s.rm; ps.rn = s.rn; ps.rk = s.rk;
-      const bool out_shared = g.buf_region[s.out] == R_SHARED;
-      ps.c_kind = out_shared ? PK_SHARED : PK_SCRATCH;
-      ps.c_off = g.buf_off[s.out] + (out_shared ? shared_base : 0);
-      const Operand* ops[2] = {&s.a, &s.b};
-      POperand* pops[2] = {&ps.a, &ps.b};
-      for (int w = 0; w < 2; ++w) {
-        const Operand& op = *ops[w];
-        POperand& po = *pops[w];
-        const int rank = (int)op.src_bits.size();
-        max_rank = std::max<int64_t>(max_rank, rank);
-        const GatherPlan gpn = make_gather_plan(op.r_in, rank, op.src_bits.data());
-        if (gpn.n_runs > P_MAX_RUNS) throw Error(BBTN_E_INTERNAL, "persistent: too many runs");
-        if (op.base) {
-          po.kind = PK_BASE;
-          po.src_off = jobs[ji].base_off[op.id];
-        } else if (g.buf_region[op.id] == R_SHARED) {
-          po.kind = PK_SHARED;
-          po.src_off = shared_base + g.buf_off[op.id];
-        } else {
-          po.kind = PK_SCRATCH;
-          po.src_off = g.buf_off[op.id];
-        }
-        po.rank = rank;
-        po.n_runs = gpn.n_runs;
-        for (int r = 0; r < gpn.n_runs; ++r) po.runs[r] = pack_run(gpn.runs[r]);
-        // programs that keep everything materialise gathered operands
-        po.mat_off = (op.temp >= 0 && g.keep_all) ? g.buf_off[op.temp] : -1;
-        po.fix_off = (int32_t)fixes.size();
-        po.n_fix = 0;
-        if (op.base)
-          for (auto& fp : op.fixed_pos) {
-            fixes.push_back(PFix{fp.first, pos_of[fp.second]});
-            po.n_fix++;
+    // a program: steps, their fixed-bit slots and fixes (offsets relative to
+    // the program), deduplicated by content
+    auto emit_program = [&](const std::vector<const Step*>& prog) {
+      std::vector<PStep> ps_v;
+      std::vector<PSlot> sl_v;
+      std::vector<PFix> fx_v;
+      for (const Step* sp : prog) {
+        const Step& s = *sp;
+        PStep ps{};
+        ps.rb = s.rb; ps.rm = s.rm; ps.rn = s.rn; ps.rk = s.rk;
+        const bool out_shared = g.buf_region[s.out] == R_SHARED;
+        ps.c_kind = out_shared ? PK_SHARED : PK_SCRATCH;
+        ps.c_off = g.buf_off[s.out];
+        const Operand* ops[2] = {&s.a, &s.b};
+        POperand* pops[2] = {&ps.a, &ps.b};
+        for (int w = 0; w < 2; ++w) {
+          const Operand& op = *ops[w];
+          POperand& po = *pops[w];
+          const int rank = (int)op.src_bits.size();
+          max_rank = std::max<int64_t>(max_rank, rank);
+          const GatherPlan gpn = make_gather_plan(op.r_in, rank, op.src_bits.data());
+          if (gpn.n_runs > P_MAX_RUNS) throw Error(BBTN_E_INTERNAL, "persistent: too many runs");
+          if (op.base) {
+            po.kind = PK_BASE;
+            po.src_off = jobs[ji].base_off[op.id] - base0;
+          } else if (g.buf_region[op.id] == R_SHARED) {
+            po.kind = PK_SHARED;
+            po.src_off = g.buf_off[op.id];
+          } else {
+            po.kind = PK_SCRATCH;
+            po.src_off = g.buf_off[op.id];
           }
+          po.rank = rank;
+          po.n_runs = gpn.n_runs;
+          for (int r = 0; r < gpn.n_runs; ++r) po.runs[r] = pack_run(gpn.runs[r]);
+          // programs that keep everything materialise gathered operands
+          po.mat_off = (op.temp >= 0 && g.keep_all) ? g.buf_off[op.temp] : -1;
+          po.slot = -1;
+          if (op.base && !op.fixed_pos.empty()) {
+            po.slot = (int32_t)sl_v.size();
+            sl_v.push_back(PSlot{(int32_t)fx_v.size(), (int32_t)op.fixed_pos.size()});
+            for (auto& fp : op.fixed_pos) fx_v.push_back(PFix{fp.first, pos_of[fp.second]});
+          }
+        }
+        ps_v.push_back(ps);
       }
-      steps.push_back(ps);
+      std::string key((const char*)ps_v.data(), ps_v.size() * sizeof(PStep));
+      key.append((const char*)sl_v.data(), sl_v.size() * sizeof(PSlot));
+      key.append((const char*)fx_v.data(), fx_v.size() * sizeof(PFix));
+      auto it = seen.find(key);
+      if (it != seen.end()) return it->second;
+      ProgRef pr{(int32_t)steps.size(), (int32_t)ps_v.size(), (int32_t)slots.size(),
+                 (int32_t)sl_v.size()};
+      const int32_t fix0 = (int32_t)fixes.size();
+      for (PSlot q : sl_v) slots.push_back(PSlot{q.fix_off + fix0, q.n_fix});
+      fixes.insert(fixes.end(), fx_v.begin(), fx_v.end());
+      steps.insert(steps.end(), ps_v.begin(), ps_v.end());
+      max_slots = std::max(max_slots, pr.n_slots);
+      seen.emplace(std::move(key), pr);
+      return pr;
     };
     // shared subtrees: one task each, run before any branch
     for (auto& rg : g.shared_ranges) {
+      std::vector<const Step*> prog;
+      for (int i = rg.first; i < rg.second; ++i) prog.push_back(&g.steps[i]);
+      const ProgRef pr = emit_program(prog);
       PTask t{};
-      t.step_off = (int32_t)steps.size();
-      for (int i = rg.first; i < rg.second; ++i) emit_step(g.steps[i]);
-      t.n_steps = (int32_t)steps.size() - t.step_off;
+      t.step_off = pr.step_off;
+      t.n_steps = pr.n_steps;
+      t.slot_off = pr.slot_off;
+      t.n_slots = pr.n_slots;
       t.assign_off = 0;
       t.out_idx = -1;
       t.root_off = -1;
+      t.base_off = base0;
+      t.shared_off = shared_base;
       shared_tasks.push_back(t);
     }
     // the branch program
-    const int32_t prog = (int32_t)steps.size();
+    std::vector<const Step*> prog;
     for (const Step& s : g.steps)
-      if (!s.shared) emit_step(s);
-    const int32_t n_prog = (int32_t)steps.size() - prog;
+      if (!s.shared) prog.push_back(&s);
+    const ProgRef pr = emit_program(prog);
     const size_t S = g.fixed_vars.size();
     out_base[ji] = n_out;
     for (int64_t l = 0; l < jobs[ji].L; ++l) {
       PTask t{};
-      t.step_off = prog;
-      t.n_steps = n_prog;
+      t.step_off = pr.step_off;
+      t.n_steps = pr.n_steps;
+      t.slot_off = pr.slot_off;
+      t.n_slots = pr.n_slots;
       t.assign_off = (int64_t)assign.size() + (int64_t)(l * S);
       t.out_idx = n_out + l;
       t.root_off = g.root_buf >= 0 ? g.buf_off[g.root_buf] : -1;
+      t.base_off = base0;
+      t.shared_off = shared_base;
       tasks.push_back(t);
     }
     assign.insert(assign.end(), jobs[ji].assign, jobs[ji].assign + jobs[ji].L * S);
@@ -147,6 +193,7 @@ void run_persistent(bbtn_ctx* ctx, const std::vector<PersistJob>& jobs, const Ba
   size_t off = 0;
   const size_t o_steps = off; off = align_up(off + steps.size() * sizeof(PStep));
   const size_t o_fixes = off; off = align_up(off + std::max<size_t>(fixes.size(), 1) * sizeof(PFix));
+  const size_t o_slots = off; off = align_up(off + std::max<size_t>(slots.size(), 1) * sizeof(PSlot));
   const size_t o_stasks = off; off = align_up(off + std::max<size_t>(shared_tasks.size(), 1) * sizeof(PTask));
   const size_t o_tasks = off; off = align_up(off + tasks.size() * sizeof(PTask));
   const size_t o_assign = off; off = align_up(off + std::max<size_t>(assign.size(), 1));
@@ -157,6 +204,7 @@ void run_persistent(bbtn_ctx* ctx, const std::vector<PersistJob>& jobs, const Ba
   std::vector<uint8_t> host(o_out, 0);
   std::memcpy(&host[o_steps], steps.data(), steps.size() * sizeof(PStep));
   if (!fixes.empty()) std::memcpy(&host[o_fixes], fixes.data(), fixes.size() * sizeof(PFix));
+  if (!slots.empty()) std::memcpy(&host[o_slots], slots.data(), slots.size() * sizeof(PSlot));
   if (!shared_tasks.empty()) std::memcpy(&host[o_stasks], shared_tasks.data(), shared_tasks.size() * sizeof(PTask));
   std::memcpy(&host[o_tasks], tasks.data(), tasks.size() * sizeof(PTask));
   if (!assign.empty()) std::memcpy(&host[o_assign], assign.data(), assign.size());
@@ -175,7 +223,7 @@ void run_persistent(bbtn_ctx* ctx, const std::vector<PersistJob>& jobs, const Ba
   auto shape_for = [&](int64_t n_tasks) {
     const int64_t cus = device_cus();
     const int threads = n_tasks >= 2 * cus ? 64 : (n_tasks >= cus / 4 ? 256 : 1024);
-    const size_t lds = persist_lds_bytes(k, lds_entries, threads);
+    const size_t lds = persist_lds_bytes(k, lds_entries, threads, max_slots);
     const int by_lds = (int)((160u << 10) / std::max<size_t>(lds, 1));
     const int by_waves = 32 / (threads / 64);
     const int per_cu = std::max(1, std::min({16, by_lds, by_waves}));
@@ -193,6 +241,8 @@ void run_persistent(bbtn_ctx* ctx, const std::vector<PersistJob>& jobs, const Ba
   PersistArgs a{};
   a.steps = (const PStep*)(dev + o_steps);
   a.fixes = (const PFix*)(dev + o_fixes);
+  a.slots = (const PSlot*)(dev + o_slots);
+  a.max_slots = max_slots;
   a.assign = dev + o_assign;
   a.base = bd.t.ptr;
   a.base_total = bd.total;

@@ -11,17 +11,25 @@ struct PFix {
   int32_t idx;  // index of the variable in the group's fixed-variable list
 };
 
+// The fixed bits of one base operand of a program: the OR of its fixes,
+// evaluated once per task (slot j of the task's table).
+struct PSlot {
+  int32_t fix_off, n_fix;
+};
+
 // where an operand is read from / an output is written to
 enum PKind { PK_SCRATCH = 0, PK_BASE = 1, PK_SHARED = 2 };
 
+// Offsets of base and shared operands are relative to the task's base_off
+// and shared_off, so that instances with the same contraction tree share one
+// copy of the program.
 struct POperand {
   int32_t kind;      // PKind: workgroup scratch, base tensors or shared region
                      // (src_off = entry offset there)
   int32_t rank;      // rank of the operand in the step's layout
   int64_t src_off;
-  int32_t n_runs, n_fix;
-  int32_t fix_off;   // into the PFix array
-  int32_t pad;
+  int32_t n_runs;
+  int32_t slot;      // fixed-bit slot of a base operand, -1 if none
   int64_t mat_off;   // >= 0: also write the staged operand to scratch here
   // runs of contiguous bits, packed as out_lo | in_lo << 8 | len << 16
   uint32_t runs[P_MAX_RUNS];
@@ -44,14 +52,20 @@ struct PStep {
 // subtree tasks (out_idx < 0) only fill the shared region.
 struct PTask {
   int32_t step_off, n_steps;
+  int32_t slot_off, n_slots;  // fixed-bit slots of the program
   int64_t assign_off;  // byte offset of the branch's fixed states
   int64_t out_idx;     // output slot, or -1
   int64_t root_off;    // scratch entry offset of the root scalar, -1 if none
+  int64_t base_off;    // entry offset of the instance's base tensors
+  int64_t shared_off;  // entry offset of the instance's shared region
 };
 
 struct PersistArgs {
   const PStep* steps;
   const PFix* fixes;
+  const PSlot* slots;
+  int32_t max_slots;  // words of the per-task fixed-bit table in LDS
+  int32_t pad0;
   const PTask* tasks;
   int64_t n_tasks;
   const uint8_t* assign;
@@ -72,7 +86,7 @@ struct PersistArgs {
 };
 
 // workgroup sizes: 64 (one wavefront), 256 or 1024 threads
-size_t persist_lds_bytes(int k, int64_t lds_entries, int threads);
+size_t persist_lds_bytes(int k, int64_t lds_entries, int threads, int slots);
 void launch_persist(int k, const PersistArgs& a, int n_blocks, int threads, hipStream_t st);
 
 }  // namespace bbtn
