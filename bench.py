@@ -35,6 +35,38 @@ VALU_PEAK_OPS = 256 * 64 * 2.4e9
 HBM_PEAK = 8.0e12
 
 
+# Per-launch HBM traffic of the persistent executor, measured by rocprofv3
+# --pmc FETCH_SIZE and WRITE_SIZE on this workload and recorded, with a hash
+# of the kernel sources, in a profiles/ summary; reported only while the
+# sources are unchanged.
+TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "persist_sg16_batch20_hbm_traffic.md")
+PERSIST_SOURCES = [os.path.join(ROOT, "paper_2602_05470_amd", "csrc", f)
+                   for f in ("k_persist.hip", "persist_dev.h", "persist.cpp")]
+
+
+def persist_sources_sha256():
+    import hashlib
+    h = hashlib.sha256()
+    for f in PERSIST_SOURCES:
+        h.update(open(f, "rb").read())
+    return h.hexdigest()
+
+
+def persist_traffic():
+    """HBM bytes per persistent-executor launch, or None when no summary
+    matches the current kernel sources."""
+    if not os.path.exists(TRAFFIC_SUMMARY):
+        return None
+    fields = {}
+    for line in open(TRAFFIC_SUMMARY):
+        if ":" in line and line.strip().startswith(("kernel-sources-sha256", "hbm-bytes-per-launch")):
+            key, val = line.strip().split(":", 1)
+            fields[key.strip()] = val.strip().strip("`")
+    if fields.get("kernel-sources-sha256") != persist_sources_sha256():
+        return None
+    return int(fields["hbm-bytes-per-launch"])
+
+
 def golden_sg16():
     out = {}
     for line in open(os.path.join(ROOT, "tests", "golden", "sg16.txt")):
@@ -115,6 +147,9 @@ def main():
     ap.add_argument("--micro-only", action="store_true",
                     help="only the counting-product micro-benchmark and a copy of known size "
                          "(for hardware-counter runs)")
+    ap.add_argument("--calibration-copy", action="store_true",
+                    help="end with a plain device copy of known size (512 MiB each way), "
+                         "the reference that scales hardware byte counters")
     ap.add_argument("--batched", type=int, default=1)
     ap.add_argument("--workers", type=int, default=4,
                     help="concurrent solver contexts (threads, one stream each): one "
@@ -241,7 +276,7 @@ def main():
         "roofline": {"bound": "alu", "kernel": dom,
                      "achieved": round(achieved / 1e12, 4), "peak": round(VALU_PEAK_OPS / 1e12, 2),
                      "unit": "TOP/s", "frac": round(achieved / VALU_PEAK_OPS, 5),
-                     "traffic": None,
+                     "traffic": persist_traffic() if dom == "persist" else None,
                      "launches": st["launches"],
                      "avg_launch_ms": round(1e3 * st["seconds"] / max(st["launches"], 1), 4),
                      "kernel_busy_share": round(st["seconds"] / dt, 4)},
@@ -277,6 +312,12 @@ def main():
         line["cpu_baseline"] = cpu_baseline(want)
     for c in ctxs:
         c.close()
+    if args.calibration_copy:
+        x = torch.ones(128 << 20, dtype=torch.int32, device="cuda")
+        y = torch.empty_like(x)
+        y.copy_(x)
+        torch.cuda.synchronize()
+        line["calibration_copy_bytes_each_way"] = 512 << 20
     print(json.dumps(line), flush=True)
 
 

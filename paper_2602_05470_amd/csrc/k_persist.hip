@@ -143,13 +143,30 @@ persist_kernel(const PersistArgs a) {
         for (int r = 0; r < P_MAX_RUNS; ++r) rr[r] = op->runs[r];
         const int n = 1 << op->rank;
         const int64_t mat = op->mat_off;
-        for (int e = tid; e < n; e += NTHR) {
-          const uint32_t s = gather_index((uint32_t)e, fixed, nr, rr);
+        // SB entries per thread in flight: all loads of a batch are issued
+        // before the first is used (one round trip to memory per batch
+        // instead of one per entry).  Entries past the end load a valid
+        // entry (the last) and are not stored, so the loads need no branch.
+        constexpr int SB = KR >= 3 ? 4 : 8;
+        for (int e0 = 0; e0 < n; e0 += NTHR * SB) {
+          uint32_t v[SB][W];
 #pragma unroll
-          for (int p = 0; p < W; ++p) {
-            const uint32_t x = src[p * sstride + s];
-            dst[p * cap + e] = x;
-            if (mat >= 0) scr[p * a.scratch_entries + mat + e] = x;
+          for (int u = 0; u < SB; ++u) {
+            const int e = min(e0 + u * NTHR + tid, n - 1);
+            const uint32_t s = gather_index((uint32_t)e, fixed, nr, rr);
+#pragma unroll
+            for (int p = 0; p < W; ++p) v[u][p] = src[p * sstride + s];
+          }
+#pragma unroll
+          for (int u = 0; u < SB; ++u) {
+            const int e = e0 + u * NTHR + tid;
+            if (e < n) {
+#pragma unroll
+              for (int p = 0; p < W; ++p) {
+                dst[p * cap + e] = v[u][p];
+                if (mat >= 0) scr[p * a.scratch_entries + mat + e] = v[u][p];
+              }
+            }
           }
         }
       }
