@@ -13,6 +13,8 @@
 // A program built to keep every intermediate also writes each staged operand
 // to scratch (configuration recovery reads them afterwards).
 // Counts use the same lazy 64-bit accumulation as the tiled product.
+#include <type_traits>
+
 #include "persist_dev.h"
 
 namespace bbtn {
@@ -145,30 +147,38 @@ persist_kernel(const PersistArgs a) {
         const int64_t mat = op->mat_off;
         // SB entries per thread in flight: all loads of a batch are issued
         // before the first is used (one round trip to memory per batch
-        // instead of one per entry).  Entries past the end load a valid
-        // entry (the last) and are not stored, so the loads need no branch.
-        constexpr int SB = KR >= 3 ? 4 : 8;
-        for (int e0 = 0; e0 < n; e0 += NTHR * SB) {
-          uint32_t v[SB][W];
+        // instead of one per entry), SB sized to the operand.  Entries past
+        // the end load a valid entry (the last) and are not stored, so the
+        // loads need no per-lane branch.
+        auto stage = [&](auto sb_tag) {
+          constexpr int SB = decltype(sb_tag)::value;
+          for (int e0 = 0; e0 < n; e0 += NTHR * SB) {
+            uint32_t v[SB][W];
 #pragma unroll
-          for (int u = 0; u < SB; ++u) {
-            const int e = min(e0 + u * NTHR + tid, n - 1);
-            const uint32_t s = gather_index((uint32_t)e, fixed, nr, rr);
+            for (int u = 0; u < SB; ++u) {
+              const int e = min(e0 + u * NTHR + tid, n - 1);
+              const uint32_t s = gather_index((uint32_t)e, fixed, nr, rr);
 #pragma unroll
-            for (int p = 0; p < W; ++p) v[u][p] = src[p * sstride + s];
-          }
+              for (int p = 0; p < W; ++p) v[u][p] = src[p * sstride + s];
+            }
 #pragma unroll
-          for (int u = 0; u < SB; ++u) {
-            const int e = e0 + u * NTHR + tid;
-            if (e < n) {
+            for (int u = 0; u < SB; ++u) {
+              const int e = e0 + u * NTHR + tid;
+              if (e < n) {
 #pragma unroll
-              for (int p = 0; p < W; ++p) {
-                dst[p * cap + e] = v[u][p];
-                if (mat >= 0) scr[p * a.scratch_entries + mat + e] = v[u][p];
+                for (int p = 0; p < W; ++p) {
+                  dst[p * cap + e] = v[u][p];
+                  if (mat >= 0) scr[p * a.scratch_entries + mat + e] = v[u][p];
+                }
               }
             }
           }
-        }
+        };
+        const int per = (n + NTHR - 1) / NTHR;  // entries per thread (uniform)
+        if (per >= 8 && KR < 3) stage(std::integral_constant<int, 8>{});
+        else if (per >= 4) stage(std::integral_constant<int, 4>{});
+        else if (per >= 2) stage(std::integral_constant<int, 2>{});
+        else stage(std::integral_constant<int, 1>{});
       }
       __syncthreads();
       // ---- product

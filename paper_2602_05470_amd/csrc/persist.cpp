@@ -226,7 +226,7 @@ void run_persistent(bbtn_ctx* ctx, const std::vector<PersistJob>& jobs, const Ba
     const size_t lds = persist_lds_bytes(k, lds_entries, threads, max_slots);
     const int by_lds = (int)((160u << 10) / std::max<size_t>(lds, 1));
     const int by_waves = 32 / (threads / 64);
-    const int per_cu = std::max(1, std::min({16, by_lds, by_waves}));
+    const int per_cu = std::max(1, std::min({32, by_lds, by_waves}));
     return Shape{threads, std::min<int64_t>(cus * per_cu, n_tasks)};
   };
   const Shape sh_shared = shape_for((int64_t)shared_tasks.size());
