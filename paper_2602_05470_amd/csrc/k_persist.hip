@@ -75,7 +75,7 @@ template <int KR, int NTHR>
 __global__ void __launch_bounds__(NTHR)
 persist_kernel(const PersistArgs a) {
   constexpr int W = 1 + KR;
-  extern __shared__ uint32_t lds[];
+  extern __shared__ __attribute__((aligned(16))) uint32_t lds[];
   const int cap = (int)a.lds_entries;  // entries per operand buffer
   uint32_t* la = lds;                  // W planes of cap entries
   uint32_t* lb = lds + W * cap;
@@ -185,14 +185,94 @@ persist_kernel(const PersistArgs a) {
       const int rn = sp->rn, rm = sp->rm, rk = sp->rk;
       const int nC = 1 << (sp->rb + rm + rn);
       const int K = 1 << rk;
+      const int c_kind = sp->c_kind;
+      const int64_t c_off = sp->c_off;
+      // wide steps: four consecutive n per thread, so that each q costs one
+      // read of A and one 16-byte read of B for four outputs
+      const bool vec4 = rn >= 2 && (nC >> 2) >= NTHR;
+      if (vec4) {
+        const int nI = nC >> 2;
+        const bool sh = c_kind == PK_SHARED;
+        uint32_t* c = (sh ? shared : scr) + c_off;
+        const int64_t cs = sh ? a.shared_entries : a.scratch_entries;
+        for (int it = tid; it < nI; it += NTHR) {
+          const int o = it << 2;
+          const int nn = o & ((1 << rn) - 1);
+          const int m = (o >> rn) & ((1 << rm) - 1);
+          const int b = o >> (rn + rm);
+          const int abase = (m << rk) | (b << (rk + rm));
+          const int bbase = nn | (b << (rn + rk));
+          const int32_t* Av = (const int32_t*)la + abase;
+          const int32_t* Bv = (const int32_t*)lb + bbase;
+          int32_t V[4] = {INT32_MIN, INT32_MIN, INT32_MIN, INT32_MIN};
+          for (int q = 0; q < K; ++q) {
+            const int32_t av = Av[q];
+            const int4 bv = *(const int4*)(Bv + (q << rn));
+            V[0] = max(V[0], av + bv.x);
+            V[1] = max(V[1], av + bv.y);
+            V[2] = max(V[2], av + bv.z);
+            V[3] = max(V[3], av + bv.w);
+          }
+          uint32_t res[4][KR > 0 ? KR : 1];
+          if constexpr (KR > 0) {
+            uint64_t acc[4][KR];
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+              for (int p = 0; p < KR; ++p) acc[i][p] = 0;
+            if (max(max(V[0], V[1]), max(V[2], V[3])) > NEG_CUT) {
+              // tie test without a compare: x = (V - 1) - a - b is -1 exactly
+              // on a tie and >= 0 otherwise; sums that wrap involve stored
+              // zeros, whose residues are 0
+              uint32_t vm1[4];
+#pragma unroll
+              for (int i = 0; i < 4; ++i) vm1[i] = (uint32_t)V[i] - 1u;
+              for (int q = 0; q < K; ++q) {
+                const uint32_t na = (uint32_t)(-Av[q]);
+                const int4 bv = *(const int4*)(Bv + (q << rn));
+                uint32_t msk[4];
+                msk[0] = (uint32_t)((int32_t)(vm1[0] + na - (uint32_t)bv.x) >> 31);
+                msk[1] = (uint32_t)((int32_t)(vm1[1] + na - (uint32_t)bv.y) >> 31);
+                msk[2] = (uint32_t)((int32_t)(vm1[2] + na - (uint32_t)bv.z) >> 31);
+                msk[3] = (uint32_t)((int32_t)(vm1[3] + na - (uint32_t)bv.w) >> 31);
+#pragma unroll
+                for (int p = 0; p < KR; ++p) {
+                  const uint32_t ac = la[(p + 1) * cap + abase + q];
+                  const uint4 bc = *(const uint4*)(lb + (p + 1) * cap + bbase + (q << rn));
+                  acc[0][p] += (uint64_t)(ac & msk[0]) * bc.x;
+                  acc[1][p] += (uint64_t)(ac & msk[1]) * bc.y;
+                  acc[2][p] += (uint64_t)(ac & msk[2]) * bc.z;
+                  acc[3][p] += (uint64_t)(ac & msk[3]) * bc.w;
+                }
+                // at most three products (< 2^62 each) between folds
+                if (q % 3 == 2) {
+#pragma unroll
+                  for (int i = 0; i < 4; ++i)
+#pragma unroll
+                    for (int p = 0; p < KR; ++p) acc[i][p] = pfold(acc[i][p], a.mod.c[p]);
+                }
+              }
+            }
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+              for (int p = 0; p < KR; ++p) res[i][p] = pmod(acc[i][p], a.mod.p[p], a.mod.c[p]);
+          }
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            const bool fin = V[i] > NEG_CUT;
+            c[o + i] = (uint32_t)(fin ? V[i] : NEG);
+#pragma unroll
+            for (int p = 0; p < KR; ++p) c[(p + 1) * cs + o + i] = fin ? res[i][p] : 0u;
+          }
+        }
+      }
       // threads per output: split K when outputs are few
       int tpo = 1;
       while (tpo * 2 <= NTHR / nC && tpo * 2 <= K) tpo *= 2;
       const int kper = K / tpo;
       const int per_round = NTHR / tpo;
-      const int c_kind = sp->c_kind;
-      const int64_t c_off = sp->c_off;
-      for (int o0 = 0; o0 < nC; o0 += per_round) {
+      for (int o0 = vec4 ? nC : 0; o0 < nC; o0 += per_round) {
         const int o = o0 + tid / tpo;
         const int j = tid % tpo;
         int32_t V = INT32_MIN;
