@@ -1,11 +1,13 @@
 // The opaque context behind bbtn_ctx: device, stream, workspace, caches.
 #pragma once
 #include <map>
+#include <memory>
 #include <mutex>
 #include <string>
 #include <tuple>
 #include "common.h"
 #include "prof.h"
+#include "plan.h"
 #include "tree.h"
 
 namespace bbtn {
@@ -77,8 +79,17 @@ struct bbtn_ctx {
   std::map<bbtn::GraphKey, hipGraphExec_t> graphs;
   // contraction trees by network structure (the variable lists of the
   // simplified tensors, which do not depend on couplings or weights)
-  std::map<std::vector<std::vector<int32_t>>, bbtn::Tree> tree_cache;
-  std::mutex tree_mu;  // planning threads share the cache
+  struct TreeEntry {
+    std::shared_ptr<const bbtn::Tree> tree;
+    uint64_t id;  // unique over the process
+  };
+  std::map<std::vector<std::vector<int32_t>>, TreeEntry> tree_cache;
+  // step programs by (tree id, keep-all, fixed set): they depend on the
+  // network's structure and the fixed variables only
+  std::map<std::tuple<uint64_t, bool, std::vector<uint64_t>>,
+           std::shared_ptr<const bbtn::GroupPlan>>
+      plan_cache;
+  std::mutex tree_mu;  // planning threads share both caches
   // second context (own stream and workspaces) that recovers the optimal
   // configuration while this one runs the counting passes
   bbtn_ctx* aux = nullptr;

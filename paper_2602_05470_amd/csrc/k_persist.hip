@@ -50,31 +50,33 @@ __device__ __forceinline__ void combine(int32_t& v, uint32_t* r, int32_t v2, con
   }
 }
 
-// source index of entry e of a staged operand: the fixed bits plus every run
-// of contiguous bits moved from e into place (runs and count are uniform)
-__device__ __forceinline__ uint32_t gather_index(uint32_t e, uint32_t fixed, int nr,
-                                                 const uint32_t (&rr)[P_MAX_RUNS]) {
-  uint32_t s = fixed;
-#pragma unroll
-  for (int r = 0; r < P_MAX_RUNS; ++r) {
-    if (r < nr) {
-      const uint32_t x = rr[r];
-      const uint32_t ol = x & 255u, il = (x >> 8) & 255u, len = x >> 16;
-      s |= ((e >> ol) & ((1u << len) - 1u)) << il;
-    }
-  }
-  return s;
+// Step programs are read-only during a launch: reading them through the
+// constant address space lets uniform descriptor reads become scalar loads.
+template <class T>
+using kptr = const __attribute__((address_space(4))) T*;
+template <class T>
+__device__ __forceinline__ kptr<T> kconst(const T* p) {
+  return (kptr<T>)p;
 }
+
+template <int N>
+struct Log2 {
+  static constexpr int value = N <= 1 ? 0 : 1 + Log2<N / 2>::value;
+};
+template <>
+struct Log2<1> {
+  static constexpr int value = 0;
+};
 
 // One workgroup per task: one wavefront when tasks are many, 256 or 1024
 // threads when they are few (the steps of a task are then wide enough to use
-// them).  The task index is made uniform, and every descriptor is read
-// through a pointer at a uniform address, so descriptors stay in scalar
-// registers.
+// them).  The task index is made uniform and every descriptor is read at a
+// uniform address, so descriptors stay in scalar registers.
 template <int KR, int NTHR>
 __global__ void __launch_bounds__(NTHR)
 persist_kernel(const PersistArgs a) {
   constexpr int W = 1 + KR;
+  constexpr int LT = Log2<NTHR>::value;
   extern __shared__ __attribute__((aligned(16))) uint32_t lds[];
   const int cap = (int)a.lds_entries;  // entries per operand buffer
   uint32_t* la = lds;                  // W planes of cap entries
@@ -101,24 +103,23 @@ persist_kernel(const PersistArgs a) {
     if (task >= a.n_tasks) break;
     uint32_t* const scr =
         a.per_task_scratch ? a.scratch + task * W * a.scratch_entries : scr_block;
-    const PTask* tk = a.tasks + task;
+    const kptr<PTask> tk = kconst(a.tasks + task);
     const uint8_t* asg = a.assign + tk->assign_off;
     const int32_t n_steps = tk->n_steps;
-    const PStep* sp = a.steps + tk->step_off;
+    kptr<PStep> sp = kconst(a.steps + tk->step_off);
     const uint32_t* const base = a.base + tk->base_off;
     uint32_t* const shared = a.shared + tk->shared_off;
     // the fixed bits of every base operand of the program, from the task's
     // states (once per task instead of once per step)
     const int32_t n_slots = tk->n_slots;
     if (n_slots > 0) {
-      const PSlot* sl = a.slots + tk->slot_off;
+      const kptr<PSlot> sl = kconst(a.slots + tk->slot_off);
+      const kptr<PFix> fxs = kconst(a.fixes);
       for (int j = tid; j < n_slots; j += NTHR) {
-        const PSlot q = sl[j];
+        const int32_t fo = sl[j].fix_off, nf = sl[j].n_fix;
         uint32_t f = 0;
-        for (int i = 0; i < q.n_fix; ++i) {
-          const PFix fx = a.fixes[q.fix_off + i];
-          f |= (uint32_t)(asg[fx.idx] & 1) << fx.pos;
-        }
+        for (int i = 0; i < nf; ++i)
+          f |= (uint32_t)(asg[fxs[fo + i].idx] & 1) << fxs[fo + i].pos;
         fixtab[j] = f;
       }
       __syncthreads();
@@ -128,7 +129,7 @@ persist_kernel(const PersistArgs a) {
       // ---- stage operands
 #pragma unroll
       for (int w = 0; w < 2; ++w) {
-        const POperand* op = w == 0 ? &sp->a : &sp->b;
+        const kptr<POperand> op = w == 0 ? &sp->a : &sp->b;
         uint32_t* dst = w == 0 ? la : lb;
         const int slot = op->slot;
         const uint32_t fixed = slot >= 0 ? fixtab[slot] : 0u;
@@ -139,32 +140,53 @@ persist_kernel(const PersistArgs a) {
         const int64_t sstride = kind == PK_BASE     ? a.base_total
                                 : kind == PK_SHARED ? a.shared_entries
                                                     : a.scratch_entries;
-        const int nr = op->n_runs;
-        uint32_t rr[P_MAX_RUNS];
+        uint32_t pw[P_MAX_RANK / 4];
 #pragma unroll
-        for (int r = 0; r < P_MAX_RUNS; ++r) rr[r] = op->runs[r];
+        for (int i = 0; i < P_MAX_RANK / 4; ++i) pw[i] = op->bitpos[i];
+        // source bit of layout bit j (j a constant after unrolling)
+        auto pos = [&](int j) { return (pw[j >> 2] >> (8 * (j & 3))) & 255u; };
         const int n = 1 << op->rank;
         const int64_t mat = op->mat_off;
-        // SB entries per thread in flight: all loads of a batch are issued
-        // before the first is used (one round trip to memory per batch
-        // instead of one per entry), SB sized to the operand.  Entries past
-        // the end load a valid entry (the last) and are not stored, so the
-        // loads need no per-lane branch.
+        // The layout-to-source index map only moves bits, so it is OR-linear
+        // over disjoint bit sets: entry e = e0 | u * NTHR | tid maps to
+        // map(e0) | map(u * NTHR) | map(tid).  The thread part is formed
+        // once per operand, the batch parts are uniform.  SB entries per
+        // thread are in flight (every load of a batch is issued before the
+        // first is used), SB sized to the operand: n and NTHR are powers of
+        // two and SB divides n / NTHR when n >= NTHR, so the batches cover
+        // the operand exactly; a smaller operand has one batch, whose lanes
+        // past the end load its last entry and store nothing.
+        const uint32_t el = (uint32_t)min(tid, n - 1);
+        uint32_t lo_bits = 0;
+#pragma unroll
+        for (int j = 0; j < LT; ++j) lo_bits |= ((el >> j) & 1u) << pos(j);
         auto stage = [&](auto sb_tag) {
           constexpr int SB = decltype(sb_tag)::value;
+          constexpr int LB = Log2<SB>::value;
+          uint32_t hu[SB];
+#pragma unroll
+          for (int u = 0; u < SB; ++u) {
+            uint32_t h = lo_bits;
+#pragma unroll
+            for (int b = 0; b < LB; ++b)
+              if ((u >> b) & 1) h |= 1u << pos(LT + b);
+            hu[u] = h;
+          }
           for (int e0 = 0; e0 < n; e0 += NTHR * SB) {
+            uint32_t he = fixed;
+#pragma unroll
+            for (int j = LT + LB; j < P_MAX_RANK; ++j) he |= (((uint32_t)e0 >> j) & 1u) << pos(j);
             uint32_t v[SB][W];
 #pragma unroll
             for (int u = 0; u < SB; ++u) {
-              const int e = min(e0 + u * NTHR + tid, n - 1);
-              const uint32_t s = gather_index((uint32_t)e, fixed, nr, rr);
+              const uint32_t s = he | hu[u];
 #pragma unroll
-              for (int p = 0; p < W; ++p) v[u][p] = src[p * sstride + s];
+              for (int p = 0; p < W; ++p) v[u][p] = (src + p * sstride)[s];
             }
 #pragma unroll
             for (int u = 0; u < SB; ++u) {
               const int e = e0 + u * NTHR + tid;
-              if (e < n) {
+              if (SB > 1 || e < n) {  // SB > 1 only when n >= 2 * NTHR
 #pragma unroll
                 for (int p = 0; p < W; ++p) {
                   dst[p * cap + e] = v[u][p];

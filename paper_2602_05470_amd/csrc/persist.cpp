@@ -23,13 +23,7 @@ bool persist_fits(const GroupPlan& g, int k) {
   if (n_slots > 4096) return false;
   int mx = 0;
   for (const Step& s : g.steps) mx = std::max({mx, (int)s.a_vars.size(), (int)s.b_vars.size()});
-  for (const Step& s : g.steps) {
-    const Operand* ops[2] = {&s.a, &s.b};
-    for (const Operand* op : ops)
-      if ((int)op->src_bits.size() > P_MAX_RUNS && make_gather_plan(op->r_in, (int)op->src_bits.size(), op->src_bits.data()).n_runs > P_MAX_RUNS)
-        return false;
-  }
-  return mx <= persist_max_rank(k);
+  return mx <= std::min(persist_max_rank(k), P_MAX_RANK);
 }
 
 namespace {
@@ -93,8 +87,7 @@ void run_persistent(bbtn_ctx* ctx, const std::vector<PersistJob>& jobs, const Ba
           POperand& po = *pops[w];
           const int rank = (int)op.src_bits.size();
           max_rank = std::max<int64_t>(max_rank, rank);
-          const GatherPlan gpn = make_gather_plan(op.r_in, rank, op.src_bits.data());
-          if (gpn.n_runs > P_MAX_RUNS) throw Error(BBTN_E_INTERNAL, "persistent: too many runs");
+          if (rank > P_MAX_RANK) throw Error(BBTN_E_INTERNAL, "persistent: operand rank too large");
           if (op.base) {
             po.kind = PK_BASE;
             po.src_off = jobs[ji].base_off[op.id] - base0;
@@ -106,8 +99,8 @@ void run_persistent(bbtn_ctx* ctx, const std::vector<PersistJob>& jobs, const Ba
             po.src_off = g.buf_off[op.id];
           }
           po.rank = rank;
-          po.n_runs = gpn.n_runs;
-          for (int r = 0; r < gpn.n_runs; ++r) po.runs[r] = pack_run(gpn.runs[r]);
+          for (int j = 0; j < rank; ++j)
+            po.bitpos[j / 4] |= (uint32_t)op.src_bits[j] << (8 * (j % 4));
           // programs that keep everything materialise gathered operands
           po.mat_off = (op.temp >= 0 && g.keep_all) ? g.buf_off[op.temp] : -1;
           po.slot = -1;
@@ -222,12 +215,17 @@ void run_persistent(bbtn_ctx* ctx, const std::vector<PersistJob>& jobs, const Ba
   };
   auto shape_for = [&](int64_t n_tasks) {
     const int64_t cus = device_cus();
-    const int threads = n_tasks >= 2 * cus ? 64 : (n_tasks >= cus / 4 ? 256 : 1024);
-    const size_t lds = persist_lds_bytes(k, lds_entries, threads, max_slots);
-    const int by_lds = (int)((160u << 10) / std::max<size_t>(lds, 1));
-    const int by_waves = 32 / (threads / 64);
-    const int per_cu = std::max(1, std::min({32, by_lds, by_waves}));
-    return Shape{threads, std::min<int64_t>(cus * per_cu, n_tasks)};
+    auto per_cu = [&](int threads) {
+      const size_t lds = persist_lds_bytes(k, lds_entries, threads, max_slots);
+      const int by_lds = (int)((160u << 10) / std::max<size_t>(lds, 1));
+      const int by_waves = 32 / (threads / 64);
+      return std::max(1, std::min({32, by_lds, by_waves}));
+    };
+    int threads = n_tasks >= 2 * cus ? 64 : (n_tasks >= cus / 4 ? 256 : 1024);
+    // one-wave workgroups whose LDS admits fewer than 8 per CU leave the CU
+    // waiting on memory: give each task four waves instead
+    if (threads == 64 && per_cu(64) < 8) threads = 256;
+    return Shape{threads, std::min<int64_t>(cus * per_cu(threads), n_tasks)};
   };
   const Shape sh_shared = shape_for((int64_t)shared_tasks.size());
   const Shape sh_branch = shape_for((int64_t)tasks.size());

@@ -4,7 +4,8 @@
 
 namespace bbtn {
 
-constexpr int P_MAX_RUNS = 16;
+// largest operand rank of a staged operand (bytes of the bit-position table)
+constexpr int P_MAX_RANK = 16;
 
 struct PFix {
   int32_t pos;  // bit position in the base tensor
@@ -28,16 +29,13 @@ struct POperand {
                      // (src_off = entry offset there)
   int32_t rank;      // rank of the operand in the step's layout
   int64_t src_off;
-  int32_t n_runs;
+  int32_t pad;
   int32_t slot;      // fixed-bit slot of a base operand, -1 if none
   int64_t mat_off;   // >= 0: also write the staged operand to scratch here
-  // runs of contiguous bits, packed as out_lo | in_lo << 8 | len << 16
-  uint32_t runs[P_MAX_RUNS];
+  // byte j of the table: the source bit of bit j of the step's layout
+  // (j < rank; zero beyond)
+  uint32_t bitpos[P_MAX_RANK / 4];
 };
-
-inline uint32_t pack_run(const GatherRun& r) {
-  return (uint32_t)r.out_lo | (uint32_t)r.in_lo << 8 | (uint32_t)r.len << 16;
-}
 
 struct PStep {
   int32_t rb, rm, rn, rk;

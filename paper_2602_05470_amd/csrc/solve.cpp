@@ -28,6 +28,52 @@ double now_s() {
   return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
 }
 
+// A contraction tree from the context's cache, with its cache id.
+struct TreeRef {
+  std::shared_ptr<const Tree> tree;
+  uint64_t id = 0;
+};
+
+TreeRef tree_for(bbtn_ctx* ctx, const Network& net) {
+  static std::atomic<uint64_t> next_id{1};
+  std::vector<std::vector<int32_t>> shape;
+  shape.reserve(net.tensors.size() + 1);
+  shape.push_back({net.n});
+  for (const auto& T : net.tensors) shape.push_back(T.vars);
+  {
+    std::lock_guard<std::mutex> lk(ctx->tree_mu);
+    auto it = ctx->tree_cache.find(shape);
+    if (it != ctx->tree_cache.end()) return TreeRef{it->second.tree, it->second.id};
+  }
+  auto tree = std::make_shared<const Tree>(greedy_tree(net));
+  std::lock_guard<std::mutex> lk(ctx->tree_mu);
+  auto it = ctx->tree_cache.find(shape);
+  if (it != ctx->tree_cache.end()) return TreeRef{it->second.tree, it->second.id};
+  if (ctx->tree_cache.size() >= 8) ctx->tree_cache.clear();
+  const uint64_t id = next_id++;
+  ctx->tree_cache.emplace(std::move(shape), bbtn_ctx::TreeEntry{tree, id});
+  return TreeRef{tree, id};
+}
+
+// The step program of fixed set `mask` on tree `t`, from the context's
+// cache (instances with the same structure and fixed set share it).
+std::shared_ptr<const GroupPlan> plan_for(bbtn_ctx* ctx, const Network& net, const TreeRef& t,
+                                          const std::vector<uint64_t>& mask, bool keep_all) {
+  auto key = std::make_tuple(t.id, keep_all, mask);
+  {
+    std::lock_guard<std::mutex> lk(ctx->tree_mu);
+    auto it = ctx->plan_cache.find(key);
+    if (it != ctx->plan_cache.end()) return it->second;
+  }
+  auto plan = std::make_shared<const GroupPlan>(build_plan(net, *t.tree, mask, keep_all));
+  std::lock_guard<std::mutex> lk(ctx->tree_mu);
+  auto it = ctx->plan_cache.find(key);
+  if (it != ctx->plan_cache.end()) return it->second;
+  if (ctx->plan_cache.size() >= 64) ctx->plan_cache.clear();
+  ctx->plan_cache.emplace(std::move(key), plan);
+  return plan;
+}
+
 // Leaves of the search in a flat order: (group, index in group).
 struct LeafRef {
   int32_t group;
@@ -55,7 +101,7 @@ int64_t leaves_per_chunk(bbtn_ctx* ctx, const GroupPlan& g, int k) {
 struct PassItem {
   const Network* net;
   const std::vector<LeafGroup>* groups;
-  std::vector<GroupPlan>* plans;
+  const std::vector<std::shared_ptr<const GroupPlan>>* plans;
   const std::vector<std::vector<int64_t>>* sel;
   PassOut* out;
 };
@@ -110,13 +156,13 @@ void run_pass(bbtn_ctx* ctx, const std::vector<PassItem>& items, const std::vect
   for (size_t ii = 0; ii < items.size(); ++ii)
     for (size_t gi = 0; gi < items[ii].groups->size(); ++gi) {
       const auto& sel = *items[ii].sel;
-      if (!batched || sel[gi].empty() || !persist_fits((*items[ii].plans)[gi], k)) continue;
+      if (!batched || sel[gi].empty() || !persist_fits(*(*items[ii].plans)[gi], k)) continue;
       job_src.push_back({ii, gi});
     }
   job_out.resize(job_src.size());
   for (size_t j = 0; j < job_src.size(); ++j) {
     const size_t ii = job_src[j].first, gi = job_src[j].second;
-    jobs.push_back(PersistJob{&(*items[ii].plans)[gi], items[ii].net, offs[ii].data(),
+    jobs.push_back(PersistJob{(*items[ii].plans)[gi].get(), items[ii].net, offs[ii].data(),
                               asg[ii][gi].data(), (int64_t)(*items[ii].sel)[gi].size(),
                               &job_out[j]});
   }
@@ -135,7 +181,7 @@ void run_pass(bbtn_ctx* ctx, const std::vector<PassItem>& items, const std::vect
     const auto& sel = *it.sel;
     for (size_t gi = 0; gi < it.groups->size(); ++gi) {
       if (sel[gi].empty()) continue;
-      const GroupPlan& g = (*it.plans)[gi];
+      const GroupPlan& g = *(*it.plans)[gi];
       if (batched && persist_fits(g, k)) continue;
       const size_t S = (*it.groups)[gi].vars.size();
       const int64_t chunk = batched ? leaves_per_chunk(ctx, g, k) : 1;
@@ -161,7 +207,7 @@ void run_pass(bbtn_ctx* ctx, const std::vector<PassItem>& items, const std::vect
 // the variables summed out while simplifying, in reverse order.
 struct RecoverItem {
   const Network* net;
-  const Tree* tree;
+  const TreeRef* tree;
   const LeafGroup* G;
   int64_t leaf;
   std::vector<int8_t>* states;
@@ -170,7 +216,8 @@ struct RecoverItem {
 // One traceback launch for the items `idx`, item idx[j] reading its
 // workspace at ws[j].
 void trace_items(bbtn_ctx* ctx, const std::vector<RecoverItem>& items,
-                 const std::vector<GroupPlan>& plans, const std::vector<size_t>& idx,
+                 const std::vector<std::shared_ptr<const GroupPlan>>& plans,
+                 const std::vector<size_t>& idx,
                  const std::vector<const int32_t*>& ws) {
   hipStream_t st = ctx->stream;
   std::vector<TraceStep> ts;
@@ -179,7 +226,7 @@ void trace_items(bbtn_ctx* ctx, const std::vector<RecoverItem>& items,
   size_t asg_bytes = 0;
   int32_t max_steps = 0, max_words = 0, max_vars = 0;
   for (size_t j = 0; j < idx.size(); ++j) {
-    const GroupPlan& g = plans[idx[j]];
+    const GroupPlan& g = *plans[idx[j]];
     ts0[j] = ts.size();
     vars0[j] = vars.size();
     for (const Step& s : g.steps) {
@@ -243,7 +290,7 @@ void recover_configs(bbtn_ctx* ctx, const std::vector<RecoverItem>& items) {
   if (items.empty()) return;
   hipStream_t st = ctx->stream;
   const size_t n_items = items.size();
-  std::vector<GroupPlan> plans(n_items);
+  std::vector<std::shared_ptr<const GroupPlan>> plans(n_items);
   std::vector<const Network*> nets(n_items);
   for (size_t i = 0; i < n_items; ++i) {
     const RecoverItem& it = items[i];
@@ -251,7 +298,7 @@ void recover_configs(bbtn_ctx* ctx, const std::vector<RecoverItem>& items) {
     it.states->assign(it.net->n, -1);
     for (size_t j = 0; j < G.vars.size(); ++j)
       (*it.states)[G.vars[j]] = (int8_t)G.assign[it.leaf * G.vars.size() + j];
-    plans[i] = build_plan(*it.net, *it.tree, G.mask, /*keep_all=*/true);
+    plans[i] = plan_for(ctx, *it.net, *it.tree, G.mask, /*keep_all=*/true);
     nets[i] = it.net;
   }
   const int pidx0 = 0;
@@ -262,8 +309,8 @@ void recover_configs(bbtn_ctx* ctx, const std::vector<RecoverItem>& items) {
   const uint64_t macs0 = ctx->last_macs;
   std::vector<size_t> pers, rest;
   for (size_t i = 0; i < n_items; ++i) {
-    if (plans[i].steps.empty()) continue;
-    if (ctx->opt.batched && persist_fits(plans[i], 0)) pers.push_back(i);
+    if (plans[i]->steps.empty()) continue;
+    if (ctx->opt.batched && persist_fits(*plans[i], 0)) pers.push_back(i);
     else rest.push_back(i);
   }
   if (!pers.empty()) {
@@ -272,7 +319,7 @@ void recover_configs(bbtn_ctx* ctx, const std::vector<RecoverItem>& items) {
     std::vector<PersistJob> jobs;
     for (size_t j = 0; j < pers.size(); ++j) {
       const RecoverItem& it = items[pers[j]];
-      jobs.push_back(PersistJob{&plans[pers[j]], it.net, offs[pers[j]].data(),
+      jobs.push_back(PersistJob{plans[pers[j]].get(), it.net, offs[pers[j]].data(),
                                 &it.G->assign[it.leaf * it.G->vars.size()], 1, &outs[j]});
     }
     int64_t scratch = 0;
@@ -291,7 +338,7 @@ void recover_configs(bbtn_ctx* ctx, const std::vector<RecoverItem>& items) {
     bdi.t = bd.t;
     ctx->leafout.ensure(64);
     const DevTensor o{ctx->leafout.as<uint32_t>(), 1};
-    run_group(ctx, *it.net, plans[i], bdi, mod, &it.G->assign[it.leaf * it.G->vars.size()], 1, o,
+    run_group(ctx, *it.net, *plans[i], bdi, mod, &it.G->assign[it.leaf * it.G->vars.size()], 1, o,
               st);
     trace_items(ctx, items, plans, {i}, {ctx->work.as<int32_t>()});
   }
@@ -335,23 +382,6 @@ bbtn_ctx* aux_context(bbtn_ctx* ctx) {
   return ctx->aux;
 }
 
-Tree tree_for(bbtn_ctx* ctx, const Network& net) {
-  std::vector<std::vector<int32_t>> shape;
-  shape.reserve(net.tensors.size() + 1);
-  shape.push_back({net.n});
-  for (const auto& T : net.tensors) shape.push_back(T.vars);
-  {
-    std::lock_guard<std::mutex> lk(ctx->tree_mu);
-    auto it = ctx->tree_cache.find(shape);
-    if (it != ctx->tree_cache.end()) return it->second;
-  }
-  Tree tree = greedy_tree(net);
-  std::lock_guard<std::mutex> lk(ctx->tree_mu);
-  if (ctx->tree_cache.size() >= 8) ctx->tree_cache.clear();
-  ctx->tree_cache.emplace(std::move(shape), tree);
-  return tree;
-}
-
 // Run f(i) for i in [0, n) on up to `threads` host threads.
 template <class F>
 void parallel_for(size_t n, int threads, F&& f) {
@@ -372,9 +402,9 @@ void parallel_for(size_t n, int threads, F&& f) {
 
 // Pipeline state of one instance.
 struct Work {
-  Tree tree;
+  TreeRef tree;
   std::vector<LeafGroup> groups;
-  std::vector<GroupPlan> plans;
+  std::vector<std::shared_ptr<const GroupPlan>> plans;
   SearchStats stats;
   int64_t incumbent = INT64_MIN;
   bool active = true;
@@ -446,11 +476,11 @@ void solve_instances(bbtn_ctx* ctx, std::vector<Instance>& insts) {
         so.incumbent = w.incumbent;
         so.values_only = values_only;
         so.deadline = deadline;
-        if (scored) so.scorer = make_var_scorer(ctx, in.net, w.tree, opt.log2_target);
-        bb_search(in.net, w.tree, so, w.groups, w.stats);
+        if (scored) so.scorer = make_var_scorer(ctx, in.net, *w.tree.tree, opt.log2_target);
+        bb_search(in.net, *w.tree.tree, so, w.groups, w.stats);
       }
       const double c = now_s();
-      for (auto& G : w.groups) w.plans.push_back(build_plan(in.net, w.tree, G.mask, false));
+      for (auto& G : w.groups) w.plans.push_back(plan_for(ctx, in.net, w.tree, G.mask, false));
       w.t_build = (b - a) + (now_s() - c);
       w.t_search = c - b;
       w.all_sel.resize(w.groups.size());
