@@ -126,6 +126,8 @@ void bbtn_destroy(bbtn_ctx* ctx) {
   ctx->leafout.release();
   ctx->misc.release();
   ctx->persist.release();
+  ctx->pin_base.release();
+  ctx->pin_persist.release();
   ctx->clear_graphs();
   if (ctx->own) (void)hipStreamDestroy(ctx->own);
   bbtn_destroy(ctx->aux);

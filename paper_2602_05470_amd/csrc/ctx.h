@@ -39,6 +39,34 @@ struct DevBuf {
   T* as() const { return (T*)p; }
 };
 
+// Growable pinned host staging buffer for host-to-device uploads (contents
+// are not preserved on growth).  The caller keeps it untouched until the
+// copies queued from it have completed.
+struct PinBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  void ensure(size_t b) {
+    if (b <= bytes) return;
+    if (p) (void)hipHostFree(p);
+    p = nullptr;
+    bytes = 0;
+    size_t want = std::max<size_t>(b + b / 4, 1 << 20);
+    if (hipHostMalloc(&p, want, hipHostMallocDefault) != hipSuccess) {
+      p = nullptr;
+      (void)hipGetLastError();
+      throw Error(BBTN_E_OOM, "pinned host allocation of " + std::to_string(want) + " bytes failed");
+    }
+    bytes = want;
+  }
+  void release() {
+    if (p) (void)hipHostFree(p);
+    p = nullptr;
+    bytes = 0;
+  }
+  template <class T>
+  T* as() const { return (T*)p; }
+};
+
 // Captured step programs: keyed by the program, its batch, residues and
 // every device pointer the launches bake in.
 using GraphKey = std::tuple<const void*, int64_t, int, void*, void*, void*, void*, void*, void*,
@@ -67,6 +95,8 @@ struct bbtn_ctx {
   bbtn::DevBuf leafout;   // per-branch results
   bbtn::DevBuf misc;      // small scratch (merge outputs, traceback)
   bbtn::DevBuf persist;   // persistent executor programs and scratch
+  bbtn::PinBuf pin_base;    // staging of the base tensors of a pass
+  bbtn::PinBuf pin_persist; // staging of a persistent launch's program
   uint64_t last_macs = 0;
   std::map<bbtn::TuneKey, bbtn::TuneVal> tune;
   bool tune_loaded = false;

@@ -43,20 +43,26 @@ void upload_bases(bbtn_ctx* ctx, const std::vector<const Network*>& nets, const 
     }
   }
   bd.total = std::max<int64_t>(total, 1);
-  std::vector<uint32_t> host((size_t)(1 + k) * bd.total, 0);
+  // staged in pinned memory: the copy is asynchronous, and the staging
+  // buffer is next written after a later synchronisation of the stream
+  const size_t words = (size_t)(1 + k) * bd.total;
+  BBTN_HIP(hipStreamSynchronize(ctx->stream));
+  ctx->pin_base.ensure(words * 4);
+  uint32_t* host = ctx->pin_base.as<uint32_t>();
   for (size_t i = 0; i < nets.size(); ++i)
     for (size_t t = 0; t < nets[i]->tensors.size(); ++t) {
       const BaseTensor& T = nets[i]->tensors[t];
-      for (int64_t e = 0; e < T.size(); ++e) {
-        host[offs[i][t] + e] = (uint32_t)T.val[e];
-        for (int p = 0; p < k; ++p)
-          host[(size_t)(p + 1) * bd.total + offs[i][t] + e] =
-              T.res[(size_t)prime_idx[p] * T.size() + e];
-      }
+      const int64_t n = T.size();
+      uint32_t* dst = host + offs[i][t];
+      std::memcpy(dst, T.val.data(), (size_t)n * 4);
+      for (int p = 0; p < k; ++p)
+        std::memcpy(dst + (size_t)(p + 1) * bd.total, &T.res[(size_t)prime_idx[p] * n],
+                    (size_t)n * 4);
     }
-  buf.ensure(host.size() * 4);
-  BBTN_HIP(hipMemcpyAsync(buf.p, host.data(), host.size() * 4, hipMemcpyHostToDevice, ctx->stream));
-  BBTN_HIP(hipStreamSynchronize(ctx->stream));
+  if (total == 0)
+    for (size_t p = 0; p < words; ++p) host[p] = 0;
+  buf.ensure(words * 4);
+  BBTN_HIP(hipMemcpyAsync(buf.p, host, words * 4, hipMemcpyHostToDevice, ctx->stream));
   bd.t = DevTensor{buf.as<uint32_t>(), bd.total};
 }
 

@@ -103,8 +103,16 @@ persist_kernel(const PersistArgs a) {
     if (task >= a.n_tasks) break;
     uint32_t* const scr =
         a.per_task_scratch ? a.scratch + task * W * a.scratch_entries : scr_block;
-    const kptr<PTask> tk = kconst(a.tasks + task);
-    const uint8_t* asg = a.assign + tk->assign_off;
+    // the run holding the task (uniform binary search over the runs)
+    int64_t lo = 0, hi = a.n_runs - 1;
+    while (lo < hi) {
+      const int64_t mid = (lo + hi + 1) >> 1;
+      if (kconst(a.tasks + mid)->first <= task) lo = mid;
+      else hi = mid - 1;
+    }
+    const kptr<PTask> tk = kconst(a.tasks + lo);
+    const int64_t ti = task - tk->first;
+    const uint8_t* asg = a.assign + tk->assign_off + ti * tk->assign_stride;
     const int32_t n_steps = tk->n_steps;
     kptr<PStep> sp = kconst(a.steps + tk->step_off);
     const uint32_t* const base = a.base + tk->base_off;
@@ -361,7 +369,7 @@ persist_kernel(const PersistArgs a) {
       __syncthreads();
     }
     // ---- branch result = root (.) folded constant
-    const int64_t l = tk->out_idx;
+    const int64_t l = tk->out_idx >= 0 ? tk->out_idx + ti : -1;
     const int64_t root_off = tk->root_off;
     if (tid == 0 && l >= 0) {
       const int32_t cv = (int32_t)a.lconst[l];

@@ -58,6 +58,16 @@ void run_persistent(bbtn_ctx* ctx, const std::vector<PersistJob>& jobs, const Ba
     int32_t step_off, n_steps, slot_off, n_slots;
   };
   std::map<std::string, ProgRef> seen;
+  // programs already emitted per plan: a job with the same plan and the
+  // same base-tensor layout (offsets relative to its first tensor) reuses
+  // them without emitting again
+  struct Emitted {
+    std::vector<int64_t> rel;  // base offsets relative to the first tensor
+    std::vector<ProgRef> shared;
+    ProgRef branch;
+  };
+  std::map<const GroupPlan*, Emitted> emitted;
+  int64_t n_branch_tasks = 0;
   for (size_t ji = 0; ji < jobs.size(); ++ji) {
     const GroupPlan& g = *jobs[ji].plan;
     const int64_t shared_base = shared_total;
@@ -65,8 +75,15 @@ void run_persistent(bbtn_ctx* ctx, const std::vector<PersistJob>& jobs, const Ba
     scratch = std::max<int64_t>(scratch, std::max(g.peak, g.subtree_peak));
     const Network& net = *jobs[ji].net;
     const int64_t base0 = net.tensors.empty() ? 0 : jobs[ji].base_off[0];
-    std::vector<int> pos_of(net.n, -1);
-    for (size_t j = 0; j < g.fixed_vars.size(); ++j) pos_of[g.fixed_vars[j]] = (int)j;
+    std::vector<int64_t> rel(net.tensors.size());
+    for (size_t t = 0; t < rel.size(); ++t) rel[t] = jobs[ji].base_off[t] - base0;
+    auto hit = emitted.find(&g);
+    const bool reuse = hit != emitted.end() && hit->second.rel == rel;
+    std::vector<int> pos_of;
+    if (!reuse) {
+      pos_of.assign(net.n, -1);
+      for (size_t j = 0; j < g.fixed_vars.size(); ++j) pos_of[g.fixed_vars[j]] = (int)j;
+    }
     // a program: steps, their fixed-bit slots and fixes (offsets relative to
     // the program), deduplicated by content
     auto emit_program = [&](const std::vector<const Step*>& prog) {
@@ -128,37 +145,51 @@ void run_persistent(bbtn_ctx* ctx, const std::vector<PersistJob>& jobs, const Ba
       return pr;
     };
     // shared subtrees: one task each, run before any branch
-    for (auto& rg : g.shared_ranges) {
+    std::vector<ProgRef> shared_refs;
+    ProgRef branch_ref;
+    if (reuse) {
+      shared_refs = hit->second.shared;
+      branch_ref = hit->second.branch;
+    } else {
+      for (auto& rg : g.shared_ranges) {
+        std::vector<const Step*> prog;
+        for (int i = rg.first; i < rg.second; ++i) prog.push_back(&g.steps[i]);
+        shared_refs.push_back(emit_program(prog));
+      }
       std::vector<const Step*> prog;
-      for (int i = rg.first; i < rg.second; ++i) prog.push_back(&g.steps[i]);
-      const ProgRef pr = emit_program(prog);
+      for (const Step& s : g.steps)
+        if (!s.shared) prog.push_back(&s);
+      branch_ref = emit_program(prog);
+      if (hit == emitted.end()) emitted.emplace(&g, Emitted{rel, shared_refs, branch_ref});
+    }
+    for (const ProgRef& pr : shared_refs) {
       PTask t{};
       t.step_off = pr.step_off;
       t.n_steps = pr.n_steps;
       t.slot_off = pr.slot_off;
       t.n_slots = pr.n_slots;
+      t.first = (int64_t)shared_tasks.size();
       t.assign_off = 0;
+      t.assign_stride = 0;
       t.out_idx = -1;
       t.root_off = -1;
       t.base_off = base0;
       t.shared_off = shared_base;
       shared_tasks.push_back(t);
     }
-    // the branch program
-    std::vector<const Step*> prog;
-    for (const Step& s : g.steps)
-      if (!s.shared) prog.push_back(&s);
-    const ProgRef pr = emit_program(prog);
+    // the branches: one run of L tasks
     const size_t S = g.fixed_vars.size();
     out_base[ji] = n_out;
-    for (int64_t l = 0; l < jobs[ji].L; ++l) {
+    if (jobs[ji].L > 0) {
       PTask t{};
-      t.step_off = pr.step_off;
-      t.n_steps = pr.n_steps;
-      t.slot_off = pr.slot_off;
-      t.n_slots = pr.n_slots;
-      t.assign_off = (int64_t)assign.size() + (int64_t)(l * S);
-      t.out_idx = n_out + l;
+      t.step_off = branch_ref.step_off;
+      t.n_steps = branch_ref.n_steps;
+      t.slot_off = branch_ref.slot_off;
+      t.n_slots = branch_ref.n_slots;
+      t.first = n_branch_tasks;
+      t.assign_off = (int64_t)assign.size();
+      t.assign_stride = (int64_t)S;
+      t.out_idx = n_out;
       t.root_off = g.root_buf >= 0 ? g.buf_off[g.root_buf] : -1;
       t.base_off = base0;
       t.shared_off = shared_base;
@@ -166,6 +197,7 @@ void run_persistent(bbtn_ctx* ctx, const std::vector<PersistJob>& jobs, const Ba
     }
     assign.insert(assign.end(), jobs[ji].assign, jobs[ji].assign + jobs[ji].L * S);
     n_out += jobs[ji].L;
+    n_branch_tasks += jobs[ji].L;
   }
   if (tasks.empty()) return;
   // folded constants per branch, gathered into (1 + k) planes of n_out
@@ -194,7 +226,12 @@ void run_persistent(bbtn_ctx* ctx, const std::vector<PersistJob>& jobs, const Ba
   const size_t o_out = off; off = align_up(off + lconst.size() * 4);
   const size_t o_queue = off; off = align_up(off + 16);
   const size_t o_shared = off; off = align_up(off + (size_t)W * std::max<int64_t>(shared_total, 1) * 4);
-  std::vector<uint8_t> host(o_out, 0);
+  // staged in pinned memory (written only after the previous launch's
+  // results were read back, which synchronised the stream)
+  BBTN_HIP(hipStreamSynchronize(st));
+  ctx->pin_persist.ensure(o_out);
+  uint8_t* host = ctx->pin_persist.as<uint8_t>();
+  std::memset(host, 0, o_out);
   std::memcpy(&host[o_steps], steps.data(), steps.size() * sizeof(PStep));
   if (!fixes.empty()) std::memcpy(&host[o_fixes], fixes.data(), fixes.size() * sizeof(PFix));
   if (!slots.empty()) std::memcpy(&host[o_slots], slots.data(), slots.size() * sizeof(PSlot));
@@ -204,7 +241,7 @@ void run_persistent(bbtn_ctx* ctx, const std::vector<PersistJob>& jobs, const Ba
   std::memcpy(&host[o_lconst], lconst.data(), lconst.size() * 4);
   ctx->persist.ensure(off);
   uint8_t* dev = ctx->persist.as<uint8_t>();
-  BBTN_HIP(hipMemcpyAsync(dev, host.data(), host.size(), hipMemcpyHostToDevice, st));
+  BBTN_HIP(hipMemcpyAsync(dev, host, o_out, hipMemcpyHostToDevice, st));
   // launch shape per launch: one-wave workgroups when tasks are plentiful,
   // wider ones when they are few; as many per CU as LDS and the wave limit
   // allow, never more than tasks
@@ -228,11 +265,11 @@ void run_persistent(bbtn_ctx* ctx, const std::vector<PersistJob>& jobs, const Ba
     return Shape{threads, std::min<int64_t>(cus * per_cu(threads), n_tasks)};
   };
   const Shape sh_shared = shape_for((int64_t)shared_tasks.size());
-  const Shape sh_branch = shape_for((int64_t)tasks.size());
+  const Shape sh_branch = shape_for(n_branch_tasks);
   int64_t most = std::max<int64_t>(shared_tasks.empty() ? 0 : sh_shared.blocks, sh_branch.blocks);
   if (per_task_scratch) {
     BBTN_REQUIRE(shared_tasks.empty(), "per-task scratch takes programs without shared steps");
-    most = (int64_t)tasks.size();
+    most = n_branch_tasks;
   }
   ctx->work.ensure((size_t)most * W * scratch * 4);
   if (scratch_entries) *scratch_entries = scratch;
@@ -268,12 +305,14 @@ void run_persistent(bbtn_ctx* ctx, const std::vector<PersistJob>& jobs, const Ba
   if (!shared_tasks.empty()) {
     // shared subtrees first, then the branches (stream order separates them)
     a.tasks = (const PTask*)(dev + o_stasks);
+    a.n_runs = (int64_t)shared_tasks.size();
     a.n_tasks = (int64_t)shared_tasks.size();
     a.queue = (unsigned long long*)(dev + o_queue);
     launch_persist(k, a, (int)sh_shared.blocks, sh_shared.threads, st);
   }
   a.tasks = (const PTask*)(dev + o_tasks);
-  a.n_tasks = (int64_t)tasks.size();
+  a.n_runs = (int64_t)tasks.size();
+  a.n_tasks = n_branch_tasks;
   a.queue = (unsigned long long*)(dev + o_queue + 8);
   launch_persist(k, a, (int)sh_branch.blocks, sh_branch.threads, st);
   ctx->prof.end(ph, st, K_PERSIST, ops, bytes);

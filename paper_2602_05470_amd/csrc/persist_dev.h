@@ -45,17 +45,21 @@ struct PStep {
   POperand a, b;
 };
 
-// A task runs steps [step_off, step_off + n_steps).  Branch tasks
-// (out_idx >= 0) then write root (.) folded constant to out[out_idx]; shared
-// subtree tasks (out_idx < 0) only fill the shared region.
+// A run of consecutive tasks of one program (steps [step_off,
+// step_off + n_steps)): task first + i reads its fixed states at
+// assign_off + i * assign_stride and, in a branch run (out_idx >= 0), writes
+// root (.) folded constant to out[out_idx + i]; a shared-subtree run
+// (out_idx < 0) only fills the shared region.
 struct PTask {
   int32_t step_off, n_steps;
   int32_t slot_off, n_slots;  // fixed-bit slots of the program
-  int64_t assign_off;  // byte offset of the branch's fixed states
-  int64_t out_idx;     // output slot, or -1
-  int64_t root_off;    // scratch entry offset of the root scalar, -1 if none
-  int64_t base_off;    // entry offset of the instance's base tensors
-  int64_t shared_off;  // entry offset of the instance's shared region
+  int64_t first;          // global index of the run's first task
+  int64_t assign_off;     // byte offset of the first task's fixed states
+  int64_t assign_stride;  // bytes of fixed states per task
+  int64_t out_idx;        // output slot of the first task, or -1
+  int64_t root_off;       // scratch entry offset of the root scalar, -1 if none
+  int64_t base_off;       // entry offset of the instance's base tensors
+  int64_t shared_off;     // entry offset of the instance's shared region
 };
 
 struct PersistArgs {
@@ -64,8 +68,9 @@ struct PersistArgs {
   const PSlot* slots;
   int32_t max_slots;  // words of the per-task fixed-bit table in LDS
   int32_t pad0;
-  const PTask* tasks;
-  int64_t n_tasks;
+  const PTask* tasks;  // runs, ascending by first
+  int64_t n_runs;
+  int64_t n_tasks;     // tasks over all runs
   const uint8_t* assign;
   const uint32_t* base;
   int64_t base_total;

@@ -10,6 +10,7 @@
 #include <cmath>
 #include <cstring>
 #include <future>
+#include <map>
 #include <mutex>
 #include <thread>
 
@@ -225,8 +226,24 @@ void trace_items(bbtn_ctx* ctx, const std::vector<RecoverItem>& items,
   std::vector<size_t> ts0(idx.size()), vars0(idx.size()), asg0(idx.size());
   size_t asg_bytes = 0;
   int32_t max_steps = 0, max_words = 0, max_vars = 0;
+  std::vector<size_t> ts_n(idx.size()), vars_n(idx.size());
+  // items with the same plan share one copy of its steps and variables
+  std::map<const GroupPlan*, size_t> first_of;
   for (size_t j = 0; j < idx.size(); ++j) {
     const GroupPlan& g = *plans[idx[j]];
+    const int32_t n = items[idx[j]].net->n;
+    asg0[j] = asg_bytes;
+    asg_bytes += (size_t)n;
+    max_vars = std::max<int32_t>(max_vars, n);
+    auto hit = first_of.find(&g);
+    if (hit != first_of.end()) {
+      ts0[j] = ts0[hit->second];
+      vars0[j] = vars0[hit->second];
+      ts_n[j] = ts_n[hit->second];
+      vars_n[j] = vars_n[hit->second];
+      continue;
+    }
+    first_of.emplace(&g, j);
     ts0[j] = ts.size();
     vars0[j] = vars.size();
     for (const Step& s : g.steps) {
@@ -239,12 +256,10 @@ void trace_items(bbtn_ctx* ctx, const std::vector<RecoverItem>& items,
       vars.insert(vars.end(), s.b_vars.begin(), s.b_vars.end());
       ts.push_back(t);
     }
-    const int32_t n = items[idx[j]].net->n;
-    asg0[j] = asg_bytes;
-    asg_bytes += (size_t)n;
-    max_steps = std::max<int32_t>(max_steps, (int32_t)(ts.size() - ts0[j]));
-    max_words = std::max<int32_t>(max_words, (int32_t)(vars.size() - vars0[j]));
-    max_vars = std::max<int32_t>(max_vars, n);
+    ts_n[j] = ts.size() - ts0[j];
+    vars_n[j] = vars.size() - vars0[j];
+    max_steps = std::max<int32_t>(max_steps, (int32_t)ts_n[j]);
+    max_words = std::max<int32_t>(max_words, (int32_t)vars_n[j]);
   }
   auto al = [](size_t b) { return (b + 255) / 256 * 256; };
   const size_t off_j = 0;
@@ -264,8 +279,8 @@ void trace_items(bbtn_ctx* ctx, const std::vector<RecoverItem>& items,
     jb.ws = ws[j];
     jb.assign = (int8_t*)(base + off_a) + asg0[j];
     jb.status = (int32_t*)(base + off_s) + j;
-    jb.n_steps = (int32_t)((j + 1 < idx.size() ? ts0[j + 1] : ts.size()) - ts0[j]);
-    jb.n_var_words = (int32_t)((j + 1 < idx.size() ? vars0[j + 1] : vars.size()) - vars0[j]);
+    jb.n_steps = (int32_t)ts_n[j];
+    jb.n_var_words = (int32_t)vars_n[j];
     jb.n_vars = items[idx[j]].net->n;
     std::memcpy(&host[off_a + asg0[j]], items[idx[j]].states->data(), (size_t)jb.n_vars);
   }

@@ -42,8 +42,22 @@ def larger():
             f.flush()
 
 
+def sg16_more():
+    """Further 16x16 seeds (20-319) for throughput runs over many distinct
+    instances (C transfer matrix)."""
+    with open(os.path.join(HERE, "sg16_more.txt"), "w") as f:
+        f.write("# +-J spin glass 16x16 open lattice, zero field, seeds 20-319:\n")
+        f.write("# seed E0 degeneracy  (oracle: exact transfer matrix, C)\n")
+        for s in range(20, 320):
+            g = I.spin_glass_square(16, s)
+            e0, deg = tm_c.spin_glass_lattice(16, 16, g["edges"], g["J"])
+            f.write("%d %d %d\n" % (s, e0, deg))
+            f.flush()
+
+
 def main():
     larger()
+    sg16_more()
     with open(os.path.join(HERE, "sg16.txt"), "w") as f:
         f.write("# +-J spin glass 16x16 open lattice, zero field, seeds 0-19:\n")
         f.write("# seed E0 degeneracy  (oracle: exact transfer matrix)\n")
