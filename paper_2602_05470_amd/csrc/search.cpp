@@ -166,64 +166,88 @@ struct Searcher {
     double gamma = INFINITY;
     std::vector<int32_t> region;
     std::vector<Cube> cubes;
-    std::unordered_map<uint32_t, int64_t> drho;  // rho reduction per fixed subset
+    // rho reduction per fixed subset of the region (few distinct subsets)
+    std::vector<std::pair<uint32_t, int64_t>> drho;
+    const int64_t* drho_of(uint32_t mask) const {
+      for (const auto& d : drho)
+        if (d.first == mask) return &d.second;
+      return nullptr;
+    }
   };
+
+  // evaluation scratch, reused across calls (one search runs on one thread)
+  std::vector<int32_t> e_tt;                 // tensors touching the region
+  std::vector<int32_t> e_rpos, e_rpos_off;   // region position of each tensor var, or -1
+  std::vector<char> e_inside;                // tensor has no free variable outside R
+  std::vector<int64_t> e_base;               // tensor's largest consistent entry at the node
+  std::vector<int32_t> e_tpos, e_tpos_off;   // region positions of a tensor's region vars
+  std::vector<int64_t> e_tval;               // largest entry per state of those vars
+  std::vector<int64_t> e_tval_off;
+  std::vector<int64_t> e_local, e_bnd, e_gmax;
+  std::vector<char> e_taken;
+  std::vector<uint32_t> e_masks;
+  std::vector<uint64_t> e_keys;
+  std::vector<int32_t> e_vs;
 
   Eval evaluate(const Node& n, const std::vector<int32_t>& R) {
     Eval ev;
     ev.region = R;
     const int r = (int)R.size();
-    std::vector<int32_t> tt;
+    std::vector<int32_t>& tt = e_tt;
+    tt.clear();
     for (int v : R) tt.insert(tt.end(), var_tensors[v].begin(), var_tensors[v].end());
     std::sort(tt.begin(), tt.end());
     tt.erase(std::unique(tt.begin(), tt.end()), tt.end());
+    const size_t nt = tt.size();
     // per touching tensor: region positions of its vars; inside/cross; base max
-    std::vector<std::vector<int32_t>> rpos(tt.size());
-    std::vector<char> inside(tt.size(), 1);
-    std::vector<int64_t> base_max(tt.size());
+    e_rpos.clear();
+    e_rpos_off.assign(nt + 1, 0);
+    e_inside.assign(nt, 1);
+    e_base.resize(nt);
     uint32_t bmask = 0;
-    for (size_t i = 0; i < tt.size(); ++i) {
+    for (size_t i = 0; i < nt; ++i) {
       const BaseTensor& T = net.tensors[tt[i]];
-      rpos[i].assign(T.vars.size(), -1);
+      e_rpos_off[i] = (int32_t)e_rpos.size();
       bool cross = false;
       for (size_t j = 0; j < T.vars.size(); ++j) {
         const int v = T.vars[j];
-        auto it = std::find(R.begin(), R.end(), v);
-        if (it != R.end()) rpos[i][j] = (int)(it - R.begin());
-        else if (!bit_get(n.fixed, v)) cross = true;
+        int pos = -1;
+        for (int q = 0; q < r; ++q)
+          if (R[q] == v) { pos = q; break; }
+        e_rpos.push_back(pos);
+        if (pos < 0 && !bit_get(n.fixed, v)) cross = true;
       }
-      inside[i] = !cross;
+      e_inside[i] = !cross;
       if (cross)
         for (size_t j = 0; j < T.vars.size(); ++j)
-          if (rpos[i][j] >= 0) bmask |= 1u << rpos[i][j];
-      base_max[i] = tensor_max(T, n.fixed, n.x);
+          if (e_rpos[e_rpos_off[i] + j] >= 0) bmask |= 1u << e_rpos[e_rpos_off[i] + j];
+      e_base[i] = tensor_max(T, n.fixed, n.x);
     }
+    e_rpos_off[nt] = (int32_t)e_rpos.size();
     const uint32_t nx = 1u << r;
     // per touching tensor: table of its largest consistent entry over the
     // states of its region variables (at most 2^|T| entries), so that every
     // region configuration costs one table lookup per tensor
-    struct Tab {
-      std::vector<int32_t> pos;   // region positions of the tensor's region vars
-      std::vector<int64_t> val;   // indexed by those bits
-      bool inside;
-      int64_t base;
-    };
-    std::vector<Tab> tabs(tt.size());
-    for (size_t i = 0; i < tt.size(); ++i) {
+    e_tpos.clear();
+    e_tpos_off.assign(nt + 1, 0);
+    e_tval.clear();
+    e_tval_off.assign(nt + 1, 0);
+    for (size_t i = 0; i < nt; ++i) {
       const BaseTensor& T = net.tensors[tt[i]];
-      Tab& tb = tabs[i];
-      tb.inside = inside[i];
-      tb.base = base_max[i];
-      std::vector<int32_t> jr;  // tensor positions that are region vars
+      const int32_t* rp = &e_rpos[e_rpos_off[i]];
+      e_tpos_off[i] = (int32_t)e_tpos.size();
       for (size_t j = 0; j < T.vars.size(); ++j)
-        if (rpos[i][j] >= 0) { jr.push_back((int)j); tb.pos.push_back(rpos[i][j]); }
-      tb.val.assign((size_t)1 << jr.size(), INT64_MIN);
-      for (uint32_t y = 0; y < (1u << jr.size()); ++y) {
+        if (rp[j] >= 0) e_tpos.push_back(rp[j]);
+      const int nj = (int)e_tpos.size() - e_tpos_off[i];
+      e_tval_off[i] = (int64_t)e_tval.size();
+      for (uint32_t y = 0; y < (1u << nj); ++y) {
         uint32_t rx = 0;
-        for (size_t q = 0; q < jr.size(); ++q) rx |= ((y >> q) & 1u) << tb.pos[q];
-        tb.val[y] = tensor_max(T, n.fixed, n.x, rpos[i].data(), rx);
+        for (int q = 0; q < nj; ++q) rx |= ((y >> q) & 1u) << e_tpos[e_tpos_off[i] + q];
+        e_tval.push_back(tensor_max(T, n.fixed, n.x, rp, rx));
       }
     }
+    e_tpos_off[nt] = (int32_t)e_tpos.size();
+    e_tval_off[nt] = (int64_t)e_tval.size();
     // Nothing can be pruned when every region variable is on the boundary
     // (boundary equivalence has one configuration per boundary state), no
     // tensor has an infeasible entry under any region state, and even the
@@ -232,73 +256,77 @@ struct Searcher {
     {
       bool may_prune = bmask != nx - 1;
       int64_t minb = n.bound;
-      for (const Tab& tb : tabs) {
+      for (size_t i = 0; i < nt; ++i) {
         int64_t mn = INT64_MAX;
-        for (int64_t v : tb.val) mn = std::min(mn, v);
+        for (int64_t q = e_tval_off[i]; q < e_tval_off[i + 1]; ++q) mn = std::min(mn, e_tval[q]);
         if (mn == INT64_MIN) { may_prune = true; break; }
-        minb += mn - tb.base;
+        minb += mn - e_base[i];
       }
       if (!may_prune && (opt.values_only ? minb > opt.incumbent : minb >= opt.incumbent)) {
         ev.cubes.reserve(nx);
         for (uint32_t x = 0; x < nx; ++x) ev.cubes.push_back(Cube{nx - 1, x});
-        std::vector<int32_t> vs(R.begin(), R.end());
-        const int64_t d = drho(n, vs);
-        ev.drho[nx - 1] = d;
+        const int64_t d = drho(n, R);
+        ev.drho.push_back({nx - 1, d});
         ev.gamma = gamma_of({{d, (int64_t)nx}});
         return ev;
       }
     }
-    std::vector<int64_t> local(nx), bnd(nx);
-    std::vector<int64_t> gmaxv(nx, INT64_MIN);  // indexed by x & bmask
+    e_local.resize(nx);
+    e_bnd.resize(nx);
+    e_gmax.assign(nx, INT64_MIN);  // indexed by x & bmask
     for (uint32_t x = 0; x < nx; ++x) {
       int64_t lc = 0, b = n.bound;
       bool feas = true;
-      for (const Tab& tb : tabs) {
+      for (size_t i = 0; i < nt; ++i) {
         uint32_t y = 0;
-        for (size_t q = 0; q < tb.pos.size(); ++q) y |= ((x >> tb.pos[q]) & 1u) << q;
-        const int64_t m = tb.val[y];
+        const int32_t q0 = e_tpos_off[i], nq = e_tpos_off[i + 1] - q0;
+        for (int q = 0; q < nq; ++q) y |= ((x >> e_tpos[q0 + q]) & 1u) << q;
+        const int64_t m = e_tval[e_tval_off[i] + y];
         if (m == INT64_MIN) { feas = false; break; }
-        b += m - tb.base;
-        if (tb.inside) lc += m;
+        b += m - e_base[i];
+        if (e_inside[i]) lc += m;
       }
-      local[x] = feas ? lc : INT64_MIN;
-      bnd[x] = feas ? b : INT64_MIN;
-      if (feas && lc > gmaxv[x & bmask]) gmaxv[x & bmask] = lc;
+      e_local[x] = feas ? lc : INT64_MIN;
+      e_bnd[x] = feas ? b : INT64_MIN;
+      if (feas && lc > e_gmax[x & bmask]) e_gmax[x & bmask] = lc;
     }
     const uint32_t full = nx - 1;
-    std::vector<char> taken;
-    if (opt.values_only) taken.assign(nx, 0);
+    if (opt.values_only) e_taken.assign(nx, 0);
     for (uint32_t x = 0; x < nx; ++x) {
-      if (local[x] == INT64_MIN) continue;
-      if (local[x] != gmaxv[x & bmask]) continue;      // boundary equivalence
+      if (e_local[x] == INT64_MIN) continue;
+      if (e_local[x] != e_gmax[x & bmask]) continue;    // boundary equivalence
       if (opt.values_only) {
         // one optimal interior per boundary state; prune what cannot beat
         // the incumbent
-        if (taken[x & bmask] || bnd[x] <= opt.incumbent) continue;
-        taken[x & bmask] = 1;
-      } else if (bnd[x] < opt.incumbent) {
+        if (e_taken[x & bmask] || e_bnd[x] <= opt.incumbent) continue;
+        e_taken[x & bmask] = 1;
+      } else if (e_bnd[x] < opt.incumbent) {
         continue;                                        // global pruning (strict)
       }
       ev.cubes.push_back(Cube{full, x});
     }
-    // delta rho per fixed subset of the region (cached)
-    std::unordered_map<uint32_t, int64_t> dcache;
+    // delta rho per fixed subset of the region (cached in ev.drho)
     auto dr = [&](uint32_t mask) {
-      auto it = dcache.find(mask);
-      if (it != dcache.end()) return it->second;
-      std::vector<int32_t> vs;
+      if (const int64_t* d = ev.drho_of(mask)) return *d;
+      e_vs.clear();
       for (int j = 0; j < r; ++j)
-        if (mask >> j & 1) vs.push_back(R[j]);
-      const int64_t d = drho(n, vs);
-      dcache[mask] = d;
-      ev.drho[mask] = d;
+        if (mask >> j & 1) e_vs.push_back(R[j]);
+      const int64_t d = drho(n, e_vs);
+      ev.drho.push_back({mask, d});
       return d;
     };
+    // gamma of a cover: one term per distinct fixed subset, ascending
     auto gam = [&](const std::vector<Cube>& cs) {
-      std::map<uint32_t, int64_t> cnt;
-      for (auto& c : cs) cnt[c.mask]++;
+      e_masks.clear();
+      for (auto& c : cs) e_masks.push_back(c.mask);
+      std::sort(e_masks.begin(), e_masks.end());
       std::vector<std::pair<int64_t, int64_t>> terms;
-      for (auto& kv : cnt) terms.push_back({dr(kv.first), kv.second});
+      for (size_t i = 0; i < e_masks.size();) {
+        size_t j = i;
+        while (j < e_masks.size() && e_masks[j] == e_masks[i]) ++j;
+        terms.push_back({dr(e_masks[i]), (int64_t)(j - i)});
+        i = j;
+      }
       return gamma_of(terms);
     };
     ev.gamma = gam(ev.cubes);
@@ -311,16 +339,17 @@ struct Searcher {
       int bestj = -1;
       double bestg = ev.gamma;
       std::vector<Cube> bestc;
+      e_keys.clear();
+      for (auto& c : ev.cubes) e_keys.push_back(((uint64_t)c.mask << 32) | c.val);
+      std::sort(e_keys.begin(), e_keys.end());
       for (int j = 0; j < r; ++j) {
         const uint32_t bj = 1u << j;
-        std::unordered_map<uint64_t, char> have;
-        for (auto& c : ev.cubes) have[((uint64_t)c.mask << 32) | c.val] = 1;
         std::vector<Cube> merged;
         bool any = false;
         for (auto& c : ev.cubes) {
           if (!(c.mask & bj)) { merged.push_back(c); continue; }
           const uint64_t partner = ((uint64_t)c.mask << 32) | (c.val ^ bj);
-          if (have.count(partner)) {
+          if (std::binary_search(e_keys.begin(), e_keys.end(), partner)) {
             if (!(c.val & bj)) { merged.push_back(Cube{c.mask & ~bj, c.val}); any = true; }
           } else {
             merged.push_back(c);
@@ -425,8 +454,8 @@ struct Searcher {
       ch.sizes = n.sizes;
       for (int v : newly)
         for (int id : tree.var_nodes[v]) ch.sizes[id]--;
-      auto it = best.drho.find(c.mask);
-      ch.rho = it != best.drho.end() ? n.rho - it->second : rho_of(tree, ch.sizes, opt.log2_target);
+      const int64_t* d = best.drho_of(c.mask);
+      ch.rho = d ? n.rho - *d : rho_of(tree, ch.sizes, opt.log2_target);
       out.push_back(std::move(ch));
     }
   }

@@ -746,6 +746,14 @@ void solve_instances(bbtn_ctx* ctx, std::vector<Instance>& insts) {
     }
     if (!w.certified) fail(i, BBTN_E_COUNT_UNCERTIFIED, "count not certified within max_primes");
   }
+  // the networks and pipeline state hold many small allocations; freeing
+  // them on one thread costs as much as the rest of a large call's host
+  // work, so they are freed on the planning threads
+  parallel_for(N, (int)std::max(1u, std::thread::hardware_concurrency()), [&](size_t i) {
+    insts[i].net = Network();
+    insts[i].ls_x = std::vector<uint8_t>();
+    W[i] = Work();
+  });
 }
 
 }  // namespace bbtn
