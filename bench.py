@@ -39,7 +39,7 @@ HBM_PEAK = 8.0e12
 # --pmc FETCH_SIZE and WRITE_SIZE on this workload and recorded, with a hash
 # of the kernel sources, in a profiles/ summary; reported only while the
 # sources are unchanged.
-TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "persist_sg16_batch20_hbm_traffic.md")
+TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "persist_sg16_batch160_hbm_traffic.md")
 PERSIST_SOURCES = [os.path.join(ROOT, "paper_2602_05470_amd", "csrc", f)
                    for f in ("k_persist.hip", "persist_dev.h", "persist.cpp")]
 
