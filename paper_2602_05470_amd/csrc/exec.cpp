@@ -217,10 +217,14 @@ void run_group(bbtn_ctx* ctx, const Network& net, const GroupPlan& g, const Base
           opnd[w] = buf(op.temp);
         } else if (!op.direct) {
           const GatherPlan gp = make_gather_plan(op.r_in, ranks[w], op.src_bits.data());
-          // a shared root is read by every branch: no branch stride
+          // a shared root is read by every branch: no branch stride; the root
+          // of a deferred subtree is sliced by each branch's fixed bits
           const int64_t stride = g.buf_region[op.id] == R_SHARED ? 0 : (1ll << op.r_in);
+          const uint64_t* fbits = (op.base_op >= 0 && !s.shared)
+                                      ? ctx->fixbits.as<uint64_t>() + (size_t)op.base_op * L
+                                      : nullptr;
           const int ph = ctx->prof.begin(st);
-          launch_gather(k, gp, Ls, stride, nullptr, buf(op.id), buf(op.temp), st);
+          launch_gather(k, gp, Ls, stride, fbits, buf(op.id), buf(op.temp), st);
           ctx->prof.end(ph, st, K_GATHER, 0, 2.0 * W * 4 * (double)(Ls << ranks[w]));
           opnd[w] = buf(op.temp);
         } else {

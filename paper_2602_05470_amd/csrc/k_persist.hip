@@ -59,6 +59,14 @@ __device__ __forceinline__ kptr<T> kconst(const T* p) {
   return (kptr<T>)p;
 }
 
+// Pointers typed by address space (global = 1, LDS = 3): staging and
+// output code written once for both sources must not be merged into one
+// body over a pointer that may be either (which would need flat accesses).
+template <class T>
+using gptr = __attribute__((address_space(1))) T*;
+template <class T>
+using lptr = __attribute__((address_space(3))) T*;
+
 template <int N>
 struct Log2 {
   static constexpr int value = N <= 1 ? 0 : 1 + Log2<N / 2>::value;
@@ -79,9 +87,14 @@ persist_kernel(const PersistArgs a) {
   constexpr int LT = Log2<NTHR>::value;
   extern __shared__ __attribute__((aligned(16))) uint32_t lds[];
   const int cap = (int)a.lds_entries;  // entries per operand buffer
+  const int ae = (int)a.arena_entries;  // entries per arena plane
+  // plane strides as locals: the lambdas below capture by reference, and a
+  // reference to the kernel argument would move it to private memory
+  const int64_t scr_stride = a.scratch_entries, sh_stride = a.shared_entries;
   uint32_t* la = lds;                  // W planes of cap entries
   uint32_t* lb = lds + W * cap;
-  int32_t* pv = (int32_t*)(lb + W * cap);  // NTHR partial values
+  uint32_t* arena = lb + W * cap;      // W planes of ae entries: small intermediates
+  int32_t* pv = (int32_t*)(arena + W * ae);  // NTHR partial values
   uint32_t* pr = (uint32_t*)(pv + NTHR);   // KR x NTHR partial residues
   uint32_t* fixtab = pr + KR * NTHR;       // the task's fixed bits per slot
   uint32_t* const scr_block = a.scratch + (int64_t)blockIdx.x * W * a.scratch_entries;
@@ -155,6 +168,7 @@ persist_kernel(const PersistArgs a) {
         auto pos = [&](int j) { return (pw[j >> 2] >> (8 * (j & 3))) & 255u; };
         const int n = 1 << op->rank;
         const int64_t mat = op->mat_off;
+        const bool from_lds = kind == PK_LDS;
         // The layout-to-source index map only moves bits, so it is OR-linear
         // over disjoint bit sets: entry e = e0 | u * NTHR | tid maps to
         // map(e0) | map(u * NTHR) | map(tid).  The thread part is formed
@@ -168,7 +182,9 @@ persist_kernel(const PersistArgs a) {
         uint32_t lo_bits = 0;
 #pragma unroll
         for (int j = 0; j < LT; ++j) lo_bits |= ((el >> j) & 1u) << pos(j);
-        auto stage = [&](auto sb_tag) {
+        // `sp_` and `ss_` are the source and its plane stride: the arena
+        // (LDS) or a global buffer, each inlined with its own address space
+        auto stage = [&](auto sb_tag, auto sp_, int64_t ss_) __attribute__((always_inline)) {
           constexpr int SB = decltype(sb_tag)::value;
           constexpr int LB = Log2<SB>::value;
           uint32_t hu[SB];
@@ -189,7 +205,7 @@ persist_kernel(const PersistArgs a) {
             for (int u = 0; u < SB; ++u) {
               const uint32_t s = he | hu[u];
 #pragma unroll
-              for (int p = 0; p < W; ++p) v[u][p] = (src + p * sstride)[s];
+              for (int p = 0; p < W; ++p) v[u][p] = (sp_ + p * ss_)[s];
             }
 #pragma unroll
             for (int u = 0; u < SB; ++u) {
@@ -198,17 +214,25 @@ persist_kernel(const PersistArgs a) {
 #pragma unroll
                 for (int p = 0; p < W; ++p) {
                   dst[p * cap + e] = v[u][p];
-                  if (mat >= 0) scr[p * a.scratch_entries + mat + e] = v[u][p];
+                  if (mat >= 0) ((gptr<uint32_t>)scr)[p * scr_stride + mat + e] = v[u][p];
                 }
               }
             }
           }
         };
         const int per = (n + NTHR - 1) / NTHR;  // entries per thread (uniform)
-        if (per >= 8 && KR < 3) stage(std::integral_constant<int, 8>{});
-        else if (per >= 4) stage(std::integral_constant<int, 4>{});
-        else if (per >= 2) stage(std::integral_constant<int, 2>{});
-        else stage(std::integral_constant<int, 1>{});
+        if (from_lds) {
+          const lptr<const uint32_t> ls = (lptr<const uint32_t>)(arena + op->src_off);
+          if (per >= 4) stage(std::integral_constant<int, 4>{}, ls, (int64_t)ae);
+          else if (per >= 2) stage(std::integral_constant<int, 2>{}, ls, (int64_t)ae);
+          else stage(std::integral_constant<int, 1>{}, ls, (int64_t)ae);
+        } else {
+          const gptr<const uint32_t> gs = (gptr<const uint32_t>)src;
+          if (per >= 8 && KR < 3) stage(std::integral_constant<int, 8>{}, gs, sstride);
+          else if (per >= 4) stage(std::integral_constant<int, 4>{}, gs, sstride);
+          else if (per >= 2) stage(std::integral_constant<int, 2>{}, gs, sstride);
+          else stage(std::integral_constant<int, 1>{}, gs, sstride);
+        }
       }
       __syncthreads();
       // ---- product
@@ -217,14 +241,30 @@ persist_kernel(const PersistArgs a) {
       const int K = 1 << rk;
       const int c_kind = sp->c_kind;
       const int64_t c_off = sp->c_off;
+      // write output entry o (tropical zero when not finite) to the arena,
+      // the shared region or the workgroup's scratch (uniform choice)
+      auto put = [&](int o, int32_t v, const uint32_t (&r)[KR > 0 ? KR : 1])
+                     __attribute__((always_inline)) {
+        const bool fin = v > NEG_CUT;
+        if (c_kind == PK_LDS) {
+          const lptr<uint32_t> cl = (lptr<uint32_t>)(arena + c_off);
+          cl[o] = (uint32_t)(fin ? v : NEG);
+#pragma unroll
+          for (int p = 0; p < KR; ++p) cl[(p + 1) * ae + o] = fin ? r[p] : 0u;
+        } else {
+          const bool sh = c_kind == PK_SHARED;
+          const gptr<uint32_t> c = (gptr<uint32_t>)((sh ? shared : scr) + c_off);
+          const int64_t cs = sh ? sh_stride : scr_stride;
+          c[o] = (uint32_t)(fin ? v : NEG);
+#pragma unroll
+          for (int p = 0; p < KR; ++p) c[(p + 1) * cs + o] = fin ? r[p] : 0u;
+        }
+      };
       // wide steps: four consecutive n per thread, so that each q costs one
       // read of A and one 16-byte read of B for four outputs
       const bool vec4 = rn >= 2 && (nC >> 2) >= NTHR;
       if (vec4) {
         const int nI = nC >> 2;
-        const bool sh = c_kind == PK_SHARED;
-        uint32_t* c = (sh ? shared : scr) + c_off;
-        const int64_t cs = sh ? a.shared_entries : a.scratch_entries;
         for (int it = tid; it < nI; it += NTHR) {
           const int o = it << 2;
           const int nn = o & ((1 << rn) - 1);
@@ -289,12 +329,7 @@ persist_kernel(const PersistArgs a) {
               for (int p = 0; p < KR; ++p) res[i][p] = pmod(acc[i][p], a.mod.p[p], a.mod.c[p]);
           }
 #pragma unroll
-          for (int i = 0; i < 4; ++i) {
-            const bool fin = V[i] > NEG_CUT;
-            c[o + i] = (uint32_t)(fin ? V[i] : NEG);
-#pragma unroll
-            for (int p = 0; p < KR; ++p) c[(p + 1) * cs + o + i] = fin ? res[i][p] : 0u;
-          }
+          for (int i = 0; i < 4; ++i) put(o + i, V[i], res[i]);
         }
       }
       // threads per output: split K when outputs are few
@@ -356,15 +391,7 @@ persist_kernel(const PersistArgs a) {
           }
           __syncthreads();
         }
-        if (j == 0 && o < nC) {
-          const bool fin = V > NEG_CUT;
-          const bool sh = c_kind == PK_SHARED;
-          uint32_t* c = (sh ? shared : scr) + c_off;
-          const int64_t cs = sh ? a.shared_entries : a.scratch_entries;
-          c[o] = (uint32_t)(fin ? V : NEG);
-#pragma unroll
-          for (int p = 0; p < KR; ++p) c[(p + 1) * cs + o] = fin ? res[p] : 0u;
-        }
+        if (j == 0 && o < nC) put(o, V, res);
       }
       __syncthreads();
     }
@@ -373,14 +400,26 @@ persist_kernel(const PersistArgs a) {
     const int64_t root_off = tk->root_off;
     if (tid == 0 && l >= 0) {
       const int32_t cv = (int32_t)a.lconst[l];
-      int32_t rv = 0;
-      const uint32_t* root = scr + root_off;
-      if (root_off >= 0) rv = (int32_t)root[0];
+      // the root scalar: value and residues (an empty program: 0 and 1)
+      uint32_t rw[W];
+      rw[0] = 0;
+#pragma unroll
+      for (int p = 0; p < KR; ++p) rw[p + 1] = 1u;
+      if (root_off >= 0) {
+        if (tk->root_kind == PK_LDS) {
+#pragma unroll
+          for (int p = 0; p < W; ++p) rw[p] = arena[p * ae + root_off];
+        } else {
+#pragma unroll
+          for (int p = 0; p < W; ++p) rw[p] = scr[p * a.scratch_entries + root_off];
+        }
+      }
+      const int32_t rv = (int32_t)rw[0];
       const bool fin = cv > NEG_CUT && rv > NEG_CUT;
       a.out[l] = (uint32_t)(fin ? cv + rv : NEG);
 #pragma unroll
       for (int p = 0; p < KR; ++p) {
-        const uint32_t rr = root_off >= 0 ? root[(p + 1) * a.scratch_entries] : 1u;
+        const uint32_t rr = rw[p + 1];
         const uint64_t x = (uint64_t)rr * a.lconst[(p + 1) * a.n_out + l];
         a.out[(p + 1) * a.n_out + l] = fin ? pmod(x, a.mod.p[p], a.mod.c[p]) : 0u;
       }
@@ -393,9 +432,10 @@ __global__ void zero_kernel(unsigned long long* q) { *q = 0; }
 
 }  // namespace
 
-size_t persist_lds_bytes(int k, int64_t lds_entries, int threads, int slots) {
-  return (size_t)2 * (1 + k) * lds_entries * 4 + (size_t)threads * 4 * (1 + k) +
-         (size_t)slots * 4;
+size_t persist_lds_bytes(int k, int64_t lds_entries, int64_t arena_entries, int threads,
+                         int slots) {
+  return (size_t)(2 * lds_entries + arena_entries) * (1 + k) * 4 +
+         (size_t)threads * 4 * (1 + k) + (size_t)slots * 4;
 }
 
 template <int NT>
@@ -419,7 +459,7 @@ static void launch_nt(int k, const PersistArgs& a, int n_blocks, size_t lds, hip
 }
 
 void launch_persist(int k, const PersistArgs& a, int n_blocks, int threads, hipStream_t st) {
-  const size_t lds = persist_lds_bytes(k, a.lds_entries, threads, a.max_slots);
+  const size_t lds = persist_lds_bytes(k, a.lds_entries, a.arena_entries, threads, a.max_slots);
   hipLaunchKernelGGL(zero_kernel, dim3(1), dim3(1), 0, st, a.queue);
   BBTN_LAUNCHED("persist queue reset");
   switch (threads) {

@@ -1,5 +1,6 @@
 #include "persist.h"
 
+#include <algorithm>
 #include <cstring>
 #include <map>
 #include <string>
@@ -11,7 +12,7 @@ namespace bbtn {
 int persist_max_rank(int k) {
   // two operand buffers of (1 + k) planes within 64 KiB of LDS
   int r = 0;
-  while (persist_lds_bytes(k, 1ll << (r + 1), 64, 0) <= (64u << 10)) ++r;
+  while (persist_lds_bytes(k, 1ll << (r + 1), 0, 64, 0) <= (64u << 10)) ++r;
   return r;
 }
 
@@ -28,6 +29,66 @@ bool persist_fits(const GroupPlan& g, int k) {
 
 namespace {
 size_t align_up(size_t x) { return (x + 255) / 256 * 256; }
+
+// Offsets in the workgroup's LDS arena for the outputs of a branch program
+// that hold at most `limit` entries: first fit over their lifetimes (from
+// the producing step to the last step reading them; the root lives to the
+// end).  Sets *entries to the arena size.
+std::map<int32_t, int64_t> lds_arena(const GroupPlan& g, const std::vector<const Step*>& prog,
+                                     int64_t limit, int64_t* entries) {
+  std::map<int32_t, std::pair<int, int>> life;  // buffer -> (def, last use)
+  for (int i = 0; i < (int)prog.size(); ++i) {
+    const Step& s = *prog[i];
+    for (const Operand* op : {&s.a, &s.b})
+      if (!op->base) {
+        auto it = life.find(op->id);
+        if (it != life.end()) it->second.second = i;
+      }
+    if (g.buf_region[s.out] == R_BRANCH && g.buf_entries[s.out] <= limit)
+      life[s.out] = {i, i};
+  }
+  if (g.root_buf >= 0) {
+    auto it = life.find(g.root_buf);
+    if (it != life.end()) it->second.second = (int)prog.size();
+  }
+  std::vector<int32_t> order;
+  for (auto& kv : life) order.push_back(kv.first);
+  std::stable_sort(order.begin(), order.end(),
+                   [&](int32_t x, int32_t y) { return life[x].first < life[y].first; });
+  std::map<int32_t, int64_t> off;
+  std::vector<int32_t> active;
+  int64_t peak = 0;
+  for (int32_t b : order) {
+    active.erase(std::remove_if(active.begin(), active.end(),
+                                [&](int32_t j) { return life[j].second < life[b].first; }),
+                 active.end());
+    std::vector<std::pair<int64_t, int64_t>> busy;
+    for (int32_t j : active) busy.push_back({off[j], off[j] + g.buf_entries[j]});
+    std::sort(busy.begin(), busy.end());
+    int64_t o = 0;
+    for (auto& bz : busy) {
+      if (o + g.buf_entries[b] <= bz.first) break;
+      o = std::max(o, bz.second);
+    }
+    off[b] = o;
+    peak = std::max(peak, o + g.buf_entries[b]);
+    active.push_back(b);
+  }
+  *entries = peak;
+  return off;
+}
+// LDS a workgroup may allocate (bytes)
+size_t lds_per_workgroup() {
+  static size_t bytes = [] {
+    int dev = 0, n = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return (size_t)64 << 10;
+    if (hipDeviceGetAttribute(&n, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess ||
+        n <= 0)
+      return (size_t)64 << 10;
+    return std::min<size_t>((size_t)n, (size_t)160 << 10);
+  }();
+  return bytes;
+}
 int device_cus() {
   static int cus = [] {
     int dev = 0, n = 0;
@@ -56,7 +117,29 @@ void run_persistent(bbtn_ctx* ctx, const std::vector<PersistJob>& jobs, const Ba
   // contraction tree and fixed set share one copy
   struct ProgRef {
     int32_t step_off, n_steps, slot_off, n_slots;
+    int64_t arena = 0;      // LDS arena entries the program uses
+    int64_t root_lds = -1;  // arena offset of the root scalar, or -1
   };
+  // branch outputs of at most lds_limit entries live in an LDS arena of the
+  // workgroup: smaller for more residues, so that the arena does not lower
+  // the workgroups per CU the operand staging admits
+  const int64_t lds_limit = k == 0 ? 256 : 128;
+  int64_t max_arena = 0;
+  // LDS left for the arena: what a workgroup may allocate, less the operand
+  // staging, the partials of the widest workgroup and the fixed-bit table of
+  // the launch's largest program
+  int rank_all = 0;
+  size_t slot_bound = 0;
+  for (const PersistJob& j : jobs) {
+    rank_all = std::max(rank_all, (int)j.plan->max_rank);
+    size_t n = 0;
+    for (const Step& st_ : j.plan->steps) n += !st_.a.fixed_pos.empty() + !st_.b.fixed_pos.empty();
+    slot_bound = std::max(slot_bound, n);
+  }
+  const size_t fixed_lds =
+      persist_lds_bytes(k, 1ll << std::min(rank_all, P_MAX_RANK), 0, 1024, (int)slot_bound);
+  const int64_t arena_budget =
+      fixed_lds < lds_per_workgroup() ? (int64_t)((lds_per_workgroup() - fixed_lds) / (4 * W)) : 0;
   std::map<std::string, ProgRef> seen;
   // programs already emitted per plan: a job with the same plan and the
   // same base-tensor layout (offsets relative to its first tensor) reuses
@@ -86,7 +169,12 @@ void run_persistent(bbtn_ctx* ctx, const std::vector<PersistJob>& jobs, const Ba
     }
     // a program: steps, their fixed-bit slots and fixes (offsets relative to
     // the program), deduplicated by content
-    auto emit_program = [&](const std::vector<const Step*>& prog) {
+    auto emit_program = [&](const std::vector<const Step*>& prog,
+                            const std::map<int32_t, int64_t>& in_lds) {
+      auto lds_off = [&](int32_t buf) {
+        auto it = in_lds.find(buf);
+        return it == in_lds.end() ? (int64_t)-1 : it->second;
+      };
       std::vector<PStep> ps_v;
       std::vector<PSlot> sl_v;
       std::vector<PFix> fx_v;
@@ -97,6 +185,10 @@ void run_persistent(bbtn_ctx* ctx, const std::vector<PersistJob>& jobs, const Ba
         const bool out_shared = g.buf_region[s.out] == R_SHARED;
         ps.c_kind = out_shared ? PK_SHARED : PK_SCRATCH;
         ps.c_off = g.buf_off[s.out];
+        if (lds_off(s.out) >= 0) {
+          ps.c_kind = PK_LDS;
+          ps.c_off = lds_off(s.out);
+        }
         const Operand* ops[2] = {&s.a, &s.b};
         POperand* pops[2] = {&ps.a, &ps.b};
         for (int w = 0; w < 2; ++w) {
@@ -111,6 +203,9 @@ void run_persistent(bbtn_ctx* ctx, const std::vector<PersistJob>& jobs, const Ba
           } else if (g.buf_region[op.id] == R_SHARED) {
             po.kind = PK_SHARED;
             po.src_off = g.buf_off[op.id];
+          } else if (lds_off(op.id) >= 0) {
+            po.kind = PK_LDS;
+            po.src_off = lds_off(op.id);
           } else {
             po.kind = PK_SCRATCH;
             po.src_off = g.buf_off[op.id];
@@ -121,7 +216,7 @@ void run_persistent(bbtn_ctx* ctx, const std::vector<PersistJob>& jobs, const Ba
           // programs that keep everything materialise gathered operands
           po.mat_off = (op.temp >= 0 && g.keep_all) ? g.buf_off[op.temp] : -1;
           po.slot = -1;
-          if (op.base && !op.fixed_pos.empty()) {
+          if (!op.fixed_pos.empty()) {  // sliced per branch: a fixed-bit slot
             po.slot = (int32_t)sl_v.size();
             sl_v.push_back(PSlot{(int32_t)fx_v.size(), (int32_t)op.fixed_pos.size()});
             for (auto& fp : op.fixed_pos) fx_v.push_back(PFix{fp.first, pos_of[fp.second]});
@@ -154,12 +249,24 @@ void run_persistent(bbtn_ctx* ctx, const std::vector<PersistJob>& jobs, const Ba
       for (auto& rg : g.shared_ranges) {
         std::vector<const Step*> prog;
         for (int i = rg.first; i < rg.second; ++i) prog.push_back(&g.steps[i]);
-        shared_refs.push_back(emit_program(prog));
+        shared_refs.push_back(emit_program(prog, {}));
       }
       std::vector<const Step*> prog;
       for (const Step& s : g.steps)
         if (!s.shared) prog.push_back(&s);
-      branch_ref = emit_program(prog);
+      int64_t arena = 0;
+      std::map<int32_t, int64_t> in_lds;
+      // the largest size limit (halving) whose arena fits the budget
+      for (int64_t lim = g.keep_all ? 0 : lds_limit; lim > 0; lim /= 2) {
+        in_lds = lds_arena(g, prog, lim, &arena);
+        if (arena <= arena_budget) break;
+        in_lds.clear();
+        arena = 0;
+      }
+      branch_ref = emit_program(prog, in_lds);
+      branch_ref.arena = arena;
+      branch_ref.root_lds = -1;
+      if (g.root_buf >= 0 && in_lds.count(g.root_buf)) branch_ref.root_lds = in_lds.at(g.root_buf);
       if (hit == emitted.end()) emitted.emplace(&g, Emitted{rel, shared_refs, branch_ref});
     }
     for (const ProgRef& pr : shared_refs) {
@@ -191,9 +298,15 @@ void run_persistent(bbtn_ctx* ctx, const std::vector<PersistJob>& jobs, const Ba
       t.assign_stride = (int64_t)S;
       t.out_idx = n_out;
       t.root_off = g.root_buf >= 0 ? g.buf_off[g.root_buf] : -1;
+      t.root_kind = PK_SCRATCH;
+      if (branch_ref.root_lds >= 0) {
+        t.root_kind = PK_LDS;
+        t.root_off = branch_ref.root_lds;
+      }
       t.base_off = base0;
       t.shared_off = shared_base;
       tasks.push_back(t);
+      max_arena = std::max(max_arena, branch_ref.arena);
     }
     assign.insert(assign.end(), jobs[ji].assign, jobs[ji].assign + jobs[ji].L * S);
     n_out += jobs[ji].L;
@@ -253,7 +366,7 @@ void run_persistent(bbtn_ctx* ctx, const std::vector<PersistJob>& jobs, const Ba
   auto shape_for = [&](int64_t n_tasks) {
     const int64_t cus = device_cus();
     auto per_cu = [&](int threads) {
-      const size_t lds = persist_lds_bytes(k, lds_entries, threads, max_slots);
+      const size_t lds = persist_lds_bytes(k, lds_entries, max_arena, threads, max_slots);
       const int by_lds = (int)((160u << 10) / std::max<size_t>(lds, 1));
       const int by_waves = 32 / (threads / 64);
       return std::max(1, std::min({32, by_lds, by_waves}));
@@ -289,6 +402,7 @@ void run_persistent(bbtn_ctx* ctx, const std::vector<PersistJob>& jobs, const Ba
   a.shared = (uint32_t*)(dev + o_shared);
   a.shared_entries = std::max<int64_t>(shared_total, 1);
   a.lds_entries = lds_entries;
+  a.arena_entries = max_arena;
   a.per_task_scratch = per_task_scratch ? 1 : 0;
   a.mod = mod;
   double ops = 0, bytes = 0;

@@ -19,14 +19,14 @@ struct PSlot {
 };
 
 // where an operand is read from / an output is written to
-enum PKind { PK_SCRATCH = 0, PK_BASE = 1, PK_SHARED = 2 };
+enum PKind { PK_SCRATCH = 0, PK_BASE = 1, PK_SHARED = 2, PK_LDS = 3 };
 
 // Offsets of base and shared operands are relative to the task's base_off
 // and shared_off, so that instances with the same contraction tree share one
 // copy of the program.
 struct POperand {
-  int32_t kind;      // PKind: workgroup scratch, base tensors or shared region
-                     // (src_off = entry offset there)
+  int32_t kind;      // PKind: workgroup scratch, base tensors, shared region
+                     // or the workgroup's LDS arena (src_off = entry offset there)
   int32_t rank;      // rank of the operand in the step's layout
   int64_t src_off;
   int32_t pad;
@@ -40,7 +40,7 @@ struct POperand {
 struct PStep {
   int32_t rb, rm, rn, rk;
   int64_t c_off;     // entry offset of the output (scratch or shared region)
-  int32_t c_kind;    // PK_SCRATCH or PK_SHARED
+  int32_t c_kind;    // PK_SCRATCH, PK_SHARED or PK_LDS
   int32_t pad2;
   POperand a, b;
 };
@@ -57,7 +57,9 @@ struct PTask {
   int64_t assign_off;     // byte offset of the first task's fixed states
   int64_t assign_stride;  // bytes of fixed states per task
   int64_t out_idx;        // output slot of the first task, or -1
-  int64_t root_off;       // scratch entry offset of the root scalar, -1 if none
+  int64_t root_off;       // entry offset of the root scalar, -1 if none
+  int32_t root_kind;      // PK_SCRATCH or PK_LDS: where the root scalar is
+  int32_t pad;
   int64_t base_off;       // entry offset of the instance's base tensors
   int64_t shared_off;     // entry offset of the instance's shared region
 };
@@ -81,7 +83,8 @@ struct PersistArgs {
   int64_t scratch_entries;
   uint32_t* shared;        // (1 + k) planes of shared_entries
   int64_t shared_entries;
-  int64_t lds_entries;
+  int64_t lds_entries;     // entries per operand staging buffer
+  int64_t arena_entries;   // entries per plane of the LDS arena
   int32_t per_task_scratch;   // scratch of task i at i * (1 + k) * scratch_entries
   int32_t pad;
   unsigned long long* queue;  // task counter, zeroed before the launch
@@ -89,7 +92,8 @@ struct PersistArgs {
 };
 
 // workgroup sizes: 64 (one wavefront), 256 or 1024 threads
-size_t persist_lds_bytes(int k, int64_t lds_entries, int threads, int slots);
+size_t persist_lds_bytes(int k, int64_t lds_entries, int64_t arena_entries, int threads,
+                         int slots);
 void launch_persist(int k, const PersistArgs& a, int n_blocks, int threads, hipStream_t st);
 
 }  // namespace bbtn

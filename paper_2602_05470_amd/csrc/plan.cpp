@@ -1,7 +1,9 @@
 #include "plan.h"
 #include "kernels.h"
 
+#include <algorithm>
 #include <cmath>
+#include <iterator>
 #include <map>
 
 namespace bbtn {
@@ -63,7 +65,7 @@ std::vector<int32_t> cat3(const std::vector<int32_t>& a, const std::vector<int32
 }  // namespace
 
 GroupPlan build_plan(const Network& net, const Tree& tree,
-                     const std::vector<uint64_t>& fixed, bool keep_all) {
+                     const std::vector<uint64_t>& fixed, bool keep_all, int defer_log2) {
   GroupPlan g;
   g.fixed = fixed;
   g.keep_all = keep_all;
@@ -101,6 +103,37 @@ GroupPlan build_plan(const Network& net, const Tree& tree,
       rep[i] = i;
     }
   }
+  // Deferred slicing.  A subtree whose tensors stay small when its fixed
+  // variables are kept as free (batch) indices is contracted once per pass
+  // with them kept, and every branch slices its root (T|_{s_S = x}, Eq. 3,
+  // applied after the subtree's contraction instead of before; no fixed
+  // variable is summed inside it, so the sliced root is the same).
+  // fx[id]: fixed variables of the non-folded base tensors below id;
+  // widest[id]: largest rank, with fx kept, of the tensors of its subtree.
+  std::vector<std::vector<int32_t>> fx(NN);
+  std::vector<int> widest(NN, 0);
+  std::vector<char> deferred(NN, 0);
+  if (sharing && defer_log2 > 0) {
+    for (int i = 0; i < tree.n_base; ++i)
+      if (status[i] == BASE) {
+        for (int v : tree.nodes[i].vars)
+          if (bit_get(fixed, v)) fx[i].push_back(v);
+        widest[i] = (int)tree.nodes[i].vars.size();
+      }
+    for (int id : tree.dfs_post) {
+      const TNode& n = tree.nodes[id];
+      std::set_union(fx[n.left].begin(), fx[n.left].end(), fx[n.right].begin(),
+                     fx[n.right].end(), std::back_inserter(fx[id]));
+      const int own = (int)free_vars(n.vars, fixed).size() + (int)fx[id].size();
+      widest[id] = std::max({own, widest[n.left], widest[n.right]});
+      deferred[id] = hasfix[id] && widest[id] <= defer_log2 && id != tree.root;
+    }
+  }
+  auto with_fx = [&](std::vector<int32_t> v, int node) {
+    std::vector<int32_t> o;
+    std::set_union(v.begin(), v.end(), fx[node].begin(), fx[node].end(), std::back_inserter(o));
+    return o;
+  };
   for (int id : tree.dfs_post) {  // subtrees are contiguous in this order
     const TNode& n = tree.nodes[id];
     const int sl = status[n.left], sr = status[n.right];
@@ -116,9 +149,12 @@ GroupPlan build_plan(const Network& net, const Tree& tree,
     status[id] = STEP;
     rep[id] = id;
     const int ra = rep[n.left], rb_ = rep[n.right];
-    const auto A = free_vars(tree.nodes[ra].vars, fixed);
-    const auto B = free_vars(tree.nodes[rb_].vars, fixed);
-    const auto C = free_vars(n.vars, fixed);
+    const bool dfr = deferred[id];
+    const auto A = dfr ? with_fx(free_vars(tree.nodes[ra].vars, fixed), ra)
+                       : free_vars(tree.nodes[ra].vars, fixed);
+    const auto B = dfr ? with_fx(free_vars(tree.nodes[rb_].vars, fixed), rb_)
+                       : free_vars(tree.nodes[rb_].vars, fixed);
+    const auto C = dfr ? with_fx(free_vars(n.vars, fixed), id) : free_vars(n.vars, fixed);
     const auto AB = isect(A, B);
     const auto batch = isect(AB, C);
     const auto K = minus(AB, C);
@@ -128,7 +164,7 @@ GroupPlan build_plan(const Network& net, const Tree& tree,
       throw Error(BBTN_E_INTERNAL, "plan: variable private to one operand");
     Step s;
     s.node = id;
-    s.shared = sharing && !hasfix[id];
+    s.shared = sharing && (!hasfix[id] || dfr);
     s.rb = (int)batch.size();
     s.rm = (int)M.size();
     s.rn = (int)N.size();
@@ -147,8 +183,9 @@ GroupPlan build_plan(const Network& net, const Tree& tree,
         op.r_in = (int)tv.size();
         for (int v : want)
           op.src_bits.push_back((int)(std::find(tv.begin(), tv.end(), v) - tv.begin()));
-        for (int j = 0; j < (int)tv.size(); ++j)
-          if (bit_get(fixed, tv[j])) op.fixed_pos.push_back({j, tv[j]});
+        if (!dfr)  // a deferred step reads base tensors whole
+          for (int j = 0; j < (int)tv.size(); ++j)
+            if (bit_get(fixed, tv[j])) op.fixed_pos.push_back({j, tv[j]});
         op.base_op = (int)g.base_ops.size();
         g.base_ops.push_back({si, which});
       } else {
@@ -162,6 +199,16 @@ GroupPlan build_plan(const Network& net, const Tree& tree,
         op.direct = (have == want) && g.buf_region[op.id] != R_SHARED;
         for (int v : want)
           op.src_bits.push_back((int)(std::find(have.begin(), have.end(), v) - have.begin()));
+        // the root of a deferred subtree holds fixed variables: sliced per
+        // branch by the branch's states, like a base tensor
+        if (!dfr)
+          for (int j = 0; j < (int)have.size(); ++j)
+            if (bit_get(fixed, have[j])) op.fixed_pos.push_back({j, have[j]});
+        if (!op.fixed_pos.empty()) {
+          op.direct = false;
+          op.base_op = (int)g.base_ops.size();
+          g.base_ops.push_back({si, which});
+        }
       }
       if (!op.direct) {
         op.temp = new_buf(1ll << want.size(), own_region);

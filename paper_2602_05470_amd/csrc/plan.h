@@ -27,8 +27,8 @@ struct Operand {
   int32_t r_in = 0;                 // rank of the source (all vars for base)
   std::vector<int32_t> src_bits;    // required-layout bit j <- source bit
   int32_t temp = -1;                // buffer receiving the gathered operand
-  std::vector<std::pair<int32_t, int32_t>> fixed_pos;  // (source bit, var) of fixed vars (base only)
-  int32_t base_op = -1;             // index into GroupPlan::base_ops
+  std::vector<std::pair<int32_t, int32_t>> fixed_pos;  // (source bit, var) of fixed vars sliced per branch
+  int32_t base_op = -1;             // index into GroupPlan::base_ops, or -1
 };
 
 // C[b, m, n] = (+)_k A[b, m, k] (.) B[b, k, n], bit layouts (low bits first):
@@ -57,7 +57,9 @@ struct GroupPlan {
   std::vector<std::pair<int32_t, int32_t>> shared_ranges;
   std::vector<int32_t> folded;      // base tensors with every variable fixed
   int32_t root_buf = -1;            // buffer of the final scalar, -1 if none
-  std::vector<std::pair<int32_t, int32_t>> base_ops;  // (step, 0=A / 1=B)
+  // operands read with per-branch fixed bits (base tensors, and roots of
+  // deferred subtrees): (step, 0=A / 1=B)
+  std::vector<std::pair<int32_t, int32_t>> base_ops;
   int32_t max_rank = 0;             // largest tensor rank in the program
   bool keep_all = false;            // every buffer kept, operands materialised
   double macs = 0;                  // per branch (branch steps)
@@ -67,8 +69,11 @@ struct GroupPlan {
 
 // keep_all: never reuse buffers and materialise every operand in its
 // required layout (values-only recontraction for configuration recovery);
-// keep_all plans share nothing.
+// keep_all plans share nothing.  defer_log2 > 0: subtrees holding fixed
+// variables whose tensors, with those variables kept, have at most
+// 2^defer_log2 entries are contracted once per pass and sliced per branch
+// afterwards (their steps are shared).
 GroupPlan build_plan(const Network& net, const Tree& tree,
-                     const std::vector<uint64_t>& fixed, bool keep_all);
+                     const std::vector<uint64_t>& fixed, bool keep_all, int defer_log2 = 0);
 
 }  // namespace bbtn

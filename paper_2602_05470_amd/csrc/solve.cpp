@@ -66,7 +66,11 @@ std::shared_ptr<const GroupPlan> plan_for(bbtn_ctx* ctx, const Network& net, con
     auto it = ctx->plan_cache.find(key);
     if (it != ctx->plan_cache.end()) return it->second;
   }
-  auto plan = std::make_shared<const GroupPlan>(build_plan(net, *t.tree, mask, keep_all));
+  // subtrees whose tensors, with their fixed variables kept, stay within
+  // T_target are contracted once per pass and sliced per branch (not in
+  // keep-all plans, whose intermediates are traced)
+  const int defer = keep_all ? 0 : std::max(0, ctx->opt.log2_target);
+  auto plan = std::make_shared<const GroupPlan>(build_plan(net, *t.tree, mask, keep_all, defer));
   std::lock_guard<std::mutex> lk(ctx->tree_mu);
   auto it = ctx->plan_cache.find(key);
   if (it != ctx->plan_cache.end()) return it->second;
