@@ -51,6 +51,17 @@ class _Result(C.Structure):
                 ("seconds", C.c_double * 8)]
 
 
+# numpy view of a _Result array (pointer fields read as addresses)
+_RESULT_DTYPE = np.dtype({
+    "names": ["value", "n_primes", "primes", "residues", "certified", "count_words", "leaves",
+              "pruned", "nodes", "macs", "seconds"],
+    "formats": [np.int64, np.int32, (np.uint32, MAX_PRIMES), (np.uint32, MAX_PRIMES), np.int32,
+                np.int32, np.uint64, np.uint64, np.uint64, np.uint64, (np.float64, 8)],
+    "offsets": [getattr(_Result, f).offset for f in
+                ("value", "n_primes", "primes", "residues", "certified", "count_words", "leaves",
+                 "pruned", "nodes", "macs", "seconds")],
+    "itemsize": C.sizeof(_Result)})
+
 _lib = None
 
 EXPORTS = ["bbtn_default_options", "bbtn_create", "bbtn_destroy", "bbtn_last_error",
@@ -284,46 +295,59 @@ class Context:
         (kind 0: spin glass, weights = J; kind 1: MWIS, weights = w or None,
         h ignored).  Returns (results, statuses)."""
         N = len(instances)
-        n_arr = (C.c_int32 * max(N, 1))()
-        m_arr = (C.c_int32 * max(N, 1))()
-        uv_arr = (C.c_void_p * max(N, 1))()
-        w_arr = (C.c_void_p * max(N, 1))()
-        h_arr = (C.c_void_p * max(N, 1))()
-        res = (_Result * max(N, 1))()
-        st = (C.c_int32 * max(N, 1))()
-        keep, cnts, cfgs = [], [], []
+        M = max(N, 1)
+        ns = np.zeros(M, np.int32)
+        ms = np.zeros(M, np.int32)
+        ptrs = np.zeros((3, M), np.uint64)  # edge, weight and field pointers
+        keep = []
         for i, (n, edges, w, h) in enumerate(instances):
-            e = _i32(edges).reshape(-1, 2)
-            ww = None if w is None else _i32(w)
-            hh = None if (h is None or kind != 0) else _i32(h)
-            keep += [e, ww, hh]
-            n_arr[i], m_arr[i] = n, len(e)
-            uv_arr[i] = e.ctypes.data
-            w_arr[i] = None if ww is None else ww.ctypes.data
-            h_arr[i] = None if hh is None else hh.ctypes.data
-            cap = (n + 64) // 32 + 2
-            cnt = (C.c_uint32 * cap)()
-            cfg = np.zeros(n, dtype=np.int8)
-            cnts.append(cnt)
-            cfgs.append(cfg)
-            res[i].count = C.cast(cnt, C.POINTER(C.c_uint32))
-            res[i].count_capacity = cap
-            res[i].config = cfg.ctypes.data_as(C.POINTER(C.c_int8))
-        s = self.lib.bbtn_solve_batch(self.h, kind, N, n_arr, m_arr, uv_arr, w_arr, h_arr, res, st)
-        statuses = [int(st[i]) for i in range(N)]
-        if s != 0 and raise_failed:
-            self._check(s)
-        out = []
+            e = _i32(edges)
+            ns[i], ms[i] = n, e.size // 2
+            ptrs[0, i] = e.ctypes.data
+            keep.append(e)
+            if w is not None:
+                ww = _i32(w)
+                ptrs[1, i] = ww.ctypes.data
+                keep.append(ww)
+            if h is not None and kind == 0:
+                hh = _i32(h)
+                ptrs[2, i] = hh.ctypes.data
+                keep.append(hh)
+        # one buffer for every count and one for every configuration
+        cap = int(ns.max() + 64) // 32 + 2 if N else 1
+        counts = np.zeros((M, cap), np.uint32)
+        nmax = int(ns.max()) if N else 1
+        cfgs = np.zeros((M, max(nmax, 1)), np.int8)
+        res = (_Result * M)()
+        cbase, fbase = counts.ctypes.data, cfgs.ctypes.data
+        u32p, i8p = C.POINTER(C.c_uint32), C.POINTER(C.c_int8)
         for i in range(N):
             r = res[i]
-            count = 0
-            for j in reversed(range(r.count_words)):
-                count = (count << 32) | int(cnts[i][j])
-            out.append(Result(value=int(r.value), count=count, certified=bool(r.certified),
-                              primes=[int(r.primes[j]) for j in range(r.n_primes)],
-                              residues=[int(r.residues[j]) for j in range(r.n_primes)],
-                              config=cfgs[i], leaves=int(r.leaves), pruned=int(r.pruned),
-                              nodes=int(r.nodes), macs=int(r.macs), seconds=list(r.seconds)))
+            r.count = C.cast(cbase + 4 * cap * i, u32p)
+            r.count_capacity = cap
+            r.config = C.cast(fbase + cfgs.shape[1] * i, i8p)
+        st = np.zeros(M, np.int32)
+        s = self.lib.bbtn_solve_batch(self.h, kind, N, ns.ctypes.data, ms.ctypes.data,
+                                      ptrs[0].ctypes.data, ptrs[1].ctypes.data,
+                                      ptrs[2].ctypes.data, res, st.ctypes.data)
+        statuses = st[:N].tolist()
+        if s != 0 and raise_failed:
+            self._check(s)
+        # read the results through one structured view of the array
+        ra = np.frombuffer(res, dtype=_RESULT_DTYPE)
+        vals, cws, certs, nps = (ra["value"].tolist(), ra["count_words"].tolist(),
+                                 ra["certified"].tolist(), ra["n_primes"].tolist())
+        primes, resid, secs = ra["primes"].tolist(), ra["residues"].tolist(), ra["seconds"].tolist()
+        lv, pr, nd, mc = (ra["leaves"].tolist(), ra["pruned"].tolist(), ra["nodes"].tolist(),
+                          ra["macs"].tolist())
+        out = []
+        for i in range(N):
+            cw = cws[i]
+            count = int.from_bytes(counts[i, :cw].tobytes(), "little") if cw > 0 else 0
+            out.append(Result(value=vals[i], count=count, certified=bool(certs[i]),
+                              primes=primes[i][:nps[i]], residues=resid[i][:nps[i]],
+                              config=cfgs[i, :int(ns[i])], leaves=lv[i], pruned=pr[i],
+                              nodes=nd[i], macs=mc[i], seconds=secs[i]))
         return out, statuses
 
     def solve_spinglass(self, n, edges, J, h=None, **kw) -> Result:

@@ -49,16 +49,30 @@ void upload_bases(bbtn_ctx* ctx, const std::vector<const Network*>& nets, const 
   BBTN_HIP(hipStreamSynchronize(ctx->stream));
   ctx->pin_base.ensure(words * 4);
   uint32_t* host = ctx->pin_base.as<uint32_t>();
-  for (size_t i = 0; i < nets.size(); ++i)
-    for (size_t t = 0; t < nets[i]->tensors.size(); ++t) {
-      const BaseTensor& T = nets[i]->tensors[t];
-      const int64_t n = T.size();
-      uint32_t* dst = host + offs[i][t];
-      std::memcpy(dst, T.val.data(), (size_t)n * 4);
-      for (int p = 0; p < k; ++p)
-        std::memcpy(dst + (size_t)(p + 1) * bd.total, &T.res[(size_t)prime_idx[p] * n],
-                    (size_t)n * 4);
+  for (size_t i = 0; i < nets.size(); ++i) {
+    const Network& net = *nets[i];
+    if (net.tensors.empty()) continue;
+    const int64_t o = offs[i][0];
+    const bool flat = net.flat_total > 0 && net.flat.size() == (size_t)(1 + NP_FLAT) * net.flat_total;
+    // whole planes from the network's flat copy where it holds them
+    for (int p = -1; p < k; ++p) {
+      const int plane = p < 0 ? 0 : p + 1;
+      if (flat && (p < 0 || prime_idx[p] < NP_FLAT)) {
+        const int src_plane = p < 0 ? 0 : prime_idx[p] + 1;
+        std::memcpy(host + (size_t)plane * bd.total + o,
+                    net.flat.data() + (size_t)src_plane * net.flat_total,
+                    (size_t)net.flat_total * 4);
+        continue;
+      }
+      for (size_t t = 0; t < net.tensors.size(); ++t) {
+        const BaseTensor& T = net.tensors[t];
+        const int64_t n = T.size();
+        uint32_t* dst = host + (size_t)plane * bd.total + offs[i][t];
+        if (p < 0) std::memcpy(dst, T.val.data(), (size_t)n * 4);
+        else std::memcpy(dst, &T.res[(size_t)prime_idx[p] * n], (size_t)n * 4);
+      }
     }
+  }
   if (total == 0)
     for (size_t p = 0; p < words; ++p) host[p] = 0;
   buf.ensure(words * 4);

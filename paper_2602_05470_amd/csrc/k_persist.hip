@@ -13,6 +13,7 @@
 // A program built to keep every intermediate also writes each staged operand
 // to scratch (configuration recovery reads them afterwards).
 // Counts use the same lazy 64-bit accumulation as the tiled product.
+#include <atomic>
 #include <type_traits>
 
 #include "persist_dev.h"
@@ -438,15 +439,26 @@ size_t persist_lds_bytes(int k, int64_t lds_entries, int64_t arena_entries, int 
          (size_t)threads * 4 * (1 + k) + (size_t)slots * 4;
 }
 
+// Raise a kernel's dynamic-LDS limit only when a launch needs more than it
+// was last set to (the attribute call is not free on every launch).
+static void raise_lds_limit(const void* fn, int bytes, std::atomic<int>& set) {
+  int cur = set.load();
+  while (bytes > cur) {
+    BBTN_HIP(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, bytes));
+    if (set.compare_exchange_weak(cur, bytes)) break;
+  }
+}
+
 template <int NT>
 static void launch_nt(int k, const PersistArgs& a, int n_blocks, size_t lds, hipStream_t st) {
   switch (k) {
 #define BBTN_PK(K)                                                                 \
-  case K:                                                                          \
-    BBTN_HIP(hipFuncSetAttribute((const void*)persist_kernel<K, NT>,                \
-                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds)); \
+  case K: {                                                                        \
+    static std::atomic<int> attr{0};                                               \
+    raise_lds_limit((const void*)persist_kernel<K, NT>, (int)lds, attr);           \
     hipLaunchKernelGGL((persist_kernel<K, NT>), dim3(n_blocks), dim3(NT), lds, st, a); \
-    break;
+    break;                                                                         \
+  }
     BBTN_PK(0)
     BBTN_PK(1)
     BBTN_PK(2)

@@ -104,6 +104,7 @@ Network build_spinglass(int32_t n, int32_t m, const int32_t* uv, const int32_t* 
   }
   for (int p = 0; p < NP; ++p) net.const_res[p] = 1;
   simplify(net);
+  flatten(net);
   return net;
 }
 
@@ -137,6 +138,7 @@ Network build_mwis(int32_t n, int32_t m, const int32_t* uv, const int32_t* w) {
   }
   for (int p = 0; p < NP; ++p) net.const_res[p] = 1;
   simplify(net);
+  flatten(net);
   return net;
 }
 
@@ -184,6 +186,22 @@ static BaseTensor sum_out(const BaseTensor& t, int j) {
     }
   }
   return o;
+}
+
+void flatten(Network& net) {
+  int64_t total = 0;
+  for (const auto& T : net.tensors) total += T.size();
+  net.flat_total = total;
+  net.flat.assign((size_t)(1 + NP_FLAT) * total, 0);
+  int64_t off = 0;
+  for (const auto& T : net.tensors) {
+    const int64_t n = T.size();
+    for (int64_t e = 0; e < n; ++e) net.flat[off + e] = (uint32_t)T.val[e];
+    for (int p = 0; p < NP_FLAT; ++p)
+      for (int64_t e = 0; e < n; ++e)
+        net.flat[(size_t)(p + 1) * total + off + e] = T.res[(size_t)p * n + e];
+    off += n;
+  }
 }
 
 void simplify(Network& net) {

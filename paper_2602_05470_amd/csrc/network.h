@@ -51,7 +51,14 @@ struct Network {
   bool infeasible = false;
   std::vector<PeelRec> peel;        // in elimination order
   int64_t abs_sum = 0;              // sum |J| + |h| (or sum w)
+  // every tensor's entries back to back, in tensor order: the value plane
+  // then the residue planes of the first NP_FLAT primes (flat_total entries
+  // each), for uploads of whole planes
+  std::vector<uint32_t> flat;
+  int64_t flat_total = 0;
 };
+
+constexpr int NP_FLAT = KMAX + 1;  // one pass's primes and its check prime
 
 Network build_spinglass(int32_t n, int32_t m, const int32_t* uv, const int32_t* J,
                         const int32_t* h);
@@ -61,5 +68,8 @@ Network build_mwis(int32_t n, int32_t m, const int32_t* uv, const int32_t* w);
 // another's (tropical product), sum out variables held by a single tensor
 // (tropical sum, recorded in `peel`), fold scalars into the constant.
 void simplify(Network& net);
+
+// Fill net.flat from the tensors (done by the builders).
+void flatten(Network& net);
 
 }  // namespace bbtn

@@ -2,6 +2,8 @@
 
 #include <algorithm>
 #include <cstring>
+#include <thread>
+#include <atomic>
 #include <map>
 #include <string>
 
@@ -320,12 +322,24 @@ void run_persistent(bbtn_ctx* ctx, const std::vector<PersistJob>& jobs, const Ba
     pidx[p] = (int)(std::find(P.begin(), P.end(), mod.p[p]) - P.begin());
   }
   std::vector<uint32_t> lconst((size_t)W * n_out);
-  for (size_t ji = 0; ji < jobs.size(); ++ji) {
-    std::vector<uint32_t> lc;
-    leaf_constants(*jobs[ji].net, *jobs[ji].plan, pidx.data(), k, jobs[ji].assign, jobs[ji].L, lc);
-    for (int p = 0; p < W; ++p)
-      std::memcpy(&lconst[(size_t)p * n_out + out_base[ji]], &lc[(size_t)p * jobs[ji].L],
-                  jobs[ji].L * 4);
+  {
+    // jobs write disjoint slices: a few host threads when there are many
+    std::atomic<size_t> next{0};
+    auto work = [&] {
+      std::vector<uint32_t> lc;
+      for (size_t ji; (ji = next.fetch_add(1)) < jobs.size();) {
+        leaf_constants(*jobs[ji].net, *jobs[ji].plan, pidx.data(), k, jobs[ji].assign,
+                       jobs[ji].L, lc);
+        for (int p = 0; p < W; ++p)
+          std::memcpy(&lconst[(size_t)p * n_out + out_base[ji]], &lc[(size_t)p * jobs[ji].L],
+                      jobs[ji].L * 4);
+      }
+    };
+    const size_t T = std::min<size_t>(8, (n_branch_tasks >> 14) + 1);
+    std::vector<std::thread> pool;
+    for (size_t t = 1; t < T; ++t) pool.emplace_back(work);
+    work();
+    for (auto& th : pool) th.join();
   }
   // one device buffer for the program and per-branch data
   size_t off = 0;
@@ -405,15 +419,22 @@ void run_persistent(bbtn_ctx* ctx, const std::vector<PersistJob>& jobs, const Ba
   a.arena_entries = max_arena;
   a.per_task_scratch = per_task_scratch ? 1 : 0;
   a.mod = mod;
+  // algorithmic work of the launch: semiring operations and operand bytes
+  // (entries of A, B and C of every step), summed once per plan
   double ops = 0, bytes = 0;
+  std::map<const GroupPlan*, std::pair<double, double>> entries;  // (shared, per branch)
   for (auto& j : jobs) {
     ops += ((double)j.L * j.plan->macs + j.plan->shared_macs) * (2 + 2 * k);
-    double e = 0;
-    for (const Step& s : j.plan->steps)
-      e += (s.shared ? 1.0 : (double)j.L) *
-           (std::ldexp(1.0, (int)s.a_vars.size()) + std::ldexp(1.0, (int)s.b_vars.size()) +
-            std::ldexp(1.0, (int)s.c_vars.size()));
-    bytes += e * W * 4;
+    auto it = entries.find(j.plan);
+    if (it == entries.end()) {
+      double sh = 0, br = 0;
+      for (const Step& s : j.plan->steps)
+        (s.shared ? sh : br) += std::ldexp(1.0, (int)s.a_vars.size()) +
+                                std::ldexp(1.0, (int)s.b_vars.size()) +
+                                std::ldexp(1.0, (int)s.c_vars.size());
+      it = entries.emplace(j.plan, std::make_pair(sh, br)).first;
+    }
+    bytes += (it->second.first + (double)j.L * it->second.second) * W * 4;
   }
   const int ph = ctx->prof.begin(st);
   if (!shared_tasks.empty()) {

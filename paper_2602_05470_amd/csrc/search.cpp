@@ -413,20 +413,35 @@ struct Searcher {
 
   // Children of a node under a branching rule: bounded, pruned if below the
   // incumbent (strict).
+  // nodes already expanded or pruned: their buffers are reused for new
+  // children (the search makes a few thousand nodes per instance)
+  std::vector<Node> spare;
+  Node take() {
+    if (spare.empty()) return Node();
+    Node nd = std::move(spare.back());
+    spare.pop_back();
+    return nd;
+  }
+  std::vector<int32_t> c_tt, c_newly;
+  std::vector<int64_t> c_base;
+
   void children(const Node& n, const Eval& best, std::vector<Node>& out, SearchStats& st) {
     // tensors touched by the region and their largest entries at the node
-    std::vector<int32_t> tt;
+    std::vector<int32_t>& tt = c_tt;
+    tt.clear();
     for (int v : best.region) tt.insert(tt.end(), var_tensors[v].begin(), var_tensors[v].end());
     std::sort(tt.begin(), tt.end());
     tt.erase(std::unique(tt.begin(), tt.end()), tt.end());
-    std::vector<int64_t> base_max(tt.size());
+    std::vector<int64_t>& base_max = c_base;
+    base_max.resize(tt.size());
     for (size_t i = 0; i < tt.size(); ++i) base_max[i] = tensor_max(net.tensors[tt[i]], n.fixed, n.x);
     for (int ci = (int)best.cubes.size() - 1; ci >= 0; --ci) {
       const Cube& c = best.cubes[ci];
-      Node ch;
+      Node ch = take();
       ch.fixed = n.fixed;
       ch.x = n.x;
-      std::vector<int32_t> newly;
+      std::vector<int32_t>& newly = c_newly;
+      newly.clear();
       for (int j = 0; j < (int)best.region.size(); ++j)
         if (c.mask >> j & 1) {
           const int v = best.region[j];
@@ -449,13 +464,21 @@ struct Searcher {
       if (ch.bound == INT64_MIN || ch.bound < opt.incumbent ||
           (opt.values_only && ch.bound == opt.incumbent)) {
         st.pruned++;
+        spare.push_back(std::move(ch));
         continue;
       }
-      ch.sizes = n.sizes;
-      for (int v : newly)
-        for (int id : tree.var_nodes[v]) ch.sizes[id]--;
+      // sizes are kept for nodes that branch again; a leaf (rho = 0) only
+      // needs its fixed states
       const int64_t* d = best.drho_of(c.mask);
-      ch.rho = d ? n.rho - *d : rho_of(tree, ch.sizes, opt.log2_target);
+      if (d && n.rho - *d == 0) {
+        ch.rho = 0;
+        ch.sizes.clear();
+      } else {
+        ch.sizes = n.sizes;
+        for (int v : newly)
+          for (int id : tree.var_nodes[v]) ch.sizes[id]--;
+        ch.rho = d ? n.rho - *d : rho_of(tree, ch.sizes, opt.log2_target);
+      }
       out.push_back(std::move(ch));
     }
   }
@@ -503,6 +526,7 @@ struct Searcher {
       if (n.rho == 0 || opt.log2_target <= 0) {
         emit(n, leaves);
         st.leaves++;
+        spare.push_back(std::move(n));
         continue;
       }
       Eval best;
@@ -550,11 +574,12 @@ struct Searcher {
         if (!best.cubes.empty() && best.cubes.size() == ((size_t)1 << best.region.size()))
           rule_memo[n.fixed] = best.region;
       }
-      if (best.cubes.empty()) { st.pruned++; continue; }
+      if (best.cubes.empty()) { st.pruned++; spare.push_back(std::move(n)); continue; }
       if (!std::isfinite(best.gamma)) throw Error(BBTN_E_INTERNAL, "no branching rule reduces rho");
       st.gamma_sum += best.gamma;
       // children, first cube on top of the stack
       children(n, best, stack, st);
+      spare.push_back(std::move(n));
     }
   }
 };
@@ -647,27 +672,39 @@ std::vector<uint8_t> local_search_spinglass(int32_t n, int32_t m, const int32_t*
   // simulated annealing (single-spin Metropolis updates, geometric
   // temperature schedule), then zero-temperature sweeps; one restart per 100
   // sweeps.  Acceptance probabilities come from a per-sweep table of
-  // exp(-dE/T) for small dE.
-  std::vector<std::vector<std::pair<int, int>>> adj(n);
+  // exp(-dE/T) for small dE.  Neighbours in compressed rows (edge order),
+  // spins as bytes: a new best state is a 1-byte-per-spin copy.
+  std::vector<int32_t> row(n + 1, 0), nb(2 * (size_t)m), wj(2 * (size_t)m);
   for (int e = 0; e < m; ++e) {
-    adj[uv[2 * e]].push_back({uv[2 * e + 1], J[e]});
-    adj[uv[2 * e + 1]].push_back({uv[2 * e], J[e]});
+    row[uv[2 * e] + 1]++;
+    row[uv[2 * e + 1] + 1]++;
+  }
+  for (int i = 0; i < n; ++i) row[i + 1] += row[i];
+  {
+    std::vector<int32_t> fill(row.begin(), row.end() - 1);
+    for (int e = 0; e < m; ++e) {
+      const int a = uv[2 * e], b = uv[2 * e + 1];
+      nb[fill[a]] = b;
+      wj[fill[a]++] = J[e];
+      nb[fill[b]] = a;
+      wj[fill[b]++] = J[e];
+    }
   }
   std::mt19937_64 rng(seed);
-  auto energy = [&](const std::vector<int>& s) {
+  auto energy = [&](const std::vector<int8_t>& s) {
     int64_t E = 0;
     for (int e = 0; e < m; ++e) E -= (int64_t)J[e] * s[uv[2 * e]] * s[uv[2 * e + 1]];
     if (h) for (int i = 0; i < n; ++i) E -= (int64_t)h[i] * s[i];
     return E;
   };
-  std::vector<int> best_s(n, 1);
+  std::vector<int8_t> best_s(n, 1);
   int64_t bestE = energy(best_s);
   const int restarts = std::max(1, sweeps / 100);
   const int per = std::max(1, std::min(sweeps, 100));
   constexpr int TAB = 64;
   double acc[TAB];
+  std::vector<int8_t> s(n);
   for (int rs = 0; rs < restarts; ++rs) {
-    std::vector<int> s(n);
     for (int i = 0; i < n; ++i) s[i] = (rng() & 1) ? 1 : -1;
     int64_t E = energy(s);
     const double T0 = 2.0, T1 = 0.05;
@@ -676,7 +713,7 @@ std::vector<uint8_t> local_search_spinglass(int32_t n, int32_t m, const int32_t*
       for (int d = 0; d < TAB; ++d) acc[d] = T > 0 ? std::exp(-(double)d / T) : 0.0;
       for (int i = 0; i < n; ++i) {
         int64_t f = h ? h[i] : 0;
-        for (auto& pr : adj[i]) f += (int64_t)pr.second * s[pr.first];
+        for (int q = row[i]; q < row[i + 1]; ++q) f += (int64_t)wj[q] * s[nb[q]];
         const int64_t dE = 2 * s[i] * f;
         bool flip = dE <= 0;
         if (!flip && T > 0) {
@@ -684,9 +721,12 @@ std::vector<uint8_t> local_search_spinglass(int32_t n, int32_t m, const int32_t*
           flip = (double)(rng() >> 11) * 0x1.0p-53 < p;
         }
         if (flip) {
-          s[i] = -s[i];
+          s[i] = (int8_t)-s[i];
           E += dE;
-          if (E < bestE) { bestE = E; best_s = s; }
+          if (E < bestE) {
+            bestE = E;
+            std::copy(s.begin(), s.end(), best_s.begin());
+          }
         }
       }
     }
