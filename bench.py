@@ -156,7 +156,7 @@ def main():
                     help="end with a plain device copy of known size (512 MiB each way), "
                          "the reference that scales hardware byte counters")
     ap.add_argument("--batched", type=int, default=1)
-    ap.add_argument("--workers", type=int, default=2,
+    ap.add_argument("--workers", type=int, default=3,
                     help="concurrent solver contexts (threads, one stream each): one "
                          "call's host planning overlaps another's contraction")
     ap.add_argument("--batch-size", type=int, default=160,
@@ -185,7 +185,12 @@ def main():
         return
     want = golden_sg16()
     insts = [I.spin_glass_square(16, s) for s in range(N_SEEDS)]
-    opts = B.Options(log2_target=10, residues_per_pass=3, branching=1, batched=args.batched)
+    # the contexts share the host: each plans its instances on half the
+    # host threads when several run at once
+    ncpu = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+    host_threads = ncpu if args.workers <= 1 else max(1, ncpu // 2)
+    opts = B.Options(log2_target=10, residues_per_pass=3, branching=1, batched=args.batched,
+                     host_threads=host_threads)
     T = max(1, args.workers)
     Bsz = max(1, args.batch_size)
     ctxs = [B.Context(opts) for _ in range(T)]
@@ -220,6 +225,7 @@ def main():
                 return
             results[i] = solve_step(c, i)
 
+    ru0 = os.times()
     t0 = time.perf_counter()
     if T == 1:
         worker(ctxs[0])
@@ -231,6 +237,8 @@ def main():
             t.join()
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    ru1 = os.times()
+    host_cpu_s = (ru1.user - ru0.user) + (ru1.system - ru0.system)
     exact = 0
     leaves = 0
     n_inst = 0
@@ -277,7 +285,8 @@ def main():
                                "call solving %d instance(s), %d concurrent contexts" % (Bsz, T),
                    "instances": n_inst, "exact": exact,
                    "leaves_per_instance": round(leaves / max(n_inst, 1), 1),
-                   "batched": args.batched, "batch_size": Bsz, "workers": T},
+                   "batched": args.batched, "batch_size": Bsz, "workers": T,
+                   "host_threads_per_context": host_threads},
         "roofline": {"bound": "alu", "kernel": dom,
                      "achieved": round(achieved / 1e12, 4), "peak": round(VALU_PEAK_OPS / 1e12, 2),
                      "unit": "TOP/s", "frac": round(achieved / VALU_PEAK_OPS, 5),
@@ -290,6 +299,11 @@ def main():
                         "GB_s": round(s["bytes"] / max(s["seconds"], 1e-12) / 1e9, 2)}
                     for n, s in stats.items()},
     }
+    # host CPU time of the process over the timed region, as a share of
+    # the wall time of all the host threads it may run on
+    ncpu = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+    line["host_cpu"] = {"seconds": round(host_cpu_s, 3), "cpus": ncpu,
+                        "utilisation": round(host_cpu_s / max(dt * ncpu, 1e-9), 3)}
     names = ["total", "build+plan", "search", "contraction", "crt+certification", "configuration"]
     line["phases_ms"] = {nm: round(1e3 * phases[i] / max(n_inst, 1), 3)
                          for i, nm in enumerate(names)}

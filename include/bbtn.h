@@ -90,6 +90,10 @@ typedef struct {
   double time_limit_s;       /* <= 0: none                                      */
   void* stream;              /* hipStream_t to run on, or NULL for the
                                 context's own stream                           */
+  int32_t host_threads;      /* host threads that plan the instances of a call
+                                (network build, order, search); <= 0: one per
+                                hardware thread.  Several contexts used
+                                concurrently share the host's cores.          */
 } bbtn_options;
 
 /* Result of a solve.  `count` and `config` are caller-owned. */

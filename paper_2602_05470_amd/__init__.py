@@ -38,7 +38,8 @@ class _Options(C.Structure):
                 ("region_max", C.c_int32), ("local_search", C.c_int32),
                 ("graphs", C.c_int32),
                 ("scorer_weights", C.c_char_p), ("autotune_cache", C.c_char_p),
-                ("time_limit_s", C.c_double), ("stream", C.c_void_p)]
+                ("time_limit_s", C.c_double), ("stream", C.c_void_p),
+                ("host_threads", C.c_int32)]
 
 
 class _Result(C.Structure):
@@ -160,12 +161,14 @@ class Options:
     autotune_cache: str | None = None
     time_limit_s: float = 0.0
     stream: int | None = None
+    host_threads: int = 0
 
     def _c(self):
         o = _Options()
         load().bbtn_default_options(C.byref(o))
         for f in ("device", "residues_per_pass", "max_primes", "log2_target", "branching",
-                  "batched", "region_max", "local_search", "graphs", "time_limit_s"):
+                  "batched", "region_max", "local_search", "graphs", "time_limit_s",
+                  "host_threads"):
             setattr(o, f, getattr(self, f))
         o.scorer_weights = self.scorer_weights.encode() if self.scorer_weights else None
         o.autotune_cache = self.autotune_cache.encode() if self.autotune_cache else None

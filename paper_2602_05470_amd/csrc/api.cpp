@@ -80,6 +80,7 @@ void bbtn_default_options(bbtn_options* o) {
   o->autotune_cache = nullptr;
   o->time_limit_s = 0;
   o->stream = nullptr;
+  o->host_threads = 0;
 }
 
 bbtn_status bbtn_create(const bbtn_options* opt, bbtn_ctx** out) {

@@ -470,7 +470,8 @@ void solve_instances(bbtn_ctx* ctx, std::vector<Instance>& insts) {
   // ---- planning: order, search and step programs, instances in parallel
   // (the learned scorer runs on the context's stream: one instance at a time)
   const bool scored = opt.branching == 2 && ctx->scorer_loaded;
-  const int threads = scored ? 1 : (int)std::max(1u, std::thread::hardware_concurrency());
+  const int hw = (int)std::max(1u, std::thread::hardware_concurrency());
+  const int threads = scored ? 1 : (opt.host_threads > 0 ? opt.host_threads : hw);
   parallel_for(N, threads, [&](size_t i) {
     Instance& in = insts[i];
     Work& w = W[i];
