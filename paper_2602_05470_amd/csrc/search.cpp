@@ -116,6 +116,45 @@ struct Searcher {
       nbr[v].erase(std::unique(nbr[v].begin(), nbr[v].end()), nbr[v].end());
     }
     dec.assign(tree.nodes.size(), 0);
+    // largest entry of every tensor of rank <= 3 under each constraint
+    // pattern (per variable: free, fixed to 0, fixed to 1)
+    tm_off.assign(net.tensors.size(), -1);
+    for (size_t i = 0; i < net.tensors.size(); ++i) {
+      const BaseTensor& T = net.tensors[i];
+      const int r = (int)T.vars.size();
+      if (r > 3) continue;
+      int patterns = 1;
+      for (int j = 0; j < r; ++j) patterns *= 3;
+      tm_off[i] = (int32_t)tm_tab.size();
+      for (int code = 0; code < patterns; ++code) {
+        uint32_t cmask = 0, cval = 0;
+        for (int j = 0, c = code; j < r; ++j, c /= 3)
+          if (c % 3) {
+            cmask |= 1u << j;
+            cval |= (uint32_t)(c % 3 - 1) << j;
+          }
+        int64_t best = INT64_MIN;
+        for (int64_t e = 0; e < T.size(); ++e)
+          if (((uint32_t)e & cmask) == cval && T.val[e] > NEG_CUT && T.val[e] > best) best = T.val[e];
+        tm_tab.push_back(best);
+      }
+    }
+  }
+
+  std::vector<int64_t> tm_tab;
+  std::vector<int32_t> tm_off;
+  // tensor_max of tensor t through the pattern table (same result)
+  int64_t tmax(int t, const std::vector<uint64_t>& fixed, const std::vector<uint8_t>& x,
+               const int32_t* rpos = nullptr, uint32_t rx = 0) const {
+    const BaseTensor& T = net.tensors[t];
+    if (tm_off[t] < 0) return tensor_max(T, fixed, x, rpos, rx);
+    int code = 0, mul = 1;
+    for (size_t j = 0; j < T.vars.size(); ++j, mul *= 3) {
+      const int v = T.vars[j];
+      if (rpos && rpos[j] >= 0) code += mul * (1 + (int)((rx >> rpos[j]) & 1u));
+      else if (bit_get(fixed, v)) code += mul * (1 + (x[v] & 1));
+    }
+    return tm_tab[tm_off[t] + code];
   }
 
   // rho reduction when the variables vs (all free at `n`) are fixed too.
@@ -147,6 +186,9 @@ struct Searcher {
     }
     if (total == 0) return 0.0;
     if (total == 1) return 1.0;
+    // one term: count * gamma^(-d) = 1 has the closed form gamma = count^(1/d)
+    if (terms.size() == 1)
+      return std::exp(std::log((double)terms[0].second) / (double)terms[0].first);
     double lam = 0;
     for (int it = 0; it < 60; ++it) {
       double f = -1, df = 0;
@@ -221,7 +263,7 @@ struct Searcher {
       if (cross)
         for (size_t j = 0; j < T.vars.size(); ++j)
           if (e_rpos[e_rpos_off[i] + j] >= 0) bmask |= 1u << e_rpos[e_rpos_off[i] + j];
-      e_base[i] = tensor_max(T, n.fixed, n.x);
+      e_base[i] = tmax(tt[i], n.fixed, n.x);
     }
     e_rpos_off[nt] = (int32_t)e_rpos.size();
     const uint32_t nx = 1u << r;
@@ -243,7 +285,7 @@ struct Searcher {
       for (uint32_t y = 0; y < (1u << nj); ++y) {
         uint32_t rx = 0;
         for (int q = 0; q < nj; ++q) rx |= ((y >> q) & 1u) << e_tpos[e_tpos_off[i] + q];
-        e_tval.push_back(tensor_max(T, n.fixed, n.x, rp, rx));
+        e_tval.push_back(tmax(tt[i], n.fixed, n.x, rp, rx));
       }
     }
     e_tpos_off[nt] = (int32_t)e_tpos.size();
@@ -434,7 +476,7 @@ struct Searcher {
     tt.erase(std::unique(tt.begin(), tt.end()), tt.end());
     std::vector<int64_t>& base_max = c_base;
     base_max.resize(tt.size());
-    for (size_t i = 0; i < tt.size(); ++i) base_max[i] = tensor_max(net.tensors[tt[i]], n.fixed, n.x);
+    for (size_t i = 0; i < tt.size(); ++i) base_max[i] = tmax(tt[i], n.fixed, n.x);
     for (int ci = (int)best.cubes.size() - 1; ci >= 0; --ci) {
       const Cube& c = best.cubes[ci];
       Node ch = take();
@@ -457,7 +499,7 @@ struct Searcher {
         for (int v : T.vars)
           if (std::find(newly.begin(), newly.end(), v) != newly.end()) { hit = true; break; }
         if (!hit) continue;
-        const int64_t m = tensor_max(T, ch.fixed, ch.x);
+        const int64_t m = tmax(tt[i], ch.fixed, ch.x);
         b = (m == INT64_MIN) ? INT64_MIN : b + (m - base_max[i]);
       }
       ch.bound = b;
