@@ -713,9 +713,9 @@ std::vector<uint8_t> local_search_spinglass(int32_t n, int32_t m, const int32_t*
                                             uint64_t seed) {
   // simulated annealing (single-spin Metropolis updates, geometric
   // temperature schedule), then zero-temperature sweeps; one restart per 100
-  // sweeps.  Acceptance probabilities come from a per-sweep table of
-  // exp(-dE/T) for small dE.  Neighbours in compressed rows (edge order),
-  // spins as bytes: a new best state is a 1-byte-per-spin copy.
+  // sweeps.  Acceptance probabilities exp(-dE/T) for small dE are tabulated
+  // per sweep as they are first needed.  Neighbours in compressed rows (edge
+  // order), spins as bytes: a new best state is a 1-byte-per-spin copy.
   std::vector<int32_t> row(n + 1, 0), nb(2 * (size_t)m), wj(2 * (size_t)m);
   for (int e = 0; e < m; ++e) {
     row[uv[2 * e] + 1]++;
@@ -745,6 +745,7 @@ std::vector<uint8_t> local_search_spinglass(int32_t n, int32_t m, const int32_t*
   const int per = std::max(1, std::min(sweeps, 100));
   constexpr int TAB = 64;
   double acc[TAB];
+  int acc_sweep[TAB];  // sweep whose temperature acc[d] was formed for
   std::vector<int8_t> s(n);
   for (int rs = 0; rs < restarts; ++rs) {
     for (int i = 0; i < n; ++i) s[i] = (rng() & 1) ? 1 : -1;
@@ -752,13 +753,20 @@ std::vector<uint8_t> local_search_spinglass(int32_t n, int32_t m, const int32_t*
     const double T0 = 2.0, T1 = 0.05;
     for (int sw = 0; sw < per + 10; ++sw) {
       const double T = sw < per ? T0 * std::pow(T1 / T0, (double)sw / std::max(1, per - 1)) : 0.0;
-      for (int d = 0; d < TAB; ++d) acc[d] = T > 0 ? std::exp(-(double)d / T) : 0.0;
+      const int tag = rs * (per + 10) + sw;
+      if (tag == 0)
+        for (int d = 0; d < TAB; ++d) acc_sweep[d] = -1;
       for (int i = 0; i < n; ++i) {
         int64_t f = h ? h[i] : 0;
         for (int q = row[i]; q < row[i + 1]; ++q) f += (int64_t)wj[q] * s[nb[q]];
         const int64_t dE = 2 * s[i] * f;
         bool flip = dE <= 0;
         if (!flip && T > 0) {
+          // exp(-dE/T), formed the first time this sweep needs it
+          if (dE < TAB && acc_sweep[dE] != tag) {
+            acc[dE] = std::exp(-(double)dE / T);
+            acc_sweep[dE] = tag;
+          }
           const double p = dE < TAB ? acc[dE] : std::exp(-(double)dE / T);
           flip = (double)(rng() >> 11) * 0x1.0p-53 < p;
         }
