@@ -35,6 +35,10 @@ __device__ __forceinline__ uint32_t pmod(uint64_t x, uint32_t p, uint32_t c) {
   return (uint32_t)x;
 }
 
+__device__ __forceinline__ int32_t max3i(int32_t a, int32_t b, int32_t c) {
+  return max(max(a, b), c);
+}
+
 template <int KR>
 __device__ __forceinline__ void combine(int32_t& v, uint32_t* r, int32_t v2, const uint32_t* r2,
                                         const Moduli& m) {
@@ -276,13 +280,29 @@ persist_kernel(const PersistArgs a) {
           const int32_t* Av = (const int32_t*)la + abase;
           const int32_t* Bv = (const int32_t*)lb + bbase;
           int32_t V[4] = {INT32_MIN, INT32_MIN, INT32_MIN, INT32_MIN};
-          for (int q = 0; q < K; ++q) {
-            const int32_t av = Av[q];
-            const int4 bv = *(const int4*)(Bv + (q << rn));
-            V[0] = max(V[0], av + bv.x);
-            V[1] = max(V[1], av + bv.y);
-            V[2] = max(V[2], av + bv.z);
-            V[3] = max(V[3], av + bv.w);
+          if (K >= 4) {
+            // four K steps at a time: one 16-byte read of A (its row starts
+            // at a multiple of K), four of B, two three-way maxima per output
+            for (int q = 0; q < K; q += 4) {
+              const int4 a4 = *(const int4*)(Av + q);
+              const int4 b0 = *(const int4*)(Bv + (q << rn));
+              const int4 b1 = *(const int4*)(Bv + ((q + 1) << rn));
+              const int4 b2 = *(const int4*)(Bv + ((q + 2) << rn));
+              const int4 b3 = *(const int4*)(Bv + ((q + 3) << rn));
+              V[0] = max3i(max3i(V[0], a4.x + b0.x, a4.y + b1.x), a4.z + b2.x, a4.w + b3.x);
+              V[1] = max3i(max3i(V[1], a4.x + b0.y, a4.y + b1.y), a4.z + b2.y, a4.w + b3.y);
+              V[2] = max3i(max3i(V[2], a4.x + b0.z, a4.y + b1.z), a4.z + b2.z, a4.w + b3.z);
+              V[3] = max3i(max3i(V[3], a4.x + b0.w, a4.y + b1.w), a4.z + b2.w, a4.w + b3.w);
+            }
+          } else {
+            for (int q = 0; q < K; ++q) {
+              const int32_t av = Av[q];
+              const int4 bv = *(const int4*)(Bv + (q << rn));
+              V[0] = max(V[0], av + bv.x);
+              V[1] = max(V[1], av + bv.y);
+              V[2] = max(V[2], av + bv.z);
+              V[3] = max(V[3], av + bv.w);
+            }
           }
           uint32_t res[4][KR > 0 ? KR : 1];
           if constexpr (KR > 0) {
