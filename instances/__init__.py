@@ -10,6 +10,8 @@ Workload families (the paper's Applications section):
   * King's subgraph (KSG): an L x L grid whose sites are kept with
     probability `fill` (0.8 in the paper), with edges between kept sites that
     are a king move apart; unit or integer vertex weights.
+  * +-J spin glass on a random 3-regular graph and on an open cubic lattice
+    (the other topologies of the paper's spin-glass experiments).
   * random tensors in the device encoding of the counting tropical algebra
     (int32 value plane + residues modulo 31-bit primes), with planted ties and
     "minus infinity" entries, for kernel-level parity tests.
@@ -60,6 +62,59 @@ def spin_glass_square(L: int, seed: int, field: int = 0):
                 edges=np.asarray(edges, dtype=np.int32).reshape(-1, 2),
                 J=np.asarray(J, dtype=np.int32),
                 h=np.full(n, field, dtype=np.int32))
+
+
+def spin_glass_random_regular(n: int, seed: int, degree: int = 3):
+    """+-J spin glass on a random `degree`-regular simple graph with n sites.
+
+    Pairing model: the n * degree half-edges (site i appears `degree` times)
+    are shuffled with numpy's default_rng(seed) and paired in order; a
+    pairing with a self-loop or a repeated pair is drawn again from the same
+    generator.  Then couplings uniform in {-1, +1}, one per edge in pairing
+    order (edge = (smaller id, larger id)).
+
+    Returns dict(n, edges[m,2] int32, J[m] int32, h[n] int32 (zero)).
+    """
+    assert n * degree % 2 == 0 and degree < n
+    rng = np.random.default_rng(seed)
+    stubs = np.repeat(np.arange(n), degree)
+    while True:
+        rng.shuffle(stubs)
+        pairs = stubs.reshape(-1, 2)
+        a = np.minimum(pairs[:, 0], pairs[:, 1])
+        b = np.maximum(pairs[:, 0], pairs[:, 1])
+        if np.all(a != b) and len(set(zip(a.tolist(), b.tolist()))) == len(a):
+            break
+    J = rng.choice([-1, 1], size=len(a))
+    return dict(n=n, edges=np.stack([a, b], axis=1).astype(np.int32),
+                J=J.astype(np.int32), h=np.zeros(n, dtype=np.int32))
+
+
+def spin_glass_cubic(Lx: int, Ly: int, Lz: int, seed: int):
+    """+-J spin glass on an Lx x Ly x Lz open-boundary cubic lattice.
+
+    Site p = (x * Ly + y) * Lz + z.  Edges per site in order: +z, +y, +x
+    neighbour (when inside the box), couplings uniform in {-1, +1} drawn in
+    edge order from numpy's default_rng(seed).
+
+    Returns dict(n, edges[m,2] int32, J[m] int32, h[n] int32 (zero)).
+    """
+    edges = []
+    for x in range(Lx):
+        for y in range(Ly):
+            for z in range(Lz):
+                p = (x * Ly + y) * Lz + z
+                if z + 1 < Lz:
+                    edges.append((p, p + 1))
+                if y + 1 < Ly:
+                    edges.append((p, p + Lz))
+                if x + 1 < Lx:
+                    edges.append((p, p + Ly * Lz))
+    rng = np.random.default_rng(seed)
+    J = rng.choice([-1, 1], size=len(edges))
+    n = Lx * Ly * Lz
+    return dict(n=n, edges=np.asarray(edges, dtype=np.int32).reshape(-1, 2),
+                J=J.astype(np.int32), h=np.zeros(n, dtype=np.int32))
 
 
 def spin_glass_rect(Lr: int, Lc: int, seed: int):
