@@ -757,9 +757,10 @@ std::vector<uint8_t> local_search_spinglass(int32_t n, int32_t m, const int32_t*
       if (tag == 0)
         for (int d = 0; d < TAB; ++d) acc_sweep[d] = -1;
       for (int i = 0; i < n; ++i) {
-        int64_t f = h ? h[i] : 0;
-        for (int q = row[i]; q < row[i + 1]; ++q) f += (int64_t)wj[q] * s[nb[q]];
-        const int64_t dE = 2 * s[i] * f;
+        // |J| + |h| sums are below 2^27, so local fields fit 32 bits
+        int32_t f = h ? h[i] : 0;
+        for (int q = row[i]; q < row[i + 1]; ++q) f += wj[q] * s[nb[q]];
+        const int32_t dE = 2 * s[i] * f;
         bool flip = dE <= 0;
         if (!flip && T > 0) {
           // exp(-dE/T), formed the first time this sweep needs it
