@@ -238,8 +238,10 @@ struct Searcher {
     std::vector<int32_t>& tt = e_tt;
     tt.clear();
     for (int v : R) tt.insert(tt.end(), var_tensors[v].begin(), var_tensors[v].end());
-    std::sort(tt.begin(), tt.end());
-    tt.erase(std::unique(tt.begin(), tt.end()), tt.end());
+    if (R.size() > 1) {  // one variable's tensor list is already ascending
+      std::sort(tt.begin(), tt.end());
+      tt.erase(std::unique(tt.begin(), tt.end()), tt.end());
+    }
     const size_t nt = tt.size();
     // per touching tensor: region positions of its vars; inside/cross; base max
     e_rpos.clear();
@@ -544,85 +546,143 @@ struct Searcher {
     g.count++;
   }
 
+  // The node being expanded: fixed set, states and sizes are changed in
+  // place on the way down and restored on the way up (a child differs from
+  // its parent by the few variables of one cube).  Depth-first, children in
+  // cube order: the same visiting order as an explicit stack with the first
+  // cube on top.
+  Node cur;
+  std::vector<double> heur, score;
+
+  // the branching rule of the current node (empty cubes: nothing to branch)
+  Eval rule_of() {
+    Eval best;
+    // Nodes with the same fixed-variable set have the same rho structure.
+    // When the rule chosen for an earlier such node pruned nothing, try it
+    // first: if it again prunes nothing it is taken as is (the branches
+    // are complete and disjoint either way; only the choice of rule is
+    // shared).
+    auto memo = rule_memo.find(cur.fixed);
+    if (memo != rule_memo.end()) {
+      Eval ev = evaluate(cur, memo->second);
+      if (ev.cubes.size() == ((size_t)1 << memo->second.size())) best = std::move(ev);
+    }
+    if (best.cubes.empty()) {
+      // overflow participation of every free variable
+      std::vector<int32_t> cand;
+      heuristic(cur, heur, cand);
+      if (cand.empty()) throw Error(BBTN_E_INTERNAL, "rho > 0 but no overflowing variable");
+      // seeds: the heuristic's two best candidates; with the learned
+      // scorer, its best candidate and the heuristic's best (the scorer
+      // ranks seeds only; regions always grow in the heuristic's order,
+      // the order its training labels were measured with)
+      std::stable_sort(cand.begin(), cand.end(), [&](int a, int b) {
+        if (heur[a] != heur[b]) return heur[a] > heur[b];
+        return a < b;
+      });
+      std::vector<int32_t> seeds;
+      if (opt.scorer) {
+        score = heur;
+        opt.scorer(cur.fixed, cur.sizes, heur, score);
+        std::vector<int32_t> by_score(cand);
+        std::stable_sort(by_score.begin(), by_score.end(),
+                         [&](int a, int b) { return score[a] > score[b]; });
+        seeds.push_back(by_score[0]);
+        if (cand[0] != by_score[0]) seeds.push_back(cand[0]);
+        else if (by_score.size() > 1) seeds.push_back(by_score[1]);
+      } else {
+        for (int si = 0; si < std::min<int>(2, (int)cand.size()); ++si) seeds.push_back(cand[si]);
+      }
+      for (int sd : seeds) {
+        Eval ev = best_from_seed(cur, sd, heur);
+        if (better(ev, best)) best = std::move(ev);
+        if (best.gamma == 0.0) break;  // every configuration pruned
+      }
+      if (!best.cubes.empty() && best.cubes.size() == ((size_t)1 << best.region.size()))
+        rule_memo[cur.fixed] = best.region;
+    }
+    return best;
+  }
+
+  void visit(std::vector<LeafGroup>& leaves, SearchStats& st) {
+    if (opt.deadline > 0 && now_s() > opt.deadline)
+      throw Error(BBTN_E_TIMEOUT, "time limit reached during the search");
+    st.nodes++;
+    if (cur.rho == 0 || opt.log2_target <= 0) {
+      emit(cur, leaves);
+      st.leaves++;
+      return;
+    }
+    const Eval best = rule_of();
+    if (best.cubes.empty()) { st.pruned++; return; }
+    if (!std::isfinite(best.gamma)) throw Error(BBTN_E_INTERNAL, "no branching rule reduces rho");
+    st.gamma_sum += best.gamma;
+    // tensors touched by the region and their largest entries at the node
+    std::vector<int32_t> tt;
+    for (int v : best.region) tt.insert(tt.end(), var_tensors[v].begin(), var_tensors[v].end());
+    std::sort(tt.begin(), tt.end());
+    tt.erase(std::unique(tt.begin(), tt.end()), tt.end());
+    std::vector<int64_t> base_max(tt.size());
+    for (size_t i = 0; i < tt.size(); ++i) base_max[i] = tmax(tt[i], cur.fixed, cur.x);
+    const int64_t rho0 = cur.rho, bound0 = cur.bound;
+    std::vector<int32_t> newly;
+    for (const Cube& c : best.cubes) {
+      newly.clear();
+      for (int j = 0; j < (int)best.region.size(); ++j)
+        if (c.mask >> j & 1) {
+          const int v = best.region[j];
+          bit_set(cur.fixed, v);
+          cur.x[v] = (uint8_t)((c.val >> j) & 1);
+          newly.push_back(v);
+        }
+      // bound: only tensors holding a newly fixed variable change
+      int64_t b = bound0;
+      for (size_t i = 0; i < tt.size() && b != INT64_MIN; ++i) {
+        const BaseTensor& T = net.tensors[tt[i]];
+        bool hit = false;
+        for (int v : T.vars)
+          if (std::find(newly.begin(), newly.end(), v) != newly.end()) { hit = true; break; }
+        if (!hit) continue;
+        const int64_t m = tmax(tt[i], cur.fixed, cur.x);
+        b = (m == INT64_MIN) ? INT64_MIN : b + (m - base_max[i]);
+      }
+      if (b == INT64_MIN || b < opt.incumbent || (opt.values_only && b == opt.incumbent)) {
+        st.pruned++;
+      } else {
+        // sizes follow the fixed set for a node that branches again; a leaf
+        // (rho = 0) only needs its fixed states
+        const int64_t* d = best.drho_of(c.mask);
+        const bool leaf = d && rho0 - *d == 0;
+        if (!leaf)
+          for (int v : newly)
+            for (int id : tree.var_nodes[v]) cur.sizes[id]--;
+        cur.rho = leaf ? 0 : (d ? rho0 - *d : rho_of(tree, cur.sizes, opt.log2_target));
+        cur.bound = b;
+        visit(leaves, st);
+        if (!leaf)
+          for (int v : newly)
+            for (int id : tree.var_nodes[v]) cur.sizes[id]++;
+      }
+      for (int v : newly) cur.fixed[v >> 6] &= ~(1ull << (v & 63));
+    }
+    cur.rho = rho0;
+    cur.bound = bound0;
+  }
+
   void run(std::vector<LeafGroup>& leaves, SearchStats& st) {
-    Node root;
-    root.fixed.assign((net.n + 63) / 64, 0);
-    root.x.assign(net.n, 0);
-    root.sizes = node_sizes(tree, root.fixed);
-    root.rho = rho_of(tree, root.sizes, opt.log2_target);
-    root.bound = node_bound(net, root.fixed, root.x);
-    if (root.bound < opt.incumbent || root.bound == INT64_MIN ||
-        (opt.values_only && root.bound == opt.incumbent)) {
+    cur.fixed.assign((net.n + 63) / 64, 0);
+    cur.x.assign(net.n, 0);
+    cur.sizes = node_sizes(tree, cur.fixed);
+    cur.rho = rho_of(tree, cur.sizes, opt.log2_target);
+    cur.bound = node_bound(net, cur.fixed, cur.x);
+    if (cur.bound < opt.incumbent || cur.bound == INT64_MIN ||
+        (opt.values_only && cur.bound == opt.incumbent)) {
       st.pruned++;
       return;
     }
-    std::vector<Node> stack;
-    stack.push_back(std::move(root));
-    std::vector<double> heur(net.n), score(net.n);
-    while (!stack.empty()) {
-      if (opt.deadline > 0 && now_s() > opt.deadline)
-        throw Error(BBTN_E_TIMEOUT, "time limit reached during the search");
-      Node n = std::move(stack.back());
-      stack.pop_back();
-      st.nodes++;
-      if (n.rho == 0 || opt.log2_target <= 0) {
-        emit(n, leaves);
-        st.leaves++;
-        spare.push_back(std::move(n));
-        continue;
-      }
-      Eval best;
-      // Nodes with the same fixed-variable set have the same rho structure.
-      // When the rule chosen for an earlier such node pruned nothing, try it
-      // first: if it again prunes nothing it is taken as is (the branches
-      // are complete and disjoint either way; only the choice of rule is
-      // shared).
-      auto memo = rule_memo.find(n.fixed);
-      if (memo != rule_memo.end()) {
-        Eval ev = evaluate(n, memo->second);
-        if (ev.cubes.size() == ((size_t)1 << memo->second.size())) best = std::move(ev);
-      }
-      if (best.cubes.empty()) {
-        // overflow participation of every free variable
-        std::vector<int32_t> cand;
-        heuristic(n, heur, cand);
-        if (cand.empty()) throw Error(BBTN_E_INTERNAL, "rho > 0 but no overflowing variable");
-        // seeds: the heuristic's two best candidates; with the learned
-        // scorer, its best candidate and the heuristic's best (the scorer
-        // ranks seeds only; regions always grow in the heuristic's order,
-        // the order its training labels were measured with)
-        std::stable_sort(cand.begin(), cand.end(), [&](int a, int b) {
-          if (heur[a] != heur[b]) return heur[a] > heur[b];
-          return a < b;
-        });
-        std::vector<int32_t> seeds;
-        if (opt.scorer) {
-          score = heur;
-          opt.scorer(n.fixed, n.sizes, heur, score);
-          std::vector<int32_t> by_score(cand);
-          std::stable_sort(by_score.begin(), by_score.end(),
-                           [&](int a, int b) { return score[a] > score[b]; });
-          seeds.push_back(by_score[0]);
-          if (cand[0] != by_score[0]) seeds.push_back(cand[0]);
-          else if (by_score.size() > 1) seeds.push_back(by_score[1]);
-        } else {
-          for (int si = 0; si < std::min<int>(2, (int)cand.size()); ++si) seeds.push_back(cand[si]);
-        }
-        for (int sd : seeds) {
-          Eval ev = best_from_seed(n, sd, heur);
-          if (better(ev, best)) best = std::move(ev);
-          if (best.gamma == 0.0) break;  // every configuration pruned
-        }
-        if (!best.cubes.empty() && best.cubes.size() == ((size_t)1 << best.region.size()))
-          rule_memo[n.fixed] = best.region;
-      }
-      if (best.cubes.empty()) { st.pruned++; spare.push_back(std::move(n)); continue; }
-      if (!std::isfinite(best.gamma)) throw Error(BBTN_E_INTERNAL, "no branching rule reduces rho");
-      st.gamma_sum += best.gamma;
-      // children, first cube on top of the stack
-      children(n, best, stack, st);
-      spare.push_back(std::move(n));
-    }
+    heur.assign(net.n, 0);
+    score.assign(net.n, 0);
+    visit(leaves, st);
   }
 };
 
