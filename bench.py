@@ -159,6 +159,9 @@ def main():
     ap.add_argument("--workers", type=int, default=3,
                     help="concurrent solver contexts (threads, one stream each): one "
                          "call's host planning overlaps another's contraction")
+    ap.add_argument("--host-threads", type=int, default=0,
+                    help="planning threads per call; 0: all host threads with one context, "
+                         "half of them with several")
     ap.add_argument("--batch-size", type=int, default=160,
                     help="instances per call (bbtn_solve_batch when > 1): their branch "
                          "sub-networks share every device launch")
@@ -186,9 +189,10 @@ def main():
     want = golden_sg16()
     insts = [I.spin_glass_square(16, s) for s in range(N_SEEDS)]
     # the contexts share the host: each plans its instances on half the
-    # host threads when several run at once
+    # host threads when several run at once (unless --host-threads is given)
     ncpu = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
-    host_threads = ncpu if args.workers <= 1 else max(1, ncpu // 2)
+    host_threads = args.host_threads if args.host_threads > 0 else (
+        ncpu if args.workers <= 1 else max(1, ncpu // 2))
     opts = B.Options(log2_target=10, residues_per_pass=3, branching=1, batched=args.batched,
                      host_threads=host_threads)
     T = max(1, args.workers)
