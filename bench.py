@@ -227,8 +227,11 @@ def main():
                 nxt[0] += 1
             if i >= args.steps:
                 return
+            ts = time.perf_counter()
             results[i] = solve_step(c, i)
+            call_s[i] = time.perf_counter() - ts
 
+    call_s = [0.0] * args.steps
     ru0 = os.times()
     t0 = time.perf_counter()
     if T == 1:
@@ -309,6 +312,12 @@ def main():
     line["host_cpu"] = {"seconds": round(host_cpu_s, 3), "cpus": ncpu,
                         "utilisation": round(host_cpu_s / max(dt * ncpu, 1e-9), 3)}
     names = ["total", "build+plan", "search", "contraction", "crt+certification", "configuration"]
+    # latency of one call (all its instances), over the timed steps; an
+    # instance counts as unsolved when its result is not exact and certified
+    cs = sorted(call_s)
+    line["latency_ms"] = {"per_call_p50": round(1e3 * cs[len(cs) // 2], 3),
+                          "per_call_max": round(1e3 * cs[-1], 3),
+                          "unsolved": n_inst - exact}
     line["phases_ms"] = {nm: round(1e3 * phases[i] / max(n_inst, 1), 3)
                          for i, nm in enumerate(names)}
     if not args.no_per_branch:
