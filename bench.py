@@ -167,7 +167,7 @@ def main():
                          "sub-networks share every device launch")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py runs on exactly one GPU: this build's path is single-GPU "
+        print("bench.py runs on exactly one GPU: the solver path is single-GPU "
               "(--gpus %d requested)" % args.gpus, file=sys.stderr)
         sys.exit(2)
     import torch

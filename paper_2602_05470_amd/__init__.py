@@ -93,7 +93,7 @@ def load(path: str = LIB_PATH):
     if _lib is not None:
         return _lib
     if not os.path.exists(path):
-        raise RuntimeError("libbbtn.so is not built (%s); run __graft_entry__.build()" % path)
+        raise RuntimeError("libbbtn.so is not built (%s); run paper_2602_05470_amd.build.build()" % path)
     lib = C.CDLL(path)
     P, I32, I64, U64 = C.c_void_p, C.c_int32, C.c_int64, C.c_uint64
     lib.bbtn_default_options.argtypes = [C.POINTER(_Options)]
