@@ -162,6 +162,11 @@ def main():
     ap.add_argument("--host-threads", type=int, default=0,
                     help="planning threads per call; 0: all host threads with one context, "
                          "half of them with several")
+    ap.add_argument("--order-refine", type=int, default=0,
+                    help="contraction order of the main run: 0 = greedy (the workload's "
+                         "plain BBTN); n > 0 = best of greedy and n annealed refinements")
+    ap.add_argument("--no-refined-order", action="store_true",
+                    help="skip the second run of the same workload with a refined order")
     ap.add_argument("--batch-size", type=int, default=160,
                     help="instances per call (bbtn_solve_batch when > 1): their branch "
                          "sub-networks share every device launch")
@@ -194,7 +199,7 @@ def main():
     host_threads = args.host_threads if args.host_threads > 0 else (
         ncpu if args.workers <= 1 else max(1, ncpu // 2))
     opts = B.Options(log2_target=10, residues_per_pass=3, branching=1, batched=args.batched,
-                     host_threads=host_threads)
+                     host_threads=host_threads, order_refine=args.order_refine)
     T = max(1, args.workers)
     Bsz = max(1, args.batch_size)
     ctxs = [B.Context(opts) for _ in range(T)]
@@ -209,43 +214,47 @@ def main():
                                   for s in seeds])
         return seeds, rs
 
-    # warm-up: every worker context runs `warmup` steps (workspace growth,
-    # code loading) before the clock starts
-    for c in ctxs:
-        for i in range(args.warmup):
-            solve_step(c, i)
-        c.profile(True)
-    torch.cuda.synchronize()
-    lock = threading.Lock()
-    nxt = [0]
-    results = [None] * args.steps
+    def timed(cs, profile):
+        """Warm-up steps on every context (workspace growth, code loading, the
+        order cache), then `steps` calls shared by the contexts' threads."""
+        for c in cs:
+            for i in range(args.warmup):
+                solve_step(c, i)
+            if profile:
+                c.profile(True)
+        torch.cuda.synchronize()
+        lock = threading.Lock()
+        nxt = [0]
+        res = [None] * args.steps
+        lat = [0.0] * args.steps
 
-    def worker(c):
-        while True:
-            with lock:
-                i = nxt[0]
-                nxt[0] += 1
-            if i >= args.steps:
-                return
-            ts = time.perf_counter()
-            results[i] = solve_step(c, i)
-            call_s[i] = time.perf_counter() - ts
+        def worker(c):
+            while True:
+                with lock:
+                    i = nxt[0]
+                    nxt[0] += 1
+                if i >= args.steps:
+                    return
+                ts = time.perf_counter()
+                res[i] = solve_step(c, i)
+                lat[i] = time.perf_counter() - ts
 
-    call_s = [0.0] * args.steps
-    ru0 = os.times()
-    t0 = time.perf_counter()
-    if T == 1:
-        worker(ctxs[0])
-    else:
-        th = [threading.Thread(target=worker, args=(c,)) for c in ctxs]
-        for t in th:
-            t.start()
-        for t in th:
-            t.join()
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    ru1 = os.times()
-    host_cpu_s = (ru1.user - ru0.user) + (ru1.system - ru0.system)
+        r0 = os.times()
+        ta = time.perf_counter()
+        if len(cs) == 1:
+            worker(cs[0])
+        else:
+            th = [threading.Thread(target=worker, args=(c,)) for c in cs]
+            for t in th:
+                t.start()
+            for t in th:
+                t.join()
+        torch.cuda.synchronize()
+        tb = time.perf_counter()
+        r1 = os.times()
+        return res, lat, tb - ta, (r1.user - r0.user) + (r1.system - r0.system)
+
+    results, call_s, dt, host_cpu_s = timed(ctxs, True)
     exact = 0
     leaves = 0
     n_inst = 0
@@ -270,7 +279,6 @@ def main():
     for c in ctxs:
         c.profile(False)
     ctx = ctxs[0]
-    dt = t1 - t0
     dom = max(stats, key=lambda n: stats[n]["seconds"])
     st = stats[dom]
     achieved = st["ops"] / max(st["seconds"], 1e-12)
@@ -293,7 +301,9 @@ def main():
                    "instances": n_inst, "exact": exact,
                    "leaves_per_instance": round(leaves / max(n_inst, 1), 1),
                    "batched": args.batched, "batch_size": Bsz, "workers": T,
-                   "host_threads_per_context": host_threads},
+                   "host_threads_per_context": host_threads,
+                   "contraction_order": "greedy" if args.order_refine == 0 else
+                                        "refined (%d candidates)" % args.order_refine},
         "roofline": {"bound": "alu", "kernel": dom,
                      "achieved": round(achieved / 1e12, 4), "peak": round(VALU_PEAK_OPS / 1e12, 2),
                      "unit": "TOP/s", "frac": round(achieved / VALU_PEAK_OPS, 5),
@@ -320,6 +330,30 @@ def main():
                           "unsolved": n_inst - exact}
     line["phases_ms"] = {nm: round(1e3 * phases[i] / max(n_inst, 1), 3)
                          for i, nm in enumerate(names)}
+    if not args.no_refined_order and args.order_refine == 0:
+        # the same workload and settings with the contraction order refined
+        # by annealing (8 candidates, chosen once for the lattice during the
+        # warm-up): fewer and cheaper leaves
+        ro = B.Options(log2_target=10, residues_per_pass=3, branching=1, batched=args.batched,
+                       host_threads=host_threads, order_refine=8)
+        rctx = [B.Context(ro) for _ in range(T)]
+        rres, rlat, rdt, rcpu = timed(rctx, False)
+        for c in rctx:
+            c.close()
+        r_ok = r_n = r_leaves = 0
+        for seeds, rs in rres:
+            for s_, r in zip(seeds, rs):
+                r_n += 1
+                r_leaves += r.leaves
+                r_ok += (r.value, r.count) == want[s_] and r.certified
+        line["refined_order"] = {
+            "value": round(3600.0 * r_ok / rdt, 1), "unit": "instances/hour",
+            "instances": r_n, "exact": r_ok,
+            "leaves_per_instance": round(r_leaves / max(r_n, 1), 1),
+            "ms_per_step": round(1e3 * rdt / args.steps, 3),
+            "host_cpu_utilisation": round(rcpu / max(rdt * ncpu, 1e-9), 3),
+            "note": "order_refine=8: best of the greedy tree and 8 annealed refinements, "
+                    "scored by a probe search"}
     if not args.no_per_branch:
         # the same path without batching: one branch at a time (step programs
         # replayed from a hipGraph), on the first instances

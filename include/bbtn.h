@@ -94,6 +94,12 @@ typedef struct {
                                 (network build, order, search); <= 0: one per
                                 hardware thread.  Several contexts used
                                 concurrently share the host's cores.          */
+  int32_t order_refine;      /* 0: greedy contraction order; n > 0: also n
+                                annealed refinements of it (local rotations),
+                                each scored by a branch-and-bound search of the
+                                first instance of a structure; the cheapest
+                                (leaf MACs plus search nodes) is cached for the
+                                structure.  n <= 64.                           */
 } bbtn_options;
 
 /* Result of a solve.  `count` and `config` are caller-owned. */
@@ -290,10 +296,11 @@ bbtn_status bbtn_solve_batch(bbtn_ctx* ctx, int32_t kind, int32_t n_inst, const 
 
 /* The planner alone, on the host (ctx may be NULL; no device is used): build
  * the network of a spin-glass (kind 0: weights = J, h) or MWIS (kind 1:
- * weights = w, h unused) instance, order it greedily, take the local-search
- * incumbent (local_search sweeps; 0 = no incumbent) and run the
- * branch-and-bound search with T_target = 2^log2_target and regions of at
- * most region_max variables ("Branch-and-Bound Tensor Network" section).
+ * weights = w, h unused) instance, choose its contraction order (as the
+ * option order_refine does, with order_refine in [0, 64]; 0 = greedy), take
+ * the local-search incumbent (local_search sweeps; 0 = no incumbent) and run
+ * the branch-and-bound search with T_target = 2^log2_target and regions of
+ * at most region_max variables ("Branch-and-Bound Tensor Network" section).
  * values_only != 0 selects the values-only pruning of residues_per_pass = 0.
  * Leaf l is written to leaves[l*n .. l*n + n): -1 for a free variable, else
  * its fixed state (s, with s = 1 meaning sigma = +1; or x).  *n_leaves
@@ -304,8 +311,23 @@ bbtn_status bbtn_solve_batch(bbtn_ctx* ctx, int32_t kind, int32_t n_inst, const 
 bbtn_status bbtn_plan_leaves(bbtn_ctx* ctx, int32_t kind, int32_t n, int32_t m,
                              const int32_t* edge_uv, const int32_t* weights, const int32_t* h,
                              int32_t log2_target, int32_t region_max, int32_t local_search,
-                             int32_t values_only, int8_t* leaves, int64_t capacity,
-                             int64_t* n_leaves, int64_t* incumbent);
+                             int32_t values_only, int32_t order_refine, int8_t* leaves,
+                             int64_t capacity, int64_t* n_leaves, int64_t* incumbent);
+
+/* Complexity of the contraction order the planner uses for an instance
+ * (host only, no context; "Tropical Tensor Networks" section): the order is
+ * chosen as bbtn_options.order_refine does (0: greedy; n in [1, 64]: the
+ * cheapest of the greedy tree and n annealed refinements, each scored by a
+ * branch-and-bound search with T_target = 2^log2_target and regions of at
+ * most region_max variables).  Outputs: *tc_log2 = log2 of the semiring
+ * multiply-accumulates of the unsliced contraction, *sc = log2 entries of
+ * its largest intermediate, *rho = the overflow measure of Eq. 4, the sum
+ * over intermediates of max(0, log2 size - log2_target).  Errors:
+ * BBTN_E_INVALID_ARG (bad graph, kind, sizes or NULL outputs). */
+bbtn_status bbtn_order_complexity(int32_t kind, int32_t n, int32_t m, const int32_t* edge_uv,
+                                  const int32_t* weights, const int32_t* h, int32_t order_refine,
+                                  int32_t log2_target, int32_t region_max, double* tc_log2,
+                                  int32_t* sc, int64_t* rho);
 
 /* Training data from the search itself: run the planner on an instance
  * (kind 0: spin glass with weights = J, h; kind 1: MWIS with weights = w)

@@ -39,7 +39,7 @@ class _Options(C.Structure):
                 ("graphs", C.c_int32),
                 ("scorer_weights", C.c_char_p), ("autotune_cache", C.c_char_p),
                 ("time_limit_s", C.c_double), ("stream", C.c_void_p),
-                ("host_threads", C.c_int32)]
+                ("host_threads", C.c_int32), ("order_refine", C.c_int32)]
 
 
 class _Result(C.Structure):
@@ -70,6 +70,7 @@ EXPORTS = ["bbtn_default_options", "bbtn_create", "bbtn_destroy", "bbtn_last_err
            "bbtn_reduce", "bbtn_bound", "bbtn_last_macs", "bbtn_profile",
            "bbtn_get_kernel_stats", "bbtn_mlp_forward", "bbtn_mlp_backward", "bbtn_mlp_adam",
            "bbtn_scorer_load", "bbtn_scorer_collect", "bbtn_scorer_train", "bbtn_plan_leaves",
+           "bbtn_order_complexity",
            "bbtn_solve_batch"]
 
 # scorer parameter layout (see include/bbtn.h)
@@ -133,9 +134,13 @@ def load(path: str = LIB_PATH):
     lib.bbtn_mlp_adam.restype = I32
     lib.bbtn_scorer_load.argtypes = [P, C.c_char_p]
     lib.bbtn_scorer_load.restype = I32
-    lib.bbtn_plan_leaves.argtypes = [P, I32, I32, I32, P, P, P, I32, I32, I32, I32, P, I64,
+    lib.bbtn_plan_leaves.argtypes = [P, I32, I32, I32, P, P, P, I32, I32, I32, I32, I32, P, I64,
                                      C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
     lib.bbtn_plan_leaves.restype = I32
+    lib.bbtn_order_complexity.argtypes = [I32, I32, I32, P, P, P, I32, I32, I32,
+                                          C.POINTER(C.c_double), C.POINTER(C.c_int32),
+                                          C.POINTER(C.c_int64)]
+    lib.bbtn_order_complexity.restype = I32
     lib.bbtn_scorer_collect.argtypes = [P, I32, I32, I32, P, P, P, I32, I32, I32, P, P, I64,
                                         C.POINTER(C.c_int64)]
     lib.bbtn_scorer_collect.restype = I32
@@ -162,13 +167,14 @@ class Options:
     time_limit_s: float = 0.0
     stream: int | None = None
     host_threads: int = 0
+    order_refine: int = 0
 
     def _c(self):
         o = _Options()
         load().bbtn_default_options(C.byref(o))
         for f in ("device", "residues_per_pass", "max_primes", "log2_target", "branching",
                   "batched", "region_max", "local_search", "graphs", "time_limit_s",
-                  "host_threads"):
+                  "host_threads", "order_refine"):
             setattr(o, f, getattr(self, f))
         o.scorer_weights = self.scorer_weights.encode() if self.scorer_weights else None
         o.autotune_cache = self.autotune_cache.encode() if self.autotune_cache else None
@@ -444,7 +450,7 @@ class Context:
 
 
 def plan_leaves(kind, n, edges, weights, h=None, log2_target=10, region_max=8, local_search=100,
-                values_only=False):
+                values_only=False, order_refine=0):
     """bbtn_plan_leaves without a device context: the leaves of the
     branch-and-bound search as an int8 array [leaves, n] (-1 = free, else the
     fixed state), and the local-search incumbent's value (None if none)."""
@@ -455,7 +461,7 @@ def plan_leaves(kind, n, edges, weights, h=None, log2_target=10, region_max=8, l
     nl = C.c_int64(0)
     inc = C.c_int64(0)
     args = (None, kind, n, len(edges), _ptr(edges), _ptr(w), _ptr(hh), log2_target, region_max,
-            local_search, int(bool(values_only)))
+            local_search, int(bool(values_only)), order_refine)
     s = lib.bbtn_plan_leaves(*args, None, 0, C.byref(nl), C.byref(inc))
     if s != 0:
         raise BBTNError(s, "bbtn_plan_leaves failed")
@@ -467,6 +473,25 @@ def plan_leaves(kind, n, edges, weights, h=None, log2_target=10, region_max=8, l
             raise BBTNError(s, "bbtn_plan_leaves failed")
     incumbent = None if inc.value == -(1 << 63) else int(inc.value)
     return out, incumbent
+
+
+def order_complexity(kind, n, edges, weights, h=None, order_refine=0, log2_target=10,
+                     region_max=8):
+    """bbtn_order_complexity: (tc_log2, sc, rho) of the contraction order the
+    planner uses for the instance (host only)."""
+    lib = load()
+    edges = _i32(edges).reshape(-1, 2)
+    w = None if weights is None else _i32(weights)
+    hh = None if h is None else _i32(h)
+    tc = C.c_double(0)
+    sc = C.c_int32(0)
+    rho = C.c_int64(0)
+    s = lib.bbtn_order_complexity(kind, n, len(edges), _ptr(edges), _ptr(w), _ptr(hh),
+                                  order_refine, log2_target, region_max, C.byref(tc),
+                                  C.byref(sc), C.byref(rho))
+    if s != 0:
+        raise BBTNError(s, "bbtn_order_complexity failed")
+    return tc.value, sc.value, rho.value
 
 
 def scorer_collect(kind, n, edges, weights, h=None, log2_target=10, max_nodes=64, cand_per_node=8):

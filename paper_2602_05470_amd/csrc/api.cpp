@@ -81,6 +81,7 @@ void bbtn_default_options(bbtn_options* o) {
   o->time_limit_s = 0;
   o->stream = nullptr;
   o->host_threads = 0;
+  o->order_refine = 0;
 }
 
 bbtn_status bbtn_create(const bbtn_options* opt, bbtn_ctx** out) {
@@ -373,17 +374,22 @@ bbtn_status bbtn_scorer_load(bbtn_ctx* ctx, const char* path) {
 bbtn_status bbtn_plan_leaves(bbtn_ctx* ctx, int32_t kind, int32_t n, int32_t m,
                              const int32_t* edge_uv, const int32_t* weights, const int32_t* h,
                              int32_t log2_target, int32_t region_max, int32_t local_search,
-                             int32_t values_only, int8_t* leaves, int64_t capacity,
-                             int64_t* n_leaves, int64_t* incumbent) {
+                             int32_t values_only, int32_t order_refine, int8_t* leaves,
+                             int64_t capacity, int64_t* n_leaves, int64_t* incumbent) {
   if (!n_leaves || !incumbent) return BBTN_E_INVALID_ARG;
   return guard(ctx, [&] {  // host-only: ctx may be NULL
     check_graph(n, m, edge_uv);
     BBTN_REQUIRE(kind == 0 || kind == 1, "kind must be 0 (spin glass) or 1 (MWIS)");
     BBTN_REQUIRE(log2_target > 0 && region_max >= 1 && local_search >= 0, "bad options");
+    BBTN_REQUIRE(order_refine >= 0 && order_refine <= 64, "order_refine must be in [0, 64]");
     if (kind == 0) BBTN_REQUIRE(weights != nullptr, "J is NULL");
     Network net = kind == 0 ? build_spinglass(n, m, edge_uv, weights, h)
                             : build_mwis(n, m, edge_uv, weights);
-    Tree tree = greedy_tree(net);
+    SearchOptions probe;
+    probe.log2_target = log2_target;
+    probe.region_max = std::min(16, region_max);
+    probe.values_only = values_only != 0;
+    Tree tree = choose_order(net, order_refine, probe);
     std::vector<uint8_t> x;
     if (local_search > 0)
       x = kind == 0 ? local_search_spinglass(n, m, edge_uv, weights, h, local_search, 12345)
@@ -411,6 +417,33 @@ bbtn_status bbtn_plan_leaves(bbtn_ctx* ctx, int32_t kind, int32_t n, int32_t m,
         for (size_t j = 0; j < g.vars.size(); ++j)
           out[g.vars[j]] = (int8_t)g.assign[(size_t)l * g.vars.size() + j];
       }
+  });
+}
+
+bbtn_status bbtn_order_complexity(int32_t kind, int32_t n, int32_t m, const int32_t* edge_uv,
+                                  const int32_t* weights, const int32_t* h, int32_t order_refine,
+                                  int32_t log2_target, int32_t region_max, double* tc_log2,
+                                  int32_t* sc, int64_t* rho) {
+  if (!tc_log2 || !sc || !rho) return BBTN_E_INVALID_ARG;
+  return guard(nullptr, [&] {
+    check_graph(n, m, edge_uv);
+    BBTN_REQUIRE(kind == 0 || kind == 1, "kind must be 0 (spin glass) or 1 (MWIS)");
+    BBTN_REQUIRE(log2_target > 0 && region_max >= 1, "bad options");
+    BBTN_REQUIRE(order_refine >= 0 && order_refine <= 64, "order_refine must be in [0, 64]");
+    if (kind == 0) BBTN_REQUIRE(weights != nullptr, "J is NULL");
+    Network net = kind == 0 ? build_spinglass(n, m, edge_uv, weights, h)
+                            : build_mwis(n, m, edge_uv, weights);
+    SearchOptions probe;
+    probe.log2_target = log2_target;
+    probe.region_max = std::min(16, region_max);
+    const Tree tree = choose_order(net, order_refine, probe);
+    const Complexity c = complexity(tree, {});
+    *tc_log2 = c.tc_log2;
+    *sc = c.sc;
+    int64_t r = 0;
+    for (int id : tree.postorder)
+      r += std::max(0, (int)tree.nodes[id].vars.size() - log2_target);
+    *rho = r;
   });
 }
 

@@ -120,6 +120,7 @@ struct bbtn_ctx {
            std::shared_ptr<const bbtn::GroupPlan>>
       plan_cache;
   std::mutex tree_mu;  // planning threads share both caches
+  std::mutex tree_build_mu;  // one refined order is built at a time
   // second context (own stream and workspaces) that recovers the optimal
   // configuration while this one runs the counting passes
   bbtn_ctx* aux = nullptr;

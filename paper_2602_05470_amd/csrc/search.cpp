@@ -1,5 +1,7 @@
 #include "search.h"
 
+#include <thread>
+
 #include "scorer.h"
 
 #include <chrono>
@@ -607,6 +609,8 @@ struct Searcher {
   void visit(std::vector<LeafGroup>& leaves, SearchStats& st) {
     if (opt.deadline > 0 && now_s() > opt.deadline)
       throw Error(BBTN_E_TIMEOUT, "time limit reached during the search");
+    if (opt.node_limit && st.nodes >= opt.node_limit->load(std::memory_order_relaxed))
+      throw Error(BBTN_E_TIMEOUT, "node limit reached during the search");
     st.nodes++;
     if (cur.rho == 0 || opt.log2_target <= 0) {
       emit(cur, leaves);
@@ -877,6 +881,58 @@ std::vector<uint8_t> local_search_mwis(int32_t n, int32_t m, const int32_t* uv,
     if (W > bestW) { bestW = W; best = x; }
   }
   return best;
+}
+
+// Candidate contraction trees for a structure when order refinement is on:
+// the greedy tree and `n` annealed refinements of it (seeds 1..n).  Each is
+// scored by a branch-and-bound search of `net` with `probe`: the semiring
+// MACs of its leaves (each leaf's sliced tree) plus a per-search-node weight
+// for the host's share, lowest score kept (the greedy tree on ties).  The
+// probes run in parallel, each stopped past 2^22 nodes; once one finishes
+// with N nodes, the others stop past 2N + 1024 nodes and are not chosen.  On
+// zero-field +-J lattices the leaves and MACs depend on the structure only,
+// so one instance's probe serves every instance of that structure.
+Tree choose_order(const Network& net, int n, const SearchOptions& probe) {
+  n = std::max(0, std::min(64, n));
+  if (n == 0) return greedy_tree(net);
+  constexpr double kNodeMacs = 131072.0;  // host time of a search node, in device MACs
+  std::vector<Tree> cand(n + 1);
+  std::vector<double> score(n + 1, HUGE_VAL);
+  cand[0] = greedy_tree(net);  // built before any thread reads it
+  std::atomic<uint64_t> limit{uint64_t(1) << 22};  // bounds the probes' time and memory
+  SearchOptions so = probe;
+  so.node_limit = &limit;
+  std::vector<std::thread> th;
+  for (int c = 0; c <= n; ++c)
+    th.emplace_back([&, c] {
+      if (c > 0) {
+        RefineOptions o;
+        o.sweeps = 200;
+        o.log2_target = probe.log2_target;
+        o.rho_weight = 0.25;
+        o.seed = (uint64_t)c;
+        cand[c] = refine_tree(net, cand[0], o);
+      }
+      std::vector<LeafGroup> groups;
+      SearchStats st;
+      try {
+        bb_search(net, cand[c], so, groups, st);
+      } catch (const std::exception&) {
+        return;  // this candidate cannot be planned (or was cut off): not chosen
+      }
+      const uint64_t mine = 2 * st.nodes + 1024;
+      uint64_t cur = limit.load();
+      while (mine < cur && !limit.compare_exchange_weak(cur, mine)) {
+      }
+      double macs = 0;
+      for (const auto& g : groups) macs += (double)g.count * std::exp2(complexity(cand[c], g.mask).tc_log2);
+      score[c] = macs + kNodeMacs * (double)st.nodes;
+    });
+  for (auto& t : th) t.join();
+  int best = 0;
+  for (int c = 1; c <= n; ++c)
+    if (score[c] < score[best]) best = c;
+  return std::move(cand[best]);
 }
 
 }  // namespace bbtn

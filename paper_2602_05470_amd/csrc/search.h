@@ -8,6 +8,7 @@
 // branches D(R) are disjoint cubes covering F(R), chosen to minimise the
 // branching factor gamma of the characteristic equation.
 #pragma once
+#include <atomic>
 #include <functional>
 #include <vector>
 #include "tree.h"
@@ -43,6 +44,9 @@ struct SearchOptions {
   // boundary equivalence keeps one optimal interior per boundary state
   bool values_only = false;
   double deadline = 0;            // absolute wall time (s) or 0
+  // when set: the search stops with BBTN_E_TIMEOUT once it has expanded more
+  // nodes than this (read at every node; may be lowered while it runs)
+  const std::atomic<uint64_t>* node_limit = nullptr;
   VarScorer scorer;
 };
 
@@ -73,5 +77,11 @@ std::vector<uint8_t> local_search_spinglass(int32_t n, int32_t m, const int32_t*
                                             uint64_t seed);
 std::vector<uint8_t> local_search_mwis(int32_t n, int32_t m, const int32_t* uv,
                                        const int32_t* w, int restarts, uint64_t seed);
+
+// The contraction order used for a structure: the greedy tree (n = 0) or the
+// cheapest of it and n <= 64 annealed refinements (refine_tree with seeds
+// 1..n), each scored by a branch-and-bound search of `net` with `probe`:
+// semiring MACs of its leaves plus a fixed weight per search node.
+Tree choose_order(const Network& net, int n, const SearchOptions& probe);
 
 }  // namespace bbtn

@@ -35,18 +35,32 @@ struct TreeRef {
   uint64_t id = 0;
 };
 
-TreeRef tree_for(bbtn_ctx* ctx, const Network& net) {
+TreeRef tree_for(bbtn_ctx* ctx, const Network& net, const SearchOptions* probe) {
   static std::atomic<uint64_t> next_id{1};
   std::vector<std::vector<int32_t>> shape;
   shape.reserve(net.tensors.size() + 1);
   shape.push_back({net.n});
   for (const auto& T : net.tensors) shape.push_back(T.vars);
-  {
+  auto lookup = [&](TreeRef& r) {
     std::lock_guard<std::mutex> lk(ctx->tree_mu);
     auto it = ctx->tree_cache.find(shape);
-    if (it != ctx->tree_cache.end()) return TreeRef{it->second.tree, it->second.id};
+    if (it == ctx->tree_cache.end()) return false;
+    r = TreeRef{it->second.tree, it->second.id};
+    return true;
+  };
+  TreeRef r;
+  if (lookup(r)) return r;
+  const bool refine = probe && ctx->opt.order_refine > 0;
+  // a refined order is costly: build it once while other planning threads
+  // of the same structure wait for it
+  std::unique_lock<std::mutex> build_lk(ctx->tree_build_mu, std::defer_lock);
+  if (refine) {
+    build_lk.lock();
+    if (lookup(r)) return r;
   }
-  auto tree = std::make_shared<const Tree>(greedy_tree(net));
+  auto tree = std::make_shared<const Tree>(
+      refine ? choose_order(net, ctx->opt.order_refine, *probe)
+             : greedy_tree(net));
   std::lock_guard<std::mutex> lk(ctx->tree_mu);
   auto it = ctx->tree_cache.find(shape);
   if (it != ctx->tree_cache.end()) return TreeRef{it->second.tree, it->second.id};
@@ -478,7 +492,11 @@ void solve_instances(bbtn_ctx* ctx, std::vector<Instance>& insts) {
     try {
       const double a = now_s();
       if (in.build) in.build(in);
-      w.tree = tree_for(ctx, in.net);
+      SearchOptions probe;
+      probe.log2_target = opt.log2_target;
+      probe.region_max = std::max(1, std::min(16, opt.region_max));
+      probe.values_only = values_only;
+      w.tree = tree_for(ctx, in.net, branch ? &probe : nullptr);
       // value (with the folded constant, like node_bound) of the local-search
       // configuration: a lower bound on the optimum, used for global pruning
       w.incumbent = in.ls_x.empty() ? INT64_MIN : network_value(in.net, in.ls_x);

@@ -2,6 +2,7 @@
 
 #include <cmath>
 #include <queue>
+#include <random>
 #include <tuple>
 
 namespace bbtn {
@@ -15,6 +16,25 @@ struct Cand {
   }
 };
 int64_t sz(size_t r) { return r >= 62 ? (1ll << 62) : (1ll << r); }
+
+// Depth-first post-order and the variable -> node index of a finished tree.
+void finish_tree(Tree& t, int32_t n_vars) {
+  t.dfs_post.clear();
+  if (t.root >= 0) {
+    std::vector<std::pair<int32_t, int>> st{{t.root, 0}};
+    while (!st.empty()) {
+      auto& top = st.back();
+      const TNode& nd = t.nodes[top.first];
+      if (nd.left < 0) { st.pop_back(); continue; }  // base tensor
+      if (top.second == 0) { top.second = 1; st.push_back({nd.left, 0}); }
+      else if (top.second == 1) { top.second = 2; st.push_back({nd.right, 0}); }
+      else { t.dfs_post.push_back(top.first); st.pop_back(); }
+    }
+  }
+  t.var_nodes.assign(n_vars, {});
+  for (int id : t.postorder)
+    for (int v : t.nodes[id].vars) t.var_nodes[v].push_back(id);
+}
 }  // namespace
 
 Tree greedy_tree(const Network& net) {
@@ -101,22 +121,141 @@ Tree greedy_tree(const Network& net) {
     for (size_t i = 1; i < rest.size(); ++i) acc = merge(acc, rest[i]);
     t.root = acc;
   }
-  // depth-first post-order from the root (iterative)
-  if (t.root >= 0) {
-    std::vector<std::pair<int32_t, int>> st{{t.root, 0}};
-    while (!st.empty()) {
-      auto& top = st.back();
-      const TNode& nd = t.nodes[top.first];
-      if (nd.left < 0) { st.pop_back(); continue; }  // base tensor
-      if (top.second == 0) { top.second = 1; st.push_back({nd.left, 0}); }
-      else if (top.second == 1) { top.second = 2; st.push_back({nd.right, 0}); }
-      else { t.dfs_post.push_back(top.first); st.pop_back(); }
+  finish_tree(t, net.n);
+  return t;
+}
+
+
+// Annealed local rotations of a contraction tree.  A rotation at internal
+// node n with children (L, R), L = (A, B), turns n into ((A, R), B) or
+// ((B, R), A) (and symmetrically through R); only the new inner node's
+// variables change: they are the variables of its two children that are
+// still held outside it, i.e. by the third subtree or by n's own output.
+Tree refine_tree(const Network& net, const Tree& in, const RefineOptions& o) {
+  Tree t = in;
+  const int N = (int)t.nodes.size();
+  if (t.root < 0 || o.sweeps <= 0 || N - t.n_base < 2) return t;
+  Complexity c0 = complexity(in, {});
+  const int sc_cap = o.sc_target > 0 ? o.sc_target : c0.sc;
+  const int lt = o.log2_target;
+  std::mt19937_64 rng(o.seed);
+  std::uniform_real_distribution<double> U(0.0, 1.0);
+  using V = std::vector<int32_t>;
+  auto uni = [](const V& a, const V& b, V& out) {
+    out.clear();
+    std::set_union(a.begin(), a.end(), b.begin(), b.end(), std::back_inserter(out));
+  };
+  auto inter = [](const V& a, const V& b, V& out) {
+    out.clear();
+    std::set_intersection(a.begin(), a.end(), b.begin(), b.end(), std::back_inserter(out));
+  };
+  // space term of a node of rank r: over the cap, and over T_target (rho)
+  auto space = [&](int r) {
+    return o.sc_weight * std::max(0, r - sc_cap) + o.rho_weight * std::max(0, r - lt);
+  };
+  V u1, u2, u3, nv;
+  std::vector<int32_t> internal;
+  for (int id = t.n_base; id < N; ++id) internal.push_back(id);
+  for (int sw = 0; sw < o.sweeps; ++sw) {
+    const double beta = o.beta0 + (o.beta1 - o.beta0) * sw / std::max(1, o.sweeps - 1);
+    std::shuffle(internal.begin(), internal.end(), rng);
+    for (int n : internal) {
+      TNode& nd = t.nodes[n];
+      // pick a child to rotate through, and which of its children stays
+      const int side = (int)(rng() & 1), keep = (int)((rng() >> 1) & 1);
+      const int c = side ? nd.right : nd.left;   // inner child (L)
+      const int r = side ? nd.left : nd.right;   // sibling moving in (R)
+      if (t.nodes[c].left < 0) continue;         // base tensor: no rotation
+      const int a = keep ? t.nodes[c].right : t.nodes[c].left;   // joins R
+      const int b = keep ? t.nodes[c].left : t.nodes[c].right;   // moves up
+      const V& va = t.nodes[a].vars;
+      const V& vb = t.nodes[b].vars;
+      const V& vr = t.nodes[r].vars;
+      const V& vc = t.nodes[c].vars;
+      // old: c = (a, b) of cost |va u vb|, n = (c, r) of cost |vc u vr|
+      uni(va, vb, u1);
+      const int old_c = (int)u1.size();
+      uni(vc, vr, u1);
+      const int old_n = (int)u1.size();
+      // new: c' = (a, r) with vars (va u vr) n (vb u vn), n = (c', b)
+      uni(va, vr, u2);
+      uni(vb, nd.vars, u3);
+      inter(u2, u3, nv);
+      const int new_c = (int)u2.size();
+      uni(nv, vb, u1);
+      const int new_n = (int)u1.size();
+      const double lo = std::log2(std::ldexp(1.0, old_c) + std::ldexp(1.0, old_n));
+      const double ln = std::log2(std::ldexp(1.0, new_c) + std::ldexp(1.0, new_n));
+      const double d = ln - lo + space((int)nv.size()) - space((int)vc.size());
+      if (d > 0 && U(rng) >= std::exp(-beta * d)) continue;
+      // apply: c keeps its id and becomes (a, r); n becomes (c, b)
+      TNode& cn = t.nodes[c];
+      cn.left = a;
+      cn.right = r;
+      cn.vars = nv;
+      t.nodes[a].parent = c;
+      t.nodes[r].parent = c;
+      if (side) { nd.right = c; nd.left = b; } else { nd.left = c; nd.right = b; }
+      t.nodes[b].parent = n;
     }
   }
-  t.var_nodes.assign(net.n, {});
-  for (int id : t.postorder)
-    for (int v : t.nodes[id].vars) t.var_nodes[v].push_back(id);
-  return t;
+  // renumber internal nodes in depth-first post-order (children first)
+  Tree out;
+  out.n_base = t.n_base;
+  out.nodes.assign(t.nodes.begin(), t.nodes.begin() + t.n_base);
+  std::vector<int32_t> id_of(N, -1);
+  for (int i = 0; i < t.n_base; ++i) id_of[i] = i;
+  std::vector<std::pair<int32_t, int>> st{{t.root, 0}};
+  while (!st.empty()) {
+    auto& top = st.back();
+    const TNode& nd = t.nodes[top.first];
+    if (nd.left < 0) { st.pop_back(); continue; }
+    if (top.second == 0) { top.second = 1; st.push_back({nd.left, 0}); }
+    else if (top.second == 1) { top.second = 2; st.push_back({nd.right, 0}); }
+    else {
+      TNode m;
+      m.left = id_of[nd.left];
+      m.right = id_of[nd.right];
+      m.vars = nd.vars;
+      const int id = (int)out.nodes.size();
+      id_of[top.first] = id;
+      out.nodes[m.left].parent = id;
+      out.nodes[m.right].parent = id;
+      out.nodes.push_back(std::move(m));
+      out.postorder.push_back(id);
+      st.pop_back();
+    }
+  }
+  out.root = id_of[t.root];
+  out.nodes[out.root].parent = -1;
+  // check every node's variables against a recount: a variable stays open
+  // while some base tensor outside the subtree still holds it
+  std::vector<int32_t> total(net.n, 0);
+  for (int i = 0; i < out.n_base; ++i)
+    for (int v : out.nodes[i].vars) ++total[v];
+  std::vector<std::vector<std::pair<int32_t, int32_t>>> held(out.nodes.size());
+  for (int i = 0; i < out.n_base; ++i)
+    for (int v : out.nodes[i].vars) held[i].push_back({v, 1});
+  for (int id : out.postorder) {
+    const auto& A = held[out.nodes[id].left];
+    const auto& B = held[out.nodes[id].right];
+    auto& H = held[id];
+    size_t i = 0, j = 0;
+    while (i < A.size() || j < B.size()) {
+      std::pair<int32_t, int32_t> e;
+      if (j == B.size() || (i < A.size() && A[i].first < B[j].first)) e = A[i++];
+      else if (i == A.size() || B[j].first < A[i].first) e = B[j++];
+      else { e = {A[i].first, A[i].second + B[j].second}; ++i; ++j; }
+      if (e.second < total[e.first]) H.push_back(e);
+    }
+    std::vector<int32_t> open;
+    for (const auto& e : H) open.push_back(e.first);
+    if (open != out.nodes[id].vars) throw Error(BBTN_E_INTERNAL, "refined tree: inconsistent variables");
+    held[out.nodes[id].left].clear();
+    held[out.nodes[id].right].clear();
+  }
+  finish_tree(out, net.n);
+  return out;
 }
 
 Complexity complexity(const Tree& t, const std::vector<uint64_t>& fixed) {

@@ -31,6 +31,23 @@ struct Tree {
 // Disconnected scalars are joined at the end.
 Tree greedy_tree(const Network& net);
 
+// Simulated-annealing refinement of a contraction tree by local rotations
+// (the tree-annealing approach to contraction orders).  Each sweep visits
+// every internal node once in random order and proposes one rotation; the
+// local change of log2(MACs) of the two affected contractions, plus the
+// space terms, is accepted with probability min(1, exp(-beta * change)),
+// beta rising linearly from beta0 to beta1.
+struct RefineOptions {
+  int sweeps = 0;          // 0: return the input tree
+  double beta0 = 1.0, beta1 = 30.0;
+  int sc_target = 0;       // <= 0: the input tree's space complexity
+  double sc_weight = 4.0;  // per log2 entry above sc_target
+  int log2_target = 0;     // T_target of the overflow measure rho
+  double rho_weight = 0.0; // per log2 entry above log2_target
+  uint64_t seed = 1;
+};
+Tree refine_tree(const Network& net, const Tree& t, const RefineOptions& o);
+
 // log2 of time (multiply-accumulates) and space (largest intermediate) of the
 // tree when the variables in `fixed` (bitmask over vars, may be empty) are
 // sliced away.

@@ -1,7 +1,8 @@
 """Writes the stored expected values used by the GPU tests.  Calls only the
 CPU oracle (exact transfer matrix) on the seeded inputs of `instances`.
 
-    python tests/golden/make_golden.py
+    python tests/golden/make_golden.py            # every table
+    python tests/golden/make_golden.py sg32x24    # one table
 """
 import os
 import sys
@@ -42,6 +43,20 @@ def larger():
             f.flush()
 
 
+def sg32x24():
+    """+-J spin glass on a 32 x 24 open lattice (rows x columns), seeds 0-1:
+    parity cases whose leaves reach 2^22 entries (C transfer matrix over the
+    24-column frontier)."""
+    with open(os.path.join(HERE, "sg32x24.txt"), "w") as f:
+        f.write("# +-J spin glass 32x24 open lattice (32 rows, 24 columns), zero field, seeds 0-1:\n")
+        f.write("# seed E0 degeneracy  (oracle: exact transfer matrix, C)\n")
+        for s in range(2):
+            g = I.spin_glass_rect(32, 24, s)
+            e0, deg = tm_c.spin_glass_lattice(32, 24, g["edges"], g["J"])
+            f.write("%d %d %d\n" % (s, e0, deg))
+            f.flush()
+
+
 def sg16_more():
     """Further 16x16 seeds (20-319) for throughput runs over many distinct
     instances (C transfer matrix)."""
@@ -57,6 +72,7 @@ def sg16_more():
 
 def main():
     larger()
+    sg32x24()
     sg16_more()
     with open(os.path.join(HERE, "sg16.txt"), "w") as f:
         f.write("# +-J spin glass 16x16 open lattice, zero field, seeds 0-19:\n")
@@ -76,4 +92,7 @@ def main():
 
 
 if __name__ == "__main__":
-    main()
+    if len(sys.argv) > 1:
+        globals()[sys.argv[1]]()  # one table, e.g. sg32x24
+    else:
+        main()

@@ -1,0 +1,68 @@
+"""Contraction-order refinement (host only): annealed rotations of the greedy
+tree keep every intermediate's variable set consistent (the library recounts
+them and fails otherwise), and on square lattices the chosen order is far
+cheaper than the greedy one ("Tropical Tensor Networks": time and space
+complexity of a contraction order; Eq. 4 for the overflow measure)."""
+import numpy as np
+import pytest
+
+import instances as I
+
+
+@pytest.fixture(scope="module")
+def B():
+    import paper_2602_05470_amd as B
+    B.load()
+    return B
+
+
+def _sg(L, seed=0):
+    g = I.spin_glass_square(L, seed)
+    return g["n"], np.asarray(g["edges"]), np.asarray(g["J"])
+
+
+@pytest.mark.parametrize("L", [4, 8])
+@pytest.mark.parametrize("refine", [0, 8])
+def test_complexity_invariants(B, L, refine):
+    """Time of a pairwise tree is at least its largest intermediate; the
+    overflow measure is zero exactly when T_target covers the largest
+    intermediate, and at least the largest overflow otherwise."""
+    n, edges, J = _sg(L)
+    t = L // 2 + 1
+    tc, sc, rho = B.order_complexity(0, n, edges, J, order_refine=refine, log2_target=t)
+    assert tc >= sc - 1e-9
+    assert sc >= 2                      # an edge tensor joins two spins
+    assert rho >= max(0, sc - t)
+    assert (rho == 0) == (sc <= t)
+
+
+@pytest.mark.parametrize("L,t", [(16, 10), (24, 16)])
+def test_refined_order_is_cheaper_than_greedy(B, L, t):
+    n, edges, J = _sg(L)
+    tc0, sc0, _ = B.order_complexity(0, n, edges, J, order_refine=0, log2_target=t)
+    tc1, sc1, _ = B.order_complexity(0, n, edges, J, order_refine=4, log2_target=t)
+    assert sc1 <= sc0
+    assert tc1 <= tc0 - 1.0, (tc0, tc1)
+
+
+def test_refined_order_other_topologies(B):
+    """The variable recount inside the refinement runs on every topology the
+    builders make: random 3-regular graphs, cubic lattices and weighted King's
+    subgraphs (MWIS, vertex tensors)."""
+    g = I.spin_glass_random_regular(40, 3)
+    B.order_complexity(0, g["n"], np.asarray(g["edges"]), np.asarray(g["J"]),
+                       order_refine=3, log2_target=4)
+    g = I.spin_glass_cubic(3, 3, 3, 1)
+    B.order_complexity(0, g["n"], np.asarray(g["edges"]), np.asarray(g["J"]),
+                       order_refine=3, log2_target=4)
+    g = I.kings_subgraph(8, 2, weights="1..10")
+    B.order_complexity(1, g["n"], np.asarray(g["edges"]).reshape(-1, 2), np.asarray(g["w"]),
+                       order_refine=3, log2_target=4)
+
+
+def test_order_refine_bounds(B):
+    n, edges, J = _sg(4)
+    with pytest.raises(B.BBTNError):
+        B.order_complexity(0, n, edges, J, order_refine=65, log2_target=2)
+    with pytest.raises(B.BBTNError):
+        B.order_complexity(0, n, edges, J, order_refine=-1, log2_target=2)

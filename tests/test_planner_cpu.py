@@ -43,14 +43,17 @@ def B():
 @pytest.mark.parametrize("seed", range(6))
 @pytest.mark.parametrize("t,rmax", [(1, 3), (2, 4), (3, 8)])
 @pytest.mark.parametrize("field", [False, True])
-def test_sg_leaves_complete_and_disjoint(B, seed, t, rmax, field):
-    """+-J on 4 x 4 (field 0.5 doubled to integers: J = +-2, h = 1)."""
+@pytest.mark.parametrize("refine", [0, 4])
+def test_sg_leaves_complete_and_disjoint(B, seed, t, rmax, field, refine):
+    """+-J on 4 x 4 (field 0.5 doubled to integers: J = +-2, h = 1), with the
+    greedy order and with an annealed refinement of it."""
     g = I.spin_glass_square(4, seed)
     n, edges, J = g["n"], np.asarray(g["edges"]), np.asarray(g["J"])
     h = None
     if field:
         J, h = 2 * J, np.ones(n, np.int64)
-    leaves, inc = B.plan_leaves(0, n, edges, J, h, log2_target=t, region_max=rmax)
+    leaves, inc = B.plan_leaves(0, n, edges, J, h, log2_target=t, region_max=rmax,
+                                order_refine=refine)
     states = _all_states(n)
     mem = _membership(leaves, states)
     assert (mem.sum(axis=1) <= 1).all()          # orthogonal
@@ -77,10 +80,11 @@ def test_sg_values_only_keeps_an_optimum(B, seed):
 
 
 @pytest.mark.parametrize("seed", range(4))
-def test_mwis_leaves_complete_and_disjoint(B, seed):
+@pytest.mark.parametrize("refine", [0, 4])
+def test_mwis_leaves_complete_and_disjoint(B, seed, refine):
     g = I.kings_subgraph(4, seed, weights="1..10")
     n, edges, w = g["n"], np.asarray(g["edges"]).reshape(-1, 2), np.asarray(g["w"])
-    leaves, inc = B.plan_leaves(1, n, edges, w, log2_target=1, region_max=4)
+    leaves, inc = B.plan_leaves(1, n, edges, w, log2_target=1, region_max=4, order_refine=refine)
     states = _all_states(n)
     mem = _membership(leaves, states)
     assert (mem.sum(axis=1) <= 1).all()
