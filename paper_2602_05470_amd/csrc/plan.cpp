@@ -113,6 +113,21 @@ GroupPlan build_plan(const Network& net, const Tree& tree,
   std::vector<std::vector<int32_t>> fx(NN);
   std::vector<int> widest(NN, 0);
   std::vector<char> deferred(NN, 0);
+  // the node whose output is the branch result: the root, or, when the root
+  // only joins subtrees whose variables are all fixed (folded), the node it
+  // aliases
+  int eff_root = tree.root;
+  if (tree.root >= tree.n_base) {
+    std::vector<char> all_folded(NN, 0);
+    for (int i = 0; i < tree.n_base; ++i) all_folded[i] = status[i] == FOLDED;
+    for (int id : tree.dfs_post)
+      all_folded[id] = all_folded[tree.nodes[id].left] && all_folded[tree.nodes[id].right];
+    while (eff_root >= tree.n_base) {
+      const TNode& n = tree.nodes[eff_root];
+      if (all_folded[n.left] == all_folded[n.right]) break;
+      eff_root = all_folded[n.left] ? n.right : n.left;
+    }
+  }
   if (sharing && defer_log2 > 0) {
     for (int i = 0; i < tree.n_base; ++i)
       if (status[i] == BASE) {
@@ -126,7 +141,7 @@ GroupPlan build_plan(const Network& net, const Tree& tree,
                      fx[n.right].end(), std::back_inserter(fx[id]));
       const int own = (int)free_vars(n.vars, fixed).size() + (int)fx[id].size();
       widest[id] = std::max({own, widest[n.left], widest[n.right]});
-      deferred[id] = hasfix[id] && widest[id] <= defer_log2 && id != tree.root;
+      deferred[id] = hasfix[id] && widest[id] <= defer_log2 && id != eff_root;
     }
   }
   auto with_fx = [&](std::vector<int32_t> v, int node) {
@@ -230,7 +245,7 @@ GroupPlan build_plan(const Network& net, const Tree& tree,
     g.steps.push_back(std::move(s));
   }
   if (tree.root >= 0 && status[tree.root] == STEP) {
-    g.root_buf = buf_of[tree.root];
+    g.root_buf = buf_of[rep[tree.root]];  // the root may alias a step below it
     use(g.root_buf, (int)g.steps.size());  // read after the last step
   } else if (tree.root >= 0 && status[tree.root] == BASE) {
     throw Error(BBTN_E_INTERNAL, "plan: root is a base tensor with free variables");

@@ -1,0 +1,73 @@
+"""Parity of the GPU path with a refined contraction order (annealed
+rotations of the greedy tree, chosen by a probe search): exact ground value,
+exact degeneracy and a configuration reaching it, against the exact transfer
+matrix ("Tropical Tensor Networks": any contraction order gives the same
+tropical contraction; only its cost changes)."""
+import os
+
+import numpy as np
+import pytest
+
+import instances as I
+from oracle import config
+
+pytestmark = pytest.mark.gpu
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _golden(name):
+    rows = []
+    for line in open(os.path.join(GOLDEN, name)):
+        if line.startswith("#") or not line.strip():
+            continue
+        rows.append([int(x) for x in line.split()])
+    return rows
+
+
+@pytest.fixture(scope="module")
+def B():
+    from tests.gpu_util import torch_cuda
+    torch_cuda()
+    import paper_2602_05470_amd as B
+    return B
+
+
+def _check_sg(r, g, want):
+    assert (r.value, r.count) == tuple(want)
+    assert r.certified
+    assert config.spin_glass_energy(r.config, g["edges"], g["J"], g.get("h")) == r.value
+
+
+def test_sg16_refined_order_batch(B):
+    """Twenty 16x16 instances in one call with order_refine = 8: the order
+    is chosen once for the lattice and every instance is exact."""
+    want = {s: (e, d) for s, e, d in _golden("sg16.txt")}
+    gs = [I.spin_glass_square(16, s) for s in range(20)]
+    with B.Context(B.Options(log2_target=10, order_refine=8)) as ctx:
+        rs, st = ctx.solve_batch(0, [(g["n"], g["edges"], g["J"], None) for g in gs])
+    assert all(s == 0 for s in st)
+    for s, (g, r) in enumerate(zip(gs, rs)):
+        _check_sg(r, g, want[s])
+        assert r.leaves <= 1024
+
+
+@pytest.mark.parametrize("seed", range(2))
+def test_sg24_refined_order(B, seed):
+    """24x24 at T_target = 2^16 with the refined order (about 1,000 leaves
+    instead of the greedy order's 2^18)."""
+    want = {s: (e, d) for s, e, d in _golden("sg24.txt")}[seed]
+    g = I.spin_glass_square(24, seed)
+    with B.Context(B.Options(log2_target=16, order_refine=8)) as ctx:
+        r = ctx.solve_spinglass(g["n"], g["edges"], g["J"])
+    _check_sg(r, g, want)
+
+
+@pytest.mark.parametrize("seed", range(2))
+def test_sg32x24_refined_order(B, seed):
+    """32 x 24 lattice at T_target = 2^20: branch tensors of up to 2^20
+    entries, contracted step by step in memory-sized chunks of branches."""
+    want = {s: (e, d) for s, e, d in _golden("sg32x24.txt")}[seed]
+    g = I.spin_glass_rect(32, 24, seed)
+    with B.Context(B.Options(log2_target=20, order_refine=8)) as ctx:
+        r = ctx.solve_spinglass(g["n"], g["edges"], g["J"])
+    _check_sg(r, g, want)
