@@ -143,41 +143,52 @@ def tgemm_micro(B, ctx, torch):
 
 def large_configs(B, I, torch, n_seeds):
     """Exact solves of the larger lattices, one instance per call, with the
-    refined contraction order (chosen on the first seed and cached)."""
+    refined contraction order (chosen on the first seed and cached), by the
+    plain planner and by the shipped learned scorer."""
+    here = os.path.dirname(os.path.abspath(__file__))
     out = {}
-    for name, make, kind, t, k in (
-            ("sg32x32", lambda s: I.spin_glass_square(32, s), 0, 26, 3),
-            ("ksg40x40", lambda s: I.kings_subgraph(40, s), 1, 24, 4)):
-        ctx = B.Context(B.Options(log2_target=t, order_refine=8, residues_per_pass=k))
-        rows = []
-        for s in range(n_seeds):
-            g = make(s)
-            print("large %s seed %d" % (name, s), file=sys.stderr, flush=True)
-            if s == 1:
-                ctx.profile(True)   # kernel figures over the seeds after the first
-            t0 = time.perf_counter()
-            if kind == 0:
-                r = ctx.solve_spinglass(g["n"], g["edges"], g["J"])
-            else:
-                r = ctx.solve_mwis(g["n"], g["edges"], g["w"])
-            torch.cuda.synchronize()
-            rows.append({"seed": s, "value": r.value, "count": str(r.count),
-                         "certified": bool(r.certified), "leaves": int(r.leaves),
-                         "macs": int(r.macs), "seconds": round(time.perf_counter() - t0, 3)})
-            print(json.dumps(rows[-1]), file=sys.stderr, flush=True)
-        ks = {}
-        for kn in ("tgemm", "persist", "gather"):
-            st = ctx.kernel_stats(kn)
-            ks[kn] = {"launches": st["launches"], "seconds": round(st["seconds"], 4),
-                      "Gop_s": round(st["ops"] / max(st["seconds"], 1e-12) / 1e9, 1),
-                      "frac_valu": round(st["ops"] / max(st["seconds"], 1e-12) / VALU_PEAK_OPS, 4),
-                      "GB_s": round(st["bytes"] / max(st["seconds"], 1e-12) / 1e9, 1)}
-        ctx.profile(False)
-        ctx.close()
-        later = rows[1:] or rows
-        out[name] = {"T_target_log2": t, "residues_per_pass": k, "instances": rows,
-                     "mean_seconds_after_first": round(sum(r["seconds"] for r in later) / len(later), 3),
-                     "kernels": ks}
+    for name, make, kind, t, k, weights in (
+            ("sg32x32", lambda s: I.spin_glass_square(32, s), 0, 26, 3, "scorer_sg.bin"),
+            ("ksg40x40", lambda s: I.kings_subgraph(40, s), 1, 24, 4, "scorer_ksg.bin")):
+        out[name] = {"T_target_log2": t, "residues_per_pass": k}
+        for variant, branching in (("plain", 1), ("scorer", 2)):
+            wpath = os.path.join(here, "paper_2602_05470_amd", weights) if branching == 2 else None
+            ctx = B.Context(B.Options(log2_target=t, order_refine=8, residues_per_pass=k,
+                                      branching=branching, scorer_weights=wpath))
+            rows = []
+            for s in range(n_seeds):
+                g = make(s)
+                print("large %s %s seed %d" % (name, variant, s), file=sys.stderr, flush=True)
+                if s == 1:
+                    ctx.profile(True)   # kernel figures over the seeds after the first
+                t0 = time.perf_counter()
+                if kind == 0:
+                    r = ctx.solve_spinglass(g["n"], g["edges"], g["J"])
+                else:
+                    r = ctx.solve_mwis(g["n"], g["edges"], g["w"])
+                torch.cuda.synchronize()
+                rows.append({"seed": s, "value": r.value, "count": str(r.count),
+                             "certified": bool(r.certified), "leaves": int(r.leaves),
+                             "macs": int(r.macs), "seconds": round(time.perf_counter() - t0, 3)})
+                print(json.dumps(rows[-1]), file=sys.stderr, flush=True)
+            ks = {}
+            for kn in ("tgemm", "persist", "gather"):
+                st = ctx.kernel_stats(kn)
+                ks[kn] = {"launches": st["launches"], "seconds": round(st["seconds"], 4),
+                          "Gop_s": round(st["ops"] / max(st["seconds"], 1e-12) / 1e9, 1),
+                          "frac_valu": round(st["ops"] / max(st["seconds"], 1e-12) / VALU_PEAK_OPS, 4),
+                          "GB_s": round(st["bytes"] / max(st["seconds"], 1e-12) / 1e9, 1)}
+            ctx.profile(False)
+            ctx.close()
+            later = rows[1:] or rows
+            out[name][variant] = {
+                "instances": rows,
+                "mean_seconds_after_first": round(sum(r["seconds"] for r in later) / len(later), 3),
+                "total_macs": sum(r["macs"] for r in rows),
+                "kernels": ks}
+        same = all((a["value"], a["count"]) == (b["value"], b["count"])
+                   for a, b in zip(out[name]["plain"]["instances"], out[name]["scorer"]["instances"]))
+        out[name]["scorer_results_identical"] = same
     return {"large_configs": out}
 
 
@@ -210,8 +221,8 @@ def main():
     ap.add_argument("--large", type=int, default=0,
                     help="instead of the throughput run: solve this many seeds each of the "
                          "+-J 32x32 lattice (T_target=2^26) and the King's subgraph 40x40 MIS "
-                         "(T_target=2^24) with the refined order, and print their times and "
-                         "kernel figures")
+                         "(T_target=2^24) with the refined order, by the plain planner and by "
+                         "the learned scorer, and print their times and kernel figures")
     ap.add_argument("--batch-size", type=int, default=160,
                     help="instances per call (bbtn_solve_batch when > 1): their branch "
                          "sub-networks share every device launch")
