@@ -100,6 +100,11 @@ typedef struct {
                                 first instance of a structure; the cheapest
                                 (leaf MACs plus search nodes) is cached for the
                                 structure.  n <= 64.                           */
+  uint64_t device_mem_cap;   /* bytes of device memory the context (with its
+                                configuration-recovery context) may hold;
+                                branch chunks are sized to it, and a solve
+                                that cannot fit fails with BBTN_E_OOM.
+                                0: no cap beyond the free memory.             */
 } bbtn_options;
 
 /* Result of a solve.  `count` and `config` are caller-owned. */

@@ -39,7 +39,8 @@ class _Options(C.Structure):
                 ("graphs", C.c_int32),
                 ("scorer_weights", C.c_char_p), ("autotune_cache", C.c_char_p),
                 ("time_limit_s", C.c_double), ("stream", C.c_void_p),
-                ("host_threads", C.c_int32), ("order_refine", C.c_int32)]
+                ("host_threads", C.c_int32), ("order_refine", C.c_int32),
+                ("device_mem_cap", C.c_uint64)]
 
 
 class _Result(C.Structure):
@@ -168,13 +169,14 @@ class Options:
     stream: int | None = None
     host_threads: int = 0
     order_refine: int = 0
+    device_mem_cap: int = 0
 
     def _c(self):
         o = _Options()
         load().bbtn_default_options(C.byref(o))
         for f in ("device", "residues_per_pass", "max_primes", "log2_target", "branching",
                   "batched", "region_max", "local_search", "graphs", "time_limit_s",
-                  "host_threads", "order_refine"):
+                  "host_threads", "order_refine", "device_mem_cap"):
             setattr(o, f, getattr(self, f))
         o.scorer_weights = self.scorer_weights.encode() if self.scorer_weights else None
         o.autotune_cache = self.autotune_cache.encode() if self.autotune_cache else None

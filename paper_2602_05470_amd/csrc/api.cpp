@@ -82,6 +82,7 @@ void bbtn_default_options(bbtn_options* o) {
   o->stream = nullptr;
   o->host_threads = 0;
   o->order_refine = 0;
+  o->device_mem_cap = 0;
 }
 
 bbtn_status bbtn_create(const bbtn_options* opt, bbtn_ctx** out) {
@@ -90,6 +91,8 @@ bbtn_status bbtn_create(const bbtn_options* opt, bbtn_ctx** out) {
   bbtn_ctx* ctx = new (std::nothrow) bbtn_ctx();
   if (!ctx) return BBTN_E_OOM;
   if (opt) ctx->opt = *opt; else bbtn_default_options(&ctx->opt);
+  ctx->attach_memcap(std::make_shared<MemCap>());
+  ctx->memcap->cap = (size_t)ctx->opt.device_mem_cap;
   bbtn_status s = guard(ctx, [&] {
     BBTN_REQUIRE(ctx->opt.residues_per_pass >= 0 && ctx->opt.residues_per_pass <= KMAX,
                  "residues_per_pass must be in [0, 4]");

@@ -1,5 +1,6 @@
 // The opaque context behind bbtn_ctx: device, stream, workspace, caches.
 #pragma once
+#include <atomic>
 #include <map>
 #include <memory>
 #include <mutex>
@@ -12,16 +13,26 @@
 
 namespace bbtn {
 
+// Device bytes held by a context and its recovery context, against the
+// option device_mem_cap (0: no cap).
+struct MemCap {
+  size_t cap = 0;
+  std::atomic<size_t> held{0};
+};
+
 // Growable device allocation (contents are not preserved on growth).
 struct DevBuf {
   void* p = nullptr;
   size_t bytes = 0;
+  MemCap* mc = nullptr;  // the owning context's account, or none
   void ensure(size_t b) {
     if (b <= bytes) return;
-    if (p) (void)hipFree(p);
-    p = nullptr;
-    bytes = 0;
     size_t want = std::max<size_t>(b, 1 << 20);
+    if (mc && mc->cap > 0 && mc->held.load() - bytes + want > mc->cap)
+      throw Error(BBTN_E_OOM, "device_mem_cap of " + std::to_string(mc->cap) +
+                                  " bytes reached (" + std::to_string(want) +
+                                  " more bytes wanted)");
+    release();
     hipError_t e = hipMalloc(&p, want);
     if (e != hipSuccess) {
       p = nullptr;
@@ -29,9 +40,11 @@ struct DevBuf {
       throw Error(BBTN_E_OOM, "device allocation of " + std::to_string(want) + " bytes failed");
     }
     bytes = want;
+    if (mc) mc->held += want;
   }
   void release() {
     if (p) (void)hipFree(p);
+    if (mc) mc->held -= bytes;
     p = nullptr;
     bytes = 0;
   }
@@ -95,6 +108,14 @@ struct bbtn_ctx {
   bbtn::DevBuf leafout;   // per-branch results
   bbtn::DevBuf misc;      // small scratch (merge outputs, traceback)
   bbtn::DevBuf persist;   // persistent executor programs and scratch
+  // account of the device bytes above, shared with the recovery context
+  std::shared_ptr<bbtn::MemCap> memcap = std::make_shared<bbtn::MemCap>();
+  void attach_memcap(std::shared_ptr<bbtn::MemCap> m) {
+    memcap = std::move(m);
+    for (bbtn::DevBuf* b : {&work, &shared_ws, &partial, &base, &fixbits, &leafconst, &leafout,
+                            &misc, &persist, &scorer_dev})
+      b->mc = memcap.get();
+  }
   bbtn::PinBuf pin_base;    // staging of the base tensors of a pass
   bbtn::PinBuf pin_persist; // staging of a persistent launch's program
   uint64_t last_macs = 0;

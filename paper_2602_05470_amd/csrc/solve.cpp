@@ -108,7 +108,10 @@ struct PassOut {
 int64_t leaves_per_chunk(bbtn_ctx* ctx, const GroupPlan& g, int k) {
   size_t freeb = 0, totalb = 0;
   if (hipMemGetInfo(&freeb, &totalb) != hipSuccess) freeb = (size_t)8 << 30;
-  const double budget = 0.45 * (double)(freeb + ctx->work.bytes);
+  double budget = 0.45 * (double)(freeb + ctx->work.bytes);
+  if (ctx->memcap->cap > 0)  // what the cap leaves, counting the workspace this replaces
+    budget = std::min(budget, 0.9 * ((double)ctx->memcap->cap - (double)ctx->memcap->held.load() +
+                                     (double)ctx->work.bytes));
   const double per = (double)(1 + k) * 4.0 * (double)std::max<int64_t>(g.peak, 1) * 1.05 +
                      (double)(1 + k) * 12.0 + 8.0 * (double)(g.base_ops.size() + 1);
   int64_t L = (int64_t)(budget / per);
@@ -409,6 +412,7 @@ bbtn_ctx* aux_context(bbtn_ctx* ctx) {
     bbtn_ctx* a = nullptr;
     const bbtn_status s = bbtn_create(&o, &a);
     if (s != BBTN_OK) throw Error(s, "cannot create the configuration-recovery context");
+    a->attach_memcap(ctx->memcap);  // one cap for both contexts
     ctx->aux = a;
   }
   ctx->aux->tune = ctx->tune;

@@ -45,3 +45,31 @@ def test_default_options_and_struct_sizes():
     o = B._Options()
     lib.bbtn_default_options(ctypes.byref(o))
     assert o.residues_per_pass == 3 and o.branching == 1 and o.batched == 1
+
+
+def test_options_and_result_layout_match_the_header(tmp_path):
+    """The binding's ctypes structures have the C layout of include/bbtn.h
+    (sizes and the offsets of every field), checked with the host C compiler."""
+    import shutil
+    import subprocess
+    import paper_2602_05470_amd as B
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    inc = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include")
+    lines = ["#include <stddef.h>", "#include <stdio.h>", '#include "bbtn.h"', "int main(void) {"]
+    for ct, name in ((B._Options, "bbtn_options"), (B._Result, "bbtn_result")):
+        lines.append('printf("%s %%zu\\n", sizeof(%s));' % (name, name))
+        for f in ct._fields_:
+            lines.append('printf("%s.%s %%zu\\n", offsetof(%s, %s));' % (name, f[0], name, f[0]))
+    lines.append("return 0; }")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-I", inc, str(src), "-o", str(exe)], check=True)
+    got = dict(l.split() for l in subprocess.run([str(exe)], check=True, capture_output=True,
+                                                   text=True).stdout.splitlines())
+    for ct, name in ((B._Options, "bbtn_options"), (B._Result, "bbtn_result")):
+        assert int(got[name]) == ctypes.sizeof(ct), name
+        for f in ct._fields_:
+            assert int(got[name + "." + f[0]]) == getattr(ct, f[0]).offset, (name, f[0])

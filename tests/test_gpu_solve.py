@@ -196,3 +196,20 @@ def test_one_context_many_instances(B):
             assert (r.value, r.count) == ksg[seed] and r.certified
         g = I.spin_glass_square(16, 5)
         _check_sg(ctx.solve_spinglass(g["n"], g["edges"], g["J"]), g, sg[5])
+
+
+def test_device_mem_cap(B):
+    """device_mem_cap: a cap below what a solve needs fails with OOM (no
+    allocation past it); a cap that only limits the branch chunks still
+    gives the exact result, through more, smaller chunks."""
+    sg = {s: (e, d) for s, e, d in _golden("sg24.txt")}
+    g = I.spin_glass_square(16, 0)
+    with B.Context(B.Options(log2_target=10, device_mem_cap=2 << 20)) as ctx:
+        with pytest.raises(B.BBTNError) as ei:
+            ctx.solve_spinglass(g["n"], g["edges"], g["J"])
+        assert ei.value.status == -2
+    g = I.spin_glass_square(24, 1)
+    with B.Context(B.Options(log2_target=16, residues_per_pass=4,
+                             device_mem_cap=1 << 30)) as ctx:
+        r = ctx.solve_spinglass(g["n"], g["edges"], g["J"])
+    _check_sg(r, g, sg[1])
