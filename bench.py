@@ -368,6 +368,8 @@ def main():
                      "unit": "TOP/s", "frac": round(achieved / VALU_PEAK_OPS, 5),
                      "traffic": persist_traffic() if dom == "persist" else None,
                      "launches": st["launches"],
+                     "launch_unit": "one executor pass (its shared-subtree and branch dispatches)"
+                                    if dom == "persist" else "one kernel dispatch",
                      "avg_launch_ms": round(1e3 * st["seconds"] / max(st["launches"], 1), 4),
                      "kernel_busy_share": round(st["seconds"] / dt, 4)},
         "kernels": {n: {"launches": s["launches"], "seconds": round(s["seconds"], 5),

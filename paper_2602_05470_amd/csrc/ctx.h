@@ -1,6 +1,7 @@
 // The opaque context behind bbtn_ctx: device, stream, workspace, caches.
 #pragma once
 #include <atomic>
+#include <future>
 #include <map>
 #include <memory>
 #include <mutex>
@@ -92,6 +93,12 @@ struct TuneVal {
   int splits;
 };
 
+// A contraction tree from a context's cache, with its cache id.
+struct TreeRef {
+  std::shared_ptr<const Tree> tree;
+  uint64_t id = 0;
+};
+
 }  // namespace bbtn
 
 struct bbtn_ctx {
@@ -141,7 +148,8 @@ struct bbtn_ctx {
            std::shared_ptr<const bbtn::GroupPlan>>
       plan_cache;
   std::mutex tree_mu;  // planning threads share both caches
-  std::mutex tree_build_mu;  // one refined order is built at a time
+  // refined orders being built, by structure (waited on by other threads)
+  std::map<std::vector<std::vector<int32_t>>, std::shared_future<bbtn::TreeRef>> tree_building;
   // second context (own stream and workspaces) that recovers the optimal
   // configuration while this one runs the counting passes
   bbtn_ctx* aux = nullptr;

@@ -29,45 +29,58 @@ double now_s() {
   return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
 }
 
-// A contraction tree from the context's cache, with its cache id.
-struct TreeRef {
-  std::shared_ptr<const Tree> tree;
-  uint64_t id = 0;
-};
-
 TreeRef tree_for(bbtn_ctx* ctx, const Network& net, const SearchOptions* probe) {
   static std::atomic<uint64_t> next_id{1};
   std::vector<std::vector<int32_t>> shape;
   shape.reserve(net.tensors.size() + 1);
   shape.push_back({net.n});
   for (const auto& T : net.tensors) shape.push_back(T.vars);
-  auto lookup = [&](TreeRef& r) {
-    std::lock_guard<std::mutex> lk(ctx->tree_mu);
-    auto it = ctx->tree_cache.find(shape);
-    if (it == ctx->tree_cache.end()) return false;
-    r = TreeRef{it->second.tree, it->second.id};
-    return true;
-  };
-  TreeRef r;
-  if (lookup(r)) return r;
   const bool refine = probe && ctx->opt.order_refine > 0;
-  // a refined order is costly: build it once while other planning threads
-  // of the same structure wait for it
-  std::unique_lock<std::mutex> build_lk(ctx->tree_build_mu, std::defer_lock);
-  if (refine) {
-    build_lk.lock();
-    if (lookup(r)) return r;
+  std::shared_ptr<std::promise<TreeRef>> mine;
+  {
+    std::unique_lock<std::mutex> lk(ctx->tree_mu);
+    auto it = ctx->tree_cache.find(shape);
+    if (it != ctx->tree_cache.end()) return TreeRef{it->second.tree, it->second.id};
+    if (refine) {
+      // a refined order is costly: one planning thread builds it, the
+      // others with the same structure wait for it; other structures are
+      // built in parallel
+      auto bt = ctx->tree_building.find(shape);
+      if (bt != ctx->tree_building.end()) {
+        std::shared_future<TreeRef> f = bt->second;
+        lk.unlock();
+        return f.get();  // rethrows the builder's error
+      }
+      mine = std::make_shared<std::promise<TreeRef>>();
+      ctx->tree_building.emplace(shape, mine->get_future().share());
+    }
   }
-  auto tree = std::make_shared<const Tree>(
-      refine ? choose_order(net, ctx->opt.order_refine, *probe)
-             : greedy_tree(net));
-  std::lock_guard<std::mutex> lk(ctx->tree_mu);
-  auto it = ctx->tree_cache.find(shape);
-  if (it != ctx->tree_cache.end()) return TreeRef{it->second.tree, it->second.id};
-  if (ctx->tree_cache.size() >= 8) ctx->tree_cache.clear();
-  const uint64_t id = next_id++;
-  ctx->tree_cache.emplace(std::move(shape), bbtn_ctx::TreeEntry{tree, id});
-  return TreeRef{tree, id};
+  try {
+    auto tree = std::make_shared<const Tree>(
+        refine ? choose_order(net, ctx->opt.order_refine, *probe) : greedy_tree(net));
+    std::lock_guard<std::mutex> lk(ctx->tree_mu);
+    TreeRef r;
+    auto it = ctx->tree_cache.find(shape);
+    if (it != ctx->tree_cache.end()) {
+      r = TreeRef{it->second.tree, it->second.id};
+    } else {
+      if (ctx->tree_cache.size() >= 8) ctx->tree_cache.clear();
+      r = TreeRef{tree, next_id++};
+      ctx->tree_cache.emplace(shape, bbtn_ctx::TreeEntry{tree, r.id});
+    }
+    if (mine) {
+      ctx->tree_building.erase(shape);
+      mine->set_value(r);
+    }
+    return r;
+  } catch (...) {
+    if (mine) {
+      std::lock_guard<std::mutex> lk(ctx->tree_mu);
+      ctx->tree_building.erase(shape);
+      mine->set_exception(std::current_exception());
+    }
+    throw;
+  }
 }
 
 // The step program of fixed set `mask` on tree `t`, from the context's
