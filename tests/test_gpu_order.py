@@ -71,3 +71,48 @@ def test_sg32x24_refined_order(B, seed):
     with B.Context(B.Options(log2_target=20, order_refine=8)) as ctx:
         r = ctx.solve_spinglass(g["n"], g["edges"], g["J"])
     _check_sg(r, g, want)
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_ksg20_refined_order(B, seed):
+    """Unweighted MIS on King's subgraphs 20x20 (vertex tensors, a different
+    network shape) at T_target = 2^10 with the refined order, 4 residues."""
+    s, n, w, c = _golden("ksg20.txt")[seed]
+    g = I.kings_subgraph(20, seed)
+    assert g["n"] == n
+    with B.Context(B.Options(log2_target=10, residues_per_pass=4, order_refine=8)) as ctx:
+        r = ctx.solve_mwis(g["n"], g["edges"], g["w"])
+    assert (r.value, r.count) == (w, c) and r.certified
+    assert config.independent_set_weight(r.config, g["edges"], g["w"]) == w
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_sg20_refined_order_values_only(B, seed):
+    """Values-only mode (no counts) on 20x20 with the refined order: the
+    ground energy and a configuration reaching it."""
+    s, e0, _ = _golden("sg20.txt")[seed]
+    g = I.spin_glass_square(20, seed)
+    with B.Context(B.Options(log2_target=10, residues_per_pass=0, order_refine=8)) as ctx:
+        r = ctx.solve_spinglass(g["n"], g["edges"], g["J"])
+    assert r.value == e0
+    assert config.spin_glass_energy(r.config, g["edges"], g["J"], None) == e0
+
+
+def test_field_and_weights_refined_order(B):
+    """A field on a rectangle and integer weights 1..10 on a King's subgraph
+    (both break the symmetries of the zero-field unit cases), refined order,
+    against the transfer matrix."""
+    from oracle import tm
+    g = I.spin_glass_rect(10, 12, 7)
+    h = np.random.default_rng(7).integers(-2, 3, size=g["n"]).astype(np.int32)
+    want = tm.spin_glass_lattice(10, 12, g["edges"], g["J"], h)
+    with B.Context(B.Options(log2_target=6, order_refine=8)) as ctx:
+        r = ctx.solve_spinglass(g["n"], g["edges"], g["J"], h)
+    assert (r.value, r.count) == tuple(want) and r.certified
+    assert config.spin_glass_energy(r.config, g["edges"], g["J"], h) == r.value
+    k = I.kings_subgraph(10, 3, weights="1..10")
+    want = tm.kings_subgraph(k)
+    with B.Context(B.Options(log2_target=6, order_refine=8)) as ctx:
+        r = ctx.solve_mwis(k["n"], k["edges"], k["w"])
+    assert (r.value, r.count) == tuple(want) and r.certified
+    assert config.independent_set_weight(r.config, k["edges"], k["w"]) == want[0]
