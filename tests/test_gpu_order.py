@@ -92,7 +92,7 @@ def test_sg20_refined_order_values_only(B, seed):
     ground energy and a configuration reaching it."""
     s, e0, _ = _golden("sg20.txt")[seed]
     g = I.spin_glass_square(20, seed)
-    with B.Context(B.Options(log2_target=10, residues_per_pass=0, order_refine=8)) as ctx:
+    with B.Context(B.Options(log2_target=12, residues_per_pass=0, order_refine=8)) as ctx:
         r = ctx.solve_spinglass(g["n"], g["edges"], g["J"])
     assert r.value == e0
     assert config.spin_glass_energy(r.config, g["edges"], g["J"], None) == e0
