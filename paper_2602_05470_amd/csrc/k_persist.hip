@@ -265,9 +265,54 @@ persist_kernel(const PersistArgs a) {
           for (int p = 0; p < KR; ++p) c[(p + 1) * cs + o] = fin ? r[p] : 0u;
         }
       };
+      // values pass, wide steps over row pairs: two m by four consecutive n
+      // per thread, so that four K steps cost two 16-byte reads of A and
+      // four of B for 32 MACs
+      const bool vec8 = KR == 0 && rn >= 2 && rm >= 1 && K >= 4 && (nC >> 3) >= NTHR;
+      if constexpr (KR == 0) {
+        if (vec8) {
+          const int nI = nC >> 3;
+          const int gb = rn - 2;  // bits of the four-wide n group
+          for (int it = tid; it < nI; it += NTHR) {
+            const int g = it & ((1 << gb) - 1);
+            const int mb = it >> gb;
+            const int m = (mb & ((1 << (rm - 1)) - 1)) << 1;
+            const int b = mb >> (rm - 1);
+            const int o = (g << 2) | (m << rn) | (b << (rn + rm));
+            const int32_t* A0 = (const int32_t*)la + ((m << rk) | (b << (rk + rm)));
+            const int32_t* A1 = A0 + K;  // row m + 1
+            const int32_t* Bv = (const int32_t*)lb + ((g << 2) | (b << (rn + rk)));
+            int32_t V[8];
+#pragma unroll
+            for (int i = 0; i < 8; ++i) V[i] = INT32_MIN;
+            for (int q = 0; q < K; q += 4) {
+              const int4 a0 = *(const int4*)(A0 + q);
+              const int4 a1 = *(const int4*)(A1 + q);
+              const int4 b0 = *(const int4*)(Bv + (q << rn));
+              const int4 b1 = *(const int4*)(Bv + ((q + 1) << rn));
+              const int4 b2 = *(const int4*)(Bv + ((q + 2) << rn));
+              const int4 b3 = *(const int4*)(Bv + ((q + 3) << rn));
+              V[0] = max3i(max3i(V[0], a0.x + b0.x, a0.y + b1.x), a0.z + b2.x, a0.w + b3.x);
+              V[1] = max3i(max3i(V[1], a0.x + b0.y, a0.y + b1.y), a0.z + b2.y, a0.w + b3.y);
+              V[2] = max3i(max3i(V[2], a0.x + b0.z, a0.y + b1.z), a0.z + b2.z, a0.w + b3.z);
+              V[3] = max3i(max3i(V[3], a0.x + b0.w, a0.y + b1.w), a0.z + b2.w, a0.w + b3.w);
+              V[4] = max3i(max3i(V[4], a1.x + b0.x, a1.y + b1.x), a1.z + b2.x, a1.w + b3.x);
+              V[5] = max3i(max3i(V[5], a1.x + b0.y, a1.y + b1.y), a1.z + b2.y, a1.w + b3.y);
+              V[6] = max3i(max3i(V[6], a1.x + b0.z, a1.y + b1.z), a1.z + b2.z, a1.w + b3.z);
+              V[7] = max3i(max3i(V[7], a1.x + b0.w, a1.y + b1.w), a1.z + b2.w, a1.w + b3.w);
+            }
+            const uint32_t none[1] = {0u};
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+              put(o + i, V[i], none);
+              put(o + (1 << rn) + i, V[4 + i], none);
+            }
+          }
+        }
+      }
       // wide steps: four consecutive n per thread, so that each q costs one
       // read of A and one 16-byte read of B for four outputs
-      const bool vec4 = rn >= 2 && (nC >> 2) >= NTHR;
+      const bool vec4 = !vec8 && rn >= 2 && (nC >> 2) >= NTHR;
       if (vec4) {
         const int nI = nC >> 2;
         for (int it = tid; it < nI; it += NTHR) {
@@ -358,7 +403,7 @@ persist_kernel(const PersistArgs a) {
       while (tpo * 2 <= NTHR / nC && tpo * 2 <= K) tpo *= 2;
       const int kper = K / tpo;
       const int per_round = NTHR / tpo;
-      for (int o0 = vec4 ? nC : 0; o0 < nC; o0 += per_round) {
+      for (int o0 = (vec4 || vec8) ? nC : 0; o0 < nC; o0 += per_round) {
         const int o = o0 + tid / tpo;
         const int j = tid % tpo;
         int32_t V = INT32_MIN;
