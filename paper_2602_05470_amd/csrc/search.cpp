@@ -889,7 +889,8 @@ std::vector<uint8_t> local_search_mwis(int32_t n, int32_t m, const int32_t* uv,
 // MACs of its leaves (each leaf's sliced tree) plus a per-search-node weight
 // for the host's share, lowest score kept (the greedy tree on ties).  The
 // probes run in parallel, each stopped past 2^22 nodes; once one finishes
-// with N nodes, the others stop past 2N + 1024 nodes and are not chosen.  On
+// with score S and N nodes, the others stop past min(S / 2^17, 2N + 1024)
+// nodes and are not chosen.  On
 // zero-field +-J lattices the leaves and MACs depend on the structure only,
 // so one instance's probe serves every instance of that structure.
 Tree choose_order(const Network& net, int n, const SearchOptions& probe) {
@@ -920,13 +921,19 @@ Tree choose_order(const Network& net, int n, const SearchOptions& probe) {
       } catch (const std::exception&) {
         return;  // this candidate cannot be planned (or was cut off): not chosen
       }
-      const uint64_t mine = 2 * st.nodes + 1024;
-      uint64_t cur = limit.load();
-      while (mine < cur && !limit.compare_exchange_weak(cur, mine)) {
-      }
       double macs = 0;
       for (const auto& g : groups) macs += (double)g.count * std::exp2(complexity(cand[c], g.mask).tc_log2);
       score[c] = macs + kNodeMacs * (double)st.nodes;
+      // a probe past score / kNodeMacs nodes already scores worse than this
+      // one; one past twice this one's nodes is taken to be worse too (a
+      // bound on the probes' time: which probes a fast finisher stops can
+      // depend on thread timing, the results of the solve never do)
+      const double lim = std::min(std::floor(score[c] / kNodeMacs) + 1,
+                                  2.0 * (double)st.nodes + 1024.0);
+      const uint64_t mine = (uint64_t)lim;
+      uint64_t cur = limit.load();
+      while (mine < cur && !limit.compare_exchange_weak(cur, mine)) {
+      }
     });
   for (auto& t : th) t.join();
   int best = 0;
