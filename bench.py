@@ -1,23 +1,31 @@
 """Benchmark: exact (E0, degeneracy) instances per hour on one MI355X.
 
 Workload (the configuration the headline metric is quoted on): +-J spin glass
-on a 16 x 16 open-boundary lattice, couplings +-1 from numpy seeds 0-19, zero
+on a 16 x 16 open-boundary lattice, couplings +-1 from numpy seeds 0-319, zero
 field; plain BBTN with T_target = 2^10 (greedy contraction order, branching on
 separator spins), counts as residues modulo 3 primes per pass, CRT-certified.
 One step = one call through the C ABI that fully solves --batch-size
-instances (default 20: seeds 0-19, bbtn_solve_batch): network build, search,
-values-only pass, counting pass, CRT and certification, configuration
-recovery; --workers contexts run steps concurrently.  Every result is
-checked against the oracle's stored exact values; only exact, certified
-results are counted.
+instances (default 160 distinct seeds, bbtn_solve_batch): network build,
+search, values-only pass, counting pass, CRT and certification,
+configuration recovery; --workers contexts (default 3) run steps
+concurrently.  Every result is checked against the oracle's stored exact
+values; only exact, certified results are counted.
 
 The JSON line also carries
-  roofline:     the dominant kernel's semiring operations per second (events
-                around its launches on its own stream, over the timed steps)
-                against the VALU integer peak;
-  cpu_baseline: the CPU oracle (exact transfer matrix in C, all host threads)
-                timed on a bounded sample of the same instances on this host;
-  tgemm_micro:  the counting tropical product alone at large shapes.
+  roofline:      the dominant kernel's semiring operations per second (events
+                 around its executor passes on its own stream, over the timed
+                 steps) against the VALU integer peak, and its HBM bytes per
+                 pass from the stored counter summary;
+  refined_order: the same run with the contraction order refined by
+                 annealing (order_refine = 8);
+  per_branch:    the same solves with one branch at a time (batched = 0);
+  cpu_baseline:  the CPU oracle (exact transfer matrix in C, all host
+                 threads) timed on a bounded sample of the same instances on
+                 this host;
+  tgemm_micro:   the counting tropical product alone at large shapes.
+
+--large N prints instead exact solves of the 32 x 32 spin glass and the
+40 x 40 King's subgraph (refined order; plain planner and learned scorer).
 """
 import argparse
 import json
