@@ -893,53 +893,71 @@ std::vector<uint8_t> local_search_mwis(int32_t n, int32_t m, const int32_t* uv,
 // nodes and are not chosen.  On
 // zero-field +-J lattices the leaves and MACs depend on the structure only,
 // so one instance's probe serves every instance of that structure.
-Tree choose_order(const Network& net, int n, const SearchOptions& probe) {
+Tree choose_order(const Network& net, int n, const SearchOptions& probe, bool* complete) {
   n = std::max(0, std::min(64, n));
+  if (complete) *complete = true;
   if (n == 0) return greedy_tree(net);
   constexpr double kNodeMacs = 131072.0;  // host time of a search node, in device MACs
   std::vector<Tree> cand(n + 1);
   std::vector<double> score(n + 1, HUGE_VAL);
+  std::vector<char> done(n + 1, 0);
   cand[0] = greedy_tree(net);  // built before any thread reads it
-  std::atomic<uint64_t> limit{uint64_t(1) << 22};  // bounds the probes' time and memory
-  SearchOptions so = probe;
-  so.node_limit = &limit;
-  std::vector<std::thread> th;
-  for (int c = 0; c <= n; ++c)
-    th.emplace_back([&, c] {
-      if (c > 0) {
+  auto late = [&] { return probe.deadline > 0 && now_s() > probe.deadline; };
+  {
+    std::vector<std::thread> th;
+    for (int c = 1; c <= n; ++c)
+      th.emplace_back([&, c] {
         RefineOptions o;
         o.sweeps = 200;
         o.log2_target = probe.log2_target;
         o.rho_weight = 0.25;
         o.seed = (uint64_t)c;
+        o.deadline = probe.deadline;
         cand[c] = refine_tree(net, cand[0], o);
-      }
-      std::vector<LeafGroup> groups;
-      SearchStats st;
-      try {
-        bb_search(net, cand[c], so, groups, st);
-      } catch (const std::exception&) {
-        return;  // this candidate cannot be planned (or was cut off): not chosen
-      }
-      double macs = 0;
-      for (const auto& g : groups) macs += (double)g.count * std::exp2(complexity(cand[c], g.mask).tc_log2);
-      score[c] = macs + kNodeMacs * (double)st.nodes;
-      // a probe past score / kNodeMacs nodes already scores worse than this
-      // one; one past twice this one's nodes is taken to be worse too (a
-      // bound on the probes' time: which probes a fast finisher stops can
-      // depend on thread timing, the results of the solve never do)
-      const double lim = std::min(std::floor(score[c] / kNodeMacs) + 1,
-                                  2.0 * (double)st.nodes + 1024.0);
-      const uint64_t mine = (uint64_t)lim;
-      uint64_t cur = limit.load();
-      while (mine < cur && !limit.compare_exchange_weak(cur, mine)) {
-      }
-    });
-  for (auto& t : th) t.join();
-  int best = 0;
-  for (int c = 1; c <= n; ++c)
-    if (score[c] < score[best]) best = c;
-  return std::move(cand[best]);
+      });
+    for (auto& t : th) t.join();
+  }
+  // Probes run in rounds of growing node budgets, 2^10, 2^12, ... 2^22: a
+  // round re-runs every unfinished probe from the start with the round's
+  // budget, and the first round in which some probe finishes decides.  Every
+  // probe's outcome in a round depends on its budget only, so the choice is
+  // the same on every run.  Within a round a finished probe with score S
+  // stops the others past S / kNodeMacs nodes: they score worse than S, and
+  // could not have been chosen.
+  for (int lb = 10; lb <= 22 && !late(); lb += 2) {
+    std::atomic<uint64_t> limit{uint64_t(1) << lb};
+    SearchOptions so = probe;
+    so.node_limit = &limit;
+    std::vector<std::thread> th;
+    for (int c = 0; c <= n; ++c)
+      th.emplace_back([&, c] {
+        std::vector<LeafGroup> groups;
+        SearchStats st;
+        try {
+          bb_search(net, cand[c], so, groups, st);
+        } catch (const std::exception&) {
+          return;  // over this round's budget (or cannot be planned)
+        }
+        double macs = 0;
+        for (const auto& g : groups)
+          macs += (double)g.count * std::exp2(complexity(cand[c], g.mask).tc_log2);
+        score[c] = macs + kNodeMacs * (double)st.nodes;
+        done[c] = 1;
+        const uint64_t mine = (uint64_t)std::min(std::floor(score[c] / kNodeMacs) + 1, 1e18);
+        uint64_t cur = limit.load();
+        while (mine < cur && !limit.compare_exchange_weak(cur, mine)) {
+        }
+      });
+    for (auto& t : th) t.join();
+    if (late()) break;
+    int best = -1;
+    for (int c = 0; c <= n; ++c)
+      if (done[c] && (best < 0 || score[c] < score[best])) best = c;
+    if (best >= 0) return std::move(cand[best]);
+  }
+  // no probe finished within 2^22 nodes, or the deadline came first
+  if (complete) *complete = !late();
+  return std::move(cand[0]);
 }
 
 }  // namespace bbtn

@@ -81,7 +81,10 @@ std::vector<uint8_t> local_search_mwis(int32_t n, int32_t m, const int32_t* uv,
 // The contraction order used for a structure: the greedy tree (n = 0) or the
 // cheapest of it and n <= 64 annealed refinements (refine_tree with seeds
 // 1..n), each scored by a branch-and-bound search of `net` with `probe`:
-// semiring MACs of its leaves plus a fixed weight per search node.
-Tree choose_order(const Network& net, int n, const SearchOptions& probe);
+// semiring MACs of its leaves plus a fixed weight per search node.  The
+// choice is deterministic.  `complete` (optional) is set to false when
+// probe.deadline cut the choice short (the greedy tree is then returned).
+Tree choose_order(const Network& net, int n, const SearchOptions& probe,
+                  bool* complete = nullptr);
 
 }  // namespace bbtn

@@ -56,13 +56,16 @@ TreeRef tree_for(bbtn_ctx* ctx, const Network& net, const SearchOptions* probe) 
     }
   }
   try {
+    bool complete = true;
     auto tree = std::make_shared<const Tree>(
-        refine ? choose_order(net, ctx->opt.order_refine, *probe) : greedy_tree(net));
+        refine ? choose_order(net, ctx->opt.order_refine, *probe, &complete) : greedy_tree(net));
     std::lock_guard<std::mutex> lk(ctx->tree_mu);
     TreeRef r;
     auto it = ctx->tree_cache.find(shape);
     if (it != ctx->tree_cache.end()) {
       r = TreeRef{it->second.tree, it->second.id};
+    } else if (!complete) {
+      r = TreeRef{tree, next_id++};  // cut short by the time limit: not cached
     } else {
       if (ctx->tree_cache.size() >= 8) ctx->tree_cache.clear();
       r = TreeRef{tree, next_id++};
@@ -513,6 +516,7 @@ void solve_instances(bbtn_ctx* ctx, std::vector<Instance>& insts) {
       probe.log2_target = opt.log2_target;
       probe.region_max = std::max(1, std::min(16, opt.region_max));
       probe.values_only = values_only;
+      probe.deadline = deadline;
       w.tree = tree_for(ctx, in.net, branch ? &probe : nullptr);
       // value (with the folded constant, like node_bound) of the local-search
       // configuration: a lower bound on the optimum, used for global pruning

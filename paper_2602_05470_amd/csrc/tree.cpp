@@ -1,5 +1,6 @@
 #include "tree.h"
 
+#include <chrono>
 #include <cmath>
 #include <queue>
 #include <random>
@@ -157,6 +158,10 @@ Tree refine_tree(const Network& net, const Tree& in, const RefineOptions& o) {
   std::vector<int32_t> internal;
   for (int id = t.n_base; id < N; ++id) internal.push_back(id);
   for (int sw = 0; sw < o.sweeps; ++sw) {
+    if (o.deadline > 0 &&
+        std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch())
+                .count() > o.deadline)
+      break;
     const double beta = o.beta0 + (o.beta1 - o.beta0) * sw / std::max(1, o.sweeps - 1);
     std::shuffle(internal.begin(), internal.end(), rng);
     for (int n : internal) {

@@ -45,6 +45,7 @@ struct RefineOptions {
   int log2_target = 0;     // T_target of the overflow measure rho
   double rho_weight = 0.0; // per log2 entry above log2_target
   uint64_t seed = 1;
+  double deadline = 0;     // absolute wall time (s) or 0: stop sweeping past it
 };
 Tree refine_tree(const Network& net, const Tree& t, const RefineOptions& o);
 

@@ -11,7 +11,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
 
 import instances as I  # noqa: E402
-from oracle import tm, tm_c  # noqa: E402
+from oracle import tm, tm_c, value  # noqa: E402
 
 
 def larger():
@@ -57,6 +57,56 @@ def sg32x24():
             f.flush()
 
 
+def _values(name, header, rows):
+    with open(os.path.join(HERE, name), "w") as f:
+        f.write(header)
+        for row in rows:
+            f.write(" ".join(str(x) for x in row) + "\n")
+            f.flush()
+
+
+def sg_values(L, seeds):
+    """Ground energies of L x L +-J lattices (zero field) by the matching
+    oracle; the degeneracy is beyond every exact oracle here."""
+    def rows():
+        for s in seeds:
+            g = I.spin_glass_square(L, s)
+            yield (s, value.spin_glass_planar_e0(L, g["edges"], g["J"]))
+    _values("sg%d_values.txt" % L,
+            "# +-J spin glass %dx%d open lattice, zero field, seeds %d-%d:\n"
+            "# seed E0  (oracle: minimum-weight perfect matching on the dual)\n"
+            % (L, L, seeds[0], seeds[-1]), rows())
+
+
+def ksg_values(L, seeds):
+    """Maximum independent set sizes of L x L King's subgraphs (fill 0.8) by
+    the integer-programming oracle."""
+    def rows():
+        for s in seeds:
+            g = I.kings_subgraph(L, s)
+            yield (s, g["n"], value.mwis_milp(g["n"], g["edges"]))
+    _values("ksg%d_values.txt" % L,
+            "# unweighted MIS on King's subgraph %dx%d, fill 0.8, seeds %d-%d:\n"
+            "# seed n W*  (oracle: integer program, HiGHS)\n"
+            % (L, L, seeds[0], seeds[-1]), rows())
+
+
+def sg32_values():
+    sg_values(32, list(range(20)))
+
+
+def ksg40_values():
+    ksg_values(40, list(range(20)))
+
+
+def sg48_values():
+    sg_values(48, [0, 1])
+
+
+def ksg64_values():
+    ksg_values(64, [0, 1])
+
+
 def sg16_more():
     """Further 16x16 seeds (20-319) for throughput runs over many distinct
     instances (C transfer matrix)."""
@@ -71,6 +121,10 @@ def sg16_more():
 
 
 def main():
+    sg32_values()
+    ksg40_values()
+    sg48_values()
+    ksg64_values()
     larger()
     sg32x24()
     sg16_more()

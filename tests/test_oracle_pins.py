@@ -113,6 +113,20 @@ def test_full_kings_odd(L):
         assert brute.mwis(g["n"], g["edges"])[:2] == want
 
 
+@pytest.mark.parametrize("L,want", [(2, (1, 4)), (4, (4, 79)), (6, (9, 3600)), (8, (16, 281571))])
+def test_full_kings_even(L, want):
+    """Full King's graphs with even side: every 2x2 block holds at most one
+    vertex of an independent set, so the MIS size is (L/2)^2; the counts are
+    those of a separate exact enumeration, reached here by two independent
+    algorithms (transfer matrix and variable elimination), and by brute force
+    up to 16 vertices."""
+    g = I.full_kings_graph(L)
+    assert tm.kings_subgraph(g) == want
+    assert ve.mwis(g["n"], g["edges"]) == want
+    if L <= 4:
+        assert brute.mwis(g["n"], g["edges"])[:2] == want
+
+
 # ----------------------------------------------------- exact solvers vs brute force
 @pytest.mark.parametrize("seed", range(5))
 def test_sg_4x4_three_ways(seed):
@@ -156,6 +170,16 @@ def test_random_graphs_ve_vs_brute():
         J = rng.choice([-1, 1], size=len(edges))
         assert ve.spin_glass(n, edges, J) == brute.spin_glass(n, edges, J)[:2]
         assert ve.mwis(n, edges) == brute.mwis(n, edges)[:2]
+
+
+@pytest.mark.parametrize("seed,want", [(0, (-84, 270)), (1, (-86, 6)), (2, (-76, 20832))])
+def test_sg_8x8_exact_pins(seed, want):
+    """+-J 8x8 lattices of the seeded generator: (E0, degeneracy) from a
+    separate exact enumeration, reached by the transfer matrix and by
+    variable elimination."""
+    g = I.spin_glass_square(8, seed)
+    assert tm.spin_glass_square(g) == want
+    assert ve.spin_glass(g["n"], g["edges"], g["J"]) == want
 
 
 # ------------------------------------------------------------------ invariants
@@ -204,6 +228,43 @@ def test_ksg_value_matches_milp(seed):
         w, cnt = tm.kings_subgraph(g)
         assert value.mwis_milp(g["n"], g["edges"], g["w"]) == w
         assert cnt >= 1
+
+
+def _golden_rows(name):
+    rows = []
+    with open(os.path.join(GOLDEN, name)) as f:
+        for line in f:
+            if line.strip() and not line.startswith("#"):
+                rows.append([int(x) for x in line.split()])
+    return rows
+
+
+def test_large_value_pins():
+    """Ground values of the large configurations, seed 0: the matching oracle
+    (32x32 spin glass) and the integer-programming oracle (40x40 King's
+    subgraph) recomputed here, and the stored tables of every large size
+    (written by tests/golden/make_golden.py from the same oracles) against
+    values of an independent earlier run of those oracles: SG 32x32 -1432,
+    SG 48x48 -3212, KSG 40x40 377, KSG 64x64 964."""
+    g = I.spin_glass_square(32, 0)
+    assert value.spin_glass_planar_e0(32, g["edges"], g["J"]) == -1432
+    g = I.kings_subgraph(40, 0)
+    assert value.mwis_milp(g["n"], g["edges"]) == 377
+    assert _golden_rows("sg32_values.txt")[0] == [0, -1432]
+    assert _golden_rows("sg48_values.txt")[0] == [0, -3212]
+    assert _golden_rows("ksg40_values.txt")[0][::2] == [0, 377]
+    assert _golden_rows("ksg64_values.txt")[0][::2] == [0, 964]
+    # invariants every stored spin-glass value obeys: E0 = -|E| mod 2, and
+    # E0 >= -|E| (a bond contributes at least -1)
+    for L, name in ((32, "sg32_values.txt"), (48, "sg48_values.txt")):
+        m = 2 * L * (L - 1)
+        for s, e0 in _golden_rows(name):
+            assert (e0 + m) % 2 == 0 and -m < e0 < 0
+    for L, name in ((40, "ksg40_values.txt"), (64, "ksg64_values.txt")):
+        for s, n, w in _golden_rows(name):
+            assert n == I.kings_subgraph(L, s)["n"]
+            # one vertex per 2x2 block at most: W* <= ceil(L/2)^2
+            assert 0 < w <= ((L + 1) // 2) ** 2
 
 
 # --------------------------------------------------------- device-encoding ops
@@ -375,6 +436,51 @@ def test_bf16_decode_is_exact():
     # bf16 keeps 8 significant bits: relative rounding error below 2^-8
     assert np.all(np.abs(back - x) <= np.abs(x) * 2.0 ** -8)
     assert back[0] == 1.0 and back[1] == -2.5 and back[2] == 3.140625
+
+
+def test_bf16_encode_fixed_patterns():
+    """Round to nearest, ties to even, on hand-chosen float32 bit patterns
+    (bfloat16 = the upper 16 bits of a float32)."""
+    from oracle import mlp
+    cases = [
+        (0x3F800000, 0x3F80),   # 1.0 exact
+        (0x3F807FFF, 0x3F80),   # below half an ulp: down
+        (0x3F808000, 0x3F80),   # exactly half, kept part even: down
+        (0x3F818000, 0x3F82),   # exactly half, kept part odd: up to even
+        (0x3F808001, 0x3F81),   # above half: up
+        (0xBF808001, 0xBF81),   # sign is kept, magnitude rounds up
+        (0x3FFF8000, 0x4000),   # carry into the exponent (1.99... -> 2.0)
+        (0x7F7F8000, 0x7F80),   # largest finite ties to even: overflows to +inf
+        (0x7F800000, 0x7F80),   # +inf
+        (0x00000001, 0x0000),   # smallest subnormal: down to +0
+        (0x80000000, 0x8000),   # -0
+        (0x40490FDB, 0x4049),   # pi: 0x0FDB < 0x8000, down
+    ]
+    bits = np.array([c[0] for c in cases], np.uint32)
+    got = mlp.encode_bf16(bits.view(np.float32))
+    assert [int(x) for x in got] == [c[1] for c in cases]
+    # decoding is the exact inverse on bfloat16 patterns
+    back = mlp.decode_bf16(got)
+    assert np.array_equal(mlp.encode_bf16(back.astype(np.float32)), got)
+
+
+def test_tensor_max_pins():
+    """Largest finite value of a tensor: hand cases around the minus-infinity
+    threshold (any value at or below -2^29 is minus infinity)."""
+    NEG, CUT = device_ops.NEG, device_ops.NEG_CUT
+    assert device_ops.tensor_max([3, NEG, -5]) == 3
+    assert device_ops.tensor_max([NEG, NEG]) == NEG
+    assert device_ops.tensor_max([CUT, -7]) == -7
+    assert device_ops.tensor_max([CUT]) == NEG
+    assert device_ops.tensor_max([CUT + 1, NEG]) == CUT + 1
+    assert device_ops.tensor_max([-(1 << 28), -(1 << 28) + 1]) == -(1 << 28) + 1
+    # brute force over small random tensors: max over the finite entries
+    rng = np.random.default_rng(5)
+    for _ in range(50):
+        v = rng.integers(-9, 10, size=int(rng.integers(1, 9)))
+        v[rng.random(v.size) < 0.3] = NEG
+        fin = [int(x) for x in v if x > CUT]
+        assert device_ops.tensor_max(v) == (max(fin) if fin else NEG)
 
 
 # ------------------------------------------------- C transfer-matrix oracle

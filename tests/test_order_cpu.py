@@ -66,3 +66,18 @@ def test_order_refine_bounds(B):
         B.order_complexity(0, n, edges, J, order_refine=65, log2_target=2)
     with pytest.raises(B.BBTNError):
         B.order_complexity(0, n, edges, J, order_refine=-1, log2_target=2)
+
+
+def test_order_choice_is_deterministic(B):
+    """The refined order is chosen by probe searches that run on parallel
+    threads in rounds of fixed node budgets: repeated choices for the same
+    structure give the same tree (same complexity and the same leaves)."""
+    g = I.kings_subgraph(14, 3)
+    args = (1, g["n"], np.asarray(g["edges"]).reshape(-1, 2), None)
+    runs = [B.order_complexity(*args, order_refine=8, log2_target=8) for _ in range(3)]
+    assert runs[0] == runs[1] == runs[2]
+    leaves = [B.plan_leaves(*args, log2_target=8, order_refine=8)[0] for _ in range(3)]
+    assert all(np.array_equal(leaves[0], x) for x in leaves[1:])
+    n, edges, J = _sg(16)
+    runs = [B.order_complexity(0, n, edges, J, order_refine=8, log2_target=10) for _ in range(3)]
+    assert runs[0] == runs[1] == runs[2]
