@@ -176,6 +176,27 @@ bbtn_status bbtn_tgemm(bbtn_ctx* ctx, int32_t k, const uint32_t* primes,
                        const void* A, const void* B, void* C, void* stream);
 
 /*
+ * bbtn_tgemm for callers that cannot allocate device memory (code under
+ * hipGraph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same product, arguments and errors, with no device allocation, no
+ * hipFree and no tile autotuning in the call (tiles come from the context's
+ * cached tuning or the shape heuristic).  When the product is split along K,
+ * the partial results go to a static device array of 2^24 32-bit words
+ * (64 MiB) that each device the library runs on holds until the process
+ * ends; the split factor is lowered until (1 + k) * splits * batch * M * N
+ * words fit in it, down to an unsplit product that needs none, so no size
+ * within bbtn_tgemm's limits is refused for its sake.  The array is shared by
+ * every call on a device and keeps the last call's partials (each call writes
+ * every partial it reads): calls on one device that overlap in time (on
+ * different streams, or from different host threads) race on it and must be
+ * serialised by the caller.  The context must have been created on this
+ * device (bbtn_create sets the array up).
+ */
+bbtn_status bbtn_tgemm_noalloc(bbtn_ctx* ctx, int32_t k, const uint32_t* primes,
+                               int64_t batch, int64_t M, int64_t N, int64_t K,
+                               const void* A, const void* B, void* C, void* stream);
+
+/*
  * Permutation and branch-variable fixing of a tensor (slicing,
  * T|_{s_Vf = x} of Eq. 3), batched over L outputs.
  * Input: tensor buffer of in_entries entries over r_in variables (in_entries

@@ -67,7 +67,7 @@ _RESULT_DTYPE = np.dtype({
 _lib = None
 
 EXPORTS = ["bbtn_default_options", "bbtn_create", "bbtn_destroy", "bbtn_last_error",
-           "bbtn_solve_spinglass", "bbtn_solve_mwis", "bbtn_tgemm", "bbtn_gather",
+           "bbtn_solve_spinglass", "bbtn_solve_mwis", "bbtn_tgemm", "bbtn_tgemm_noalloc", "bbtn_gather",
            "bbtn_reduce", "bbtn_bound", "bbtn_last_macs", "bbtn_profile",
            "bbtn_get_kernel_stats", "bbtn_mlp_forward", "bbtn_mlp_backward", "bbtn_mlp_adam",
            "bbtn_scorer_load", "bbtn_scorer_collect", "bbtn_scorer_train", "bbtn_plan_leaves",
@@ -116,6 +116,8 @@ def load(path: str = LIB_PATH):
     lib.bbtn_solve_batch.restype = I32
     lib.bbtn_tgemm.argtypes = [P, I32, P, I64, I64, I64, I64, P, P, P, P]
     lib.bbtn_tgemm.restype = I32
+    lib.bbtn_tgemm_noalloc.argtypes = [P, I32, P, I64, I64, I64, I64, P, P, P, P]
+    lib.bbtn_tgemm_noalloc.restype = I32
     lib.bbtn_gather.argtypes = [P, I32, I32, I32, P, I64, I64, P, P, I64, P, P]
     lib.bbtn_gather.restype = I32
     lib.bbtn_reduce.argtypes = [P, I32, P, I64, I64, I64, I64, P, I64, P, P]
@@ -377,6 +379,13 @@ class Context:
         pr = (C.c_uint32 * k)(*[int(p) for p in primes[:k]])
         self._check(self.lib.bbtn_tgemm(self.h, k, pr, batch, M, N, K, _dptr(A), _dptr(B),
                                         _dptr(Cout), _stream(stream)))
+
+    def tgemm_noalloc(self, k, primes, batch, M, N, K, A, B, Cout, stream=None):
+        """bbtn_tgemm_noalloc: bbtn_tgemm with no device allocation (split-K
+        partials in the library's static device scratch)."""
+        pr = (C.c_uint32 * k)(*[int(p) for p in primes[:k]])
+        self._check(self.lib.bbtn_tgemm_noalloc(self.h, k, pr, batch, M, N, K, _dptr(A),
+                                                _dptr(B), _dptr(Cout), _stream(stream)))
 
     def gather(self, k, r_in, r_out, src_bits, L, in_stride, fixed_bits, inp, in_entries, out,
                stream=None):

@@ -107,6 +107,9 @@ bbtn_status bbtn_create(const bbtn_options* opt, bbtn_ctx** out) {
       ctx->stream = ctx->own;
     }
     (void)prime_table();
+    // once per device, with the device current: the address of its copy of
+    // the allocation-free product's scratch array
+    noalloc_scratch_init(ctx->opt.device);
     if (ctx->opt.autotune_cache) load_tune_cache(ctx, ctx->opt.autotune_cache);
     if (ctx->opt.scorer_weights) load_scorer(ctx, ctx->opt.scorer_weights);
   });
@@ -265,6 +268,39 @@ bbtn_status bbtn_tgemm(bbtn_ctx* ctx, int32_t k, const uint32_t* primes, int64_t
                  tv.cfg, tv.splits, part, st);
     ctx->prof.end(ph, st, K_TGEMM, (double)batch * M * N * K * (2 + 2 * k),
                   (double)(1 + k) * 4 * (double)batch * (double)(M * K + K * N + M * N));
+  });
+}
+
+bbtn_status bbtn_tgemm_noalloc(bbtn_ctx* ctx, int32_t k, const uint32_t* primes, int64_t batch,
+                               int64_t M, int64_t N, int64_t K, const void* A, const void* B,
+                               void* C, void* stream) {
+  if (!ctx) return BBTN_E_INVALID_ARG;
+  return guard(ctx, [&] {
+    BBTN_REQUIRE(k >= 1 && k <= KMAX, "k must be in [1, 4]");
+    BBTN_REQUIRE(primes != nullptr, "primes is NULL");
+    BBTN_REQUIRE(batch >= 1 && M >= 1 && N >= 1 && K >= 1, "empty product");
+    BBTN_REQUIRE(A && B && C, "NULL operand");
+    BBTN_REQUIRE(batch * M * K < (1ll << 40) && batch * K * N < (1ll << 40) &&
+                     batch * M * N < (1ll << 40), "operand too large");
+    BBTN_HIP(hipSetDevice(ctx->opt.device));
+    uint32_t* scr = noalloc_scratch(ctx->opt.device);
+    BBTN_REQUIRE(scr != nullptr, "scratch array not set up on this device");
+    const Moduli mod = make_moduli(k, primes);
+    // no tuning here (it allocates): the cached choice or the heuristic, with
+    // the split-K factor lowered until the partial results fit the scratch
+    TuneVal tv = cached_or_heuristic_tiles(ctx, k, batch, M, N, K);
+    const int64_t outer = batch * M * N;
+    int splits = tv.splits;
+    while (splits > 1 &&
+           (int64_t)(1 + k) * tgemm_partial_entries(tv.cfg, splits, K, outer) > kNoAllocScratchWords)
+      splits = splits / 2;
+    const int64_t pe = tgemm_partial_entries(tv.cfg, splits, K, outer);
+    DevTensor part{};
+    if (pe > 0) part = DevTensor{scr, pe};
+    GemmShape sh{batch, M, N, K, M * K, K * N, M * N};
+    launch_tgemm(k, mod, sh, DevTensor{(uint32_t*)A, batch * M * K},
+                 DevTensor{(uint32_t*)B, batch * K * N}, DevTensor{(uint32_t*)C, outer}, tv.cfg,
+                 splits, part, pick_stream(ctx, stream));
   });
 }
 

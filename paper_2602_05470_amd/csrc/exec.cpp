@@ -86,10 +86,14 @@ static int ilog2_bucket(int64_t x) {
   return b;
 }
 
-TuneVal choose_tiles(bbtn_ctx* ctx, int k, int64_t batch, int64_t M, int64_t N, int64_t K) {
-  const TuneKey key{k, std::min(ilog2_bucket(batch), 20), ilog2_bucket(M), ilog2_bucket(N),
-                    ilog2_bucket(K)};
-  auto it = ctx->tune.find(key);
+static TuneKey tune_key(int k, int64_t batch, int64_t M, int64_t N, int64_t K) {
+  return TuneKey{k, std::min(ilog2_bucket(batch), 20), ilog2_bucket(M), ilog2_bucket(N),
+                 ilog2_bucket(K)};
+}
+
+TuneVal cached_or_heuristic_tiles(const bbtn_ctx* ctx, int k, int64_t batch, int64_t M,
+                                  int64_t N, int64_t K) {
+  auto it = ctx->tune.find(tune_key(k, batch, M, N, K));
   if (it != ctx->tune.end()) return it->second;
   TuneVal tv{2, 1};
   if (M == 1 && N >= 64) tv.cfg = 5;
@@ -108,6 +112,13 @@ TuneVal choose_tiles(bbtn_ctx* ctx, int k, int64_t batch, int64_t M, int64_t N, 
     int64_t sp = std::min<int64_t>(K / 64, (2048 + tiles - 1) / tiles);
     tv.splits = (int)std::max<int64_t>(1, std::min<int64_t>(sp, 256));
   }
+  return tv;
+}
+
+TuneVal choose_tiles(bbtn_ctx* ctx, int k, int64_t batch, int64_t M, int64_t N, int64_t K) {
+  const TuneKey key = tune_key(k, batch, M, N, K);
+  if (ctx->tune.count(key)) return ctx->tune[key];
+  TuneVal tv = cached_or_heuristic_tiles(ctx, k, batch, M, N, K);
   // measured choice for products large enough to matter
   if (ctx->opt.autotune_cache && (double)batch * M * N * K >= (double)(1 << 24)) {
     tv = autotune_shape(ctx, k, batch, M, N, K, tv);

@@ -31,6 +31,10 @@ void save_tune_cache(bbtn_ctx* ctx, const char* path);
 // autotuner's cached choice, else (tuning when a cache path is set) a
 // measured one, else a shape heuristic.
 TuneVal choose_tiles(bbtn_ctx* ctx, int k, int64_t batch, int64_t M, int64_t N, int64_t K);
+// The same choice without tuning: the cached measured choice, else the shape
+// heuristic.  Allocates nothing on the device.
+TuneVal cached_or_heuristic_tiles(const bbtn_ctx* ctx, int k, int64_t batch, int64_t M,
+                                  int64_t N, int64_t K);
 
 // Run the program `g` for L branches.  assign[l * |S| + j] is the state of
 // the j-th fixed variable (ascending ids) of branch l.  Writes, for every

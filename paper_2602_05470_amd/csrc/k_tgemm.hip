@@ -16,6 +16,8 @@
 // thread reads its RM (RN) consecutive rows (columns) of a slice.  Workgroups
 // are remapped so that each XCD works on a contiguous range of tiles (tiles
 // sharing rows of A land in the same L2).
+#include <mutex>
+
 #include "kernels.h"
 
 namespace bbtn {
@@ -464,6 +466,49 @@ void launch_tgemm_values(const GemmShape& s, const int32_t* A, const int32_t* B,
   a.mod = make_moduli(0, nullptr);
   int cfg = (s.M >= 32 && s.N >= 32) ? 0 : (s.M == 1 ? 5 : (s.N == 1 ? 6 : 2));
   launch_core(0, a, cfg, st);
+}
+
+// ---------------------------------------------------- allocation-free product
+// Split-K partial results of bbtn_tgemm_noalloc live in this file-scope device
+// array (kNoAllocScratchWords 32-bit words, 64 MiB), which every device the
+// library runs on holds until the process ends.  In host code the name below
+// is only a stand-in for the device copy: host code takes the address that
+// hipGetSymbolAddress returns for the current device and never passes the
+// name itself to a kernel or a copy.
+static __device__ __align__(256) uint32_t scratch[kNoAllocScratchWords];
+
+namespace {
+constexpr int kMaxScratchDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxScratchDevices] = {};
+}  // namespace
+
+void noalloc_scratch_init(int device) {
+  BBTN_REQUIRE(device >= 0 && device < kMaxScratchDevices, "device ordinal out of range");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (g_scratch_ptr[device]) return;
+  int cur = -1;
+  BBTN_HIP(hipGetDevice(&cur));
+  BBTN_REQUIRE(cur == device, "scratch set-up needs its device to be current");
+  void* p = nullptr;
+  BBTN_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+  BBTN_REQUIRE(p != nullptr, "no device address for the scratch array");
+  g_scratch_ptr[device] = p;
+}
+
+uint32_t* noalloc_scratch(int device) {
+  if (device < 0 || device >= kMaxScratchDevices) return nullptr;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  return (uint32_t*)g_scratch_ptr[device];
+}
+
+int64_t tgemm_partial_entries(int cfg, int splits, int64_t K, int64_t outer) {
+  BBTN_REQUIRE(cfg >= 0 && cfg < N_TILE_CFGS, "tile config out of range");
+  const int tk = kTileCfgs[cfg].tk;
+  if (splits <= 1 || K <= tk) return 0;
+  int64_t kchunk = (K + splits - 1) / splits;
+  kchunk = (kchunk + tk - 1) / tk * tk;
+  return (K + kchunk - 1) / kchunk * outer;
 }
 
 }  // namespace bbtn

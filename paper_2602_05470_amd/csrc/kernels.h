@@ -27,6 +27,19 @@ void launch_tgemm(int k, const Moduli& mod, const GemmShape& s, DevTensor A,
                   DevTensor B, DevTensor C, int cfg, int splits,
                   DevTensor partial, hipStream_t st);
 
+// Entries of the split-K partial buffer launch_tgemm needs for `splits`
+// chunks of K with tile config `cfg` and outer = batch * M * N outputs (0 when
+// the product runs unsplit).
+int64_t tgemm_partial_entries(int cfg, int splits, int64_t K, int64_t outer);
+
+// Device scratch of the allocation-free product: a static device array of
+// kNoAllocScratchWords words per device.  noalloc_scratch_init(d), called
+// once per device with d current, looks up the array's address on d;
+// noalloc_scratch(d) returns it (nullptr before set-up).
+constexpr int64_t kNoAllocScratchWords = 1ll << 24;
+void noalloc_scratch_init(int device);
+uint32_t* noalloc_scratch(int device);
+
 // Values-only variant (k = 0): the max-plus product used for bounds and
 // configuration recovery.
 void launch_tgemm_values(const GemmShape& s, const int32_t* A, const int32_t* B,
