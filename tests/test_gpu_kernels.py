@@ -132,8 +132,18 @@ def test_tgemm_rejects_bad_prime(ctx):
     dict(r_in=4, src=[0, 1, 2, 3], L=3, fixed=None, per_leaf=True),
     dict(r_in=12, src=list(range(11, -1, -1)), L=2, fixed=None, per_leaf=True),
     dict(r_in=3, src=[], L=4, fixed="rand"),
+    # LDS-tiled path: low output bits read high input bits (transposes),
+    # fixed low input bits, several branches, tiles with and without bits
+    # outside the tile
+    dict(r_in=10, src=list(range(5, 10)) + list(range(5)), L=1, fixed=None),
+    dict(r_in=12, src=[6, 7, 8, 9, 10, 11, 0, 1, 2, 3, 4, 5], L=2, fixed=None, per_leaf=True),
+    dict(r_in=14, src=[13, 1, 12, 3, 11, 5, 10, 7, 9, 2, 8], L=3, fixed="rand"),
+    dict(r_in=16, src=[15 - j for j in range(16)], L=1, fixed=None),
+    dict(r_in=18, src=[9, 10, 11, 12, 13, 14, 15, 16, 17, 0, 2, 4, 6, 8], L=2, fixed="rand",
+         per_leaf=True),
+    dict(r_in=20, src=list(range(8, 20)) + list(range(2, 8)), L=1, fixed="rand"),
 ])
-@pytest.mark.parametrize("k", [0, 3])
+@pytest.mark.parametrize("k", [0, 3, 4])
 def test_gather_matches_oracle(ctx, case, k):
     torch = torch_cuda()
     r_in, src, L = case["r_in"], case["src"], case["L"]
