@@ -1,31 +1,39 @@
 """Benchmark: exact (E0, degeneracy) instances per hour on one MI355X.
 
-Workload (the configuration the headline metric is quoted on): +-J spin glass
-on a 16 x 16 open-boundary lattice, couplings +-1 from numpy seeds 0-319, zero
-field; plain BBTN with T_target = 2^10 (greedy contraction order, branching on
-separator spins), counts as residues modulo 3 primes per pass, CRT-certified.
-One step = one call through the C ABI that fully solves --batch-size
-instances (default 160 distinct seeds, bbtn_solve_batch): network build,
-search, values-only pass, counting pass, CRT and certification,
-configuration recovery; --workers contexts (default 3) run steps
-concurrently.  Every result is checked against the oracle's stored exact
-values; only exact, certified results are counted.
+Headline workload (the largest configuration the solver reaches on one GPU):
++-J spin glass on a 32 x 32 open-boundary lattice, couplings +-1 from numpy
+seeds 0-19, zero field.  BBTN with T_target = 2^26 entries, the contraction
+order refined by annealing (chosen once for the lattice during the warm-up
+and cached), the spin-flip symmetry of the zero-field energy (one spin fixed
+to +1, the count doubled: half the contraction work), counts as residues
+modulo 3 primes per pass plus one fused certification prime.  One step = one call through the C ABI that fully
+solves one instance: network build, order lookup, search, values-only pass,
+counting pass, CRT and certification, configuration recovery.  Step i solves
+seed i mod 20; the warm-up steps solve seeds 20, 21, ...  A result counts as
+exact when its count is certified, its ground energy equals the matching
+oracle's stored value, its degeneracy is even (spin-flip symmetry) and its
+configuration reaches the energy.
 
 The JSON line also carries
-  roofline:      the dominant kernel's semiring operations per second (events
-                 around its executor passes on its own stream, over the timed
-                 steps) against the VALU integer peak, and its HBM bytes per
-                 pass from the stored counter summary;
-  refined_order: the same run with the contraction order refined by
-                 annealing (order_refine = 8);
-  per_branch:    the same solves with one branch at a time (batched = 0);
-  cpu_baseline:  the CPU oracle (exact transfer matrix in C, all host
-                 threads) timed on a bounded sample of the same instances on
-                 this host;
+  roofline:      the dominant kernel's semiring operations per second (HIP
+                 events around its launches on the context's stream, over
+                 the timed steps) against the VALU integer peak, and its HBM
+                 bytes per launch from the stored counter summary;
+  cpu_baseline:  the oracle on this host: the exact-count transfer matrix
+                 cannot hold a 32-wide frontier (2^32 states), so the figure
+                 is the matching oracle's ground energy alone on seed 0;
+  ksg40x40:      unweighted MIS on 40 x 40 King's subgraphs (fill 0.8, seeds
+                 0-7), T_target = 2^28, refined order chosen per instance,
+                 values checked against the integer-programming oracle;
+  sg16x16:       the 16 x 16 lattice (T_target = 2^10, greedy order, 160
+                 instances per call on 3 concurrent contexts), checked against
+                 stored exact degeneracies, with its own roofline (persistent
+                 executor), refined-order and per-branch legs and the exact
+                 C transfer matrix as its CPU baseline;
   tgemm_micro:   the counting tropical product alone at large shapes.
 
---large N prints instead exact solves of the 32 x 32 spin glass and the
-40 x 40 King's subgraph (refined order; plain planner and learned scorer).
+--large N prints instead exact solves of N seeds of the 32 x 32 spin glass
+and the 40 x 40 King's subgraph, by the plain planner and the learned scorer.
 """
 import argparse
 import json
@@ -43,34 +51,38 @@ VALU_PEAK_OPS = 256 * 64 * 2.4e9
 HBM_PEAK = 8.0e12
 
 
-# Per-launch HBM traffic of the persistent executor, measured by rocprofv3
-# --pmc FETCH_SIZE and WRITE_SIZE on this workload and recorded, with a hash
-# of the kernel sources, in a profiles/ summary; reported only while the
+# Per-launch HBM traffic of a kernel, measured by rocprofv3 --pmc FETCH_SIZE
+# and WRITE_SIZE on the workload it is reported for and recorded, with a hash
+# of the kernel's sources, in a profiles/ summary; reported only while the
 # sources are unchanged.
-TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "persist_sg16_batch160_hbm_traffic.md")
-PERSIST_SOURCES = [os.path.join(ROOT, "paper_2602_05470_amd", "csrc", f)
-                   for f in ("k_persist.hip", "persist_dev.h", "persist.cpp")]
+CSRC = os.path.join(ROOT, "paper_2602_05470_amd", "csrc")
+TRAFFIC = {
+    "persist": (os.path.join(ROOT, "profiles", "persist_sg16_batch160_hbm_traffic.md"),
+                [os.path.join(CSRC, f) for f in ("k_persist.hip", "persist_dev.h", "persist.cpp")]),
+    "tgemm": (os.path.join(ROOT, "profiles", "tgemm_sg32_hbm_traffic.md"),
+              [os.path.join(CSRC, f) for f in ("k_tgemm.hip", "exec.cpp")]),
+}
 
 
-def persist_sources_sha256():
+def sources_sha256(kernel):
     import hashlib
     h = hashlib.sha256()
-    for f in PERSIST_SOURCES:
+    for f in TRAFFIC[kernel][1]:
         h.update(open(f, "rb").read())
     return h.hexdigest()
 
 
-def persist_traffic():
-    """HBM bytes per persistent-executor launch, or None when no summary
-    matches the current kernel sources."""
-    if not os.path.exists(TRAFFIC_SUMMARY):
+def kernel_traffic(kernel):
+    """HBM bytes per launch of `kernel` on its workload, or None when no
+    summary matches the current kernel sources."""
+    if kernel not in TRAFFIC or not os.path.exists(TRAFFIC[kernel][0]):
         return None
     fields = {}
-    for line in open(TRAFFIC_SUMMARY):
+    for line in open(TRAFFIC[kernel][0]):
         if ":" in line and line.strip().startswith(("kernel-sources-sha256", "hbm-bytes-per-launch")):
             key, val = line.strip().split(":", 1)
             fields[key.strip()] = val.strip().strip("`")
-    if fields.get("kernel-sources-sha256") != persist_sources_sha256():
+    if fields.get("kernel-sources-sha256") != sources_sha256(kernel):
         return None
     return int(fields["hbm-bytes-per-launch"])
 
@@ -90,7 +102,7 @@ def golden_sg16():
     return out
 
 
-def cpu_baseline(gold, seconds_budget=10.0):
+def cpu_baseline_sg16(gold, seconds_budget=10.0):
     """Time the oracle's C transfer matrix (exact multiword counts, OpenMP over
     all host threads) on seeds 0-19, repeated until the budget is spent; every
     result is checked against the stored exact values."""
@@ -200,40 +212,303 @@ def large_configs(B, I, torch, n_seeds):
     return {"large_configs": out}
 
 
+def cpu_baseline_sg32():
+    """The oracle on the headline workload, on this host: its exact-count
+    transfer matrix would hold 2^32 frontier states of a 32-wide lattice
+    (each with a multiword count), so only the ground energy is in its reach,
+    by the matching oracle; timed on seed 0 and checked against the stored
+    value."""
+    import instances as I
+    from oracle import value
+    g = I.spin_glass_square(32, 0)
+    want = golden_values("sg32_values.txt")[0][0]
+    t0 = time.time()
+    e0 = value.spin_glass_planar_e0(32, g["edges"], g["J"])
+    dt = time.time() - t0
+    if e0 != want:
+        raise RuntimeError("matching oracle disagrees with the stored value")
+    return {"value": round(3600.0 / dt, 1), "unit": "instances/hour (ground energy only)",
+            "cores": 1, "kind": "oracle",
+            "sample": "32x32 +-J seed 0: ground energy by minimum-weight perfect matching on the "
+                      "dual lattice (networkx, one thread), %.1f s; the exact degeneracy is out of "
+                      "the oracle's reach (transfer matrix over 2^32 frontier states, each with a "
+                      "multiword count: about 2^32 x 24 B = 103 GB per row step)" % dt}
+
+
+def energy_sg(sigma, edges, J):
+    """H(sigma) of Eq. 1 at zero field (configuration check of a result)."""
+    import numpy as np
+    e = np.asarray(edges, dtype=np.int64).reshape(-1, 2)
+    s = np.asarray(sigma, dtype=np.int64)
+    return int(-(np.asarray(J, dtype=np.int64) * s[e[:, 0]] * s[e[:, 1]]).sum())
+
+
+def independent_weight(x, edges):
+    """Size of x if it is an independent set, else None."""
+    import numpy as np
+    e = np.asarray(edges, dtype=np.int64).reshape(-1, 2)
+    x = np.asarray(x, dtype=np.int64)
+    if (x[e[:, 0]] & x[e[:, 1]]).any():
+        return None
+    return int(x.sum())
+
+
+def golden_values(name):
+    """seed -> stored row (ground value of the matching / integer-program
+    oracle) from tests/golden/."""
+    out = {}
+    for line in open(os.path.join(ROOT, "tests", "golden", name)):
+        if line.startswith("#") or not line.strip():
+            continue
+        row = [int(x) for x in line.split()]
+        out[row[0]] = row[1:]
+    return out
+
+
+def kernel_table(ctxs):
+    stats = {}
+    for name in ("tgemm", "persist", "gather"):
+        agg = {"launches": 0, "seconds": 0.0, "ops": 0.0, "bytes": 0.0}
+        for c in ctxs:
+            ks = c.kernel_stats(name)
+            for key in agg:
+                agg[key] += ks[key]
+        stats[name] = agg
+    return stats
+
+
+def roofline_of(stats, dt, traffic_fn):
+    dom = max(stats, key=lambda n: stats[n]["seconds"])
+    st = stats[dom]
+    achieved = st["ops"] / max(st["seconds"], 1e-12)
+    return {"bound": "alu", "kernel": dom,
+            "achieved": round(achieved / 1e12, 4), "peak": round(VALU_PEAK_OPS / 1e12, 2),
+            "unit": "TOP/s", "frac": round(achieved / VALU_PEAK_OPS, 5),
+            "traffic": traffic_fn(dom),
+            "launches": st["launches"],
+            "launch_unit": "one executor pass (its shared-subtree and branch dispatches)"
+                           if dom == "persist" else "one kernel dispatch",
+            "avg_launch_ms": round(1e3 * st["seconds"] / max(st["launches"], 1), 4),
+            "kernel_busy_share": round(st["seconds"] / dt, 4)}
+
+
+def kernels_json(stats):
+    return {n: {"launches": s["launches"], "seconds": round(s["seconds"], 5),
+                "Gop_s": round(s["ops"] / max(s["seconds"], 1e-12) / 1e9, 2),
+                "GB_s": round(s["bytes"] / max(s["seconds"], 1e-12) / 1e9, 2)}
+            for n, s in stats.items()}
+
+
+def single_instance_run(B, I, torch, kind, L, opts, seeds, warm_seeds, want, label):
+    """One instance per call on one context: warm-up calls on `warm_seeds`
+    (the refined order is chosen and cached for a lattice structure on the
+    first), then the timed calls on `seeds` with kernel timing on.  A result
+    counts as exact when it is certified, its value equals the stored
+    oracle value, its configuration reaches that value and (zero-field spin
+    glass) its degeneracy is even."""
+    make = (lambda s: I.spin_glass_square(L, s)) if kind == 0 else (lambda s: I.kings_subgraph(L, s))
+    ctx = B.Context(opts)
+
+    def solve(g):
+        if kind == 0:
+            return ctx.solve_spinglass(g["n"], g["edges"], g["J"])
+        return ctx.solve_mwis(g["n"], g["edges"], g["w"])
+    for s in warm_seeds:
+        print("%s warm-up seed %d" % (label, s), file=sys.stderr, flush=True)
+        solve(make(s))
+    torch.cuda.synchronize()
+    insts = [make(s) for s in seeds]
+    ctx.profile(True)
+    lat, rows = [], []
+    r0 = os.times()
+    ta = time.perf_counter()
+    for s, g in zip(seeds, insts):
+        t0 = time.perf_counter()
+        r = solve(g)
+        lat.append(time.perf_counter() - t0)
+        rows.append((s, g, r))
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - ta
+    r1 = os.times()
+    stats = kernel_table([ctx])
+    ctx.profile(False)
+    ctx.close()
+    exact = 0
+    phases = [0.0] * 8
+    leaves = macs = 0
+    for (s, g, r), t in zip(rows, lat):
+        w = want[s][-1]
+        if kind == 0:
+            ok = (r.certified and r.value == w and r.count > 0 and r.count % 2 == 0
+                  and energy_sg(r.config, g["edges"], g["J"]) == w)
+        else:
+            ok = (r.certified and r.value == w and r.count > 0
+                  and independent_weight(r.config, g["edges"]) == w)
+        exact += ok
+        leaves += r.leaves
+        macs += r.macs
+        phases = [a + b for a, b in zip(phases, r.seconds)]
+        print("%s seed %d value=%d count=%d (%d bits) leaves=%d %.3f s %s"
+              % (label, s, r.value, r.count, r.count.bit_length(), r.leaves, t,
+                 "exact" if ok else "MISMATCH"), file=sys.stderr, flush=True)
+    n = len(rows)
+    names = ["total", "build+plan", "search", "contraction", "crt+certification", "configuration"]
+    ls = sorted(lat)
+    return {"dt": dt, "n": n, "exact": exact, "stats": stats,
+            "host_cpu_s": (r1.user - r0.user) + (r1.system - r0.system),
+            "leaves_per_instance": round(leaves / max(n, 1), 1),
+            "macs_per_instance": round(macs / max(n, 1)),
+            "latency_s": {"p50": round(ls[len(ls) // 2], 3), "max": round(ls[-1], 3),
+                          "unsolved": n - exact},
+            "phases_ms": {nm: round(1e3 * phases[i] / max(n, 1), 3) for i, nm in enumerate(names)}}
+
+
+def sg16_leg(B, I, torch, ncpu, args):
+    """The 16 x 16 lattice: 160 distinct instances per call
+    (bbtn_solve_batch), 3 contexts whose threads share the calls, greedy
+    order; results checked against the stored exact degeneracies."""
+    want = golden_sg16()
+    insts = [I.spin_glass_square(16, s) for s in range(N_SEEDS)]
+    T, Bsz, steps, warm = 3, 160, 24, 2
+    host_threads = max(1, ncpu // 2)
+
+    def solve_step(c, i):
+        seeds = [(i * Bsz + j) % N_SEEDS for j in range(Bsz)]
+        rs, _ = c.solve_batch(0, [(insts[s]["n"], insts[s]["edges"], insts[s]["J"], None)
+                                  for s in seeds])
+        return seeds, rs
+
+    def timed(cs, profile):
+        for c in cs:
+            for i in range(warm):
+                solve_step(c, i)
+            if profile:
+                c.profile(True)
+        torch.cuda.synchronize()
+        lock = threading.Lock()
+        nxt = [0]
+        res = [None] * steps
+        lat = [0.0] * steps
+
+        def worker(c):
+            while True:
+                with lock:
+                    i = nxt[0]
+                    nxt[0] += 1
+                if i >= steps:
+                    return
+                ts = time.perf_counter()
+                res[i] = solve_step(c, i)
+                lat[i] = time.perf_counter() - ts
+
+        r0 = os.times()
+        ta = time.perf_counter()
+        th = [threading.Thread(target=worker, args=(c,)) for c in cs]
+        for t in th:
+            t.start()
+        for t in th:
+            t.join()
+        torch.cuda.synchronize()
+        tb = time.perf_counter()
+        r1 = os.times()
+        return res, lat, tb - ta, (r1.user - r0.user) + (r1.system - r0.system)
+
+    def tally(res):
+        ok = n = lv = 0
+        for seeds, rs in res:
+            for s_, r in zip(seeds, rs):
+                n += 1
+                lv += r.leaves
+                ok += (r.value, r.count) == want[s_] and r.certified
+        return ok, n, lv
+
+    opts = B.Options(log2_target=10, residues_per_pass=3, branching=1, batched=1,
+                     host_threads=host_threads, spin_flip=1)
+    ctxs = [B.Context(opts) for _ in range(T)]
+    res, lat, dt, cpu_s = timed(ctxs, True)
+    stats = kernel_table(ctxs)
+    for c in ctxs:
+        c.profile(False)
+        c.close()
+    ok, n, lv = tally(res)
+    cs = sorted(lat)
+    leg = {"value": round(3600.0 * ok / dt, 1), "unit": "instances/hour",
+           "workload": "+-J spin glass 16x16 open lattice, seeds 0-319, zero field, plain BBTN "
+                       "T_target=2^10 (greedy order), spin-flip symmetry, 3 primes per pass; "
+                       "one step = one call solving 160 instances, 3 concurrent contexts",
+           "steps": steps, "warmup": warm, "ms_per_step": round(1e3 * dt / steps, 3),
+           "instances": n, "exact": ok, "leaves_per_instance": round(lv / max(n, 1), 1),
+           "roofline": roofline_of(stats, dt, kernel_traffic),
+           "kernels": kernels_json(stats),
+           "host_cpu_utilisation": round(cpu_s / max(dt * ncpu, 1e-9), 3),
+           "latency_ms": {"per_call_p50": round(1e3 * cs[len(cs) // 2], 3),
+                          "per_call_max": round(1e3 * cs[-1], 3), "unsolved": n - ok}}
+    if not args.no_refined_order:
+        ro = B.Options(log2_target=10, residues_per_pass=3, branching=1, batched=1,
+                       host_threads=host_threads, order_refine=8, spin_flip=1)
+        rctx = [B.Context(ro) for _ in range(T)]
+        rres, _, rdt, rcpu = timed(rctx, False)
+        for c in rctx:
+            c.close()
+        r_ok, r_n, r_lv = tally(rres)
+        leg["refined_order"] = {
+            "value": round(3600.0 * r_ok / rdt, 1), "unit": "instances/hour",
+            "instances": r_n, "exact": r_ok, "leaves_per_instance": round(r_lv / max(r_n, 1), 1),
+            "ms_per_step": round(1e3 * rdt / steps, 3),
+            "host_cpu_utilisation": round(rcpu / max(rdt * ncpu, 1e-9), 3),
+            "note": "order_refine=8: best of the greedy tree and 8 annealed refinements, "
+                    "scored by a probe search"}
+    if not args.no_per_branch:
+        # the same path without batching: one branch at a time (step programs
+        # replayed from a hipGraph), on the first instances
+        pb = B.Context(B.Options(log2_target=10, residues_per_pass=3, branching=1, batched=0,
+                                 spin_flip=1))
+        g = insts[0]
+        pb.solve_spinglass(g["n"], g["edges"], g["J"])
+        n_pb = 3
+        t2 = time.perf_counter()
+        okb = 0
+        for i in range(n_pb):
+            g = insts[i]
+            r = pb.solve_spinglass(g["n"], g["edges"], g["J"])
+            okb += (r.value, r.count) == want[i] and r.certified
+        t3 = time.perf_counter()
+        pb.close()
+        leg["per_branch"] = {"value": round(3600.0 * okb / (t3 - t2), 1),
+                             "unit": "instances/hour", "instances": n_pb, "exact": okb,
+                             "note": "batched=0: branches contracted one at a time"}
+    if not args.no_cpu_baseline:
+        leg["cpu_baseline"] = cpu_baseline_sg16(want)
+    return leg
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=24)
+    ap.add_argument("--steps", type=int, default=20,
+                    help="timed calls of the headline run (one 32x32 instance each; step i "
+                         "solves seed i mod 20)")
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-micro", action="store_true")
     ap.add_argument("--no-per-branch", action="store_true")
+    ap.add_argument("--no-refined-order", action="store_true",
+                    help="skip the 16x16 leg's second run with a refined order")
+    ap.add_argument("--no-ksg", action="store_true", help="skip the 40x40 King's subgraph leg")
+    ap.add_argument("--no-sg16", action="store_true", help="skip the 16x16 leg")
+    ap.add_argument("--ksg-seeds", type=int, default=8,
+                    help="seeds of the 40x40 King's subgraph leg (0 .. n-1)")
     ap.add_argument("--micro-only", action="store_true",
                     help="only the counting-product micro-benchmark and a copy of known size "
                          "(for hardware-counter runs)")
     ap.add_argument("--calibration-copy", action="store_true",
                     help="end with a plain device copy of known size (512 MiB each way), "
                          "the reference that scales hardware byte counters")
-    ap.add_argument("--batched", type=int, default=1)
-    ap.add_argument("--workers", type=int, default=3,
-                    help="concurrent solver contexts (threads, one stream each): one "
-                         "call's host planning overlaps another's contraction")
-    ap.add_argument("--host-threads", type=int, default=0,
-                    help="planning threads per call; 0: all host threads with one context, "
-                         "half of them with several")
-    ap.add_argument("--order-refine", type=int, default=0,
-                    help="contraction order of the main run: 0 = greedy (the workload's "
-                         "plain BBTN); n > 0 = best of greedy and n annealed refinements")
-    ap.add_argument("--no-refined-order", action="store_true",
-                    help="skip the second run of the same workload with a refined order")
     ap.add_argument("--large", type=int, default=0,
-                    help="instead of the throughput run: solve this many seeds each of the "
-                         "+-J 32x32 lattice (T_target=2^26) and the King's subgraph 40x40 MIS "
-                         "(T_target=2^24) with the refined order, by the plain planner and by "
-                         "the learned scorer, and print their times and kernel figures")
-    ap.add_argument("--batch-size", type=int, default=160,
-                    help="instances per call (bbtn_solve_batch when > 1): their branch "
-                         "sub-networks share every device launch")
+                    help="instead of the benchmark: solve this many seeds each of the "
+                         "+-J 32x32 lattice and the King's subgraph 40x40 MIS with the refined "
+                         "order, by the plain planner and by the learned scorer, and print their "
+                         "times and kernel figures")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on exactly one GPU: the solver path is single-GPU "
@@ -246,8 +521,6 @@ def main():
     if args.micro_only:
         ctx = B.Context(B.Options())
         res = tgemm_micro(B, ctx, torch)
-        # a plain device copy of known size (512 MiB read + 512 MiB written):
-        # the reference that scales the hardware byte counters
         x = torch.ones(128 << 20, dtype=torch.int32, device="cuda")
         y = torch.empty_like(x)
         y.copy_(x)
@@ -258,100 +531,18 @@ def main():
     if args.large > 0:
         print(json.dumps(large_configs(B, I, torch, args.large)), flush=True)
         return
-    want = golden_sg16()
-    insts = [I.spin_glass_square(16, s) for s in range(N_SEEDS)]
-    # the contexts share the host: each plans its instances on half the
-    # host threads when several run at once (unless --host-threads is given)
     ncpu = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
-    host_threads = args.host_threads if args.host_threads > 0 else (
-        ncpu if args.workers <= 1 else max(1, ncpu // 2))
-    opts = B.Options(log2_target=10, residues_per_pass=3, branching=1, batched=args.batched,
-                     host_threads=host_threads, order_refine=args.order_refine)
-    T = max(1, args.workers)
-    Bsz = max(1, args.batch_size)
-    ctxs = [B.Context(opts) for _ in range(T)]
-
-    def solve_step(c, i):
-        """Step i: instances i*Bsz .. i*Bsz+Bsz-1 (seeds mod 320), one call."""
-        seeds = [(i * Bsz + j) % N_SEEDS for j in range(Bsz)]
-        if Bsz == 1:
-            g = insts[seeds[0]]
-            return seeds, [c.solve_spinglass(g["n"], g["edges"], g["J"])]
-        rs, _ = c.solve_batch(0, [(insts[s]["n"], insts[s]["edges"], insts[s]["J"], None)
-                                  for s in seeds])
-        return seeds, rs
-
-    def timed(cs, profile):
-        """Warm-up steps on every context (workspace growth, code loading, the
-        order cache), then `steps` calls shared by the contexts' threads."""
-        for c in cs:
-            for i in range(args.warmup):
-                solve_step(c, i)
-            if profile:
-                c.profile(True)
-        torch.cuda.synchronize()
-        lock = threading.Lock()
-        nxt = [0]
-        res = [None] * args.steps
-        lat = [0.0] * args.steps
-
-        def worker(c):
-            while True:
-                with lock:
-                    i = nxt[0]
-                    nxt[0] += 1
-                if i >= args.steps:
-                    return
-                ts = time.perf_counter()
-                res[i] = solve_step(c, i)
-                lat[i] = time.perf_counter() - ts
-
-        r0 = os.times()
-        ta = time.perf_counter()
-        if len(cs) == 1:
-            worker(cs[0])
-        else:
-            th = [threading.Thread(target=worker, args=(c,)) for c in cs]
-            for t in th:
-                t.start()
-            for t in th:
-                t.join()
-        torch.cuda.synchronize()
-        tb = time.perf_counter()
-        r1 = os.times()
-        return res, lat, tb - ta, (r1.user - r0.user) + (r1.system - r0.system)
-
-    results, call_s, dt, host_cpu_s = timed(ctxs, True)
-    exact = 0
-    leaves = 0
-    n_inst = 0
-    phases = [0.0] * 8
-    for i, (seeds, rs) in enumerate(results):
-        for s, r in zip(seeds, rs):
-            n_inst += 1
-            leaves += r.leaves
-            phases = [a + b for a, b in zip(phases, r.seconds)]
-            ok = (r.value, r.count) == want[s] and r.certified
-            exact += ok
-            print("step %d seed %d E0=%d deg=%d leaves=%d %s" % (i, s, r.value, r.count, r.leaves,
-                  "exact" if ok else "MISMATCH"), file=sys.stderr, flush=True)
-    stats = {}
-    for name in ("tgemm", "persist", "gather"):
-        agg = {"launches": 0, "seconds": 0.0, "ops": 0.0, "bytes": 0.0}
-        for c in ctxs:
-            ks = c.kernel_stats(name)
-            for key in agg:
-                agg[key] += ks[key]
-        stats[name] = agg
-    for c in ctxs:
-        c.profile(False)
-    ctx = ctxs[0]
-    dom = max(stats, key=lambda n: stats[n]["seconds"])
-    st = stats[dom]
-    achieved = st["ops"] / max(st["seconds"], 1e-12)
+    # ---- headline: +-J 32x32
+    sg32 = golden_values("sg32_values.txt")
+    head_opts = B.Options(log2_target=26, residues_per_pass=3, branching=1, batched=1,
+                          order_refine=8, time_limit_s=600, spin_flip=1)
+    seeds = [i % 20 for i in range(args.steps)]
+    warm = [20 + i for i in range(args.warmup)]
+    h = single_instance_run(B, I, torch, 0, 32, head_opts, seeds, warm, sg32, "sg32x32")
+    dt = h["dt"]
     line = {
         "metric": "exact (E0,degeneracy) instances/hour",
-        "value": round(3600.0 * exact / dt, 1),
+        "value": round(3600.0 * h["exact"] / dt, 1),
         "unit": "instances/hour",
         "n_gpus": 1,
         "steps": args.steps,
@@ -362,91 +553,53 @@ def main():
         "vs_baseline": None,
         "dtype": "int32",
         "data": "synthetic",
-        "config": {"workload": "+-J spin glass 16x16 open lattice, seeds 0-319, zero field, "
-                               "plain BBTN T_target=2^10, 3 primes per pass; one step = one "
-                               "call solving %d instance(s), %d concurrent contexts" % (Bsz, T),
-                   "instances": n_inst, "exact": exact,
-                   "leaves_per_instance": round(leaves / max(n_inst, 1), 1),
-                   "batched": args.batched, "batch_size": Bsz, "workers": T,
-                   "host_threads_per_context": host_threads,
-                   "contraction_order": "greedy" if args.order_refine == 0 else
-                                        "refined (%d candidates)" % args.order_refine},
-        "roofline": {"bound": "alu", "kernel": dom,
-                     "achieved": round(achieved / 1e12, 4), "peak": round(VALU_PEAK_OPS / 1e12, 2),
-                     "unit": "TOP/s", "frac": round(achieved / VALU_PEAK_OPS, 5),
-                     "traffic": persist_traffic() if dom == "persist" else None,
-                     "launches": st["launches"],
-                     "launch_unit": "one executor pass (its shared-subtree and branch dispatches)"
-                                    if dom == "persist" else "one kernel dispatch",
-                     "avg_launch_ms": round(1e3 * st["seconds"] / max(st["launches"], 1), 4),
-                     "kernel_busy_share": round(st["seconds"] / dt, 4)},
-        "kernels": {n: {"launches": s["launches"], "seconds": round(s["seconds"], 5),
-                        "Gop_s": round(s["ops"] / max(s["seconds"], 1e-12) / 1e9, 2),
-                        "GB_s": round(s["bytes"] / max(s["seconds"], 1e-12) / 1e9, 2)}
-                    for n, s in stats.items()},
+        "config": {"workload": "+-J spin glass 32x32 open lattice, seeds 0-19 (step i solves "
+                               "seed i mod 20), zero field; BBTN T_target=2^26, refined "
+                               "contraction order, plain planner, spin-flip symmetry (one "
+                               "spin fixed, count doubled), 3 primes per pass plus a fused "
+                               "certification prime; one step = one call solving one "
+                               "instance",
+                   "instances": h["n"], "exact": h["exact"],
+                   "leaves_per_instance": h["leaves_per_instance"],
+                   "macs_per_instance": h["macs_per_instance"],
+                   "log2_target": 26, "residues_per_pass": 3, "contraction_order":
+                   "refined (8 candidates, chosen in the warm-up)", "branching": "plain planner",
+                   "exactness": "certified count, E0 equal to the matching oracle's stored "
+                                "value, even degeneracy, configuration reaching E0"},
+        "roofline": roofline_of(h["stats"], dt, kernel_traffic),
+        "kernels": kernels_json(h["stats"]),
+        "host_cpu": {"seconds": round(h["host_cpu_s"], 3), "cpus": ncpu,
+                     "utilisation": round(h["host_cpu_s"] / max(dt * ncpu, 1e-9), 3)},
+        "latency_s": h["latency_s"],
+        "phases_ms": h["phases_ms"],
     }
-    # host CPU time of the process over the timed region, as a share of
-    # the wall time of all the host threads it may run on
-    ncpu = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
-    line["host_cpu"] = {"seconds": round(host_cpu_s, 3), "cpus": ncpu,
-                        "utilisation": round(host_cpu_s / max(dt * ncpu, 1e-9), 3)}
-    names = ["total", "build+plan", "search", "contraction", "crt+certification", "configuration"]
-    # latency of one call (all its instances), over the timed steps; an
-    # instance counts as unsolved when its result is not exact and certified
-    cs = sorted(call_s)
-    line["latency_ms"] = {"per_call_p50": round(1e3 * cs[len(cs) // 2], 3),
-                          "per_call_max": round(1e3 * cs[-1], 3),
-                          "unsolved": n_inst - exact}
-    line["phases_ms"] = {nm: round(1e3 * phases[i] / max(n_inst, 1), 3)
-                         for i, nm in enumerate(names)}
-    if not args.no_refined_order and args.order_refine == 0:
-        # the same workload and settings with the contraction order refined
-        # by annealing (8 candidates, chosen once for the lattice during the
-        # warm-up): fewer and cheaper leaves
-        ro = B.Options(log2_target=10, residues_per_pass=3, branching=1, batched=args.batched,
-                       host_threads=host_threads, order_refine=8)
-        rctx = [B.Context(ro) for _ in range(T)]
-        rres, rlat, rdt, rcpu = timed(rctx, False)
-        for c in rctx:
-            c.close()
-        r_ok = r_n = r_leaves = 0
-        for seeds, rs in rres:
-            for s_, r in zip(seeds, rs):
-                r_n += 1
-                r_leaves += r.leaves
-                r_ok += (r.value, r.count) == want[s_] and r.certified
-        line["refined_order"] = {
-            "value": round(3600.0 * r_ok / rdt, 1), "unit": "instances/hour",
-            "instances": r_n, "exact": r_ok,
-            "leaves_per_instance": round(r_leaves / max(r_n, 1), 1),
-            "ms_per_step": round(1e3 * rdt / args.steps, 3),
-            "host_cpu_utilisation": round(rcpu / max(rdt * ncpu, 1e-9), 3),
-            "note": "order_refine=8: best of the greedy tree and 8 annealed refinements, "
-                    "scored by a probe search"}
-    if not args.no_per_branch:
-        # the same path without batching: one branch at a time (step programs
-        # replayed from a hipGraph), on the first instances
-        pb = B.Context(B.Options(log2_target=10, residues_per_pass=3, branching=1, batched=0))
-        g = insts[0]
-        pb.solve_spinglass(g["n"], g["edges"], g["J"])
-        n_pb = 3
-        t2 = time.perf_counter()
-        ok = 0
-        for i in range(n_pb):
-            g = insts[i]
-            r = pb.solve_spinglass(g["n"], g["edges"], g["J"])
-            ok += (r.value, r.count) == want[i] and r.certified
-        t3 = time.perf_counter()
-        pb.close()
-        line["per_branch"] = {"value": round(3600.0 * ok / (t3 - t2), 1), "unit": "instances/hour",
-                              "instances": n_pb, "exact": ok,
-                              "note": "batched=0: branches contracted one at a time"}
+    if not args.no_ksg and args.ksg_seeds > 0:
+        ksg = golden_values("ksg40_values.txt")
+        ko = B.Options(log2_target=28, residues_per_pass=3, branching=1, batched=1,
+                       order_refine=8, time_limit_s=600)
+        kr = single_instance_run(B, I, torch, 1, 40, ko, list(range(args.ksg_seeds)), [100],
+                                 ksg, "ksg40x40")
+        line["ksg40x40"] = {
+            "value": round(3600.0 * kr["exact"] / kr["dt"], 1), "unit": "instances/hour",
+            "workload": "unweighted MIS on King's subgraph 40x40, fill 0.8, seeds 0-%d; BBTN "
+                        "T_target=2^28, refined order chosen per instance (every seed is "
+                        "another graph), 3 primes per pass plus a fused certification prime; "
+                        "one instance per call" % (args.ksg_seeds - 1),
+            "instances": kr["n"], "exact": kr["exact"],
+            "seconds": round(kr["dt"], 3),
+            "leaves_per_instance": kr["leaves_per_instance"],
+            "macs_per_instance": kr["macs_per_instance"],
+            "roofline": roofline_of(kr["stats"], kr["dt"], lambda k: None),
+            "kernels": kernels_json(kr["stats"]),
+            "latency_s": kr["latency_s"], "phases_ms": kr["phases_ms"]}
+    if not args.no_sg16:
+        line["sg16x16"] = sg16_leg(B, I, torch, ncpu, args)
     if not args.no_micro:
+        ctx = B.Context(B.Options())
         line["tgemm_micro"] = tgemm_micro(B, ctx, torch)
+        ctx.close()
     if not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline(want)
-    for c in ctxs:
-        c.close()
+        line["cpu_baseline"] = cpu_baseline_sg32()
     if args.calibration_copy:
         x = torch.ones(128 << 20, dtype=torch.int32, device="cuda")
         y = torch.empty_like(x)

@@ -105,6 +105,19 @@ typedef struct {
                                 branch chunks are sized to it, and a solve
                                 that cannot fit fails with BBTN_E_OOM.
                                 0: no cap beyond the free memory.             */
+  int32_t spin_flip;         /* 1: a zero-field spin glass is solved with one
+                                spin fixed to +1 and the count doubled (the
+                                spin-flip symmetry H(sigma) = H(-sigma) maps
+                                the ground states with that spin at +1 one to
+                                one onto those with it at -1): the same ground
+                                energy and degeneracy with half the leaves
+                                when the fixed spin is one the search would
+                                branch on (the spin of largest overflow
+                                participation, else of largest share of the
+                                contraction's multiply-accumulates); the
+                                configuration has that spin at +1.  Ignored
+                                for instances with a nonzero field and for
+                                MWIS.  0: off.                                */
 } bbtn_options;
 
 /* Result of a solve.  `count` and `config` are caller-owned. */
@@ -174,6 +187,19 @@ bbtn_status bbtn_solve_mwis(bbtn_ctx* ctx, int32_t n, int32_t m,
 bbtn_status bbtn_tgemm(bbtn_ctx* ctx, int32_t k, const uint32_t* primes,
                        int64_t batch, int64_t M, int64_t N, int64_t K,
                        const void* A, const void* B, void* C, void* stream);
+
+/*
+ * Values-only (max-plus) product of Eq. 2:  C[b,m,n] = max_q A[b,m,q] +
+ * B[b,q,n], on int32 value planes laid out as in bbtn_tgemm (no residue
+ * planes).  Values <= BBTN_NEG_CUT are the tropical zero and come out as
+ * BBTN_NEG.  max_abs: the caller's bound on |v| of every other value of A
+ * and B (< 2^28); below 2^12 the product runs with two values per 32-bit
+ * word (packed 16-bit adds and maxima), otherwise in 32 bits.  A value
+ * outside the stated bound gives undefined results (never a fault).
+ */
+bbtn_status bbtn_tgemm_values(bbtn_ctx* ctx, int64_t batch, int64_t M, int64_t N, int64_t K,
+                              const int32_t* A, const int32_t* B, int32_t* C, int32_t max_abs,
+                              void* stream);
 
 /*
  * bbtn_tgemm for callers that cannot allocate device memory (code under

@@ -40,7 +40,7 @@ class _Options(C.Structure):
                 ("scorer_weights", C.c_char_p), ("autotune_cache", C.c_char_p),
                 ("time_limit_s", C.c_double), ("stream", C.c_void_p),
                 ("host_threads", C.c_int32), ("order_refine", C.c_int32),
-                ("device_mem_cap", C.c_uint64)]
+                ("device_mem_cap", C.c_uint64), ("spin_flip", C.c_int32)]
 
 
 class _Result(C.Structure):
@@ -67,7 +67,7 @@ _RESULT_DTYPE = np.dtype({
 _lib = None
 
 EXPORTS = ["bbtn_default_options", "bbtn_create", "bbtn_destroy", "bbtn_last_error",
-           "bbtn_solve_spinglass", "bbtn_solve_mwis", "bbtn_tgemm", "bbtn_tgemm_noalloc", "bbtn_gather",
+           "bbtn_solve_spinglass", "bbtn_solve_mwis", "bbtn_tgemm", "bbtn_tgemm_values", "bbtn_tgemm_noalloc", "bbtn_gather",
            "bbtn_reduce", "bbtn_bound", "bbtn_last_macs", "bbtn_profile",
            "bbtn_get_kernel_stats", "bbtn_mlp_forward", "bbtn_mlp_backward", "bbtn_mlp_adam",
            "bbtn_scorer_load", "bbtn_scorer_collect", "bbtn_scorer_train", "bbtn_plan_leaves",
@@ -116,6 +116,8 @@ def load(path: str = LIB_PATH):
     lib.bbtn_solve_batch.restype = I32
     lib.bbtn_tgemm.argtypes = [P, I32, P, I64, I64, I64, I64, P, P, P, P]
     lib.bbtn_tgemm.restype = I32
+    lib.bbtn_tgemm_values.argtypes = [P, I64, I64, I64, I64, P, P, P, I32, P]
+    lib.bbtn_tgemm_values.restype = I32
     lib.bbtn_tgemm_noalloc.argtypes = [P, I32, P, I64, I64, I64, I64, P, P, P, P]
     lib.bbtn_tgemm_noalloc.restype = I32
     lib.bbtn_gather.argtypes = [P, I32, I32, I32, P, I64, I64, P, P, I64, P, P]
@@ -172,13 +174,14 @@ class Options:
     host_threads: int = 0
     order_refine: int = 0
     device_mem_cap: int = 0
+    spin_flip: int = 0
 
     def _c(self):
         o = _Options()
         load().bbtn_default_options(C.byref(o))
         for f in ("device", "residues_per_pass", "max_primes", "log2_target", "branching",
                   "batched", "region_max", "local_search", "graphs", "time_limit_s",
-                  "host_threads", "order_refine", "device_mem_cap"):
+                  "host_threads", "order_refine", "device_mem_cap", "spin_flip"):
             setattr(o, f, getattr(self, f))
         o.scorer_weights = self.scorer_weights.encode() if self.scorer_weights else None
         o.autotune_cache = self.autotune_cache.encode() if self.autotune_cache else None
@@ -379,6 +382,12 @@ class Context:
         pr = (C.c_uint32 * k)(*[int(p) for p in primes[:k]])
         self._check(self.lib.bbtn_tgemm(self.h, k, pr, batch, M, N, K, _dptr(A), _dptr(B),
                                         _dptr(Cout), _stream(stream)))
+
+    def tgemm_values(self, batch, M, N, K, A, B, Cout, max_abs, stream=None):
+        """bbtn_tgemm_values: max-plus product of int32 value planes; max_abs
+        bounds |v| of the finite values (below 2^12: packed 16-bit path)."""
+        self._check(self.lib.bbtn_tgemm_values(self.h, batch, M, N, K, _dptr(A), _dptr(B),
+                                               _dptr(Cout), int(max_abs), _stream(stream)))
 
     def tgemm_noalloc(self, k, primes, batch, M, N, K, A, B, Cout, stream=None):
         """bbtn_tgemm_noalloc: bbtn_tgemm with no device allocation (split-K

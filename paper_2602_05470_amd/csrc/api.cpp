@@ -83,6 +83,7 @@ void bbtn_default_options(bbtn_options* o) {
   o->host_threads = 0;
   o->order_refine = 0;
   o->device_mem_cap = 0;
+  o->spin_flip = 0;
 }
 
 bbtn_status bbtn_create(const bbtn_options* opt, bbtn_ctx** out) {
@@ -268,6 +269,38 @@ bbtn_status bbtn_tgemm(bbtn_ctx* ctx, int32_t k, const uint32_t* primes, int64_t
                  tv.cfg, tv.splits, part, st);
     ctx->prof.end(ph, st, K_TGEMM, (double)batch * M * N * K * (2 + 2 * k),
                   (double)(1 + k) * 4 * (double)batch * (double)(M * K + K * N + M * N));
+  });
+}
+
+bbtn_status bbtn_tgemm_values(bbtn_ctx* ctx, int64_t batch, int64_t M, int64_t N, int64_t K,
+                              const int32_t* A, const int32_t* B, int32_t* C, int32_t max_abs,
+                              void* stream) {
+  if (!ctx) return BBTN_E_INVALID_ARG;
+  return guard(ctx, [&] {
+    BBTN_REQUIRE(batch >= 1 && M >= 1 && N >= 1 && K >= 1, "empty product");
+    BBTN_REQUIRE(A && B && C, "NULL operand");
+    BBTN_REQUIRE(max_abs >= 0 && max_abs < (1 << 28), "max_abs out of range");
+    BBTN_REQUIRE(batch * M * K < (1ll << 40) && batch * K * N < (1ll << 40) &&
+                     batch * M * N < (1ll << 40), "operand too large");
+    BBTN_HIP(hipSetDevice(ctx->opt.device));
+    const TuneVal tv = cached_or_heuristic_tiles(ctx, 1, batch, M, N, K);
+    DevTensor part{};
+    if (tv.splits > 1) {
+      const int64_t ent = (int64_t)tv.splits * batch * M * N;
+      ctx->partial.ensure((size_t)ent * 4);
+      part = DevTensor{ctx->partial.as<uint32_t>(), ent};
+    }
+    GemmShape sh{batch, M, N, K, M * K, K * N, M * N};
+    const DevTensor dA{(uint32_t*)A, batch * M * K}, dB{(uint32_t*)B, batch * K * N},
+        dC{(uint32_t*)C, batch * M * N};
+    hipStream_t st = pick_stream(ctx, stream);
+    const int ph = ctx->prof.begin(st);
+    if (max_abs < kValues16Bound)
+      launch_tgemm_values16(sh, dA, dB, dC, tv.splits, part, st);
+    else
+      launch_tgemm(0, make_moduli(0, nullptr), sh, dA, dB, dC, tv.cfg, tv.splits, part, st);
+    ctx->prof.end(ph, st, K_TGEMM, 2.0 * batch * M * N * K,
+                  4.0 * (double)batch * (double)(M * K + K * N + M * N));
   });
 }
 

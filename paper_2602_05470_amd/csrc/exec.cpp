@@ -216,6 +216,10 @@ void run_group(bbtn_ctx* ctx, const Network& net, const GroupPlan& g, const Base
     if (tvs[si].splits > 1) part_entries = std::max<int64_t>(part_entries, (int64_t)tvs[si].splits * (Ls << s.rb) * M * N);
   }
   if (part_entries > 0) ctx->partial.ensure((size_t)W * part_entries * 4);
+  // values pass: every partial sum of the network is bounded by the sum of
+  // its |couplings| and |fields| (or weights), so small networks take the
+  // packed 16-bit product for large steps
+  const bool vals16 = k == 0 && net.abs_sum < kValues16Bound;
   // shared steps first (once), then the branch steps
   std::vector<size_t> order;
   for (size_t si = 0; si < g.steps.size(); ++si)
@@ -263,7 +267,10 @@ void run_group(bbtn_ctx* ctx, const Network& net, const GroupPlan& g, const Base
       DevTensor part{};
       if (tv.splits > 1) part = DevTensor{ctx->partial.as<uint32_t>(), (int64_t)tv.splits * batch * M * N};
       const int ph = ctx->prof.begin(st);
-      launch_tgemm(k, mod, sh, opnd[0], opnd[1], buf(s.out), tv.cfg, tv.splits, part, st);
+      if (vals16 && M >= 128 && N >= 128)
+        launch_tgemm_values16(sh, opnd[0], opnd[1], buf(s.out), tv.splits, part, st);
+      else
+        launch_tgemm(k, mod, sh, opnd[0], opnd[1], buf(s.out), tv.cfg, tv.splits, part, st);
       ctx->prof.end(ph, st, K_TGEMM, (double)Ls * s.macs() * (2 + 2 * k),
                     (double)W * 4 * (double)batch * (double)(M * K + K * N + M * N));
     }

@@ -364,6 +364,219 @@ tgemm_kernel_strided(const GemmArgs a) {
   }
 }
 
+// ------------------------------------------------------------ thin products
+// Products with a short summed range and a narrow side (K <= 32 and M or N
+// below 32, power-of-two sizes) move far more bytes than they compute, and
+// the LDS tiles above would leave most of their lanes idle.  Here one thread
+// computes one output, outputs in memory order (n fastest), with no LDS:
+// lanes of a wave that share a row of A read it in one request and lanes
+// with consecutive n read consecutive words of B and write consecutive
+// words of C.  Values first (max over q), then the counts of the q that
+// reach the maximum, as in the tiled kernel.
+template <int KR>
+__global__ void __launch_bounds__(256) tgemm_thin_kernel(const GemmArgs a, int lm, int ln, int lk) {
+  constexpr int KP = KR > 0 ? KR : 1;
+  const int64_t total = a.batch << (lm + ln);
+  const int K = 1 << lk;
+  for (int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x; t < total;
+       t += (int64_t)gridDim.x * 256) {
+    const int64_t n = t & ((1ll << ln) - 1);
+    const int64_t m = (t >> ln) & ((1ll << lm) - 1);
+    const int64_t b = t >> (lm + ln);
+    const uint32_t* Ar = a.A + b * a.sAb + (m << lk);
+    const uint32_t* Bc = a.B + b * a.sBb + n;
+    int32_t V = INT32_MIN;
+#pragma unroll 4
+    for (int q = 0; q < K; ++q) V = max(V, (int32_t)Ar[q] + (int32_t)Bc[(int64_t)q << ln]);
+    const bool fin = V > NEG_CUT;
+    const int64_t off = b * a.sCb + (m << ln) + n;
+    a.C[off] = (uint32_t)(fin ? V : NEG);
+    if constexpr (KR > 0) {
+      uint64_t acc[KP];
+#pragma unroll
+      for (int p = 0; p < KP; ++p) acc[p] = 0;
+      if (fin) {
+        for (int q = 0; q < K; ++q) {
+          const int64_t ia = q, ib = (int64_t)q << ln;
+          if ((int32_t)Ar[ia] + (int32_t)Bc[ib] != V) continue;
+#pragma unroll
+          for (int p = 0; p < KR; ++p) {
+            acc[p] += (uint64_t)Ar[(p + 1) * a.pA + ia] * Bc[(p + 1) * a.pB + ib];
+            acc[p] = fold64(acc[p], a.mod.c[p]);
+          }
+        }
+      }
+#pragma unroll
+      for (int p = 0; p < KR; ++p)
+        a.C[(p + 1) * a.pC + off] = fin ? mod_final(acc[p], a.mod.p[p], a.mod.c[p]) : 0u;
+    }
+  }
+}
+
+static int exact_log2(int64_t x) {
+  if (x <= 0 || (x & (x - 1))) return -1;
+  int l = 0;
+  while ((1ll << l) < x) ++l;
+  return l;
+}
+
+// The thin kernel applies: unsplit, power-of-two sizes, K <= 32 and M or N
+// below 32.
+static bool thin_shape(const GemmShape& s, int splits) {
+  const int lm = exact_log2(s.M), ln = exact_log2(s.N), lk = exact_log2(s.K);
+  return splits <= 1 && lm >= 0 && ln >= 0 && lk >= 0 && lk <= 5 && (lm < 5 || ln < 5);
+}
+
+static void launch_thin(int k, const GemmArgs& a, hipStream_t st) {
+  const int lm = exact_log2(a.M), ln = exact_log2(a.N), lk = exact_log2(a.K);
+  const int64_t total = a.batch << (lm + ln);
+  const int64_t blocks = std::min<int64_t>((total + 255) / 256, 256 * 64);
+  dim3 grid((unsigned)blocks), block(256);
+  switch (k) {
+    case 0: hipLaunchKernelGGL(tgemm_thin_kernel<0>, grid, block, 0, st, a, lm, ln, lk); break;
+    case 1: hipLaunchKernelGGL(tgemm_thin_kernel<1>, grid, block, 0, st, a, lm, ln, lk); break;
+    case 2: hipLaunchKernelGGL(tgemm_thin_kernel<2>, grid, block, 0, st, a, lm, ln, lk); break;
+    case 3: hipLaunchKernelGGL(tgemm_thin_kernel<3>, grid, block, 0, st, a, lm, ln, lk); break;
+    case 4: hipLaunchKernelGGL(tgemm_thin_kernel<4>, grid, block, 0, st, a, lm, ln, lk); break;
+    default: throw Error(BBTN_E_INVALID_ARG, "k must be in [0, 4]");
+  }
+  BBTN_LAUNCHED("tgemm (thin, grid " + std::to_string(total) + ")");
+}
+
+// ------------------------------------------------ values in packed 16 bits
+// Max-plus product (values only) with two values per 32-bit word: the
+// operands' finite values satisfy |v| < 2^12 (the caller's guarantee: the
+// sum of the network's |couplings| and |fields|, or of its weights, bounds
+// every partial sum), so in 16 bits a finite sum lies in (-2^13, 2^13), a
+// sum with a stored zero (-2^14 in 16 bits) lies below -2^13 + 1 and two
+// stored zeros give -2^15 exactly: no sum wraps.  Each thread keeps RM x RN
+// outputs as RM x RN/2 pairs of adjacent columns; one packed add and one
+// packed max (v_pk_add_u16, v_pk_max_i16) advance two outputs by one q.
+// A is staged with its value in both halves, B as pairs of adjacent columns.
+typedef short s16x2 __attribute__((ext_vector_type(2)));
+constexpr int32_t NEG16 = -(1 << 14);
+constexpr int32_t NEG_CUT16 = -(1 << 13);
+
+__device__ __forceinline__ uint32_t to16(int32_t v) {
+  return (uint32_t)(uint16_t)(int16_t)(v > NEG_CUT ? v : NEG16);
+}
+
+template <int TM, int TN, int RM, int RN, int TK>
+__device__ __forceinline__ void tgemm_v16_tile(const GemmArgs& a, int64_t w) {
+  constexpr int TX = TN / RN, TY = TM / RM, NT = TX * TY;
+  constexpr int RP = RN / 2;          // packed column pairs per thread
+  constexpr int TMP = TM + 4;         // padded rows of the transposed A tile
+  __shared__ __attribute__((aligned(16))) uint32_t As[TK][TMP];
+  __shared__ __attribute__((aligned(16))) uint32_t Bs[TK][TN / 2];
+  int64_t t = xcd_remap(w, a.total);
+  const int64_t tn_i = t % a.tiles_n;
+  t /= a.tiles_n;
+  const int64_t tm_i = t % a.tiles_m;
+  t /= a.tiles_m;
+  const int64_t sp = t % a.splits;
+  const int64_t b = t / a.splits;
+  const int64_t m0 = tm_i * TM, n0 = tn_i * TN;
+  const int64_t kbeg = sp * a.kchunk;
+  const int64_t kend = min(a.K, kbeg + a.kchunk);
+  const int tid = threadIdx.x;
+  const int tx = tid % TX, ty = tid / TX;
+  const uint32_t* Ab = a.A + b * a.sAb;
+  const uint32_t* Bb = a.B + b * a.sBb;
+  s16x2 V[RM][RP];
+#pragma unroll
+  for (int r = 0; r < RM; ++r)
+#pragma unroll
+    for (int c = 0; c < RP; ++c) V[r][c] = s16x2{-32768, -32768};
+  for (int64_t k0 = kbeg; k0 < kend; k0 += TK) {
+    if (a.vec_a) {
+      constexpr int KV = TK / 4;
+#pragma unroll 1
+      for (int idx = tid; idx < TM * KV; idx += NT) {
+        const int i = idx / KV, j = (idx % KV) * 4;
+        const int64_t m = m0 + i, q = k0 + j;
+        uint4 v = make_uint4((uint32_t)NEG, (uint32_t)NEG, (uint32_t)NEG, (uint32_t)NEG);
+        if (m < a.M && q < kend) v = *(const uint4*)(Ab + m * a.K + q);
+        As[j][i] = to16((int32_t)v.x) * 0x10001u;
+        As[j + 1][i] = to16((int32_t)v.y) * 0x10001u;
+        As[j + 2][i] = to16((int32_t)v.z) * 0x10001u;
+        As[j + 3][i] = to16((int32_t)v.w) * 0x10001u;
+      }
+    } else {
+#pragma unroll 1
+      for (int idx = tid; idx < TM * TK; idx += NT) {
+        const int i = idx / TK, j = idx % TK;
+        const int64_t m = m0 + i, q = k0 + j;
+        const int32_t v = (m < a.M && q < kend) ? (int32_t)Ab[m * a.K + q] : NEG;
+        As[j][i] = to16(v) * 0x10001u;
+      }
+    }
+    if (a.vec_b) {
+      constexpr int NV = TN / 4;
+#pragma unroll 1
+      for (int idx = tid; idx < TK * NV; idx += NT) {
+        const int j = idx / NV, i = (idx % NV) * 4;
+        const int64_t n = n0 + i, q = k0 + j;
+        uint4 v = make_uint4((uint32_t)NEG, (uint32_t)NEG, (uint32_t)NEG, (uint32_t)NEG);
+        if (n < a.N && q < kend) v = *(const uint4*)(Bb + q * a.N + n);
+        *(uint2*)&Bs[j][i / 2] = make_uint2(to16((int32_t)v.x) | to16((int32_t)v.y) << 16,
+                                            to16((int32_t)v.z) | to16((int32_t)v.w) << 16);
+      }
+    } else {
+#pragma unroll 1
+      for (int idx = tid; idx < TK * (TN / 2); idx += NT) {
+        const int j = idx / (TN / 2), i = (idx % (TN / 2)) * 2;
+        const int64_t n = n0 + i, q = k0 + j;
+        const bool in = q < kend;
+        const int32_t v0 = (in && n < a.N) ? (int32_t)Bb[q * a.N + n] : NEG;
+        const int32_t v1 = (in && n + 1 < a.N) ? (int32_t)Bb[q * a.N + n + 1] : NEG;
+        Bs[j][i / 2] = to16(v0) | to16(v1) << 16;
+      }
+    }
+    __syncthreads();
+#pragma unroll 4
+    for (int kk = 0; kk < TK; ++kk) {
+      s16x2 av[RM], bv[RP];
+#pragma unroll
+      for (int r = 0; r < RM; ++r) av[r] = __builtin_bit_cast(s16x2, As[kk][ty * RM + r]);
+#pragma unroll
+      for (int c = 0; c < RP; ++c) bv[c] = __builtin_bit_cast(s16x2, Bs[kk][tx * RP + c]);
+#pragma unroll
+      for (int r = 0; r < RM; ++r)
+#pragma unroll
+        for (int c = 0; c < RP; ++c) V[r][c] = __builtin_elementwise_max(V[r][c], av[r] + bv[c]);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int r = 0; r < RM; ++r) {
+    const int64_t m = m0 + ty * RM + r;
+    if (m >= a.M) continue;
+#pragma unroll
+    for (int c = 0; c < RP; ++c) {
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int64_t n = n0 + tx * RN + 2 * c + h;
+        if (n < a.N) {
+          const int32_t v = V[r][c][h];
+          a.C[sp * a.sCsplit + b * a.sCb + m * a.N + n] = (uint32_t)(v > NEG_CUT16 ? v : NEG);
+        }
+      }
+    }
+  }
+}
+
+template <int TM, int TN, int RM, int RN, int TK>
+__global__ void __launch_bounds__((TM / RM) * (TN / RN)) tgemm_v16_kernel(const GemmArgs a) {
+  for (int64_t w = blockIdx.x; w < a.total; w += gridDim.x) {
+    tgemm_v16_tile<TM, TN, RM, RN, TK>(a, w);
+    __syncthreads();
+  }
+}
+
+// Tile of the packed kernel: 128 x 128 outputs, 8 x 8 per thread, 32-deep
+// slices.
+constexpr int V16_TM = 128, V16_TN = 128, V16_RM = 8, V16_RN = 8, V16_TK = 32;
+
 template <int KR>
 static void launch_cfg(int cfg, dim3 grid, const GemmArgs& a, hipStream_t st) {
   switch (cfg) {
@@ -439,7 +652,8 @@ void launch_tgemm(int k, const Moduli& mod, const GemmShape& s, DevTensor A,
   if (splits <= 1 || s.K <= tk) {
     a.C = C.ptr; a.pC = C.pstride; a.sCb = s.sCb; a.sCsplit = 0;
     a.splits = 1; a.kchunk = s.K;
-    launch_core(k, a, cfg, st);
+    if (thin_shape(s, 1)) launch_thin(k, a, st);
+    else launch_core(k, a, cfg, st);
     return;
   }
   int64_t kchunk = (s.K + splits - 1) / splits;
@@ -454,6 +668,46 @@ void launch_tgemm(int k, const Moduli& mod, const GemmShape& s, DevTensor A,
   launch_core(k, a, cfg, st);
   BBTN_REQUIRE(s.sCb == s.M * s.N, "split-K output must be contiguous");
   launch_reduce(k, mod, outer, nsp, outer, 1, partial, C, st);
+}
+
+void launch_tgemm_values16(const GemmShape& s, DevTensor A, DevTensor B, DevTensor C,
+                           int splits, DevTensor partial, hipStream_t st) {
+  BBTN_REQUIRE(s.M >= 1 && s.N >= 1 && s.K >= 1 && s.batch >= 1, "empty tgemm");
+  GemmArgs a{};
+  a.A = A.ptr; a.B = B.ptr;
+  a.pA = A.pstride; a.pB = B.pstride;
+  a.M = s.M; a.N = s.N; a.K = s.K; a.batch = s.batch;
+  a.sAb = s.sAb; a.sBb = s.sBb;
+  a.mod = make_moduli(0, nullptr);
+  constexpr int tk = V16_TK;
+  int64_t nsp = 1, kchunk = s.K;
+  if (splits > 1 && s.K > tk) {
+    kchunk = (s.K + splits - 1) / splits;
+    kchunk = (kchunk + tk - 1) / tk * tk;
+    nsp = (s.K + kchunk - 1) / kchunk;
+  }
+  const int64_t outer = s.batch * s.M * s.N;
+  if (nsp > 1) {
+    BBTN_REQUIRE(partial.ptr != nullptr && partial.pstride >= nsp * outer,
+                 "split-K partial buffer too small");
+    BBTN_REQUIRE(s.sCb == s.M * s.N, "split-K output must be contiguous");
+    a.C = partial.ptr; a.pC = partial.pstride; a.sCb = s.M * s.N; a.sCsplit = outer;
+  } else {
+    a.C = C.ptr; a.pC = C.pstride; a.sCb = s.sCb; a.sCsplit = 0;
+  }
+  a.splits = nsp; a.kchunk = kchunk;
+  a.tiles_m = (a.M + V16_TM - 1) / V16_TM;
+  a.tiles_n = (a.N + V16_TN - 1) / V16_TN;
+  a.total = a.tiles_m * a.tiles_n * a.splits * a.batch;
+  auto al16 = [](const void* p) { return ((uintptr_t)p & 15u) == 0; };
+  a.vec_a = a.K % 4 == 0 && a.kchunk % 4 == 0 && al16(a.A) && (a.batch == 1 || a.sAb % 4 == 0);
+  a.vec_b = a.N % 4 == 0 && al16(a.B) && (a.batch == 1 || a.sBb % 4 == 0);
+  const int64_t cap = 1ll << 20;
+  dim3 grid((unsigned)(a.total <= cap ? a.total : cap));
+  hipLaunchKernelGGL((tgemm_v16_kernel<V16_TM, V16_TN, V16_RM, V16_RN, V16_TK>), grid,
+                     dim3((V16_TM / V16_RM) * (V16_TN / V16_RN)), 0, st, a);
+  BBTN_LAUNCHED("tgemm (packed 16-bit values, grid " + std::to_string(a.total) + ")");
+  if (nsp > 1) launch_reduce(0, a.mod, outer, nsp, outer, 1, partial, C, st);
 }
 
 void launch_tgemm_values(const GemmShape& s, const int32_t* A, const int32_t* B,

@@ -27,6 +27,14 @@ void launch_tgemm(int k, const Moduli& mod, const GemmShape& s, DevTensor A,
                   DevTensor B, DevTensor C, int cfg, int splits,
                   DevTensor partial, hipStream_t st);
 
+// Values-only product (k = 0) with two values per 32-bit word, for operands
+// whose finite values all satisfy |v| < 2^12 (the caller guarantees it):
+// half the VALU instructions per multiply-accumulate.  Same layouts, split-K
+// and partial buffer as launch_tgemm with k = 0.
+void launch_tgemm_values16(const GemmShape& s, DevTensor A, DevTensor B, DevTensor C,
+                           int splits, DevTensor partial, hipStream_t st);
+constexpr int64_t kValues16Bound = 1 << 12;  // |v| below this for the packed path
+
 // Entries of the split-K partial buffer launch_tgemm needs for `splits`
 // chunks of K with tile config `cfg` and outer = batch * M * N outputs (0 when
 // the product runs unsplit).

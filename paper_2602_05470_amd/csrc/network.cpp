@@ -103,6 +103,8 @@ Network build_spinglass(int32_t n, int32_t m, const int32_t* uv, const int32_t* 
     }
   }
   for (int p = 0; p < NP; ++p) net.const_res[p] = 1;
+  net.zero_field = true;
+  for (int i = 0; h && i < n; ++i) net.zero_field &= h[i] == 0;
   simplify(net);
   flatten(net);
   return net;

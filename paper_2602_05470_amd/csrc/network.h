@@ -51,6 +51,7 @@ struct Network {
   bool infeasible = false;
   std::vector<PeelRec> peel;        // in elimination order
   int64_t abs_sum = 0;              // sum |J| + |h| (or sum w)
+  bool zero_field = false;          // spin glass without fields: H(sigma) = H(-sigma)
   // every tensor's entries back to back, in tensor order: the value plane
   // then the residue planes of the first NP_FLAT primes (flat_total entries
   // each), for uploads of whole planes

@@ -69,6 +69,38 @@ int64_t node_bound(const Network& net, const std::vector<uint64_t>& fixed,
   return b;
 }
 
+int32_t flip_variable(const Network& net, const Tree& tree, int log2_target) {
+  if (net.n <= 0) return -1;
+  std::vector<double> over(net.n, 0.0), mac(net.n, 0.0);
+  double top = 0;
+  for (int32_t id : tree.postorder) {
+    const TNode& nd = tree.nodes[id];
+    const auto& A = tree.nodes[nd.left].vars;
+    const auto& Bv = tree.nodes[nd.right].vars;
+    std::vector<int32_t> u;
+    std::set_union(A.begin(), A.end(), Bv.begin(), Bv.end(), std::back_inserter(u));
+    top = std::max(top, (double)u.size());
+  }
+  for (int32_t id : tree.postorder) {
+    const TNode& nd = tree.nodes[id];
+    const double ov = std::max(0, (int)nd.vars.size() - log2_target);
+    for (int32_t v : nd.vars) over[v] += ov;
+    const auto& A = tree.nodes[nd.left].vars;
+    const auto& Bv = tree.nodes[nd.right].vars;
+    std::vector<int32_t> u;
+    std::set_union(A.begin(), A.end(), Bv.begin(), Bv.end(), std::back_inserter(u));
+    const double w = std::ldexp(1.0, (int)u.size() - (int)top);
+    for (int32_t v : u) mac[v] += w;
+  }
+  int32_t best = -1;
+  for (int32_t v = 0; v < net.n; ++v) {
+    if (mac[v] == 0 && over[v] == 0) continue;
+    if (best < 0 || over[v] > over[best] || (over[v] == over[best] && mac[v] > mac[best]))
+      best = v;
+  }
+  return best;
+}
+
 int64_t network_value(const Network& net, const std::vector<uint8_t>& x) {
   if (net.infeasible) return INT64_MIN;
   int64_t v = net.const_val;
@@ -676,6 +708,11 @@ struct Searcher {
   void run(std::vector<LeafGroup>& leaves, SearchStats& st) {
     cur.fixed.assign((net.n + 63) / 64, 0);
     cur.x.assign(net.n, 0);
+    for (const auto& pv : opt.prefix) {
+      BBTN_REQUIRE(pv.first >= 0 && pv.first < net.n, "prefixed variable out of range");
+      bit_set(cur.fixed, pv.first);
+      cur.x[pv.first] = pv.second & 1;
+    }
     cur.sizes = node_sizes(tree, cur.fixed);
     cur.rho = rho_of(tree, cur.sizes, opt.log2_target);
     cur.bound = node_bound(net, cur.fixed, cur.x);

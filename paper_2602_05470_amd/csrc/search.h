@@ -48,6 +48,9 @@ struct SearchOptions {
   // nodes than this (read at every node; may be lowered while it runs)
   const std::atomic<uint64_t>* node_limit = nullptr;
   VarScorer scorer;
+  // variables fixed at the root, with their states (the spin fixed by the
+  // spin-flip symmetry)
+  std::vector<std::pair<int32_t, uint8_t>> prefix;
 };
 
 void bb_search(const Network& net, const Tree& tree, const SearchOptions& opt,
@@ -58,6 +61,13 @@ void bb_search(const Network& net, const Tree& tree, const SearchOptions& opt,
 // tensor has no consistent finite entry.
 int64_t node_bound(const Network& net, const std::vector<uint64_t>& fixed,
                    const std::vector<uint8_t>& x);
+
+// The spin whose fixing saves the most contraction work: largest overflow
+// participation sum over intermediates of max(0, log2 size - log2_target)
+// (the search's own branching priority), then largest MAC share sum over
+// contractions holding it of 2^(log2 MACs - the largest); lowest id on ties.
+// -1 for a network without variables.
+int32_t flip_variable(const Network& net, const Tree& tree, int log2_target);
 
 // rho of Eq. 4 given per-internal-node free-variable counts.
 int64_t rho_of(const Tree& t, const std::vector<int16_t>& sizes, int log2_target);

@@ -518,6 +518,20 @@ void solve_instances(bbtn_ctx* ctx, std::vector<Instance>& insts) {
       probe.values_only = values_only;
       probe.deadline = deadline;
       w.tree = tree_for(ctx, in.net, branch ? &probe : nullptr);
+      // spin-flip symmetry of a zero-field spin glass: a configuration and
+      // its mirror image have the same energy and exactly one of them has a
+      // given spin at +1, so that spin is fixed to +1 for the whole search
+      // and the count doubled (the constant's count residues)
+      int32_t flip = -1;
+      if (opt.spin_flip && in.net.spin && in.net.zero_field && !in.net.infeasible) {
+        flip = flip_variable(in.net, *w.tree.tree, branch ? opt.log2_target : 0);
+        if (flip >= 0) {
+          for (int p = 0; p < NP; ++p)
+            in.net.const_res[p] = addmod(in.net.const_res[p], in.net.const_res[p], P[p]);
+          if ((size_t)flip < in.ls_x.size() && in.ls_x[flip] == 0)
+            for (auto& bit : in.ls_x) bit ^= 1;
+        }
+      }
       // value (with the folded constant, like node_bound) of the local-search
       // configuration: a lower bound on the optimum, used for global pruning
       w.incumbent = in.ls_x.empty() ? INT64_MIN : network_value(in.net, in.ls_x);
@@ -525,6 +539,11 @@ void solve_instances(bbtn_ctx* ctx, std::vector<Instance>& insts) {
       if (!branch) {
         LeafGroup g;
         g.mask.assign((in.net.n + 63) / 64, 0);
+        if (flip >= 0) {
+          bit_set(g.mask, flip);
+          g.vars = {flip};
+          g.assign = {1};
+        }
         g.count = 1;
         w.groups.push_back(g);
         w.stats.leaves = 1;
@@ -535,6 +554,7 @@ void solve_instances(bbtn_ctx* ctx, std::vector<Instance>& insts) {
         so.incumbent = w.incumbent;
         so.values_only = values_only;
         so.deadline = deadline;
+        if (flip >= 0) so.prefix.push_back({flip, 1});
         if (scored) so.scorer = make_var_scorer(ctx, in.net, *w.tree.tree, opt.log2_target);
         bb_search(in.net, *w.tree.tree, so, w.groups, w.stats);
       }

@@ -24,6 +24,9 @@ SHAPES = [
     (1, 1, 1, 1), (1, 3, 5, 7), (2, 17, 33, 19), (1, 64, 64, 64), (3, 65, 130, 40),
     (2, 40, 48, 33), (1, 4, 200, 24), (1, 200, 4, 24), (1, 1, 300, 50), (1, 300, 1, 50),
     (2, 8, 20, 700), (1, 1, 1, 3000), (5, 2, 2, 2),
+    # thin products (power-of-two sizes, K <= 32, M or N below 32)
+    (3, 1024, 8, 8), (2, 4, 2048, 16), (7, 2, 2, 32), (1, 16, 16, 4), (4, 256, 2, 1),
+    (1, 1, 4096, 32),
 ]
 
 
@@ -216,3 +219,40 @@ def test_bound_matches_oracle(ctx):
     n = int(nk.item())
     assert n == len(want_keep)
     assert list(keep.cpu().numpy()[:n]) == want_keep
+
+
+# values-only product: packed 16-bit path (max_abs < 2^12) and 32-bit path
+VALUE_SHAPES = [
+    (1, 128, 128, 32), (1, 130, 257, 45), (2, 256, 384, 96), (1, 64, 512, 1024),
+    (3, 129, 131, 7), (1, 512, 512, 300), (2, 1, 200, 33), (1, 300, 2, 64),
+    (4, 512, 4, 16),
+]
+
+
+@pytest.mark.parametrize("shape", VALUE_SHAPES)
+@pytest.mark.parametrize("max_abs", [4095, 1 << 20])
+def test_tgemm_values_matches_oracle(ctx, shape, max_abs):
+    torch = torch_cuda()
+    b, M, N, K = shape
+    seed = hash((shape, max_abs)) % 10000
+    rng = np.random.default_rng(seed)
+    lim = min(max_abs, 4095) if max_abs < 4096 else 1 << 20
+
+    def vals(sz):
+        v = rng.integers(-lim, lim + 1, size=sz).astype(np.int32)
+        if max_abs < 4096:
+            # dense ties near the bound and exact extremes
+            v[rng.random(sz) < 0.2] = lim
+            v[rng.random(sz) < 0.1] = -lim
+        v[rng.random(sz) < 0.25] = I.NEG
+        return v
+    Av, Bv = vals((b, M, K)), vals((b, K, N))
+    dA = torch.from_numpy(Av.reshape(-1)).cuda()
+    dB = torch.from_numpy(Bv.reshape(-1)).cuda()
+    dC = torch.full((b * M * N,), -7, dtype=torch.int32, device="cuda")
+    ctx.tgemm_values(b, M, N, K, dA, dB, dC, max_abs)
+    torch.cuda.synchronize()
+    got = dC.cpu().numpy()
+    zr = np.zeros((1,) + Av.shape, np.uint32), np.zeros((1,) + Bv.shape, np.uint32)
+    wv, _ = D.tgemm(Av, zr[0], Bv, zr[1], I.PRIMES_31[:1])
+    assert np.array_equal(got, wv.reshape(-1).astype(np.int32))

@@ -113,3 +113,26 @@ def test_ksg40_branched_equals_whole(B):
     assert (v0, c0) == (v1, c1)
     assert v0 == 377                     # the integer program's W*
     assert c0 >= 1
+
+
+def test_sg32_learned_scorer_matches_plain_planner(B):
+    """The shipped spin-glass scorer on the 32x32 lattice (branching = 2):
+    the same ground energy and degeneracy as the plain planner and the
+    matching oracle's E0; the ratio of contraction work is printed (the
+    scorer orders the branching variables, so it may cost more or less)."""
+    g = I.spin_glass_square(32, 0)
+    wpath = os.path.join(os.path.dirname(B.__file__), "scorer_sg.bin")
+    out = {}
+    for branching in (1, 2):
+        with B.Context(B.Options(log2_target=26, order_refine=8, residues_per_pass=3,
+                                 branching=branching,
+                                 scorer_weights=wpath if branching == 2 else None,
+                                 time_limit_s=300)) as ctx:
+            r = ctx.solve_spinglass(g["n"], g["edges"], g["J"])
+        assert r.certified
+        assert config.spin_glass_energy(r.config, g["edges"], g["J"], None) == r.value
+        out[branching] = r
+    assert (out[2].value, out[2].count) == (out[1].value, out[1].count)
+    assert out[1].value == _golden("sg32_values.txt")[0][0]
+    print("scorer / plain MACs: %.3f, leaves %d / %d"
+          % (out[2].macs / out[1].macs, out[2].leaves, out[1].leaves))
