@@ -78,6 +78,25 @@ __device__ __forceinline__ int64_t xcd_remap(int64_t w, int64_t G) {
                    : rem * (per + 1) + (xcd - rem) * per + local;
 }
 
+// Output tile of work item t (after the XCD remap), plus the batch/split
+// index `rest`: tiles in groups of GM tile rows, tile rows fastest within a
+// group, so that the workgroups running at once on an XCD share column
+// blocks of B while the group's rows of A stay in that XCD's L2.
+constexpr int64_t GM = 8;
+__device__ __forceinline__ void tile_coords(int64_t t, int64_t tiles_m, int64_t tiles_n,
+                                            int64_t& tm, int64_t& tn, int64_t& rest) {
+  const int64_t per = tiles_m * tiles_n;
+  rest = t / per;
+  t -= rest * per;
+  const int64_t in_group = GM * tiles_n;
+  const int64_t g = t / in_group;
+  const int64_t first = g * GM;
+  const int64_t gsz = min(tiles_m - first, GM);
+  const int64_t r = t - g * in_group;
+  tm = first + r % gsz;
+  tn = r / gsz;
+}
+
 // One output tile (tile index w of a.total, before the XCD remap).
 template <int KR, int TM, int TN, int RM, int RN, int TK, bool VEC>
 __device__ __forceinline__ void tgemm_tile(const GemmArgs& a, int64_t w) {
@@ -100,11 +119,8 @@ __device__ __forceinline__ void tgemm_tile(const GemmArgs& a, int64_t w) {
   auto Ac = [&](int p, int kk, int i) -> uint32_t& { return As[(1 + p) * TK + kk][i]; };
   auto Bc = [&](int p, int kk, int i) -> uint32_t& { return Bs[(1 + p) * TK + kk][i]; };
 
-  int64_t t = xcd_remap(w, a.total);
-  const int64_t tn_i = t % a.tiles_n;
-  t /= a.tiles_n;
-  const int64_t tm_i = t % a.tiles_m;
-  t /= a.tiles_m;
+  int64_t tm_i, tn_i, t;
+  tile_coords(xcd_remap(w, a.total), a.tiles_m, a.tiles_n, tm_i, tn_i, t);
   const int64_t sp = t % a.splits;
   const int64_t b = t / a.splits;
   const int64_t m0 = tm_i * TM, n0 = tn_i * TN;
@@ -468,11 +484,8 @@ __device__ __forceinline__ void tgemm_v16_tile(const GemmArgs& a, int64_t w) {
   constexpr int TMP = TM + 4;         // padded rows of the transposed A tile
   __shared__ __attribute__((aligned(16))) uint32_t As[TK][TMP];
   __shared__ __attribute__((aligned(16))) uint32_t Bs[TK][TN / 2];
-  int64_t t = xcd_remap(w, a.total);
-  const int64_t tn_i = t % a.tiles_n;
-  t /= a.tiles_n;
-  const int64_t tm_i = t % a.tiles_m;
-  t /= a.tiles_m;
+  int64_t tm_i, tn_i, t;
+  tile_coords(xcd_remap(w, a.total), a.tiles_m, a.tiles_n, tm_i, tn_i, t);
   const int64_t sp = t % a.splits;
   const int64_t b = t / a.splits;
   const int64_t m0 = tm_i * TM, n0 = tn_i * TN;
