@@ -273,9 +273,12 @@ uint64_t bbtn_last_macs(const bbtn_ctx* ctx);
  * Kernel timing.  When enabled, HIP events are recorded on the launch stream
  * around every launch of the kernels below, and their durations, launch
  * counts and algorithmic work are accumulated.  Enabling or disabling clears
- * the counters.  Kernel ids: 0 counting tropical product (bbtn_tgemm and the
- * step-by-step executor), 1 persistent work-queue executor, 2 gather
- * (permutation / slicing), 3 segmented reduction (not instrumented yet).
+ * the counters.  Kernel ids: 0 counting tropical product on LDS tiles
+ * (bbtn_tgemm, bbtn_tgemm_values and the step-by-step executor), 1
+ * persistent work-queue executor, 2 gather (permutation / slicing), 3
+ * segmented reduction (not instrumented yet), 4 thin product (the same
+ * products when the summed range is short and one side narrow: one thread
+ * per output, no LDS).
  * ops: semiring operations, (2 + 2k) per multiply-accumulate (one value add
  * and one max, one modular multiply and one modular add per residue).
  * bytes: algorithmic bytes (operands read once + results written once).
@@ -288,6 +291,10 @@ typedef struct {
 } bbtn_kernel_stats;
 
 bbtn_status bbtn_profile(bbtn_ctx* ctx, int32_t enable);
+/* As bbtn_profile, timing only the kernels whose id bit is set in mask
+ * (bit i: kernel id i; 0 disables): fewer events in the launch stream when
+ * only one kernel's figures are wanted. */
+bbtn_status bbtn_profile_mask(bbtn_ctx* ctx, uint32_t mask);
 bbtn_status bbtn_get_kernel_stats(bbtn_ctx* ctx, int32_t kernel, bbtn_kernel_stats* out);
 
 /* ------------------------------------------------------------------------

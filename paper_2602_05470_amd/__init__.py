@@ -69,7 +69,7 @@ _lib = None
 EXPORTS = ["bbtn_default_options", "bbtn_create", "bbtn_destroy", "bbtn_last_error",
            "bbtn_solve_spinglass", "bbtn_solve_mwis", "bbtn_tgemm", "bbtn_tgemm_values", "bbtn_tgemm_noalloc", "bbtn_gather",
            "bbtn_reduce", "bbtn_bound", "bbtn_last_macs", "bbtn_profile",
-           "bbtn_get_kernel_stats", "bbtn_mlp_forward", "bbtn_mlp_backward", "bbtn_mlp_adam",
+           "bbtn_get_kernel_stats", "bbtn_profile_mask", "bbtn_mlp_forward", "bbtn_mlp_backward", "bbtn_mlp_adam",
            "bbtn_scorer_load", "bbtn_scorer_collect", "bbtn_scorer_train", "bbtn_plan_leaves",
            "bbtn_order_complexity",
            "bbtn_solve_batch"]
@@ -86,7 +86,7 @@ class _KStats(C.Structure):
                 ("bytes", C.c_double)]
 
 
-KERNELS = {"tgemm": 0, "persist": 1, "gather": 2, "reduce": 3}
+KERNELS = {"tgemm": 0, "persist": 1, "gather": 2, "reduce": 3, "thin": 4}
 
 
 def load(path: str = LIB_PATH):
@@ -128,6 +128,8 @@ def load(path: str = LIB_PATH):
     lib.bbtn_bound.restype = I32
     lib.bbtn_profile.argtypes = [P, I32]
     lib.bbtn_profile.restype = I32
+    lib.bbtn_profile_mask.argtypes = [P, C.c_uint32]
+    lib.bbtn_profile_mask.restype = I32
     lib.bbtn_get_kernel_stats.argtypes = [P, I32, C.POINTER(_KStats)]
     lib.bbtn_get_kernel_stats.restype = I32
     F = C.c_float
@@ -273,9 +275,16 @@ class Context:
     def last_macs(self):
         return int(self.lib.bbtn_last_macs(self.h))
 
-    def profile(self, enable=True):
-        """bbtn_profile: start (and clear) or stop per-kernel event timing."""
-        self._check(self.lib.bbtn_profile(self.h, 1 if enable else 0))
+    def profile(self, enable=True, kernels=None):
+        """bbtn_profile: start (and clear) or stop per-kernel event timing;
+        with `kernels` (names), bbtn_profile_mask: only those kernels."""
+        if kernels is None or not enable:
+            self._check(self.lib.bbtn_profile(self.h, 1 if enable else 0))
+        else:
+            mask = 0
+            for k in kernels:
+                mask |= 1 << KERNELS[k]
+            self._check(self.lib.bbtn_profile_mask(self.h, mask))
 
     def kernel_stats(self, kernel):
         """bbtn_get_kernel_stats: dict(launches, seconds, ops, bytes)."""

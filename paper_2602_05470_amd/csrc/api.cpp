@@ -148,11 +148,16 @@ const char* bbtn_last_error(const bbtn_ctx* ctx) { return ctx ? ctx->err.c_str()
 uint64_t bbtn_last_macs(const bbtn_ctx* ctx) { return ctx ? ctx->last_macs : 0; }
 
 bbtn_status bbtn_profile(bbtn_ctx* ctx, int32_t enable) {
+  return bbtn_profile_mask(ctx, enable != 0 ? ~0u : 0u);
+}
+
+bbtn_status bbtn_profile_mask(bbtn_ctx* ctx, uint32_t mask) {
   if (!ctx) return BBTN_E_INVALID_ARG;
   return guard(ctx, [&] {
     BBTN_HIP(hipSetDevice(ctx->opt.device));
     ctx->prof.clear();
-    ctx->prof.on = enable != 0;
+    ctx->prof.on = (mask & ((1u << K_COUNT) - 1)) != 0;
+    ctx->prof.mask = mask;
   });
 }
 
@@ -263,11 +268,12 @@ bbtn_status bbtn_tgemm(bbtn_ctx* ctx, int32_t k, const uint32_t* primes, int64_t
     }
     GemmShape sh{batch, M, N, K, M * K, K * N, M * N};
     hipStream_t st = pick_stream(ctx, stream);
-    const int ph = ctx->prof.begin(st);
+    const int kid = tv.splits <= 1 && tgemm_is_thin(sh, 1) ? K_THIN : K_TGEMM;
+    const int ph = ctx->prof.begin(st, kid);
     launch_tgemm(k, mod, sh, DevTensor{(uint32_t*)A, batch * M * K},
                  DevTensor{(uint32_t*)B, batch * K * N}, DevTensor{(uint32_t*)C, batch * M * N},
                  tv.cfg, tv.splits, part, st);
-    ctx->prof.end(ph, st, K_TGEMM, (double)batch * M * N * K * (2 + 2 * k),
+    ctx->prof.end(ph, st, kid, (double)batch * M * N * K * (2 + 2 * k),
                   (double)(1 + k) * 4 * (double)batch * (double)(M * K + K * N + M * N));
   });
 }
@@ -294,12 +300,14 @@ bbtn_status bbtn_tgemm_values(bbtn_ctx* ctx, int64_t batch, int64_t M, int64_t N
     const DevTensor dA{(uint32_t*)A, batch * M * K}, dB{(uint32_t*)B, batch * K * N},
         dC{(uint32_t*)C, batch * M * N};
     hipStream_t st = pick_stream(ctx, stream);
-    const int ph = ctx->prof.begin(st);
-    if (max_abs < kValues16Bound)
+    const bool packed = max_abs < kValues16Bound;
+    const int kid = !packed && tgemm_is_thin(sh, tv.splits) ? K_THIN : K_TGEMM;
+    const int ph = ctx->prof.begin(st, kid);
+    if (packed)
       launch_tgemm_values16(sh, dA, dB, dC, tv.splits, part, st);
     else
       launch_tgemm(0, make_moduli(0, nullptr), sh, dA, dB, dC, tv.cfg, tv.splits, part, st);
-    ctx->prof.end(ph, st, K_TGEMM, 2.0 * batch * M * N * K,
+    ctx->prof.end(ph, st, kid, 2.0 * batch * M * N * K,
                   4.0 * (double)batch * (double)(M * K + K * N + M * N));
   });
 }

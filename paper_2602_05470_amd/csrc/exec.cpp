@@ -240,7 +240,7 @@ void run_group(bbtn_ctx* ctx, const Network& net, const GroupPlan& g, const Base
           const DevTensor src{bd.t.ptr + bd.off[op.id], bd.total};
           const uint64_t* fbits =
               s.shared ? nullptr : ctx->fixbits.as<uint64_t>() + (size_t)op.base_op * L;
-          const int ph = ctx->prof.begin(st);
+          const int ph = ctx->prof.begin(st, K_GATHER);
           launch_gather(k, gp, Ls, 0, fbits, src, buf(op.temp), st);
           ctx->prof.end(ph, st, K_GATHER, 0, 2.0 * W * 4 * (double)(Ls << ranks[w]));
           opnd[w] = buf(op.temp);
@@ -252,7 +252,7 @@ void run_group(bbtn_ctx* ctx, const Network& net, const GroupPlan& g, const Base
           const uint64_t* fbits = (op.base_op >= 0 && !s.shared)
                                       ? ctx->fixbits.as<uint64_t>() + (size_t)op.base_op * L
                                       : nullptr;
-          const int ph = ctx->prof.begin(st);
+          const int ph = ctx->prof.begin(st, K_GATHER);
           launch_gather(k, gp, Ls, stride, fbits, buf(op.id), buf(op.temp), st);
           ctx->prof.end(ph, st, K_GATHER, 0, 2.0 * W * 4 * (double)(Ls << ranks[w]));
           opnd[w] = buf(op.temp);
@@ -266,12 +266,14 @@ void run_group(bbtn_ctx* ctx, const Network& net, const GroupPlan& g, const Base
       const TuneVal tv = tvs[si];
       DevTensor part{};
       if (tv.splits > 1) part = DevTensor{ctx->partial.as<uint32_t>(), (int64_t)tv.splits * batch * M * N};
-      const int ph = ctx->prof.begin(st);
-      if (vals16 && M >= 128 && N >= 128)
+      const bool packed = vals16 && M >= 128 && N >= 128;
+      const int kid = !packed && tgemm_is_thin(sh, tv.splits) ? K_THIN : K_TGEMM;
+      const int ph = ctx->prof.begin(st, kid);
+      if (packed)
         launch_tgemm_values16(sh, opnd[0], opnd[1], buf(s.out), tv.splits, part, st);
       else
         launch_tgemm(k, mod, sh, opnd[0], opnd[1], buf(s.out), tv.cfg, tv.splits, part, st);
-      ctx->prof.end(ph, st, K_TGEMM, (double)Ls * s.macs() * (2 + 2 * k),
+      ctx->prof.end(ph, st, kid, (double)Ls * s.macs() * (2 + 2 * k),
                     (double)W * 4 * (double)batch * (double)(M * K + K * N + M * N));
     }
     if (g.root_buf >= 0) {

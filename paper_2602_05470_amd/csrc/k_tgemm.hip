@@ -443,6 +443,8 @@ static bool thin_shape(const GemmShape& s, int splits) {
   return splits <= 1 && lm >= 0 && ln >= 0 && lk >= 0 && lk <= 5 && (lm < 5 || ln < 5);
 }
 
+bool tgemm_is_thin(const GemmShape& s, int splits) { return thin_shape(s, splits); }
+
 static void launch_thin(int k, const GemmArgs& a, hipStream_t st) {
   const int lm = exact_log2(a.M), ln = exact_log2(a.N), lk = exact_log2(a.K);
   const int64_t total = a.batch << (lm + ln);

@@ -27,6 +27,11 @@ void launch_tgemm(int k, const Moduli& mod, const GemmShape& s, DevTensor A,
                   DevTensor B, DevTensor C, int cfg, int splits,
                   DevTensor partial, hipStream_t st);
 
+// True when launch_tgemm runs the product with the thin kernel (one thread
+// per output, no LDS): unsplit, power-of-two sizes, K <= 32 and M or N
+// below 32.
+bool tgemm_is_thin(const GemmShape& s, int splits);
+
 // Values-only product (k = 0) with two values per 32-bit word, for operands
 // whose finite values all satisfy |v| < 2^12 (the caller guarantees it):
 // half the VALU instructions per multiply-accumulate.  Same layouts, split-K

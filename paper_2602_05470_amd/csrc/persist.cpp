@@ -436,7 +436,7 @@ void run_persistent(bbtn_ctx* ctx, const std::vector<PersistJob>& jobs, const Ba
     }
     bytes += (it->second.first + (double)j.L * it->second.second) * W * 4;
   }
-  const int ph = ctx->prof.begin(st);
+  const int ph = ctx->prof.begin(st, K_PERSIST);
   if (!shared_tasks.empty()) {
     // shared subtrees first, then the branches (stream order separates them)
     a.tasks = (const PTask*)(dev + o_stasks);

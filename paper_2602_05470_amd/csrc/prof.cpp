@@ -15,8 +15,8 @@ hipEvent_t Prof::get() {
   return e;
 }
 
-int Prof::begin(hipStream_t st) {
-  if (!on) return -1;
+int Prof::begin(hipStream_t st, int id) {
+  if (!on || id < 0 || id >= K_COUNT || !(mask >> id & 1)) return -1;
   Pending p{};
   p.a = get();
   p.b = get();

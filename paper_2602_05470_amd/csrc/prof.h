@@ -8,7 +8,7 @@ struct bbtn_ctx;
 
 namespace bbtn {
 
-enum KernelId { K_TGEMM = 0, K_PERSIST = 1, K_GATHER = 2, K_REDUCE = 3, K_COUNT = 4 };
+enum KernelId { K_TGEMM = 0, K_PERSIST = 1, K_GATHER = 2, K_REDUCE = 3, K_THIN = 4, K_COUNT = 5 };
 
 struct KStat {
   uint64_t launches = 0;
@@ -19,6 +19,7 @@ struct KStat {
 
 struct Prof {
   bool on = false;
+  uint32_t mask = ~0u;  // kernel ids timed while on (bit i: kernel i)
   KStat stat[K_COUNT];
   struct Pending {
     int id;
@@ -28,8 +29,9 @@ struct Prof {
   std::vector<Pending> pending;
   std::vector<hipEvent_t> pool;
   hipEvent_t get();
-  // bracket a launch: begin() before, end() after
-  int begin(hipStream_t st);
+  // bracket a launch of kernel `id`: begin() before, end() after (a
+  // kernel outside the mask is not timed: begin returns -1)
+  int begin(hipStream_t st, int id);
   void end(int h, hipStream_t st, int id, double ops, double bytes);
   void resolve();  // after a stream synchronisation
   void clear();
