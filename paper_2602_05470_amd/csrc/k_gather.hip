@@ -198,11 +198,11 @@ void launch_gather(int k, const GatherPlan& gp, int64_t L, int64_t in_stride,
     const int64_t blocks = std::min<int64_t>(tiles, 256 * 32);
     dim3 grid((unsigned)blocks), block(256);
     switch (k) {
-      case 0: hipLaunchKernelGGL(gather_tiled_kernel<1>, grid, block, 0, st, g, t); break;
-      case 1: hipLaunchKernelGGL(gather_tiled_kernel<2>, grid, block, 0, st, g, t); break;
-      case 2: hipLaunchKernelGGL(gather_tiled_kernel<3>, grid, block, 0, st, g, t); break;
-      case 3: hipLaunchKernelGGL(gather_tiled_kernel<4>, grid, block, 0, st, g, t); break;
-      case 4: hipLaunchKernelGGL(gather_tiled_kernel<5>, grid, block, 0, st, g, t); break;
+      case 0: launch_kernel(gather_tiled_kernel<1>, grid, block, 0, st, true, g, t); break;
+      case 1: launch_kernel(gather_tiled_kernel<2>, grid, block, 0, st, true, g, t); break;
+      case 2: launch_kernel(gather_tiled_kernel<3>, grid, block, 0, st, true, g, t); break;
+      case 3: launch_kernel(gather_tiled_kernel<4>, grid, block, 0, st, true, g, t); break;
+      case 4: launch_kernel(gather_tiled_kernel<5>, grid, block, 0, st, true, g, t); break;
       default: throw Error(BBTN_E_INVALID_ARG, "k must be in [0, 4]");
     }
     BBTN_LAUNCHED("gather (tiled)");
@@ -211,11 +211,11 @@ void launch_gather(int k, const GatherPlan& gp, int64_t L, int64_t in_stride,
   const int64_t blocks = std::min<int64_t>((total + 255) / 256, 256 * 64);
   dim3 grid((unsigned)blocks), block(256);
   switch (k) {
-    case 0: hipLaunchKernelGGL(gather_kernel<1>, grid, block, 0, st, g); break;
-    case 1: hipLaunchKernelGGL(gather_kernel<2>, grid, block, 0, st, g); break;
-    case 2: hipLaunchKernelGGL(gather_kernel<3>, grid, block, 0, st, g); break;
-    case 3: hipLaunchKernelGGL(gather_kernel<4>, grid, block, 0, st, g); break;
-    case 4: hipLaunchKernelGGL(gather_kernel<5>, grid, block, 0, st, g); break;
+    case 0: launch_kernel(gather_kernel<1>, grid, block, 0, st, true, g); break;
+    case 1: launch_kernel(gather_kernel<2>, grid, block, 0, st, true, g); break;
+    case 2: launch_kernel(gather_kernel<3>, grid, block, 0, st, true, g); break;
+    case 3: launch_kernel(gather_kernel<4>, grid, block, 0, st, true, g); break;
+    case 4: launch_kernel(gather_kernel<5>, grid, block, 0, st, true, g); break;
     default: throw Error(BBTN_E_INVALID_ARG, "k must be in [0, 4]");
   }
   BBTN_LAUNCHED("gather");

@@ -143,10 +143,10 @@ template <int KR>
 void reduce_dispatch(const ReduceArgs& a, hipStream_t st) {
   if (a.S >= 512 && a.outer <= 4096) {
     const int64_t blocks = std::min<int64_t>(a.outer, 4096);
-    hipLaunchKernelGGL(reduce_block_kernel<KR>, dim3((unsigned)blocks), dim3(256), 0, st, a);
+    launch_kernel(reduce_block_kernel<KR>, dim3((unsigned)blocks), dim3(256), 0, st, true, a);
   } else {
     const int64_t blocks = std::min<int64_t>((a.outer + 255) / 256, 256 * 64);
-    hipLaunchKernelGGL(reduce_thread_kernel<KR>, dim3((unsigned)blocks), dim3(256), 0, st, a);
+    launch_kernel(reduce_thread_kernel<KR>, dim3((unsigned)blocks), dim3(256), 0, st, true, a);
   }
 }
 

@@ -451,11 +451,11 @@ static void launch_thin(int k, const GemmArgs& a, hipStream_t st) {
   const int64_t blocks = std::min<int64_t>((total + 255) / 256, 256 * 64);
   dim3 grid((unsigned)blocks), block(256);
   switch (k) {
-    case 0: hipLaunchKernelGGL(tgemm_thin_kernel<0>, grid, block, 0, st, a, lm, ln, lk); break;
-    case 1: hipLaunchKernelGGL(tgemm_thin_kernel<1>, grid, block, 0, st, a, lm, ln, lk); break;
-    case 2: hipLaunchKernelGGL(tgemm_thin_kernel<2>, grid, block, 0, st, a, lm, ln, lk); break;
-    case 3: hipLaunchKernelGGL(tgemm_thin_kernel<3>, grid, block, 0, st, a, lm, ln, lk); break;
-    case 4: hipLaunchKernelGGL(tgemm_thin_kernel<4>, grid, block, 0, st, a, lm, ln, lk); break;
+    case 0: launch_kernel(tgemm_thin_kernel<0>, grid, block, 0, st, true, a, lm, ln, lk); break;
+    case 1: launch_kernel(tgemm_thin_kernel<1>, grid, block, 0, st, true, a, lm, ln, lk); break;
+    case 2: launch_kernel(tgemm_thin_kernel<2>, grid, block, 0, st, true, a, lm, ln, lk); break;
+    case 3: launch_kernel(tgemm_thin_kernel<3>, grid, block, 0, st, true, a, lm, ln, lk); break;
+    case 4: launch_kernel(tgemm_thin_kernel<4>, grid, block, 0, st, true, a, lm, ln, lk); break;
     default: throw Error(BBTN_E_INVALID_ARG, "k must be in [0, 4]");
   }
   BBTN_LAUNCHED("tgemm (thin, grid " + std::to_string(total) + ")");
@@ -593,16 +593,16 @@ __global__ void __launch_bounds__((TM / RM) * (TN / RN)) tgemm_v16_kernel(const 
 constexpr int V16_TM = 128, V16_TN = 128, V16_RM = 8, V16_RN = 8, V16_TK = 32;
 
 template <int KR>
-static void launch_cfg(int cfg, dim3 grid, const GemmArgs& a, hipStream_t st) {
+static void launch_cfg(int cfg, dim3 grid, const GemmArgs& a, hipStream_t st, bool last) {
   switch (cfg) {
 #define BBTN_TG_CASE(I, TM, TN, RM, RN, TK, VEC)                                  \
   case I:                                                                          \
     if (a.total == (int64_t)grid.x)                                                \
-      hipLaunchKernelGGL((tgemm_kernel<KR, TM, TN, RM, RN, TK, VEC>), grid,         \
-                         dim3((TM / RM) * (TN / RN)), 0, st, a);                   \
+      launch_kernel((tgemm_kernel<KR, TM, TN, RM, RN, TK, VEC>), grid,              \
+                    dim3((TM / RM) * (TN / RN)), 0, st, last, a);                  \
     else                                                                           \
-      hipLaunchKernelGGL((tgemm_kernel_strided<KR, TM, TN, RM, RN, TK, VEC>), grid, \
-                         dim3((TM / RM) * (TN / RN)), 0, st, a);                   \
+      launch_kernel((tgemm_kernel_strided<KR, TM, TN, RM, RN, TK, VEC>), grid,      \
+                    dim3((TM / RM) * (TN / RN)), 0, st, last, a);                  \
     break;
     BBTN_TG_CASE(0, 64, 64, 4, 4, 24, false)
     BBTN_TG_CASE(1, 32, 32, 2, 2, 24, false)
@@ -622,7 +622,7 @@ static void launch_cfg(int cfg, dim3 grid, const GemmArgs& a, hipStream_t st) {
   }
 }
 
-static void launch_core(int k, const GemmArgs& a0, int cfg, hipStream_t st) {
+static void launch_core(int k, const GemmArgs& a0, int cfg, hipStream_t st, bool last = true) {
   const TileCfg& tc = kTileCfgs[cfg];
   GemmArgs a = a0;
   a.tiles_m = (a.M + tc.tm - 1) / tc.tm;
@@ -641,11 +641,11 @@ static void launch_core(int k, const GemmArgs& a0, int cfg, hipStream_t st) {
   const int64_t cap = 1ll << 20;
   dim3 grid((unsigned)(total <= cap ? total : cap));
   switch (k) {
-    case 0: launch_cfg<0>(cfg, grid, a, st); break;
-    case 1: launch_cfg<1>(cfg, grid, a, st); break;
-    case 2: launch_cfg<2>(cfg, grid, a, st); break;
-    case 3: launch_cfg<3>(cfg, grid, a, st); break;
-    case 4: launch_cfg<4>(cfg, grid, a, st); break;
+    case 0: launch_cfg<0>(cfg, grid, a, st, last); break;
+    case 1: launch_cfg<1>(cfg, grid, a, st, last); break;
+    case 2: launch_cfg<2>(cfg, grid, a, st, last); break;
+    case 3: launch_cfg<3>(cfg, grid, a, st, last); break;
+    case 4: launch_cfg<4>(cfg, grid, a, st, last); break;
     default: throw Error(BBTN_E_INVALID_ARG, "k must be in [0, 4]");
   }
   BBTN_LAUNCHED("tgemm (tile config " + std::to_string(cfg) + ", k " + std::to_string(k) +
@@ -680,7 +680,7 @@ void launch_tgemm(int k, const Moduli& mod, const GemmShape& s, DevTensor A,
   a.C = partial.ptr; a.pC = partial.pstride;
   a.sCb = s.M * s.N; a.sCsplit = outer;
   a.splits = nsp; a.kchunk = kchunk;
-  launch_core(k, a, cfg, st);
+  launch_core(k, a, cfg, st, false);
   BBTN_REQUIRE(s.sCb == s.M * s.N, "split-K output must be contiguous");
   launch_reduce(k, mod, outer, nsp, outer, 1, partial, C, st);
 }
@@ -719,8 +719,8 @@ void launch_tgemm_values16(const GemmShape& s, DevTensor A, DevTensor B, DevTens
   a.vec_b = a.N % 4 == 0 && al16(a.B) && (a.batch == 1 || a.sBb % 4 == 0);
   const int64_t cap = 1ll << 20;
   dim3 grid((unsigned)(a.total <= cap ? a.total : cap));
-  hipLaunchKernelGGL((tgemm_v16_kernel<V16_TM, V16_TN, V16_RM, V16_RN, V16_TK>), grid,
-                     dim3((V16_TM / V16_RM) * (V16_TN / V16_RN)), 0, st, a);
+  launch_kernel((tgemm_v16_kernel<V16_TM, V16_TN, V16_RM, V16_RN, V16_TK>), grid,
+                dim3((V16_TM / V16_RM) * (V16_TN / V16_RN)), 0, st, nsp <= 1, a);
   BBTN_LAUNCHED("tgemm (packed 16-bit values, grid " + std::to_string(a.total) + ")");
   if (nsp > 1) launch_reduce(0, a.mod, outer, nsp, outer, 1, partial, C, st);
 }

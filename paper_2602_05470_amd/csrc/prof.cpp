@@ -1,6 +1,7 @@
 #include "prof.h"
 
 #include "ctx.h"
+#include "kernels.h"
 
 namespace bbtn {
 
@@ -15,12 +16,22 @@ hipEvent_t Prof::get() {
   return e;
 }
 
+TimedLaunch& timed_launch() {
+  static thread_local TimedLaunch slot;
+  return slot;
+}
+
 int Prof::begin(hipStream_t st, int id) {
   if (!on || id < 0 || id >= K_COUNT || !(mask >> id & 1)) return -1;
   Pending p{};
   p.a = get();
   p.b = get();
-  BBTN_HIP(hipEventRecord(p.a, st));
+  p.ext = id != K_PERSIST;
+  if (p.ext) {
+    timed_launch() = TimedLaunch{p.a, p.b};
+  } else {
+    BBTN_HIP(hipEventRecord(p.a, st));
+  }
   pending.push_back(p);
   return (int)pending.size() - 1;
 }
@@ -31,14 +42,26 @@ void Prof::end(int h, hipStream_t st, int id, double ops, double bytes) {
   p.id = id;
   p.ops = ops;
   p.bytes = bytes;
-  BBTN_HIP(hipEventRecord(p.b, st));
+  if (p.ext) {
+    // a launch path that did not take the events (none should): record
+    // what is left on the stream, so the pair stays valid
+    TimedLaunch& t = timed_launch();
+    if (t.start) BBTN_HIP(hipEventRecord(t.start, st));
+    if (t.stop) BBTN_HIP(hipEventRecord(t.stop, st));
+    t = TimedLaunch{};
+  } else {
+    BBTN_HIP(hipEventRecord(p.b, st));
+  }
 }
 
 void Prof::resolve() {
   for (auto& p : pending) {
-    BBTN_HIP(hipEventSynchronize(p.b));
     float ms = 0;
-    BBTN_HIP(hipEventElapsedTime(&ms, p.a, p.b));
+    // a pair left unrecorded by a launch that failed is counted as 0 s
+    if (hipEventSynchronize(p.b) != hipSuccess || hipEventElapsedTime(&ms, p.a, p.b) != hipSuccess) {
+      ms = 0;
+      (void)hipGetLastError();
+    }
     KStat& s = stat[p.id];
     s.launches++;
     s.seconds += ms * 1e-3;

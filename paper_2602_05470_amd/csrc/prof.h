@@ -25,12 +25,16 @@ struct Prof {
     int id;
     hipEvent_t a, b;
     double ops, bytes;
+    bool ext;  // events taken by the kernel launches themselves
   };
   std::vector<Pending> pending;
   std::vector<hipEvent_t> pool;
   hipEvent_t get();
   // bracket a launch of kernel `id`: begin() before, end() after (a
-  // kernel outside the mask is not timed: begin returns -1)
+  // kernel outside the mask is not timed: begin returns -1).  Products and
+  // gathers hand their events to the kernel launches (launch_kernel in
+  // kernels.h); the executor pass records them on the stream around its
+  // dispatches.
   int begin(hipStream_t st, int id);
   void end(int h, hipStream_t st, int id, double ops, double bytes);
   void resolve();  // after a stream synchronisation
