@@ -522,6 +522,9 @@ def main():
                     help="skip the 16x16 leg's second run with a refined order")
     ap.add_argument("--no-ksg", action="store_true", help="skip the 40x40 King's subgraph leg")
     ap.add_argument("--no-sg16", action="store_true", help="skip the 16x16 leg")
+    ap.add_argument("--residues", type=int, default=3,
+                    help="residues per pass of the headline run (a further certification "
+                         "prime is fused into the pass)")
     ap.add_argument("--ksg-seeds", type=int, default=8,
                     help="seeds of the 40x40 King's subgraph leg (0 .. n-1)")
     ap.add_argument("--micro-only", action="store_true",
@@ -560,7 +563,7 @@ def main():
     ncpu = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
     # ---- headline: +-J 32x32
     sg32 = golden_values("sg32_values.txt")
-    head_opts = B.Options(log2_target=26, residues_per_pass=3, branching=1, batched=1,
+    head_opts = B.Options(log2_target=26, residues_per_pass=args.residues, branching=1, batched=1,
                           order_refine=8, time_limit_s=600, spin_flip=1)
     seeds = [i % 20 for i in range(args.steps)]
     warm = [20 + i for i in range(args.warmup)]
@@ -582,13 +585,13 @@ def main():
         "config": {"workload": "+-J spin glass 32x32 open lattice, seeds 0-19 (step i solves "
                                "seed i mod 20), zero field; BBTN T_target=2^26, refined "
                                "contraction order, plain planner, spin-flip symmetry (one "
-                               "spin fixed, count doubled), 3 primes per pass plus a fused "
+                               "spin fixed, count doubled), %d primes per pass plus a fused "
                                "certification prime; one step = one call solving one "
-                               "instance",
+                               "instance" % args.residues,
                    "instances": h["n"], "exact": h["exact"],
                    "leaves_per_instance": h["leaves_per_instance"],
                    "macs_per_instance": h["macs_per_instance"],
-                   "log2_target": 26, "residues_per_pass": 3, "contraction_order":
+                   "log2_target": 26, "residues_per_pass": args.residues, "contraction_order":
                    "refined (8 candidates, chosen in the warm-up)", "branching": "plain planner",
                    "exactness": "certified count, E0 equal to the matching oracle's stored "
                                 "value, even degeneracy, configuration reaching E0"},

@@ -95,7 +95,7 @@ bbtn_status bbtn_create(const bbtn_options* opt, bbtn_ctx** out) {
   ctx->attach_memcap(std::make_shared<MemCap>());
   ctx->memcap->cap = (size_t)ctx->opt.device_mem_cap;
   bbtn_status s = guard(ctx, [&] {
-    BBTN_REQUIRE(ctx->opt.residues_per_pass >= 0 && ctx->opt.residues_per_pass <= KMAX,
+    BBTN_REQUIRE(ctx->opt.residues_per_pass >= 0 && ctx->opt.residues_per_pass <= KUSER,
                  "residues_per_pass must be in [0, 4]");
     int ndev = 0;
     BBTN_HIP(hipGetDeviceCount(&ndev));
@@ -251,7 +251,7 @@ bbtn_status bbtn_tgemm(bbtn_ctx* ctx, int32_t k, const uint32_t* primes, int64_t
                        int64_t N, int64_t K, const void* A, const void* B, void* C, void* stream) {
   if (!ctx) return BBTN_E_INVALID_ARG;
   return guard(ctx, [&] {
-    BBTN_REQUIRE(k >= 1 && k <= KMAX, "k must be in [1, 4]");
+    BBTN_REQUIRE(k >= 1 && k <= KUSER, "k must be in [1, 4]");
     BBTN_REQUIRE(primes != nullptr, "primes is NULL");
     BBTN_REQUIRE(batch >= 1 && M >= 1 && N >= 1 && K >= 1, "empty product");
     BBTN_REQUIRE(A && B && C, "NULL operand");
@@ -317,7 +317,7 @@ bbtn_status bbtn_tgemm_noalloc(bbtn_ctx* ctx, int32_t k, const uint32_t* primes,
                                void* C, void* stream) {
   if (!ctx) return BBTN_E_INVALID_ARG;
   return guard(ctx, [&] {
-    BBTN_REQUIRE(k >= 1 && k <= KMAX, "k must be in [1, 4]");
+    BBTN_REQUIRE(k >= 1 && k <= KUSER, "k must be in [1, 4]");
     BBTN_REQUIRE(primes != nullptr, "primes is NULL");
     BBTN_REQUIRE(batch >= 1 && M >= 1 && N >= 1 && K >= 1, "empty product");
     BBTN_REQUIRE(A && B && C, "NULL operand");
@@ -351,7 +351,7 @@ bbtn_status bbtn_gather(bbtn_ctx* ctx, int32_t k, int32_t r_in, int32_t r_out,
                         void* stream) {
   if (!ctx) return BBTN_E_INVALID_ARG;
   return guard(ctx, [&] {
-    BBTN_REQUIRE(k >= 0 && k <= KMAX, "k must be in [0, 4]");
+    BBTN_REQUIRE(k >= 0 && k <= KUSER, "k must be in [0, 4]");
     BBTN_REQUIRE(L >= 1 && in && out, "bad gather arguments");
     BBTN_REQUIRE(r_out == 0 || src_bits != nullptr, "src_bits is NULL");
     BBTN_REQUIRE(r_in <= 36, "r_in too large");
@@ -370,7 +370,7 @@ bbtn_status bbtn_reduce(bbtn_ctx* ctx, int32_t k, const uint32_t* primes, int64_
                         int64_t in_entries, void* out, void* stream) {
   if (!ctx) return BBTN_E_INVALID_ARG;
   return guard(ctx, [&] {
-    BBTN_REQUIRE(k >= 1 && k <= KMAX, "k must be in [1, 4]");
+    BBTN_REQUIRE(k >= 1 && k <= KUSER, "k must be in [1, 4]");
     BBTN_REQUIRE(primes && in && out, "NULL argument");
     BBTN_REQUIRE(outer >= 1 && S >= 1 && seg_stride >= 0 && elem_stride >= 0, "bad sizes");
     BBTN_REQUIRE((S - 1) * seg_stride + (outer - 1) * elem_stride < in_entries,

@@ -12,7 +12,10 @@ namespace bbtn {
 
 constexpr int32_t NEG = BBTN_NEG;
 constexpr int32_t NEG_CUT = BBTN_NEG_CUT;
-constexpr int KMAX = BBTN_MAX_RESIDUES;
+// Residues a pass may carry per entry: the caller's k (at most
+// BBTN_MAX_RESIDUES) plus one certification prime fused into the same pass.
+constexpr int KUSER = BBTN_MAX_RESIDUES;
+constexpr int KMAX = BBTN_MAX_RESIDUES + 1;
 
 // Error carried from deep host code to the C ABI.
 struct Error : std::runtime_error {

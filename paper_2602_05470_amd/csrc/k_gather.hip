@@ -20,7 +20,7 @@
 //    of the tile are split into a low and a high 6-bit half whose offsets add
 //    (a bit permutation is additive over disjoint bits), kept as 64-entry
 //    tables in LDS.
-#include "kernels.h"
+#include "launch.h"
 
 namespace bbtn {
 
@@ -203,7 +203,8 @@ void launch_gather(int k, const GatherPlan& gp, int64_t L, int64_t in_stride,
       case 2: launch_kernel(gather_tiled_kernel<3>, grid, block, 0, st, true, g, t); break;
       case 3: launch_kernel(gather_tiled_kernel<4>, grid, block, 0, st, true, g, t); break;
       case 4: launch_kernel(gather_tiled_kernel<5>, grid, block, 0, st, true, g, t); break;
-      default: throw Error(BBTN_E_INVALID_ARG, "k must be in [0, 4]");
+      case 5: launch_kernel(gather_tiled_kernel<6>, grid, block, 0, st, true, g, t); break;
+      default: throw Error(BBTN_E_INVALID_ARG, "k must be in [0, 5]");
     }
     BBTN_LAUNCHED("gather (tiled)");
     return;
@@ -216,7 +217,8 @@ void launch_gather(int k, const GatherPlan& gp, int64_t L, int64_t in_stride,
     case 2: launch_kernel(gather_kernel<3>, grid, block, 0, st, true, g); break;
     case 3: launch_kernel(gather_kernel<4>, grid, block, 0, st, true, g); break;
     case 4: launch_kernel(gather_kernel<5>, grid, block, 0, st, true, g); break;
-    default: throw Error(BBTN_E_INVALID_ARG, "k must be in [0, 4]");
+    case 5: launch_kernel(gather_kernel<6>, grid, block, 0, st, true, g); break;
+    default: throw Error(BBTN_E_INVALID_ARG, "k must be in [0, 5]");
   }
   BBTN_LAUNCHED("gather");
 }

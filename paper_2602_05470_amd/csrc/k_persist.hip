@@ -529,9 +529,10 @@ static void launch_nt(int k, const PersistArgs& a, int n_blocks, size_t lds, hip
     BBTN_PK(2)
     BBTN_PK(3)
     BBTN_PK(4)
+    BBTN_PK(5)
 #undef BBTN_PK
     default:
-      throw Error(BBTN_E_INVALID_ARG, "k must be in [0, 4]");
+      throw Error(BBTN_E_INVALID_ARG, "k must be in [0, 5]");
   }
 }
 

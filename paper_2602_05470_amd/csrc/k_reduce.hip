@@ -14,7 +14,7 @@
 //   tensor.  A branch is kept iff the bound is not below the incumbent; ties
 //   are kept because they carry counts.  Kept branch ids are compacted in
 //   ascending order.
-#include "kernels.h"
+#include "launch.h"
 
 namespace bbtn {
 
@@ -238,7 +238,8 @@ void launch_reduce(int k, const Moduli& mod, int64_t outer, int64_t S,
     case 2: reduce_dispatch<2>(a, st); break;
     case 3: reduce_dispatch<3>(a, st); break;
     case 4: reduce_dispatch<4>(a, st); break;
-    default: throw Error(BBTN_E_INVALID_ARG, "k must be in [0, 4]");
+    case 5: reduce_dispatch<5>(a, st); break;
+    default: throw Error(BBTN_E_INVALID_ARG, "k must be in [0, 5]");
   }
   BBTN_LAUNCHED("reduce");
 }
@@ -291,7 +292,8 @@ void launch_otimes(int k, const Moduli& mod, int64_t L, DevTensor a, DevTensor b
     case 2: hipLaunchKernelGGL(otimes_kernel<2>, dim3(blocks), dim3(256), 0, st, L, a.ptr, a.pstride, b.ptr, b.pstride, out.ptr, out.pstride, mod); break;
     case 3: hipLaunchKernelGGL(otimes_kernel<3>, dim3(blocks), dim3(256), 0, st, L, a.ptr, a.pstride, b.ptr, b.pstride, out.ptr, out.pstride, mod); break;
     case 4: hipLaunchKernelGGL(otimes_kernel<4>, dim3(blocks), dim3(256), 0, st, L, a.ptr, a.pstride, b.ptr, b.pstride, out.ptr, out.pstride, mod); break;
-    default: throw Error(BBTN_E_INVALID_ARG, "k must be in [0, 4]");
+    case 5: hipLaunchKernelGGL(otimes_kernel<5>, dim3(blocks), dim3(256), 0, st, L, a.ptr, a.pstride, b.ptr, b.pstride, out.ptr, out.pstride, mod); break;
+    default: throw Error(BBTN_E_INVALID_ARG, "k must be in [0, 5]");
   }
   BBTN_LAUNCHED("otimes");
 }

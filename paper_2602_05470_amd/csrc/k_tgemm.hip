@@ -18,7 +18,7 @@
 // sharing rows of A land in the same L2).
 #include <mutex>
 
-#include "kernels.h"
+#include "launch.h"
 
 namespace bbtn {
 
@@ -456,7 +456,8 @@ static void launch_thin(int k, const GemmArgs& a, hipStream_t st) {
     case 2: launch_kernel(tgemm_thin_kernel<2>, grid, block, 0, st, true, a, lm, ln, lk); break;
     case 3: launch_kernel(tgemm_thin_kernel<3>, grid, block, 0, st, true, a, lm, ln, lk); break;
     case 4: launch_kernel(tgemm_thin_kernel<4>, grid, block, 0, st, true, a, lm, ln, lk); break;
-    default: throw Error(BBTN_E_INVALID_ARG, "k must be in [0, 4]");
+    case 5: launch_kernel(tgemm_thin_kernel<5>, grid, block, 0, st, true, a, lm, ln, lk); break;
+    default: throw Error(BBTN_E_INVALID_ARG, "k must be in [0, 5]");
   }
   BBTN_LAUNCHED("tgemm (thin, grid " + std::to_string(total) + ")");
 }
@@ -592,17 +593,29 @@ __global__ void __launch_bounds__((TM / RM) * (TN / RN)) tgemm_v16_kernel(const 
 // slices.
 constexpr int V16_TM = 128, V16_TN = 128, V16_RM = 8, V16_RN = 8, V16_TK = 32;
 
+// LDS slice depth for KR residues: the configuration's TK, halved while the
+// tile's operand slices (values and KR residue planes) would pass 64 KiB.
+constexpr int tk_for(int KR, int TM, int TN, int TK) {
+  const int kp = KR > 0 ? KR : 1;
+  const int tmp = TM >= 8 ? TM + 4 : TM;
+  int tk = TK;
+  while ((1 + kp) * tk * (tmp + TN) * 4 > 65536) tk /= 2;
+  return tk;
+}
+
 template <int KR>
 static void launch_cfg(int cfg, dim3 grid, const GemmArgs& a, hipStream_t st, bool last) {
   switch (cfg) {
 #define BBTN_TG_CASE(I, TM, TN, RM, RN, TK, VEC)                                  \
-  case I:                                                                          \
+  case I: {                                                                        \
+    constexpr int TKK = tk_for(KR, TM, TN, TK);                                    \
     if (a.total == (int64_t)grid.x)                                                \
-      launch_kernel((tgemm_kernel<KR, TM, TN, RM, RN, TK, VEC>), grid,              \
+      launch_kernel((tgemm_kernel<KR, TM, TN, RM, RN, TKK, VEC>), grid,             \
                     dim3((TM / RM) * (TN / RN)), 0, st, last, a);                  \
     else                                                                           \
-      launch_kernel((tgemm_kernel_strided<KR, TM, TN, RM, RN, TK, VEC>), grid,      \
+      launch_kernel((tgemm_kernel_strided<KR, TM, TN, RM, RN, TKK, VEC>), grid,     \
                     dim3((TM / RM) * (TN / RN)), 0, st, last, a);                  \
+  }                                                                                \
     break;
     BBTN_TG_CASE(0, 64, 64, 4, 4, 24, false)
     BBTN_TG_CASE(1, 32, 32, 2, 2, 24, false)
@@ -646,7 +659,8 @@ static void launch_core(int k, const GemmArgs& a0, int cfg, hipStream_t st, bool
     case 2: launch_cfg<2>(cfg, grid, a, st, last); break;
     case 3: launch_cfg<3>(cfg, grid, a, st, last); break;
     case 4: launch_cfg<4>(cfg, grid, a, st, last); break;
-    default: throw Error(BBTN_E_INVALID_ARG, "k must be in [0, 4]");
+    case 5: launch_cfg<5>(cfg, grid, a, st, last); break;
+    default: throw Error(BBTN_E_INVALID_ARG, "k must be in [0, 5]");
   }
   BBTN_LAUNCHED("tgemm (tile config " + std::to_string(cfg) + ", k " + std::to_string(k) +
                 ", grid " + std::to_string(total) + ")");

@@ -1,7 +1,6 @@
 // Host-side launchers of the HIP kernels.  All launches are asynchronous on
 // the given stream; shapes are validated by the callers.
 #pragma once
-#include <hip/hip_ext.h>
 #include "common.h"
 
 namespace bbtn {
@@ -14,23 +13,7 @@ namespace bbtn {
 struct TimedLaunch {
   hipEvent_t start = nullptr, stop = nullptr;
 };
-TimedLaunch& timed_launch();  // this host thread's slot
-
-// Launch `kernel`; `last` marks the final kernel of the operation being
-// timed (it takes the stop event).
-template <class F, class... Args>
-inline void launch_kernel(F kernel, dim3 grid, dim3 block, uint32_t shm, hipStream_t st,
-                          bool last, Args... args) {
-  TimedLaunch& t = timed_launch();
-  hipEvent_t a = t.start, b = last ? t.stop : nullptr;
-  if (a || b) {
-    t.start = nullptr;
-    if (last) t.stop = nullptr;
-    hipExtLaunchKernelGGL(kernel, grid, block, shm, st, a, b, 0u, args...);
-  } else {
-    hipLaunchKernelGGL(kernel, grid, block, shm, st, args...);
-  }
-}
+TimedLaunch& timed_launch();  // this host thread's slot (launch_kernel in launch.h)
 
 // Tile shape of the counting tropical GEMM: TM x TN outputs per workgroup,
 // RM x RN per thread, TK-deep LDS stages.

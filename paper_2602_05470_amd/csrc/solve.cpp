@@ -498,7 +498,7 @@ void solve_instances(bbtn_ctx* ctx, std::vector<Instance>& insts) {
     for (int i = 0; i < 8; ++i) in.res->seconds[i] = 0;
   const bool branch = opt.branching != 0 && opt.log2_target > 0;
   const bool values_only = opt.residues_per_pass == 0;
-  const int k = values_only ? 0 : std::max(1, std::min(KMAX, opt.residues_per_pass));
+  const int k = values_only ? 0 : std::max(1, std::min(KUSER, opt.residues_per_pass));
   const int max_primes = std::max(k, std::min(BBTN_MAX_PRIMES, opt.max_primes));
   const auto& P = prime_table();
   // ---- planning: order, search and step programs, instances in parallel
