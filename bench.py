@@ -4,7 +4,8 @@ Headline workload (the largest configuration the solver reaches on one GPU):
 +-J spin glass on a 32 x 32 open-boundary lattice, couplings +-1 from numpy
 seeds 0-19, zero field.  BBTN with T_target = 2^26 entries, the contraction
 order refined by annealing (chosen once for the lattice during the warm-up
-and cached), the spin-flip symmetry of the zero-field energy (one spin fixed
+and cached), the learned branching scorer (its candidate variables added to
+the planner's), the spin-flip symmetry of the zero-field energy (one spin fixed
 to +1, the count doubled: half the contraction work), counts as residues
 modulo 3 primes per pass plus one fused certification prime.  One step = one call through the C ABI that fully
 solves one instance: network build, order lookup, search, values-only pass,
@@ -525,6 +526,9 @@ def main():
     ap.add_argument("--residues", type=int, default=3,
                     help="residues per pass of the headline run (a further certification "
                          "prime is fused into the pass)")
+    ap.add_argument("--branching", type=int, default=2,
+                    help="branching rule of the headline run: 1 plain planner, 2 learned "
+                         "scorer (shipped spin-glass weights) with the planner's candidates")
     ap.add_argument("--ksg-seeds", type=int, default=8,
                     help="seeds of the 40x40 King's subgraph leg (0 .. n-1)")
     ap.add_argument("--micro-only", action="store_true",
@@ -563,8 +567,10 @@ def main():
     ncpu = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
     # ---- headline: +-J 32x32
     sg32 = golden_values("sg32_values.txt")
-    head_opts = B.Options(log2_target=26, residues_per_pass=args.residues, branching=1, batched=1,
-                          order_refine=8, time_limit_s=600, spin_flip=1)
+    scorer_sg = os.path.join(ROOT, "paper_2602_05470_amd", "scorer_sg.bin")
+    head_opts = B.Options(log2_target=26, residues_per_pass=args.residues,
+                          branching=args.branching, batched=1, order_refine=8, time_limit_s=600,
+                          spin_flip=1, scorer_weights=scorer_sg if args.branching == 2 else None)
     seeds = [i % 20 for i in range(args.steps)]
     warm = [20 + i for i in range(args.warmup)]
     h = single_instance_run(B, I, torch, 0, 32, head_opts, seeds, warm, sg32, "sg32x32")
@@ -584,15 +590,17 @@ def main():
         "data": "synthetic",
         "config": {"workload": "+-J spin glass 32x32 open lattice, seeds 0-19 (step i solves "
                                "seed i mod 20), zero field; BBTN T_target=2^26, refined "
-                               "contraction order, plain planner, spin-flip symmetry (one "
+                               "contraction order, %s, spin-flip symmetry (one "
                                "spin fixed, count doubled), %d primes per pass plus a fused "
                                "certification prime; one step = one call solving one "
-                               "instance" % args.residues,
+                               "instance" % ("learned branching scorer" if args.branching == 2
+                                             else "plain planner", args.residues),
                    "instances": h["n"], "exact": h["exact"],
                    "leaves_per_instance": h["leaves_per_instance"],
                    "macs_per_instance": h["macs_per_instance"],
                    "log2_target": 26, "residues_per_pass": args.residues, "contraction_order":
-                   "refined (8 candidates, chosen in the warm-up)", "branching": "plain planner",
+                   "refined (8 candidates, chosen in the warm-up)",
+                   "branching": "learned scorer" if args.branching == 2 else "plain planner",
                    "exactness": "certified count, E0 equal to the matching oracle's stored "
                                 "value, even degeneracy, configuration reaching E0"},
         "roofline": roofline_of(h["stats"], dt, kernel_traffic),

@@ -607,25 +607,25 @@ struct Searcher {
       heuristic(cur, heur, cand);
       if (cand.empty()) throw Error(BBTN_E_INTERNAL, "rho > 0 but no overflowing variable");
       // seeds: the heuristic's two best candidates; with the learned
-      // scorer, its best candidate and the heuristic's best (the scorer
-      // ranks seeds only; regions always grow in the heuristic's order,
-      // the order its training labels were measured with)
+      // scorer, also its two best (the scorer ranks seeds only; regions
+      // always grow in the heuristic's order, the order its training labels
+      // were measured with).  The lowest gamma over all seeds wins, so the
+      // scorer's picks add to the heuristic's and never displace them.
       std::stable_sort(cand.begin(), cand.end(), [&](int a, int b) {
         if (heur[a] != heur[b]) return heur[a] > heur[b];
         return a < b;
       });
       std::vector<int32_t> seeds;
+      for (int si = 0; si < std::min<int>(2, (int)cand.size()); ++si) seeds.push_back(cand[si]);
       if (opt.scorer) {
         score = heur;
         opt.scorer(cur.fixed, cur.sizes, heur, score);
         std::vector<int32_t> by_score(cand);
         std::stable_sort(by_score.begin(), by_score.end(),
                          [&](int a, int b) { return score[a] > score[b]; });
-        seeds.push_back(by_score[0]);
-        if (cand[0] != by_score[0]) seeds.push_back(cand[0]);
-        else if (by_score.size() > 1) seeds.push_back(by_score[1]);
-      } else {
-        for (int si = 0; si < std::min<int>(2, (int)cand.size()); ++si) seeds.push_back(cand[si]);
+        for (int si = 0; si < std::min<int>(2, (int)by_score.size()); ++si)
+          if (std::find(seeds.begin(), seeds.end(), by_score[si]) == seeds.end())
+            seeds.push_back(by_score[si]);
       }
       for (int sd : seeds) {
         Eval ev = best_from_seed(cur, sd, heur);
