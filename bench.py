@@ -32,7 +32,9 @@ The JSON line also carries
                  stored exact degeneracies, with its own roofline (persistent
                  executor), refined-order and per-branch legs and the exact
                  C transfer matrix as its CPU baseline;
-  tgemm_micro:   the counting tropical product alone at large shapes.
+  tgemm_micro:   the counting tropical product alone at large shapes;
+  gather_micro:  the permutation kernel alone (a copy and a transposition of
+                 a 1 GiB tensor) against the HBM peak.
 
 --large N prints instead exact solves of N seeds of the 32 x 32 spin glass
 and the 40 x 40 King's subgraph, by the plain planner and the learned scorer.
@@ -160,6 +162,33 @@ def tgemm_micro(B, ctx, torch):
         res.append({"shape_bMNK": [b, M, N, K], "k": k,
                     "ms": round(1e3 * st["seconds"] / max(st["launches"], 1), 3),
                     "Gop_s": round(ops / 1e9, 1), "frac_valu": round(ops / VALU_PEAK_OPS, 4)})
+    return res
+
+
+def gather_micro(B, ctx, torch):
+    """The permutation kernel alone on a 2^26-entry tensor with 3 residue
+    planes (1 GiB in, 1 GiB out): the identity (direct kernel, a plain copy)
+    and the transposition of its low and high 13 bits (LDS-tiled kernel),
+    against the HBM peak."""
+    k, r = 3, 26
+    n = 1 << r
+    inp = torch.arange((1 + k) * n, dtype=torch.int32, device="cuda")
+    out = torch.empty_like(inp)
+    res = []
+    for name, src in (("identity", list(range(r))),
+                      ("transpose 13|13", list(range(13, 26)) + list(range(13)))):
+        ctx.gather(k, r, r, src, 1, 0, None, inp, n, out)
+        torch.cuda.synchronize()
+        ctx.profile(True, kernels=("gather",))
+        for _ in range(3):
+            ctx.gather(k, r, r, src, 1, 0, None, inp, n, out)
+        torch.cuda.synchronize()
+        st = ctx.kernel_stats("gather")
+        ctx.profile(False)
+        bw = 2.0 * (1 + k) * 4 * n * st["launches"] / max(st["seconds"], 1e-12)
+        res.append({"permutation": name, "entries": n, "planes": 1 + k,
+                    "ms": round(1e3 * st["seconds"] / max(st["launches"], 1), 3),
+                    "GB_s": round(bw / 1e9, 1), "frac_hbm": round(bw / HBM_PEAK, 4)})
     return res
 
 
@@ -554,12 +583,14 @@ def main():
     if args.micro_only:
         ctx = B.Context(B.Options())
         res = tgemm_micro(B, ctx, torch)
+        gres = gather_micro(B, ctx, torch)
         x = torch.ones(128 << 20, dtype=torch.int32, device="cuda")
         y = torch.empty_like(x)
         y.copy_(x)
         torch.cuda.synchronize()
         ctx.close()
-        print(json.dumps({"tgemm_micro": res, "copy_bytes_each_way": 512 << 20}), flush=True)
+        print(json.dumps({"tgemm_micro": res, "gather_micro": gres,
+                          "copy_bytes_each_way": 512 << 20}), flush=True)
         return
     if args.large > 0:
         print(json.dumps(large_configs(B, I, torch, args.large)), flush=True)
@@ -634,6 +665,7 @@ def main():
     if not args.no_micro:
         ctx = B.Context(B.Options())
         line["tgemm_micro"] = tgemm_micro(B, ctx, torch)
+        line["gather_micro"] = gather_micro(B, ctx, torch)
         ctx.close()
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline_sg32()

@@ -57,6 +57,23 @@ def sg32x24():
             f.flush()
 
 
+def strips():
+    """+-J spin glass strips as long as the 48x48 and 64x64 lattices (48x20
+    and 64x16, rows x columns), seeds 0-1: exact values for parity cases of
+    branching along the long dimension (C transfer matrix over the narrow
+    frontier)."""
+    for Lr, Lc in ((48, 20), (64, 16)):
+        with open(os.path.join(HERE, "sg%dx%d.txt" % (Lr, Lc)), "w") as f:
+            f.write("# +-J spin glass %dx%d open lattice (%d rows, %d columns), zero field, "
+                    "seeds 0-1:\n" % (Lr, Lc, Lr, Lc))
+            f.write("# seed E0 degeneracy  (oracle: exact transfer matrix, C)\n")
+            for s in range(2):
+                g = I.spin_glass_rect(Lr, Lc, s)
+                e0, deg = tm_c.spin_glass_lattice(Lr, Lc, g["edges"], g["J"])
+                f.write("%d %d %d\n" % (s, e0, deg))
+                f.flush()
+
+
 def _values(name, header, rows):
     with open(os.path.join(HERE, name), "w") as f:
         f.write(header)
@@ -127,6 +144,7 @@ def main():
     ksg64_values()
     larger()
     sg32x24()
+    strips()
     sg16_more()
     with open(os.path.join(HERE, "sg16.txt"), "w") as f:
         f.write("# +-J spin glass 16x16 open lattice, zero field, seeds 0-19:\n")
