@@ -558,6 +558,10 @@ def main():
     ap.add_argument("--branching", type=int, default=2,
                     help="branching rule of the headline run: 1 plain planner, 2 learned "
                          "scorer (shipped spin-glass weights) with the planner's candidates")
+    ap.add_argument("--autotune", default=None,
+                    help="tile autotuner cache file for the headline run (products of 2^24 "
+                         "MACs or more are timed over the tile candidates on first use, in "
+                         "the warm-up)")
     ap.add_argument("--ksg-seeds", type=int, default=8,
                     help="seeds of the 40x40 King's subgraph leg (0 .. n-1)")
     ap.add_argument("--micro-only", action="store_true",
@@ -601,7 +605,8 @@ def main():
     scorer_sg = os.path.join(ROOT, "paper_2602_05470_amd", "scorer_sg.bin")
     head_opts = B.Options(log2_target=26, residues_per_pass=args.residues,
                           branching=args.branching, batched=1, order_refine=8, time_limit_s=600,
-                          spin_flip=1, scorer_weights=scorer_sg if args.branching == 2 else None)
+                          spin_flip=1, scorer_weights=scorer_sg if args.branching == 2 else None,
+                          autotune_cache=args.autotune)
     seeds = [i % 20 for i in range(args.steps)]
     warm = [20 + i for i in range(args.warmup)]
     h = single_instance_run(B, I, torch, 0, 32, head_opts, seeds, warm, sg32, "sg32x32")

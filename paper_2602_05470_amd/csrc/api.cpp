@@ -360,8 +360,11 @@ bbtn_status bbtn_gather(bbtn_ctx* ctx, int32_t k, int32_t r_in, int32_t r_out,
     BBTN_REQUIRE(in_entries >= (in_stride == 0 ? sz : L * sz), "input buffer too small");
     BBTN_HIP(hipSetDevice(ctx->opt.device));
     const GatherPlan gp = make_gather_plan(r_in, r_out, src_bits);
+    hipStream_t st = pick_stream(ctx, stream);
+    const int ph = ctx->prof.begin(st, K_GATHER);
     launch_gather(k, gp, L, in_stride, fixed_bits, DevTensor{(uint32_t*)in, in_entries},
-                  DevTensor{(uint32_t*)out, L << r_out}, pick_stream(ctx, stream));
+                  DevTensor{(uint32_t*)out, L << r_out}, st);
+    ctx->prof.end(ph, st, K_GATHER, 0, 2.0 * (1 + k) * 4 * (double)(L << r_out));
   });
 }
 

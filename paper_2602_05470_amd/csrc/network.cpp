@@ -139,6 +139,32 @@ Network build_mwis(int32_t n, int32_t m, const int32_t* uv, const int32_t* w) {
     net.tensors.push_back(std::move(t));
   }
   for (int p = 0; p < NP; ++p) net.const_res[p] = 1;
+  // clique partition: each vertex in id order, with every later unassigned
+  // neighbour adjacent to all members taken so far
+  auto g = std::make_shared<MisGraph>();
+  g->adj.assign(n, {});
+  for (auto& e : es) {
+    g->adj[e.first].push_back(e.second);
+    g->adj[e.second].push_back(e.first);
+  }
+  for (auto& a : g->adj) std::sort(a.begin(), a.end());
+  g->w.resize(n);
+  for (int i = 0; i < n; ++i) g->w[i] = w ? w[i] : 1;
+  std::vector<char> taken(n, 0);
+  for (int v = 0; v < n; ++v) {
+    if (taken[v]) continue;
+    std::vector<int32_t> q{v};
+    taken[v] = 1;
+    for (int u : g->adj[v]) {
+      if (taken[u]) continue;
+      bool all = true;
+      for (int x : q)
+        if (x != v && !std::binary_search(g->adj[u].begin(), g->adj[u].end(), x)) { all = false; break; }
+      if (all) { q.push_back(u); taken[u] = 1; }
+    }
+    g->cliques.push_back(std::move(q));
+  }
+  net.mis = std::move(g);
   simplify(net);
   flatten(net);
   return net;

@@ -3,6 +3,7 @@
 // vertex vectors w^i, bond index s_i shared by every tensor touching i).
 #pragma once
 #include <array>
+#include <memory>
 #include <vector>
 #include "common.h"
 
@@ -42,6 +43,15 @@ struct PeelRec {
   std::vector<int32_t> tval;
 };
 
+// The graph of an independent-set instance, kept for a bound the tensors do
+// not give: a partition of the vertices into cliques (an independent set
+// holds at most one vertex of each), built greedily.
+struct MisGraph {
+  std::vector<std::vector<int32_t>> adj;      // neighbours, ascending
+  std::vector<int64_t> w;                     // vertex weights
+  std::vector<std::vector<int32_t>> cliques;  // disjoint, covering every vertex
+};
+
 struct Network {
   int32_t n = 0;
   bool spin = true;                 // spin glass (true) or MWIS (false)
@@ -51,7 +61,8 @@ struct Network {
   bool infeasible = false;
   std::vector<PeelRec> peel;        // in elimination order
   int64_t abs_sum = 0;              // sum |J| + |h| (or sum w)
-  bool zero_field = false;          // spin glass without fields: H(sigma) = H(-sigma)
+  bool zero_field = false;
+  std::shared_ptr<const MisGraph> mis;  // independent-set instances only          // spin glass without fields: H(sigma) = H(-sigma)
   // every tensor's entries back to back, in tensor order: the value plane
   // then the residue planes of the first NP_FLAT primes (flat_total entries
   // each), for uploads of whole planes

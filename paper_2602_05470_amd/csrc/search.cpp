@@ -69,6 +69,36 @@ int64_t node_bound(const Network& net, const std::vector<uint64_t>& fixed,
   return b;
 }
 
+int64_t clique_bound(const Network& net, const std::vector<uint64_t>& fixed,
+                     const std::vector<uint8_t>& x) {
+  if (!net.mis) return INT64_MAX;
+  const MisGraph& g = *net.mis;
+  const int n = (int)g.w.size();
+  // a vertex can still join the set iff it is free and no neighbour is in
+  std::vector<char> out(n, 0);
+  int64_t b = 0;
+  for (int v = 0; v < n; ++v) {
+    if (!bit_get(fixed, v)) continue;
+    out[v] = 1;
+    if (x[v] & 1) {
+      b += g.w[v];
+      for (int u : g.adj[v]) out[u] = 1;
+    }
+  }
+  // at most one vertex of each clique; a clique holding a chosen vertex
+  // adds nothing more
+  for (const auto& q : g.cliques) {
+    int64_t best = 0;
+    bool has = false;
+    for (int v : q) {
+      if (bit_get(fixed, v) && (x[v] & 1)) { has = true; break; }
+      if (!out[v]) best = std::max(best, g.w[v]);
+    }
+    if (!has) b += best;
+  }
+  return b;
+}
+
 int32_t flip_variable(const Network& net, const Tree& tree, int log2_target) {
   if (net.n <= 0) return -1;
   std::vector<double> over(net.n, 0.0), mac(net.n, 0.0);
@@ -682,7 +712,11 @@ struct Searcher {
         const int64_t m = tmax(tt[i], cur.fixed, cur.x);
         b = (m == INT64_MIN) ? INT64_MIN : b + (m - base_max[i]);
       }
-      if (b == INT64_MIN || b < opt.incumbent || (opt.values_only && b == opt.incumbent)) {
+      // the node keeps its tensor bound (later bounds update it in place);
+      // an independent-set network may also be pruned by the clique bound
+      int64_t bp = b;
+      if (b != INT64_MIN && net.mis) bp = std::min(b, clique_bound(net, cur.fixed, cur.x));
+      if (bp == INT64_MIN || bp < opt.incumbent || (opt.values_only && bp == opt.incumbent)) {
         st.pruned++;
       } else {
         // sizes follow the fixed set for a node that branches again; a leaf
@@ -716,8 +750,9 @@ struct Searcher {
     cur.sizes = node_sizes(tree, cur.fixed);
     cur.rho = rho_of(tree, cur.sizes, opt.log2_target);
     cur.bound = node_bound(net, cur.fixed, cur.x);
-    if (cur.bound < opt.incumbent || cur.bound == INT64_MIN ||
-        (opt.values_only && cur.bound == opt.incumbent)) {
+    int64_t bp = cur.bound;
+    if (bp != INT64_MIN && net.mis) bp = std::min(bp, clique_bound(net, cur.fixed, cur.x));
+    if (bp < opt.incumbent || bp == INT64_MIN || (opt.values_only && bp == opt.incumbent)) {
       st.pruned++;
       return;
     }
@@ -888,6 +923,95 @@ std::vector<uint8_t> local_search_spinglass(int32_t n, int32_t m, const int32_t*
   return x;
 }
 
+// Iterated local search on an independent set (the swap moves and
+// perturbations of Andrade, Resende and Werneck, 2012, in weighted form):
+// insert free vertices (no neighbour in the set); replace a set vertex v by
+// one or two non-adjacent neighbours whose only set neighbour is v when
+// that adds weight; then perturb by forcing a random outside vertex in
+// (dropping its set neighbours), re-optimise, and keep the result when it
+// is no lighter.  x and W are updated to the best set found.
+static void improve_independent_set(const std::vector<std::vector<int>>& adj,
+                                    const int32_t* w, std::vector<uint8_t>& x, int64_t& W,
+                                    int iterations, std::mt19937_64& rng) {
+  const int n = (int)adj.size();
+  if (n == 0) return;
+  auto wt = [&](int v) -> int64_t { return w ? w[v] : 1; };
+  std::vector<int> tau(n, 0);  // set neighbours of each vertex
+  for (int v = 0; v < n; ++v)
+    if (x[v])
+      for (int u : adj[v]) tau[u]++;
+  auto ins = [&](int v) {
+    x[v] = 1;
+    W += wt(v);
+    for (int u : adj[v]) tau[u]++;
+  };
+  auto del = [&](int v) {
+    x[v] = 0;
+    W -= wt(v);
+    for (int u : adj[v]) tau[u]--;
+  };
+  auto adjacent = [&](int a, int b) {
+    const auto& A = adj[a].size() < adj[b].size() ? adj[a] : adj[b];
+    const int o = adj[a].size() < adj[b].size() ? b : a;
+    return std::find(A.begin(), A.end(), o) != A.end();
+  };
+  std::vector<int> cand;
+  auto local_opt = [&]() {
+    for (bool again = true; again;) {
+      again = false;
+      for (int v = 0; v < n; ++v)
+        if (!x[v] && tau[v] == 0) ins(v);
+      for (int v = 0; v < n; ++v) {
+        if (!x[v]) continue;
+        cand.clear();
+        for (int u : adj[v])
+          if (!x[u] && tau[u] == 1) cand.push_back(u);
+        int b1 = -1, b2 = -1;
+        int64_t gain = 0;
+        for (size_t i = 0; i < cand.size(); ++i) {
+          if (wt(cand[i]) - wt(v) > gain) { gain = wt(cand[i]) - wt(v); b1 = cand[i]; b2 = -1; }
+          for (size_t j = i + 1; j < cand.size(); ++j)
+            if (wt(cand[i]) + wt(cand[j]) - wt(v) > gain && !adjacent(cand[i], cand[j])) {
+              gain = wt(cand[i]) + wt(cand[j]) - wt(v);
+              b1 = cand[i];
+              b2 = cand[j];
+            }
+        }
+        if (b1 < 0) continue;
+        del(v);
+        ins(b1);
+        if (b2 >= 0) ins(b2);
+        again = true;
+      }
+    }
+  };
+  local_opt();
+  std::vector<uint8_t> best = x;
+  int64_t bestW = W;
+  std::vector<uint8_t> keep;
+  for (int it = 0; it < iterations; ++it) {
+    keep = x;
+    const int64_t W0 = W;
+    int u = (int)(rng() % (uint64_t)n);
+    for (int t = 0; t < n && x[u]; ++t) u = (u + 1) % n;
+    if (x[u]) break;
+    for (int nb : adj[u])
+      if (x[nb]) del(nb);
+    ins(u);
+    local_opt();
+    if (W < W0) {
+      // restore the previous set and its neighbour counts
+      for (int v = 0; v < n; ++v)
+        if (x[v] != keep[v]) (keep[v] ? ins(v) : del(v));
+    } else if (W > bestW) {
+      bestW = W;
+      best = x;
+    }
+  }
+  x = best;
+  W = bestW;
+}
+
 std::vector<uint8_t> local_search_mwis(int32_t n, int32_t m, const int32_t* uv,
                                        const int32_t* w, int restarts, uint64_t seed) {
   std::vector<std::vector<int>> adj(n);
@@ -915,6 +1039,7 @@ std::vector<uint8_t> local_search_mwis(int32_t n, int32_t m, const int32_t* uv,
       W += w ? w[i] : 1;
       for (int j : adj[i]) blocked[j] = 1;
     }
+    improve_independent_set(adj, w, x, W, 200, rng);
     if (W > bestW) { bestW = W; best = x; }
   }
   return best;

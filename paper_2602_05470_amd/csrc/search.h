@@ -69,6 +69,14 @@ int64_t node_bound(const Network& net, const std::vector<uint64_t>& fixed,
 // -1 for a network without variables.
 int32_t flip_variable(const Network& net, const Tree& tree, int log2_target);
 
+// Upper bound on the weight of an independent set that agrees with the
+// fixed states (independent-set networks; INT64_MAX otherwise): the fixed
+// vertices in the set, plus, per clique of the network's clique partition,
+// the largest weight of a vertex that can still join (free, no neighbour in
+// the set); nothing for a clique that already holds a vertex of the set.
+int64_t clique_bound(const Network& net, const std::vector<uint64_t>& fixed,
+                     const std::vector<uint8_t>& x);
+
 // rho of Eq. 4 given per-internal-node free-variable counts.
 int64_t rho_of(const Tree& t, const std::vector<int16_t>& sizes, int log2_target);
 
