@@ -96,10 +96,14 @@ typedef struct {
                                 concurrently share the host's cores.          */
   int32_t order_refine;      /* 0: greedy contraction order; n > 0: also n
                                 annealed refinements of it (local rotations),
+                                the min-fill order and one refinement of that,
                                 each scored by a branch-and-bound search of the
                                 first instance of a structure; the cheapest
                                 (leaf MACs plus search nodes) is cached for the
-                                structure.  n <= 64.                           */
+                                structure.  n <= 64.  -1: the min-fill order
+                                alone (a min-fill elimination order of the
+                                variables, tensors holding each eliminated
+                                variable contracted pairwise).                */
   uint64_t device_mem_cap;   /* bytes of device memory the context (with its
                                 configuration-recovery context) may hold;
                                 branch chunks are sized to it, and a solve
@@ -356,7 +360,8 @@ bbtn_status bbtn_solve_batch(bbtn_ctx* ctx, int32_t kind, int32_t n_inst, const 
 /* The planner alone, on the host (ctx may be NULL; no device is used): build
  * the network of a spin-glass (kind 0: weights = J, h) or MWIS (kind 1:
  * weights = w, h unused) instance, choose its contraction order (as the
- * option order_refine does, with order_refine in [0, 64]; 0 = greedy), take
+ * option order_refine does, with order_refine in [-1, 64]; 0 = greedy,
+ * -1 = min-fill), take
  * the local-search incumbent (local_search sweeps; 0 = no incumbent) and run
  * the branch-and-bound search with T_target = 2^log2_target and regions of
  * at most region_max variables ("Branch-and-Bound Tensor Network" section).
@@ -375,8 +380,9 @@ bbtn_status bbtn_plan_leaves(bbtn_ctx* ctx, int32_t kind, int32_t n, int32_t m,
 
 /* Complexity of the contraction order the planner uses for an instance
  * (host only, no context; "Tropical Tensor Networks" section): the order is
- * chosen as bbtn_options.order_refine does (0: greedy; n in [1, 64]: the
- * cheapest of the greedy tree and n annealed refinements, each scored by a
+ * chosen as bbtn_options.order_refine does (0: greedy; -1: min-fill;
+ * n in [1, 64]: the cheapest of the greedy tree, n annealed refinements,
+ * the min-fill tree and one refinement of it, each scored by a
  * branch-and-bound search with T_target = 2^log2_target and regions of at
  * most region_max variables).  Outputs: *tc_log2 = log2 of the semiring
  * multiply-accumulates of the unsliced contraction, *sc = log2 entries of

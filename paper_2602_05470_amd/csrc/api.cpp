@@ -464,7 +464,7 @@ bbtn_status bbtn_plan_leaves(bbtn_ctx* ctx, int32_t kind, int32_t n, int32_t m,
     check_graph(n, m, edge_uv);
     BBTN_REQUIRE(kind == 0 || kind == 1, "kind must be 0 (spin glass) or 1 (MWIS)");
     BBTN_REQUIRE(log2_target > 0 && region_max >= 1 && local_search >= 0, "bad options");
-    BBTN_REQUIRE(order_refine >= 0 && order_refine <= 64, "order_refine must be in [0, 64]");
+    BBTN_REQUIRE(order_refine >= -1 && order_refine <= 64, "order_refine must be in [-1, 64]");
     if (kind == 0) BBTN_REQUIRE(weights != nullptr, "J is NULL");
     Network net = kind == 0 ? build_spinglass(n, m, edge_uv, weights, h)
                             : build_mwis(n, m, edge_uv, weights);
@@ -512,7 +512,7 @@ bbtn_status bbtn_order_complexity(int32_t kind, int32_t n, int32_t m, const int3
     check_graph(n, m, edge_uv);
     BBTN_REQUIRE(kind == 0 || kind == 1, "kind must be 0 (spin glass) or 1 (MWIS)");
     BBTN_REQUIRE(log2_target > 0 && region_max >= 1, "bad options");
-    BBTN_REQUIRE(order_refine >= 0 && order_refine <= 64, "order_refine must be in [0, 64]");
+    BBTN_REQUIRE(order_refine >= -1 && order_refine <= 64, "order_refine must be in [-1, 64]");
     if (kind == 0) BBTN_REQUIRE(weights != nullptr, "J is NULL");
     Network net = kind == 0 ? build_spinglass(n, m, edge_uv, weights, h)
                             : build_mwis(n, m, edge_uv, weights);

@@ -1056,18 +1056,24 @@ std::vector<uint8_t> local_search_mwis(int32_t n, int32_t m, const int32_t* uv,
 // zero-field +-J lattices the leaves and MACs depend on the structure only,
 // so one instance's probe serves every instance of that structure.
 Tree choose_order(const Network& net, int n, const SearchOptions& probe, bool* complete) {
-  n = std::max(0, std::min(64, n));
   if (complete) *complete = true;
+  if (n < 0) return minfill_tree(net);
+  n = std::min(64, n);
   if (n == 0) return greedy_tree(net);
   constexpr double kNodeMacs = 131072.0;  // host time of a search node, in device MACs
-  std::vector<Tree> cand(n + 1);
-  std::vector<double> score(n + 1, HUGE_VAL);
-  std::vector<char> done(n + 1, 0);
+  // candidates: the greedy tree, its n refinements, the min-fill tree and
+  // one refinement of it
+  const int nc = n + 3;
+  std::vector<Tree> cand(nc);
+  std::vector<double> score(nc, HUGE_VAL);
+  std::vector<char> done(nc, 0);
   cand[0] = greedy_tree(net);  // built before any thread reads it
+  cand[n + 1] = minfill_tree(net);
   auto late = [&] { return probe.deadline > 0 && now_s() > probe.deadline; };
   {
     std::vector<std::thread> th;
-    for (int c = 1; c <= n; ++c)
+    for (int c = 1; c <= n + 2; ++c) {
+      if (c == n + 1) continue;
       th.emplace_back([&, c] {
         RefineOptions o;
         o.sweeps = 200;
@@ -1075,8 +1081,9 @@ Tree choose_order(const Network& net, int n, const SearchOptions& probe, bool* c
         o.rho_weight = 0.25;
         o.seed = (uint64_t)c;
         o.deadline = probe.deadline;
-        cand[c] = refine_tree(net, cand[0], o);
+        cand[c] = refine_tree(net, c <= n ? cand[0] : cand[n + 1], o);
       });
+    }
     for (auto& t : th) t.join();
   }
   // Probes run in rounds of growing node budgets, 2^10, 2^12, ... 2^22: a
@@ -1091,7 +1098,7 @@ Tree choose_order(const Network& net, int n, const SearchOptions& probe, bool* c
     SearchOptions so = probe;
     so.node_limit = &limit;
     std::vector<std::thread> th;
-    for (int c = 0; c <= n; ++c)
+    for (int c = 0; c < nc; ++c)
       th.emplace_back([&, c] {
         std::vector<LeafGroup> groups;
         SearchStats st;
@@ -1113,7 +1120,7 @@ Tree choose_order(const Network& net, int n, const SearchOptions& probe, bool* c
     for (auto& t : th) t.join();
     if (late()) break;
     int best = -1;
-    for (int c = 0; c <= n; ++c)
+    for (int c = 0; c < nc; ++c)
       if (done[c] && (best < 0 || score[c] < score[best])) best = c;
     if (best >= 0) return std::move(cand[best]);
   }

@@ -58,7 +58,8 @@ TreeRef tree_for(bbtn_ctx* ctx, const Network& net, const SearchOptions* probe) 
   try {
     bool complete = true;
     auto tree = std::make_shared<const Tree>(
-        refine ? choose_order(net, ctx->opt.order_refine, *probe, &complete) : greedy_tree(net));
+        refine ? choose_order(net, ctx->opt.order_refine, *probe, &complete)
+               : (ctx->opt.order_refine < 0 ? minfill_tree(net) : greedy_tree(net)));
     std::lock_guard<std::mutex> lk(ctx->tree_mu);
     TreeRef r;
     auto it = ctx->tree_cache.find(shape);

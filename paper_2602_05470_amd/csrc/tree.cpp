@@ -4,6 +4,7 @@
 #include <cmath>
 #include <queue>
 #include <random>
+#include <set>
 #include <tuple>
 
 namespace bbtn {
@@ -126,6 +127,134 @@ Tree greedy_tree(const Network& net) {
   return t;
 }
 
+
+// Min-fill elimination order turned into a pairwise tree.  The interaction
+// graph joins variables that share a tensor; each step eliminates the
+// variable whose elimination adds the fewest edges among its neighbours
+// (fewest neighbours, then lowest id, on ties), and the tree contracts the
+// tensors holding it, two at a time, smallest result first, so that the
+// variable is summed out as soon as its last holder is formed.  On planar
+// grids this follows the separators of the lattice, where the greedy pair
+// order (smallest size increase first) can leave a much wider frontier.
+Tree minfill_tree(const Network& net) {
+  Tree t;
+  const int T = (int)net.tensors.size();
+  const int n = net.n;
+  t.n_base = T;
+  t.nodes.resize(T);
+  std::vector<std::vector<int32_t>> hold(n);
+  std::vector<std::set<int32_t>> g(n);
+  for (int i = 0; i < T; ++i) {
+    t.nodes[i].base = i;
+    t.nodes[i].vars = net.tensors[i].vars;
+    const auto& vs = t.nodes[i].vars;
+    for (int v : vs) hold[v].push_back(i);
+    for (size_t a = 0; a < vs.size(); ++a)
+      for (size_t b = a + 1; b < vs.size(); ++b) {
+        g[vs[a]].insert(vs[b]);
+        g[vs[b]].insert(vs[a]);
+      }
+  }
+  std::vector<char> live(T, 1);
+  auto out_vars = [&](int a, int b) {
+    std::vector<int32_t> u;
+    const auto& A = t.nodes[a].vars;
+    const auto& B = t.nodes[b].vars;
+    std::set_union(A.begin(), A.end(), B.begin(), B.end(), std::back_inserter(u));
+    std::vector<int32_t> o;
+    for (int v : u) {
+      bool elsewhere = false;
+      for (int h : hold[v])
+        if (h != a && h != b) { elsewhere = true; break; }
+      if (elsewhere) o.push_back(v);
+    }
+    return o;
+  };
+  auto merge = [&](int a, int b) {
+    TNode nd;
+    nd.left = a;
+    nd.right = b;
+    nd.vars = out_vars(a, b);
+    const int id = (int)t.nodes.size();
+    t.nodes[a].parent = id;
+    t.nodes[b].parent = id;
+    std::vector<int32_t> u;
+    std::set_union(t.nodes[a].vars.begin(), t.nodes[a].vars.end(), t.nodes[b].vars.begin(),
+                   t.nodes[b].vars.end(), std::back_inserter(u));
+    for (int v : u) {
+      auto& h = hold[v];
+      h.erase(std::remove_if(h.begin(), h.end(), [&](int x) { return x == a || x == b; }), h.end());
+    }
+    for (int v : nd.vars) hold[v].push_back(id);
+    t.nodes.push_back(std::move(nd));
+    live.push_back(1);
+    live[a] = live[b] = 0;
+    t.postorder.push_back(id);
+    return id;
+  };
+  auto fill_of = [&](int v) {
+    int64_t f = 0;
+    for (auto i = g[v].begin(); i != g[v].end(); ++i) {
+      auto j = i;
+      for (++j; j != g[v].end(); ++j) f += !g[*i].count(*j);
+    }
+    return f;
+  };
+  // keys (fill, degree, id) of the remaining variables, updated for the
+  // neighbourhood of each eliminated variable
+  using Key = std::tuple<int64_t, int64_t, int32_t>;
+  std::set<Key> order;
+  std::vector<Key> key(n);
+  for (int v = 0; v < n; ++v) {
+    key[v] = Key{fill_of(v), (int64_t)g[v].size(), v};
+    order.insert(key[v]);
+  }
+  std::vector<char> gone(n, 0);
+  while (!order.empty()) {
+    const int v = std::get<2>(*order.begin());
+    order.erase(order.begin());
+    gone[v] = 1;
+    // contract the tensors holding v, smallest result first
+    while (hold[v].size() > 1) {
+      int ba = -1, bb = -1;
+      size_t bs = 0;
+      for (size_t i = 0; i < hold[v].size(); ++i)
+        for (size_t j = i + 1; j < hold[v].size(); ++j) {
+          const size_t o = out_vars(hold[v][i], hold[v][j]).size();
+          if (ba < 0 || o < bs) { ba = hold[v][i]; bb = hold[v][j]; bs = o; }
+        }
+      merge(std::min(ba, bb), std::max(ba, bb));
+    }
+    for (int a : g[v])
+      for (int b : g[v])
+        if (a != b) g[a].insert(b);
+    for (int a : g[v]) g[a].erase(v);
+    std::set<int32_t> touched;
+    for (int a : g[v]) {
+      touched.insert(a);
+      for (int b : g[a]) touched.insert(b);
+    }
+    g[v].clear();
+    for (int u : touched) {
+      if (gone[u]) continue;
+      order.erase(key[u]);
+      key[u] = Key{fill_of(u), (int64_t)g[u].size(), u};
+      order.insert(key[u]);
+    }
+  }
+  std::vector<int> rest;
+  for (int i = 0; i < (int)t.nodes.size(); ++i)
+    if (live[i]) rest.push_back(i);
+  if (rest.empty()) {
+    t.root = -1;
+  } else {
+    int acc = rest[0];
+    for (size_t i = 1; i < rest.size(); ++i) acc = merge(acc, rest[i]);
+    t.root = acc;
+  }
+  finish_tree(t, n);
+  return t;
+}
 
 // Annealed local rotations of a contraction tree.  A rotation at internal
 // node n with children (L, R), L = (A, B), turns n into ((A, R), B) or

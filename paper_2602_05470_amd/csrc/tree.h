@@ -31,6 +31,11 @@ struct Tree {
 // Disconnected scalars are joined at the end.
 Tree greedy_tree(const Network& net);
 
+// Tree from a min-fill elimination order of the variables: the tensors
+// holding the eliminated variable are contracted pairwise (smallest result
+// first); deterministic.
+Tree minfill_tree(const Network& net);
+
 // Simulated-annealing refinement of a contraction tree by local rotations
 // (the tree-annealing approach to contraction orders).  Each sweep visits
 // every internal node once in random order and proposes one rotation; the

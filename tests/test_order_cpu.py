@@ -65,7 +65,18 @@ def test_order_refine_bounds(B):
     with pytest.raises(B.BBTNError):
         B.order_complexity(0, n, edges, J, order_refine=65, log2_target=2)
     with pytest.raises(B.BBTNError):
-        B.order_complexity(0, n, edges, J, order_refine=-1, log2_target=2)
+        B.order_complexity(0, n, edges, J, order_refine=-2, log2_target=2)
+
+
+def test_minfill_beats_greedy_on_kings_64(B):
+    """On the 64 x 64 King's subgraph (seed 0) the greedy pairwise order has
+    space complexity 2^98; the min-fill elimination tree stays far below it
+    (2^61), which is what makes it a starting order worth refining there."""
+    g = I.kings_subgraph(64, 0)
+    args = (1, g["n"], np.asarray(g["edges"]).reshape(-1, 2), None)
+    tc_g, sc_g, _ = B.order_complexity(*args, order_refine=0, log2_target=64)
+    tc_m, sc_m, _ = B.order_complexity(*args, order_refine=-1, log2_target=64)
+    assert sc_m < sc_g - 20 and tc_m < tc_g - 20
 
 
 def test_order_choice_is_deterministic(B):

@@ -43,10 +43,11 @@ def B():
 @pytest.mark.parametrize("seed", range(6))
 @pytest.mark.parametrize("t,rmax", [(1, 3), (2, 4), (3, 8)])
 @pytest.mark.parametrize("field", [False, True])
-@pytest.mark.parametrize("refine", [0, 4])
+@pytest.mark.parametrize("refine", [-1, 0, 4])
 def test_sg_leaves_complete_and_disjoint(B, seed, t, rmax, field, refine):
     """+-J on 4 x 4 (field 0.5 doubled to integers: J = +-2, h = 1), with the
-    greedy order and with an annealed refinement of it."""
+    min-fill tree (refine -1), the greedy order and an annealed refinement of
+    it."""
     g = I.spin_glass_square(4, seed)
     n, edges, J = g["n"], np.asarray(g["edges"]), np.asarray(g["J"])
     h = None
@@ -80,7 +81,7 @@ def test_sg_values_only_keeps_an_optimum(B, seed):
 
 
 @pytest.mark.parametrize("seed", range(4))
-@pytest.mark.parametrize("refine", [0, 4])
+@pytest.mark.parametrize("refine", [-1, 0, 4])
 def test_mwis_leaves_complete_and_disjoint(B, seed, refine):
     g = I.kings_subgraph(4, seed, weights="1..10")
     n, edges, w = g["n"], np.asarray(g["edges"]).reshape(-1, 2), np.asarray(g["w"])
