@@ -78,7 +78,12 @@ typedef struct {
                                 weights)                                        */
   int32_t batched;           /* 0: per-branch step-by-step launches;
                                 1: all branch sub-networks in one persistent
-                                   work-queue launch where they fit             */
+                                   work-queue launch where they fit; in the
+                                   programs that do not fit, the small steps
+                                   that run once per pass (subtrees whose
+                                   operands fit LDS) go through one persistent
+                                   launch per program, the rest step by step;
+                                2: as 1 without that fusion of small steps  */
   int32_t region_max;        /* largest branching region |R| (<= 16)            */
   int32_t local_search;      /* > 0: seed the incumbent of global pruning with
                                 this many local-search sweeps                   */

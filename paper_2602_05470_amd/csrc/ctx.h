@@ -81,10 +81,11 @@ struct PinBuf {
   T* as() const { return (T*)p; }
 };
 
-// Captured step programs: keyed by the program, its batch, residues and
-// every device pointer the launches bake in.
+// Captured step programs: keyed by the program, its batch, residues, every
+// device pointer the launches bake in and the base tensors' offsets (a hash:
+// instances of one structure share a program but not their offsets).
 using GraphKey = std::tuple<const void*, int64_t, int, void*, void*, void*, void*, void*, void*,
-                            uint32_t, void*>;
+                            uint32_t, void*, void*, uint64_t>;
 
 // Autotuner key: residues, log2 of (batch, M, N, K) buckets.
 using TuneKey = std::tuple<int, int, int, int, int>;
@@ -115,12 +116,13 @@ struct bbtn_ctx {
   bbtn::DevBuf leafout;   // per-branch results
   bbtn::DevBuf misc;      // small scratch (merge outputs, traceback)
   bbtn::DevBuf persist;   // persistent executor programs and scratch
+  bbtn::DevBuf forest;    // small-step forests: root region, scratch, program
   // account of the device bytes above, shared with the recovery context
   std::shared_ptr<bbtn::MemCap> memcap = std::make_shared<bbtn::MemCap>();
   void attach_memcap(std::shared_ptr<bbtn::MemCap> m) {
     memcap = std::move(m);
     for (bbtn::DevBuf* b : {&work, &shared_ws, &partial, &base, &fixbits, &leafconst, &leafout,
-                            &misc, &persist, &scorer_dev})
+                            &misc, &persist, &forest, &scorer_dev})
       b->mc = memcap.get();
   }
   bbtn::PinBuf pin_base;    // staging of the base tensors of a pass

@@ -1,4 +1,5 @@
 #include "exec.h"
+#include "persist.h"
 
 #include <cstring>
 
@@ -166,7 +167,23 @@ void run_group(bbtn_ctx* ctx, const Network& net, const GroupPlan& g, const Base
   ctx->shared_ws.ensure((size_t)W * std::max<int64_t>(g.subtree_peak + g.shared_total, 1) * 4);
   uint32_t* ws = ctx->work.as<uint32_t>();
   uint32_t* sw = ctx->shared_ws.as<uint32_t>();
+  // small steps that run once per pass: one persistent launch (a forest of
+  // subtrees, one workgroup each) instead of a launch per step and operand;
+  // their subtree roots live in the forest's root region
+  SmallForest fr;
+  if (ctx->opt.batched == 1) fr = plan_small_forest(g, bd.off, k, L);
+  std::vector<uint8_t> fimg;
+  uint8_t* fdev = nullptr;
+  if (!fr.tasks.empty()) {
+    fimg = small_forest_image(fr);
+    ctx->forest.ensure(small_forest_bytes(fr, k));
+    fdev = ctx->forest.as<uint8_t>();
+    BBTN_HIP(hipMemcpyAsync(fdev + small_forest_prog_off(fr, k), fimg.data(), fimg.size(),
+                            hipMemcpyHostToDevice, st));
+  }
   auto buf = [&](int id) {
+    if (!fr.root_off.empty() && fr.root_off[id] >= 0)
+      return DevTensor{(uint32_t*)fdev + (size_t)W * fr.root_off[id], g.buf_entries[id]};
     switch (g.buf_region[id]) {
       case R_SUBTREE: return DevTensor{sw + (size_t)W * g.buf_off[id], g.buf_entries[id]};
       case R_SHARED:
@@ -227,7 +244,13 @@ void run_group(bbtn_ctx* ctx, const Network& net, const GroupPlan& g, const Base
   for (size_t si = 0; si < g.steps.size(); ++si)
     if (!g.steps[si].shared) order.push_back(si);
   auto issue = [&]() {
+    if (!fr.tasks.empty()) {
+      const int ph = ctx->prof.begin(st, K_PERSIST);
+      launch_small_forest(fr, k, mod, bd, fdev, st);
+      ctx->prof.end(ph, st, K_PERSIST, fr.ops, fr.bytes);
+    }
     for (size_t si : order) {
+      if (!fr.in.empty() && fr.in[si]) continue;
       const Step& s = g.steps[si];
       const int64_t Ls = s.shared ? 1 : L;
       DevTensor opnd[2];
@@ -290,9 +313,11 @@ void run_group(bbtn_ctx* ctx, const Network& net, const GroupPlan& g, const Base
   // and replayed: its device inputs (fixed bits, constants) sit in the same
   // buffers, refreshed before every replay.
   if (reuse && ctx->opt.graphs && !ctx->prof.on && g.steps.size() >= 2) {
+    uint64_t off_hash = 1469598103934665603ull;  // FNV-1a over the base offsets
+    for (int64_t o : bd.off) off_hash = (off_hash ^ (uint64_t)o) * 1099511628211ull;
     const GraphKey key{(const void*)&g, L, k, ctx->work.p, ctx->partial.p, ctx->fixbits.p,
                        ctx->leafconst.p, (void*)out.ptr, (void*)bd.t.ptr, mod.p[0],
-                       ctx->shared_ws.p};
+                       ctx->shared_ws.p, (void*)fdev, off_hash};
     auto it = ctx->graphs.find(key);
     if (it == ctx->graphs.end()) {
       hipGraph_t graph;

@@ -163,9 +163,10 @@ persist_kernel(const PersistArgs a) {
         const uint32_t* src = kind == PK_BASE     ? base + op->src_off
                               : kind == PK_SHARED ? shared + op->src_off
                                                   : scr + op->src_off;
-        const int64_t sstride = kind == PK_BASE     ? a.base_total
-                                : kind == PK_SHARED ? a.shared_entries
-                                                    : a.scratch_entries;
+        const int64_t sstride = kind == PK_BASE ? a.base_total
+                                : kind == PK_SHARED
+                                    ? (op->stride > 0 ? (int64_t)op->stride : a.shared_entries)
+                                    : a.scratch_entries;
         uint32_t pw[P_MAX_RANK / 4];
 #pragma unroll
         for (int i = 0; i < P_MAX_RANK / 4; ++i) pw[i] = op->bitpos[i];
@@ -246,6 +247,7 @@ persist_kernel(const PersistArgs a) {
       const int K = 1 << rk;
       const int c_kind = sp->c_kind;
       const int64_t c_off = sp->c_off;
+      const int64_t c_sh = sp->c_stride > 0 ? (int64_t)sp->c_stride : sh_stride;
       // write output entry o (tropical zero when not finite) to the arena,
       // the shared region or the workgroup's scratch (uniform choice)
       auto put = [&](int o, int32_t v, const uint32_t (&r)[KR > 0 ? KR : 1])
@@ -259,7 +261,7 @@ persist_kernel(const PersistArgs a) {
         } else {
           const bool sh = c_kind == PK_SHARED;
           const gptr<uint32_t> c = (gptr<uint32_t>)((sh ? shared : scr) + c_off);
-          const int64_t cs = sh ? sh_stride : scr_stride;
+          const int64_t cs = sh ? c_sh : scr_stride;
           c[o] = (uint32_t)(fin ? v : NEG);
 #pragma unroll
           for (int p = 0; p < KR; ++p) c[(p + 1) * cs + o] = fin ? r[p] : 0u;
@@ -505,7 +507,9 @@ size_t persist_lds_bytes(int k, int64_t lds_entries, int64_t arena_entries, int 
 }
 
 // Raise a kernel's dynamic-LDS limit only when a launch needs more than it
-// was last set to (the attribute call is not free on every launch).
+// was last set to (the attribute call is not free on every launch).  The
+// default limit is 64 KiB: launches within it make no attribute call, so they
+// may be recorded into a graph.
 static void raise_lds_limit(const void* fn, int bytes, std::atomic<int>& set) {
   int cur = set.load();
   while (bytes > cur) {
@@ -519,7 +523,7 @@ static void launch_nt(int k, const PersistArgs& a, int n_blocks, size_t lds, hip
   switch (k) {
 #define BBTN_PK(K)                                                                 \
   case K: {                                                                        \
-    static std::atomic<int> attr{0};                                               \
+    static std::atomic<int> attr{64 << 10};                                        \
     raise_lds_limit((const void*)persist_kernel<K, NT>, (int)lds, attr);           \
     hipLaunchKernelGGL((persist_kernel<K, NT>), dim3(n_blocks), dim3(NT), lds, st, a); \
     break;                                                                         \

@@ -1,6 +1,7 @@
 #include "persist.h"
 
 #include <algorithm>
+#include <array>
 #include <cstring>
 #include <thread>
 #include <atomic>
@@ -465,6 +466,195 @@ void run_persistent(bbtn_ctx* ctx, const std::vector<PersistJob>& jobs, const Ba
   uint64_t macs = 0;
   for (auto& j : jobs) macs += (uint64_t)(j.L * j.plan->macs + j.plan->shared_macs);
   ctx->last_macs += macs;
+}
+
+SmallForest plan_small_forest(const GroupPlan& g, const std::vector<int64_t>& base_off, int k,
+                              int64_t L) {
+  SmallForest f;
+  const int W = 1 + k;
+  const int n = (int)g.steps.size();
+  f.in.assign(n, 0);
+  f.root_off.assign(g.buf_entries.size(), -1);
+  if (g.keep_all || n == 0) return f;
+  // operand staging within the default 64 KiB of LDS
+  int rmax = 0;
+  while (rmax < P_MAX_RANK &&
+         persist_lds_bytes(k, 1ll << (rmax + 1), 0, f.threads, 0) <= (64u << 10))
+    ++rmax;
+  std::vector<int> prod(g.buf_entries.size(), -1), cons(g.buf_entries.size(), -1);
+  for (int i = 0; i < n; ++i) {
+    prod[g.steps[i].out] = i;
+    for (const Operand* op : {&g.steps[i].a, &g.steps[i].b})
+      if (!op->base) cons[op->id] = i;
+  }
+  for (int i = 0; i < n; ++i) {
+    const Step& s = g.steps[i];
+    bool ok = (s.shared || L == 1) && s.a.fixed_pos.empty() && s.b.fixed_pos.empty();
+    ok = ok && std::max({(int)s.a_vars.size(), (int)s.b_vars.size(), (int)s.c_vars.size(),
+                         s.a.r_in, s.b.r_in}) <= rmax;
+    for (const Operand* op : {&s.a, &s.b})
+      if (!op->base) ok = ok && prod[op->id] >= 0 && f.in[prod[op->id]];
+    f.in[i] = ok;
+  }
+  // tasks: a root (output read outside the forest, or the program's result)
+  // opens one; every other forest step joins its consumer's
+  std::vector<int> task_of(n, -1);
+  int n_tasks = 0;
+  for (int i = n - 1; i >= 0; --i) {
+    if (!f.in[i]) continue;
+    const int out = g.steps[i].out;
+    const int c = cons[out];
+    const bool root = c < 0 || !f.in[c] || out == g.root_buf;
+    task_of[i] = root ? n_tasks++ : task_of[c];
+    if (root) {
+      f.root_off[out] = f.root_entries;
+      f.root_entries += g.buf_entries[out];
+    }
+  }
+  if (n_tasks == 0) return f;
+  std::vector<std::vector<int>> members(n_tasks);
+  for (int i = 0; i < n; ++i)
+    if (f.in[i]) members[task_of[i]].push_back(i);
+  std::vector<int> order(n_tasks);
+  for (int t = 0; t < n_tasks; ++t) order[t] = t;
+  std::stable_sort(order.begin(), order.end(),
+                   [&](int x, int y) { return members[x].size() > members[y].size(); });
+  std::vector<int64_t> scr_off(g.buf_entries.size(), -1);
+  for (int t : order) {
+    const std::vector<int>& m = members[t];
+    // scratch offsets of the task's intermediates: first fit over their
+    // lifetimes (local step index of the producer to that of the consumer)
+    std::map<int, int> local;
+    for (int j = 0; j < (int)m.size(); ++j) local[m[j]] = j;
+    int64_t peak = 0;
+    std::vector<std::array<int64_t, 3>> busy;  // off, end, last use
+    for (int j = 0; j < (int)m.size(); ++j) {
+      const Step& s = g.steps[m[j]];
+      if (f.root_off[s.out] >= 0) continue;
+      const int last = local.at(cons[s.out]);
+      busy.erase(std::remove_if(busy.begin(), busy.end(),
+                                [&](const std::array<int64_t, 3>& b) { return b[2] < j; }),
+                 busy.end());
+      std::sort(busy.begin(), busy.end());
+      const int64_t e = g.buf_entries[s.out];
+      int64_t o = 0;
+      for (auto& b : busy) {
+        if (o + e <= b[0]) break;
+        o = std::max(o, b[1]);
+      }
+      scr_off[s.out] = o;
+      busy.push_back({o, o + e, (int64_t)last});
+      peak = std::max(peak, o + e);
+    }
+    f.scratch_entries = std::max(f.scratch_entries, peak);
+    PTask tk{};
+    tk.step_off = (int32_t)f.steps.size();
+    tk.n_steps = (int32_t)m.size();
+    tk.first = (int64_t)f.tasks.size();
+    tk.out_idx = -1;
+    tk.root_off = -1;
+    for (int i : m) {
+      const Step& s = g.steps[i];
+      PStep ps{};
+      ps.rb = s.rb; ps.rm = s.rm; ps.rn = s.rn; ps.rk = s.rk;
+      if (f.root_off[s.out] >= 0) {
+        ps.c_kind = PK_SHARED;
+        ps.c_off = (int64_t)W * f.root_off[s.out];
+        ps.c_stride = (int32_t)g.buf_entries[s.out];
+      } else {
+        ps.c_kind = PK_SCRATCH;
+        ps.c_off = scr_off[s.out];
+      }
+      const Operand* ops[2] = {&s.a, &s.b};
+      POperand* pops[2] = {&ps.a, &ps.b};
+      for (int w = 0; w < 2; ++w) {
+        const Operand& op = *ops[w];
+        POperand& po = *pops[w];
+        const int rank = (int)op.src_bits.size();
+        f.max_rank = std::max(f.max_rank, rank);
+        if (op.base) {
+          po.kind = PK_BASE;
+          po.src_off = base_off[op.id];
+        } else {
+          po.kind = PK_SCRATCH;
+          po.src_off = scr_off[op.id];
+          if (po.src_off < 0) throw Error(BBTN_E_INTERNAL, "small forest: operand outside its task");
+        }
+        po.rank = rank;
+        for (int j = 0; j < rank; ++j) po.bitpos[j / 4] |= (uint32_t)op.src_bits[j] << (8 * (j % 4));
+        po.mat_off = -1;
+        po.slot = -1;
+      }
+      f.steps.push_back(ps);
+      f.ops += s.macs() * (2 + 2 * k);
+      f.bytes += (std::ldexp(1.0, (int)s.a_vars.size()) + std::ldexp(1.0, (int)s.b_vars.size()) +
+                  std::ldexp(1.0, (int)s.c_vars.size())) * W * 4;
+    }
+    f.tasks.push_back(tk);
+  }
+  return f;
+}
+
+namespace {
+int64_t forest_blocks(const SmallForest& f, int k) {
+  const size_t lds = persist_lds_bytes(k, 1ll << f.max_rank, 0, f.threads, 0);
+  const int per_cu = std::max(1, std::min<int>((int)((160u << 10) / std::max<size_t>(lds, 1)),
+                                               32 / (f.threads / 64)));
+  return std::min<int64_t>((int64_t)device_cus() * per_cu, (int64_t)f.tasks.size());
+}
+size_t forest_scratch_off(const SmallForest& f, int k) {
+  return align_up((size_t)(1 + k) * f.root_entries * 4);
+}
+}  // namespace
+
+size_t small_forest_prog_off(const SmallForest& f, int k) {
+  return forest_scratch_off(f, k) +
+         align_up((size_t)forest_blocks(f, k) * (1 + k) * std::max<int64_t>(f.scratch_entries, 1) * 4);
+}
+
+std::vector<uint8_t> small_forest_image(const SmallForest& f) {
+  const size_t o_tasks = align_up(f.steps.size() * sizeof(PStep));
+  const size_t o_queue = o_tasks + align_up(f.tasks.size() * sizeof(PTask));
+  std::vector<uint8_t> img(o_queue + 16, 0);
+  std::memcpy(img.data(), f.steps.data(), f.steps.size() * sizeof(PStep));
+  std::memcpy(img.data() + o_tasks, f.tasks.data(), f.tasks.size() * sizeof(PTask));
+  return img;
+}
+
+size_t small_forest_bytes(const SmallForest& f, int k) {
+  return small_forest_prog_off(f, k) + small_forest_image(f).size();
+}
+
+void launch_small_forest(const SmallForest& f, int k, const Moduli& mod, const BaseDev& bd,
+                         uint8_t* dev, hipStream_t st) {
+  if (f.tasks.empty()) return;
+  const size_t o_prog = small_forest_prog_off(f, k);
+  const size_t o_tasks = align_up(f.steps.size() * sizeof(PStep));
+  const size_t o_queue = o_tasks + align_up(f.tasks.size() * sizeof(PTask));
+  PersistArgs a{};
+  a.steps = (const PStep*)(dev + o_prog);
+  a.fixes = nullptr;  // no fixed-bit slots: never read
+  a.slots = nullptr;
+  a.max_slots = 0;
+  a.tasks = (const PTask*)(dev + o_prog + o_tasks);
+  a.n_runs = (int64_t)f.tasks.size();
+  a.n_tasks = (int64_t)f.tasks.size();
+  a.assign = nullptr;
+  a.base = bd.t.ptr;
+  a.base_total = bd.total;
+  a.lconst = nullptr;  // no branch results: never read
+  a.out = nullptr;
+  a.n_out = 0;
+  a.scratch = (uint32_t*)(dev + forest_scratch_off(f, k));
+  a.scratch_entries = std::max<int64_t>(f.scratch_entries, 1);
+  a.shared = (uint32_t*)dev;  // the root region (per-tensor plane strides)
+  a.shared_entries = std::max<int64_t>(f.root_entries, 1);
+  a.lds_entries = 1ll << f.max_rank;
+  a.arena_entries = 0;
+  a.per_task_scratch = 0;
+  a.queue = (unsigned long long*)(dev + o_prog + o_queue);
+  a.mod = mod;
+  launch_persist(k, a, (int)forest_blocks(f, k), f.threads, st);
 }
 
 }  // namespace bbtn

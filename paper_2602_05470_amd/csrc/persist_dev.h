@@ -29,7 +29,7 @@ struct POperand {
                      // or the workgroup's LDS arena (src_off = entry offset there)
   int32_t rank;      // rank of the operand in the step's layout
   int64_t src_off;
-  int32_t pad;
+  int32_t stride;    // PK_SHARED: plane stride in entries (0: the region's)
   int32_t slot;      // fixed-bit slot of a base operand, -1 if none
   int64_t mat_off;   // >= 0: also write the staged operand to scratch here
   // byte j of the table: the source bit of bit j of the step's layout
@@ -41,7 +41,7 @@ struct PStep {
   int32_t rb, rm, rn, rk;
   int64_t c_off;     // entry offset of the output (scratch or shared region)
   int32_t c_kind;    // PK_SCRATCH, PK_SHARED or PK_LDS
-  int32_t pad2;
+  int32_t c_stride;  // PK_SHARED: plane stride of the output (0: the region's)
   POperand a, b;
 };
 
