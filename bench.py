@@ -330,7 +330,34 @@ def kernels_json(stats):
             for n, s in stats.items()}
 
 
-def single_instance_run(B, I, torch, kind, L, opts, seeds, warm_seeds, want, label, workers=1):
+def tune_order(B, ctx, kind, make, warm_seeds, n_cand, label):
+    """Contraction order by measurement: the context's candidate orders of the
+    structure (ranked by probe score), the first `n_cand` each timed on the
+    warm-up instances, the fastest kept for the rest of the run.  Returns
+    (chosen index, seconds per candidate)."""
+    g0 = make(warm_seeds[0])
+    w = g0["J"] if kind == 0 else g0.get("w")
+    n = ctx.order_candidates(kind, g0["n"], g0["edges"], w)
+    times = []
+    for i in range(min(n, n_cand)):
+        ctx.order_use(kind, g0["n"], g0["edges"], w, which=i)
+        t0 = time.perf_counter()
+        for s in warm_seeds:
+            g = make(s)
+            if kind == 0:
+                ctx.solve_spinglass(g["n"], g["edges"], g["J"])
+            else:
+                ctx.solve_mwis(g["n"], g["edges"], g["w"])
+        times.append(time.perf_counter() - t0)
+        print("%s order candidate %d: %.3f s" % (label, i, times[-1]), file=sys.stderr, flush=True)
+    best = min(range(len(times)), key=times.__getitem__) if times else 0
+    if times:
+        ctx.order_use(kind, g0["n"], g0["edges"], w, which=best)
+    return best, times
+
+
+def single_instance_run(B, I, torch, kind, L, opts, seeds, warm_seeds, want, label, workers=1,
+                        order_tune=0):
     """One instance per call: warm-up calls on `warm_seeds` on every context
     (the refined order is chosen and cached for a lattice structure on the
     first), then the timed calls on `seeds` with kernel timing on, shared by
@@ -345,6 +372,16 @@ def single_instance_run(B, I, torch, kind, L, opts, seeds, warm_seeds, want, lab
         if kind == 0:
             return ctx.solve_spinglass(g["n"], g["edges"], g["J"])
         return ctx.solve_mwis(g["n"], g["edges"], g["w"])
+    tuned = None
+    if order_tune > 0:
+        # one structure for every seed: time the candidates on the first
+        # context, then install the same candidate on the others
+        tuned = tune_order(B, ctxs[0], kind, make, warm_seeds[:2], order_tune, label)
+        g0 = make(warm_seeds[0])
+        w0 = g0["J"] if kind == 0 else g0.get("w")
+        for ctx in ctxs[1:]:
+            ctx.order_candidates(kind, g0["n"], g0["edges"], w0)
+            ctx.order_use(kind, g0["n"], g0["edges"], w0, which=tuned[0])
     for ctx in ctxs:
         for s in warm_seeds:
             print("%s warm-up seed %d" % (label, s), file=sys.stderr, flush=True)
@@ -410,7 +447,7 @@ def single_instance_run(B, I, torch, kind, L, opts, seeds, warm_seeds, want, lab
     n = len(rows)
     names = ["total", "build+plan", "search", "contraction", "crt+certification", "configuration"]
     ls = sorted(lat)
-    return {"dt": dt, "n": n, "exact": exact, "stats": stats,
+    return {"dt": dt, "n": n, "exact": exact, "stats": stats, "tuned": tuned,
             "host_cpu_s": (r1.user - r0.user) + (r1.system - r0.system),
             "leaves_per_instance": round(leaves / max(n, 1), 1),
             "macs_per_instance": round(macs / max(n, 1)),
@@ -562,6 +599,11 @@ def main():
                     help="tile autotuner cache file for the headline run (products of 2^24 "
                          "MACs or more are timed over the tile candidates on first use, in "
                          "the warm-up)")
+    ap.add_argument("--order-refine", type=int, default=32,
+                    help="annealed refinements among the headline's candidate orders")
+    ap.add_argument("--order-tune", type=int, default=8,
+                    help="headline: time this many candidate orders on two warm-up "
+                         "instances each and keep the fastest (0: probe score alone)")
     ap.add_argument("--ksg-seeds", type=int, default=8,
                     help="seeds of the 40x40 King's subgraph leg (0 .. n-1)")
     ap.add_argument("--micro-only", action="store_true",
@@ -604,12 +646,21 @@ def main():
     sg32 = golden_values("sg32_values.txt")
     scorer_sg = os.path.join(ROOT, "paper_2602_05470_amd", "scorer_sg.bin")
     head_opts = B.Options(log2_target=26, residues_per_pass=args.residues,
-                          branching=args.branching, batched=1, order_refine=8, time_limit_s=600,
+                          branching=args.branching, batched=1, order_refine=args.order_refine,
+                          time_limit_s=600,
                           spin_flip=1, scorer_weights=scorer_sg if args.branching == 2 else None,
                           autotune_cache=args.autotune)
     seeds = [i % 20 for i in range(args.steps)]
     warm = [20 + i for i in range(args.warmup)]
-    h = single_instance_run(B, I, torch, 0, 32, head_opts, seeds, warm, sg32, "sg32x32")
+    h = single_instance_run(B, I, torch, 0, 32, head_opts, seeds, warm, sg32, "sg32x32",
+                            order_tune=args.order_tune if len(warm) >= 2 else 0)
+    if h["tuned"] is not None:
+        order_desc = ("measured: the %d cheapest of %d candidate orders by probe score each "
+                      "timed on warm-up seeds %d-%d, candidate %d kept (%s s)"
+                      % (len(h["tuned"][1]), 2 * args.order_refine + 3, warm[0], warm[1],
+                         h["tuned"][0], ", ".join("%.2f" % t for t in h["tuned"][1])))
+    else:
+        order_desc = "refined (%d candidates, probe score)" % (args.order_refine + 3)
     dt = h["dt"]
     line = {
         "metric": "exact (E0,degeneracy) instances/hour",
@@ -625,17 +676,19 @@ def main():
         "dtype": "int32",
         "data": "synthetic",
         "config": {"workload": "+-J spin glass 32x32 open lattice, seeds 0-19 (step i solves "
-                               "seed i mod 20), zero field; BBTN T_target=2^26, refined "
-                               "contraction order, %s, spin-flip symmetry (one "
-                               "spin fixed, count doubled), %d primes per pass plus a fused "
-                               "certification prime; one step = one call solving one "
-                               "instance" % ("learned branching scorer" if args.branching == 2
-                                             else "plain planner", args.residues),
+                               "seed i mod 20), zero field; BBTN T_target=2^26, %s, %s, "
+                               "spin-flip symmetry (one spin fixed, count doubled), %d primes "
+                               "per pass plus a fused certification prime; one step = one "
+                               "call solving one instance"
+                               % ("contraction order chosen by measurement in the warm-up"
+                                  if h["tuned"] is not None else "refined contraction order",
+                                  "learned branching scorer" if args.branching == 2
+                                  else "plain planner", args.residues),
                    "instances": h["n"], "exact": h["exact"],
                    "leaves_per_instance": h["leaves_per_instance"],
                    "macs_per_instance": h["macs_per_instance"],
                    "log2_target": 26, "residues_per_pass": args.residues, "contraction_order":
-                   "refined (8 candidates, chosen in the warm-up)",
+                   order_desc,
                    "branching": "learned scorer" if args.branching == 2 else "plain planner",
                    "exactness": "certified count, E0 equal to the matching oracle's stored "
                                 "value, even degeneracy, configuration reaching E0"},

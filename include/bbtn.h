@@ -146,7 +146,8 @@ typedef struct {
   uint64_t nodes;      /* search-tree nodes expanded                           */
   uint64_t macs;       /* semiring multiply-accumulates on the device          */
   double seconds[8];   /* [0] total [1] build+plan [2] search [3] contraction
-                          [4] CRT+certification [5] configuration [6] H2D/D2H  */
+                          [4] CRT+certification [5] configuration [6] H2D/D2H
+                          [7] values pass (part of [3])                      */
 } bbtn_result;
 
 void bbtn_default_options(bbtn_options* opt);
@@ -398,6 +399,36 @@ bbtn_status bbtn_order_complexity(int32_t kind, int32_t n, int32_t m, const int3
                                   const int32_t* weights, const int32_t* h, int32_t order_refine,
                                   int32_t log2_target, int32_t region_max, double* tc_log2,
                                   int32_t* sc, int64_t* rho);
+
+/* Contraction orders chosen by measurement ("Tropical Tensor Networks"
+ * section: the cost of a contraction order; Eq. 4 for the overflow that the
+ * branching removes).  The probe score that bbtn_options.order_refine uses
+ * models device time from multiply-accumulates and memory traffic, but the
+ * time of a solve also depends on which leaves hold the optimum (only those
+ * are counted), so a caller that solves many instances of one structure may
+ * time a few orders and keep the fastest:
+ *   bbtn_order_candidates builds, for the structure of the given instance
+ *   (its simplified tensors' variable lists; couplings and weights do not
+ *   matter), the candidate orders of order_refine = n = max(1, the
+ *   context's order_refine): the greedy tree, the n refinements, the
+ *   min-fill tree and its refinement, and n more refinements under varied
+ *   annealing objectives (lighter overflow weight, memory traffic in the
+ *   move score), each probed with the context's log2_target and
+ *   region_max (budget 2^22 search nodes), and keeps those that finish,
+ *   cheapest probe score first, in the context (once per structure; later
+ *   calls return the same list).  *n_out receives their number.
+ *   bbtn_order_use makes candidate `which` (0 = cheapest probe score) the
+ *   structure's order for every later solve on this context.
+ * Host only (ctx holds the lists; no device work).  Errors:
+ * BBTN_E_INVALID_ARG (NULL ctx or output, bad graph or kind, log2_target of
+ * the context <= 0, `which` out of range or no candidates built for the
+ * structure). */
+bbtn_status bbtn_order_candidates(bbtn_ctx* ctx, int32_t kind, int32_t n, int32_t m,
+                                  const int32_t* edge_uv, const int32_t* weights,
+                                  const int32_t* h, int32_t* n_out);
+bbtn_status bbtn_order_use(bbtn_ctx* ctx, int32_t kind, int32_t n, int32_t m,
+                           const int32_t* edge_uv, const int32_t* weights, const int32_t* h,
+                           int32_t which);
 
 /* Training data from the search itself: run the planner on an instance
  * (kind 0: spin glass with weights = J, h; kind 1: MWIS with weights = w)

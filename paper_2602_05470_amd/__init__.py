@@ -71,7 +71,7 @@ EXPORTS = ["bbtn_default_options", "bbtn_create", "bbtn_destroy", "bbtn_last_err
            "bbtn_reduce", "bbtn_bound", "bbtn_last_macs", "bbtn_profile",
            "bbtn_get_kernel_stats", "bbtn_profile_mask", "bbtn_mlp_forward", "bbtn_mlp_backward", "bbtn_mlp_adam",
            "bbtn_scorer_load", "bbtn_scorer_collect", "bbtn_scorer_train", "bbtn_plan_leaves",
-           "bbtn_order_complexity",
+           "bbtn_order_complexity", "bbtn_order_candidates", "bbtn_order_use",
            "bbtn_solve_batch"]
 
 # scorer parameter layout (see include/bbtn.h)
@@ -148,6 +148,10 @@ def load(path: str = LIB_PATH):
                                           C.POINTER(C.c_double), C.POINTER(C.c_int32),
                                           C.POINTER(C.c_int64)]
     lib.bbtn_order_complexity.restype = I32
+    lib.bbtn_order_candidates.argtypes = [P, I32, I32, I32, P, P, P, C.POINTER(C.c_int32)]
+    lib.bbtn_order_candidates.restype = I32
+    lib.bbtn_order_use.argtypes = [P, I32, I32, I32, P, P, P, I32]
+    lib.bbtn_order_use.restype = I32
     lib.bbtn_scorer_collect.argtypes = [P, I32, I32, I32, P, P, P, I32, I32, I32, P, P, I64,
                                         C.POINTER(C.c_int64)]
     lib.bbtn_scorer_collect.restype = I32
@@ -384,6 +388,25 @@ class Context:
         """bbtn_solve_mwis: W*, number of maximum-weight independent sets,
         one of them (x in {0,1})."""
         return self._solve(self.lib.bbtn_solve_mwis, n, edges, w, **kw)
+
+    def order_candidates(self, kind, n, edges, weights=None, h=None) -> int:
+        """bbtn_order_candidates: build and rank the candidate contraction
+        orders of the instance's structure on this context; their number."""
+        e = _i32(edges).reshape(-1, 2)
+        w = None if weights is None else _i32(weights)
+        hh = None if h is None else _i32(h)
+        cnt = C.c_int32(0)
+        self._check(self.lib.bbtn_order_candidates(self.h, kind, n, len(e), _ptr(e), _ptr(w),
+                                                   _ptr(hh), C.byref(cnt)))
+        return cnt.value
+
+    def order_use(self, kind, n, edges, weights=None, h=None, which=0):
+        """bbtn_order_use: make candidate `which` the structure's order."""
+        e = _i32(edges).reshape(-1, 2)
+        w = None if weights is None else _i32(weights)
+        hh = None if h is None else _i32(h)
+        self._check(self.lib.bbtn_order_use(self.h, kind, n, len(e), _ptr(e), _ptr(w), _ptr(hh),
+                                            int(which)))
 
     # ------------------------------------------------------- kernel entries
     def tgemm(self, k, primes, batch, M, N, K, A, B, Cout, stream=None):

@@ -97,6 +97,7 @@ bbtn_status bbtn_create(const bbtn_options* opt, bbtn_ctx** out) {
   bbtn_status s = guard(ctx, [&] {
     BBTN_REQUIRE(ctx->opt.residues_per_pass >= 0 && ctx->opt.residues_per_pass <= KUSER,
                  "residues_per_pass must be in [0, 4]");
+    BBTN_REQUIRE(ctx->opt.batched >= 0 && ctx->opt.batched <= 2, "batched must be 0, 1 or 2");
     int ndev = 0;
     BBTN_HIP(hipGetDeviceCount(&ndev));
     BBTN_REQUIRE(ctx->opt.device >= 0 && ctx->opt.device < ndev, "no such device");
@@ -527,6 +528,36 @@ bbtn_status bbtn_order_complexity(int32_t kind, int32_t n, int32_t m, const int3
     for (int id : tree.postorder)
       r += std::max(0, (int)tree.nodes[id].vars.size() - log2_target);
     *rho = r;
+  });
+}
+
+static Network order_network(bbtn_ctx* ctx, int32_t kind, int32_t n, int32_t m,
+                             const int32_t* edge_uv, const int32_t* weights, const int32_t* h) {
+  BBTN_REQUIRE(ctx != nullptr, "NULL context");
+  check_graph(n, m, edge_uv);
+  BBTN_REQUIRE(kind == 0 || kind == 1, "kind must be 0 (spin glass) or 1 (MWIS)");
+  BBTN_REQUIRE(ctx->opt.log2_target > 0, "order candidates need log2_target > 0");
+  if (kind == 0) BBTN_REQUIRE(weights != nullptr, "J is NULL");
+  return kind == 0 ? build_spinglass(n, m, edge_uv, weights, h) : build_mwis(n, m, edge_uv, weights);
+}
+
+bbtn_status bbtn_order_candidates(bbtn_ctx* ctx, int32_t kind, int32_t n, int32_t m,
+                                  const int32_t* edge_uv, const int32_t* weights,
+                                  const int32_t* h, int32_t* n_out) {
+  if (!ctx || !n_out) return BBTN_E_INVALID_ARG;
+  return guard(ctx, [&] {
+    const Network net = order_network(ctx, kind, n, m, edge_uv, weights, h);
+    *n_out = order_candidates(ctx, net);
+  });
+}
+
+bbtn_status bbtn_order_use(bbtn_ctx* ctx, int32_t kind, int32_t n, int32_t m,
+                           const int32_t* edge_uv, const int32_t* weights, const int32_t* h,
+                           int32_t which) {
+  if (!ctx) return BBTN_E_INVALID_ARG;
+  return guard(ctx, [&] {
+    const Network net = order_network(ctx, kind, n, m, edge_uv, weights, h);
+    order_use(ctx, net, which);
   });
 }
 

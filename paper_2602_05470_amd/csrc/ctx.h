@@ -82,10 +82,11 @@ struct PinBuf {
 };
 
 // Captured step programs: keyed by the program, its batch, residues, every
-// device pointer the launches bake in and the base tensors' offsets (a hash:
-// instances of one structure share a program but not their offsets).
+// device pointer the launches bake in, the base tensors' offsets (a hash:
+// instances of one structure share a program but not their offsets) and
+// whether the shared steps are skipped (chunks after a pass's first).
 using GraphKey = std::tuple<const void*, int64_t, int, void*, void*, void*, void*, void*, void*,
-                            uint32_t, void*, void*, uint64_t>;
+                            uint32_t, void*, void*, uint64_t, bool>;
 
 // Autotuner key: residues, log2 of (batch, M, N, K) buckets.
 using TuneKey = std::tuple<int, int, int, int, int>;
@@ -144,6 +145,9 @@ struct bbtn_ctx {
     uint64_t id;  // unique over the process
   };
   std::map<std::vector<std::vector<int32_t>>, TreeEntry> tree_cache;
+  // ranked candidate orders by structure (order_candidates / order_use)
+  std::map<std::vector<std::vector<int32_t>>, std::vector<std::shared_ptr<const bbtn::Tree>>>
+      order_cands;
   // step programs by (tree id, keep-all, fixed set): they depend on the
   // network's structure and the fixed variables only
   std::map<std::tuple<uint64_t, bool, std::vector<uint64_t>>,

@@ -40,10 +40,16 @@ TuneVal cached_or_heuristic_tiles(const bbtn_ctx* ctx, int k, int64_t batch, int
 // the j-th fixed variable (ascending ids) of branch l.  Writes, for every
 // branch, root (.) folded constant into `out` (tensor buffer of L entries).
 // With reuse (the same program will run again with the same shapes) the
-// launches are captured into a hipGraph once and replayed.
+// launches are captured into a hipGraph once and replayed.  A group whose
+// branches run in several chunks passes its branch count as L_group (the
+// forest of small steps depends on it) and, for every chunk after the first
+// of a pass, shared_ready: the shared steps (and the forest) already ran
+// for the first chunk with the same workspaces, and their results are read
+// again instead of being recomputed.
 void run_group(bbtn_ctx* ctx, const Network& net, const GroupPlan& g, const BaseDev& bd,
                const Moduli& mod, const uint8_t* assign, int64_t L, DevTensor out,
-               hipStream_t st, bool reuse = false);
+               hipStream_t st, bool reuse = false, bool shared_ready = false,
+               int64_t L_group = -1);
 
 // Per-branch folded constants on the host: value and k residues.
 void leaf_constants(const Network& net, const GroupPlan& g, const int* prime_idx, int k,

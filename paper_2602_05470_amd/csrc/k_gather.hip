@@ -10,7 +10,7 @@
 //  * direct: one thread per output entry, grid-stride; writes coalesced,
 //    reads follow the permutation.  Used for small outputs and for
 //    permutations whose lowest output bits already map onto the lowest free
-//    input bits (reads then come in runs of at least 16 entries).
+//    input bits (reads then come in runs of at least 64 entries).
 //  * tiled: a workgroup moves one tile through LDS.  The tile's variables T
 //    are the (up to) 6 lowest output bits together with the output bits that
 //    read the (up to) 6 lowest free input bits, at most 12 bits, 4096
@@ -128,7 +128,8 @@ __global__ void __launch_bounds__(256) gather_tiled_kernel(const GatherArgs g, c
 
 // Tile for the LDS kernel, or tb = 0 when the direct kernel reads well
 // enough: small outputs, or lowest output bits that already read a run of
-// at least 16 (or all) of the lowest free input bits.
+// at least 64 (or all) of the lowest free input entries, a whole 256-byte
+// segment per wavefront and plane.
 static GatherTile choose_tile(const GatherPlan& gp) {
   GatherTile t{};
   const int r_out = gp.r_out;
@@ -142,7 +143,7 @@ static GatherTile choose_tile(const GatherPlan& gp) {
   for (int i = 0; i < gp.r_in; ++i)
     if (out_of[i] >= 0) { low_free = i; break; }
   const GatherRun& r0 = gp.runs[0];
-  if (gp.n_runs > 0 && r0.out_lo == 0 && r0.in_lo == low_free && r0.len >= std::min(4, r_out))
+  if (gp.n_runs > 0 && r0.out_lo == 0 && r0.in_lo == low_free && r0.len >= std::min(6, r_out))
     return t;
   bool in_t[64] = {};
   for (int j = 0; j < std::min(6, r_out); ++j) in_t[j] = true;

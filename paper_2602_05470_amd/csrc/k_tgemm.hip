@@ -429,6 +429,137 @@ __global__ void __launch_bounds__(256) tgemm_thin_kernel(const GemmArgs a, int l
   }
 }
 
+// Staged thin products for large contiguous operands (A rows, B and C
+// without batch gaps).  The one-thread-per-output kernel above re-reads the
+// wide operand once per row of the narrow side, and with gigabyte operands
+// those re-reads miss the caches.  Here a workgroup stages one block of the
+// wide operand and the whole narrow operand in LDS with consecutive lanes
+// reading consecutive words, then computes the block's outputs from LDS and
+// writes them in memory order: every operand word crosses HBM once.
+//
+// Rows form (N <= 16): the block is BR consecutive rows r = b * M + m of A
+// (BR * K contiguous words) with the B matrices of the batches they belong
+// to (contiguous too); its outputs are BR * N contiguous words of C.
+template <int KR>
+__global__ void __launch_bounds__(256)
+tgemm_thin_rows_kernel(const GemmArgs a, int lm, int ln, int lk, int lbr, int b_cap) {
+  constexpr int W = 1 + KR;
+  extern __shared__ __attribute__((aligned(16))) uint32_t sm[];
+  const int a_cap = 1 << (lbr + lk);
+  uint32_t* const As = sm;               // W planes of a_cap words
+  uint32_t* const Bs = sm + W * a_cap;   // W planes of b_cap words
+  const int tid = threadIdx.x;
+  const int64_t R = a.batch << lm;
+  const int64_t tiles = (R + (1 << lbr) - 1) >> lbr;
+  const int N = 1 << ln, K = 1 << lk;
+  for (int64_t tile = blockIdx.x; tile < tiles; tile += gridDim.x) {
+    const int64_t r0 = tile << lbr;
+    const int rows = (int)min<int64_t>((int64_t)1 << lbr, R - r0);
+    const int64_t b0 = r0 >> lm;
+    const int nb = (int)(((r0 + rows - 1) >> lm) - b0 + 1);
+    const int na = rows << lk, nbe = nb << (lk + ln);
+#pragma unroll
+    for (int p = 0; p < W; ++p) {
+      const uint32_t* srcA = a.A + p * a.pA + (r0 << lk);
+      for (int e = tid; e < na; e += 256) As[p * a_cap + e] = srcA[e];
+      const uint32_t* srcB = a.B + p * a.pB + (b0 << (lk + ln));
+      for (int e = tid; e < nbe; e += 256) Bs[p * b_cap + e] = srcB[e];
+    }
+    __syncthreads();
+    const int nout = rows << ln;
+    for (int o = tid; o < nout; o += 256) {
+      const int rl = o >> ln, n = o & (N - 1);
+      const int bl = (int)(((r0 + rl) >> lm) - b0);
+      const int ia0 = rl << lk, ib0 = (bl << (lk + ln)) + n;
+      int32_t V = INT32_MIN;
+      for (int q = 0; q < K; ++q) V = max(V, (int32_t)As[ia0 + q] + (int32_t)Bs[ib0 + (q << ln)]);
+      const bool fin = V > NEG_CUT;
+      const int64_t off = (r0 << ln) + o;
+      a.C[off] = (uint32_t)(fin ? V : NEG);
+      if constexpr (KR > 0) {
+        uint64_t acc[KR];
+#pragma unroll
+        for (int p = 0; p < KR; ++p) acc[p] = 0;
+        if (fin) {
+          for (int q = 0; q < K; ++q) {
+            const int ia = ia0 + q, ib = ib0 + (q << ln);
+            if ((int32_t)As[ia] + (int32_t)Bs[ib] != V) continue;
+#pragma unroll
+            for (int p = 0; p < KR; ++p) {
+              acc[p] += (uint64_t)As[(p + 1) * a_cap + ia] * Bs[(p + 1) * b_cap + ib];
+              acc[p] = fold64(acc[p], a.mod.c[p]);
+            }
+          }
+        }
+#pragma unroll
+        for (int p = 0; p < KR; ++p)
+          a.C[(p + 1) * a.pC + off] = fin ? mod_final(acc[p], a.mod.p[p], a.mod.c[p]) : 0u;
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// Columns form (M <= 16, N >= 32): the block is BN consecutive columns
+// n0.. of one batch's B (K segments of BN contiguous words) with that
+// batch's whole A (M * K words); its outputs are M segments of BN
+// contiguous words of C.
+template <int KR>
+__global__ void __launch_bounds__(256)
+tgemm_thin_cols_kernel(const GemmArgs a, int lm, int ln, int lk, int lbn) {
+  constexpr int W = 1 + KR;
+  extern __shared__ __attribute__((aligned(16))) uint32_t sm[];
+  const int a_cap = 1 << (lm + lk), b_cap = 1 << (lk + lbn);
+  uint32_t* const As = sm;
+  uint32_t* const Bs = sm + W * a_cap;
+  const int tid = threadIdx.x;
+  const int K = 1 << lk, BN = 1 << lbn;
+  const int lblk = ln - lbn;  // column blocks per batch (log2)
+  const int64_t tiles = a.batch << lblk;
+  for (int64_t tile = blockIdx.x; tile < tiles; tile += gridDim.x) {
+    const int64_t b = tile >> lblk;
+    const int64_t n0 = (tile & ((1ll << lblk) - 1)) << lbn;
+#pragma unroll
+    for (int p = 0; p < W; ++p) {
+      const uint32_t* srcA = a.A + p * a.pA + (b << (lm + lk));
+      for (int e = tid; e < a_cap; e += 256) As[p * a_cap + e] = srcA[e];
+      const uint32_t* srcB = a.B + p * a.pB + (b << (lk + ln)) + n0;
+      for (int e = tid; e < b_cap; e += 256) Bs[p * b_cap + e] = srcB[((int64_t)(e >> lbn) << ln) + (e & (BN - 1))];
+    }
+    __syncthreads();
+    const int nout = 1 << (lm + lbn);
+    for (int o = tid; o < nout; o += 256) {
+      const int j = o & (BN - 1), m = o >> lbn;
+      const int ia0 = m << lk;
+      int32_t V = INT32_MIN;
+      for (int q = 0; q < K; ++q) V = max(V, (int32_t)As[ia0 + q] + (int32_t)Bs[(q << lbn) + j]);
+      const bool fin = V > NEG_CUT;
+      const int64_t off = (b << (lm + ln)) + ((int64_t)m << ln) + n0 + j;
+      a.C[off] = (uint32_t)(fin ? V : NEG);
+      if constexpr (KR > 0) {
+        uint64_t acc[KR];
+#pragma unroll
+        for (int p = 0; p < KR; ++p) acc[p] = 0;
+        if (fin) {
+          for (int q = 0; q < K; ++q) {
+            const int ia = ia0 + q, ib = (q << lbn) + j;
+            if ((int32_t)As[ia] + (int32_t)Bs[ib] != V) continue;
+#pragma unroll
+            for (int p = 0; p < KR; ++p) {
+              acc[p] += (uint64_t)As[(p + 1) * a_cap + ia] * Bs[(p + 1) * b_cap + ib];
+              acc[p] = fold64(acc[p], a.mod.c[p]);
+            }
+          }
+        }
+#pragma unroll
+        for (int p = 0; p < KR; ++p)
+          a.C[(p + 1) * a.pC + off] = fin ? mod_final(acc[p], a.mod.p[p], a.mod.c[p]) : 0u;
+      }
+    }
+    __syncthreads();
+  }
+}
+
 static int exact_log2(int64_t x) {
   if (x <= 0 || (x & (x - 1))) return -1;
   int l = 0;
@@ -445,8 +576,58 @@ static bool thin_shape(const GemmShape& s, int splits) {
 
 bool tgemm_is_thin(const GemmShape& s, int splits) { return thin_shape(s, splits); }
 
+// Staged forms, for contiguous operands with at least 4096 outputs.  LDS
+// words per plane: A block <= 1024 and B block <= 1024 (rows), A <= 512 and
+// B block <= 2048 (columns), so that six planes stay within 64 KiB.
+static bool launch_thin_staged(int k, const GemmArgs& a, int lm, int ln, int lk,
+                               hipStream_t st) {
+  if (a.sAb != a.M * a.K || a.sBb != a.K * a.N || a.sCb != a.M * a.N) return false;
+  const int64_t total = a.batch << (lm + ln);
+  if (total < 4096) return false;
+  const int W = 1 + k;
+  if (ln < 5) {
+    // rows: BR * K <= 1024 and the batches of a block: ceil(BR / M) * K * N <= 1024
+    int lbr = 10 - lk;
+    while (lbr > 0 && (lbr > lm ? (1 << (lbr - lm)) : 1) * (1 << (lk + ln)) > 1024) --lbr;
+    const int64_t R = a.batch << lm;
+    while (lbr > 0 && ((int64_t)1 << lbr) > R) --lbr;
+    // blocks start at multiples of BR (M and BR are powers of two): a block
+    // holds BR / M whole batches, or lies within one
+    const int b_cap = (lbr > lm ? (1 << (lbr - lm)) : 1) << (lk + ln);
+    const size_t lds = (size_t)W * ((1u << (lbr + lk)) + b_cap) * 4;
+    const int64_t tiles = (R + (1 << lbr) - 1) >> lbr;
+    dim3 grid((unsigned)std::min<int64_t>(tiles, 256 * 16)), block(256);
+    switch (k) {
+#define BBTN_TR(KK) case KK: launch_kernel(tgemm_thin_rows_kernel<KK>, grid, block, (uint32_t)lds, st, true, a, lm, ln, lk, lbr, b_cap); break;
+      BBTN_TR(0) BBTN_TR(1) BBTN_TR(2) BBTN_TR(3) BBTN_TR(4) BBTN_TR(5)
+#undef BBTN_TR
+      default: throw Error(BBTN_E_INVALID_ARG, "k must be in [0, 5]");
+    }
+    BBTN_LAUNCHED("tgemm (thin rows)");
+    return true;
+  }
+  if (lm < 5) {
+    // columns: K * BN <= 2048, BN <= N, M * K <= 512 always
+    int lbn = std::min(ln, 11 - lk);
+    lbn = std::min(lbn, 10);
+    const size_t lds = (size_t)W * ((1u << (lm + lk)) + (1u << (lk + lbn))) * 4;
+    const int64_t tiles = a.batch << (ln - lbn);
+    dim3 grid((unsigned)std::min<int64_t>(tiles, 256 * 16)), block(256);
+    switch (k) {
+#define BBTN_TC(KK) case KK: launch_kernel(tgemm_thin_cols_kernel<KK>, grid, block, (uint32_t)lds, st, true, a, lm, ln, lk, lbn); break;
+      BBTN_TC(0) BBTN_TC(1) BBTN_TC(2) BBTN_TC(3) BBTN_TC(4) BBTN_TC(5)
+#undef BBTN_TC
+      default: throw Error(BBTN_E_INVALID_ARG, "k must be in [0, 5]");
+    }
+    BBTN_LAUNCHED("tgemm (thin columns)");
+    return true;
+  }
+  return false;
+}
+
 static void launch_thin(int k, const GemmArgs& a, hipStream_t st) {
   const int lm = exact_log2(a.M), ln = exact_log2(a.N), lk = exact_log2(a.K);
+  if (launch_thin_staged(k, a, lm, ln, lk, st)) return;
   const int64_t total = a.batch << (lm + ln);
   const int64_t blocks = std::min<int64_t>((total + 255) / 256, 256 * 64);
   dim3 grid((unsigned)blocks), block(256);

@@ -1045,73 +1045,103 @@ std::vector<uint8_t> local_search_mwis(int32_t n, int32_t m, const int32_t* uv,
   return best;
 }
 
-// Candidate contraction trees for a structure when order refinement is on:
-// the greedy tree and `n` annealed refinements of it (seeds 1..n).  Each is
-// scored by a branch-and-bound search of `net` with `probe`: the semiring
-// MACs of its leaves (each leaf's sliced tree) plus a per-search-node weight
-// for the host's share, lowest score kept (the greedy tree on ties).  The
-// probes run in parallel, each stopped past 2^22 nodes; once one finishes
-// with score S and N nodes, the others stop past min(S / 2^17, 2N + 1024)
-// nodes and are not chosen.  On
-// zero-field +-J lattices the leaves and MACs depend on the structure only,
-// so one instance's probe serves every instance of that structure.
+namespace {
+constexpr double kNodeMacs = 131072.0;  // host time of a search node, in device MACs
+// device time of moving one tensor entry (all its residue words) through
+// HBM, in multiply-accumulates of the counting product: about 3.3e12 MACs
+// against 1.75e11 entries of 20 bytes per second
+constexpr double kKappa = 16.0;
+
+// Candidate trees: the greedy tree, its n annealed refinements (seeds 1..n,
+// overflow weight 0.25, multiply-accumulates alone), the min-fill tree and
+// one refinement of that.  With `varied`, n more refinements of the greedy
+// tree (seeds 1..n again) vary the annealer's objective: the overflow
+// weight alternates between 0.25 and 0.1 (a lighter one trades more
+// overflow, hence more leaves, for fewer multiply-accumulates) and the
+// memory weight kappa cycles through 0, 4 and 6.  Their leaves cost less or
+// more depending on the structure and on where the optimum lies, which a
+// probe does not see, so they are offered only to a choice by measurement.
+std::vector<Tree> order_candidates(const Network& net, int n, const SearchOptions& probe,
+                                   bool varied) {
+  const int nc = n + 3 + (varied ? n : 0);
+  std::vector<Tree> cand(nc);
+  cand[0] = greedy_tree(net);  // built before any thread reads it
+  cand[n + 1] = minfill_tree(net);
+  std::vector<std::thread> th;
+  for (int c = 1; c < nc; ++c) {
+    if (c == n + 1) continue;
+    th.emplace_back([&, c] {
+      RefineOptions o;
+      o.sweeps = 200;
+      o.log2_target = probe.log2_target;
+      o.rho_weight = 0.25;
+      o.deadline = probe.deadline;
+      if (c <= n + 2) {
+        o.seed = (uint64_t)c;
+        cand[c] = refine_tree(net, c <= n ? cand[0] : cand[n + 1], o);
+      } else {
+        const int j = c - (n + 2);  // 1..n
+        static const double kappas[3] = {0.0, 4.0, 6.0};
+        o.rho_weight = j % 2 == 0 ? 0.1 : 0.25;
+        o.kappa = kappas[(j / 2) % 3];
+        o.seed = (uint64_t)j;
+        cand[c] = refine_tree(net, cand[0], o);
+      }
+    });
+  }
+  for (auto& t : th) t.join();
+  return cand;
+}
+
+// Probe score of a candidate: the cost model of its leaves (time_cost with
+// kKappa, shared contractions once per group) plus kNodeMacs per search
+// node; HUGE_VAL when the search passes `limit` nodes.
+double probe_score(const Network& net, const Tree& t, const SearchOptions& probe,
+                   std::atomic<uint64_t>* limit) {
+  SearchOptions so = probe;
+  so.node_limit = limit;
+  std::vector<LeafGroup> groups;
+  SearchStats st;
+  try {
+    bb_search(net, t, so, groups, st);
+  } catch (const std::exception&) {
+    return HUGE_VAL;  // over the budget (or cannot be planned)
+  }
+  double cost = 0;
+  for (const auto& g : groups) {
+    const TimeCost tc = time_cost(t, g.mask, kKappa);
+    cost += (double)g.count * tc.branch + tc.shared;
+  }
+  return cost + kNodeMacs * (double)st.nodes;
+}
+}  // namespace
+
+// The candidates are scored by a branch-and-bound search of `net` with
+// `probe` (probe_score).  Probes run in parallel in rounds of growing node
+// budgets, 2^10, 2^12, ... 2^22: a round re-runs every unfinished probe from
+// the start with the round's budget, and the first round in which some probe
+// finishes decides.  Every probe's outcome in a round depends on its budget
+// only, so the choice is the same on every run.  Within a round a finished
+// probe with score S stops the others past S / kNodeMacs nodes: they score
+// worse than S, and could not have been chosen.  On zero-field +-J lattices
+// the leaves depend on the structure only, so one instance's probe serves
+// every instance of that structure.
 Tree choose_order(const Network& net, int n, const SearchOptions& probe, bool* complete) {
   if (complete) *complete = true;
   if (n < 0) return minfill_tree(net);
   n = std::min(64, n);
   if (n == 0) return greedy_tree(net);
-  constexpr double kNodeMacs = 131072.0;  // host time of a search node, in device MACs
-  // candidates: the greedy tree, its n refinements, the min-fill tree and
-  // one refinement of it
-  const int nc = n + 3;
-  std::vector<Tree> cand(nc);
+  std::vector<Tree> cand = order_candidates(net, n, probe, false);
+  const int nc = (int)cand.size();
   std::vector<double> score(nc, HUGE_VAL);
-  std::vector<char> done(nc, 0);
-  cand[0] = greedy_tree(net);  // built before any thread reads it
-  cand[n + 1] = minfill_tree(net);
   auto late = [&] { return probe.deadline > 0 && now_s() > probe.deadline; };
-  {
-    std::vector<std::thread> th;
-    for (int c = 1; c <= n + 2; ++c) {
-      if (c == n + 1) continue;
-      th.emplace_back([&, c] {
-        RefineOptions o;
-        o.sweeps = 200;
-        o.log2_target = probe.log2_target;
-        o.rho_weight = 0.25;
-        o.seed = (uint64_t)c;
-        o.deadline = probe.deadline;
-        cand[c] = refine_tree(net, c <= n ? cand[0] : cand[n + 1], o);
-      });
-    }
-    for (auto& t : th) t.join();
-  }
-  // Probes run in rounds of growing node budgets, 2^10, 2^12, ... 2^22: a
-  // round re-runs every unfinished probe from the start with the round's
-  // budget, and the first round in which some probe finishes decides.  Every
-  // probe's outcome in a round depends on its budget only, so the choice is
-  // the same on every run.  Within a round a finished probe with score S
-  // stops the others past S / kNodeMacs nodes: they score worse than S, and
-  // could not have been chosen.
   for (int lb = 10; lb <= 22 && !late(); lb += 2) {
     std::atomic<uint64_t> limit{uint64_t(1) << lb};
-    SearchOptions so = probe;
-    so.node_limit = &limit;
     std::vector<std::thread> th;
     for (int c = 0; c < nc; ++c)
       th.emplace_back([&, c] {
-        std::vector<LeafGroup> groups;
-        SearchStats st;
-        try {
-          bb_search(net, cand[c], so, groups, st);
-        } catch (const std::exception&) {
-          return;  // over this round's budget (or cannot be planned)
-        }
-        double macs = 0;
-        for (const auto& g : groups)
-          macs += (double)g.count * std::exp2(complexity(cand[c], g.mask).tc_log2);
-        score[c] = macs + kNodeMacs * (double)st.nodes;
-        done[c] = 1;
+        score[c] = probe_score(net, cand[c], probe, &limit);
+        if (score[c] == HUGE_VAL) return;
         const uint64_t mine = (uint64_t)std::min(std::floor(score[c] / kNodeMacs) + 1, 1e18);
         uint64_t cur = limit.load();
         while (mine < cur && !limit.compare_exchange_weak(cur, mine)) {
@@ -1121,12 +1151,35 @@ Tree choose_order(const Network& net, int n, const SearchOptions& probe, bool* c
     if (late()) break;
     int best = -1;
     for (int c = 0; c < nc; ++c)
-      if (done[c] && (best < 0 || score[c] < score[best])) best = c;
+      if (score[c] < HUGE_VAL && (best < 0 || score[c] < score[best])) best = c;
     if (best >= 0) return std::move(cand[best]);
   }
   // no probe finished within 2^22 nodes, or the deadline came first
   if (complete) *complete = !late();
   return std::move(cand[0]);
+}
+
+std::vector<Tree> rank_orders(const Network& net, int n, const SearchOptions& probe) {
+  n = std::max(1, std::min(64, n));
+  std::vector<Tree> cand = order_candidates(net, n, probe, true);
+  const int nc = (int)cand.size();
+  std::vector<double> score(nc, HUGE_VAL);
+  {
+    std::vector<std::thread> th;
+    for (int c = 0; c < nc; ++c)
+      th.emplace_back([&, c] {
+        std::atomic<uint64_t> limit{uint64_t(1) << 22};
+        score[c] = probe_score(net, cand[c], probe, &limit);
+      });
+    for (auto& t : th) t.join();
+  }
+  std::vector<int> idx;
+  for (int c = 0; c < nc; ++c)
+    if (score[c] < HUGE_VAL) idx.push_back(c);
+  std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) { return score[a] < score[b]; });
+  std::vector<Tree> out;
+  for (int c : idx) out.push_back(std::move(cand[c]));
+  return out;
 }
 
 }  // namespace bbtn

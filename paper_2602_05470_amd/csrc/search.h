@@ -96,13 +96,22 @@ std::vector<uint8_t> local_search_spinglass(int32_t n, int32_t m, const int32_t*
 std::vector<uint8_t> local_search_mwis(int32_t n, int32_t m, const int32_t* uv,
                                        const int32_t* w, int restarts, uint64_t seed);
 
-// The contraction order used for a structure: the greedy tree (n = 0) or the
-// cheapest of it and n <= 64 annealed refinements (refine_tree with seeds
-// 1..n), each scored by a branch-and-bound search of `net` with `probe`:
-// semiring MACs of its leaves plus a fixed weight per search node.  The
-// choice is deterministic.  `complete` (optional) is set to false when
-// probe.deadline cut the choice short (the greedy tree is then returned).
+// The contraction order used for a structure: the greedy tree (n = 0), the
+// min-fill tree (n < 0), or the cheapest of the greedy tree, n <= 64
+// annealed refinements of it, the min-fill tree and one refinement of that,
+// each scored by a branch-and-bound search of `net` with `probe`: a cost
+// model of its leaves (multiply-accumulates plus memory traffic) plus a
+// fixed weight per search node.  The choice is deterministic.  `complete`
+// (optional) is set to false when probe.deadline cut the choice short (the
+// greedy tree is then returned).
 Tree choose_order(const Network& net, int n, const SearchOptions& probe,
                   bool* complete = nullptr);
+
+// The candidates of choose_order with n refinements (n >= 1) and n more
+// refinements under varied annealing objectives (overflow weight 0.25 or
+// 0.1, memory weight 0, 4 or 6), each probed with a budget of 2^22 search
+// nodes, those that finish ranked by their score, cheapest first (ties in
+// candidate order).  For choosing among the first few by measurement.
+std::vector<Tree> rank_orders(const Network& net, int n, const SearchOptions& probe);
 
 }  // namespace bbtn

@@ -29,12 +29,21 @@ double now_s() {
   return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
 }
 
-TreeRef tree_for(bbtn_ctx* ctx, const Network& net, const SearchOptions* probe) {
-  static std::atomic<uint64_t> next_id{1};
+// tree ids, unique over the process (step programs are cached by them)
+std::atomic<uint64_t> next_id{1};
+
+// A network's structure: the variable lists of its simplified tensors,
+// which do not depend on couplings or weights.
+std::vector<std::vector<int32_t>> shape_of(const Network& net) {
   std::vector<std::vector<int32_t>> shape;
   shape.reserve(net.tensors.size() + 1);
   shape.push_back({net.n});
   for (const auto& T : net.tensors) shape.push_back(T.vars);
+  return shape;
+}
+
+TreeRef tree_for(bbtn_ctx* ctx, const Network& net, const SearchOptions* probe) {
+  const std::vector<std::vector<int32_t>> shape = shape_of(net);
   const bool refine = probe && ctx->opt.order_refine > 0;
   std::shared_ptr<std::promise<TreeRef>> mine;
   {
@@ -229,7 +238,8 @@ void run_pass(bbtn_ctx* ctx, const std::vector<PassItem>& items, const std::vect
         ctx->leafout.ensure((size_t)(1 + k) * L * 4);
         const DevTensor o{ctx->leafout.as<uint32_t>(), L};
         run_group(ctx, *it.net, g, bdi, mod, &asg[ii][gi][c0 * S], L, o, st,
-                  /*reuse=*/sel[gi].size() > (size_t)chunk);
+                  /*reuse=*/sel[gi].size() > (size_t)chunk, /*shared_ready=*/c0 > 0,
+                  /*L_group=*/(int64_t)sel[gi].size());
         std::vector<uint32_t> h((size_t)(1 + k) * L);
         BBTN_HIP(hipMemcpyAsync(h.data(), o.ptr, h.size() * 4, hipMemcpyDeviceToHost, st));
         BBTN_HIP(hipStreamSynchronize(st));
@@ -780,6 +790,7 @@ void solve_instances(bbtn_ctx* ctx, std::vector<Instance>& insts) {
     const int64_t value = w.use_inc ? w.incumbent : (int64_t)w.best + net.const_val;
     res->value = net.spin ? -value : value;
     res->seconds[3] = (t_values - t_planned) + (t_counted - t_values);
+    res->seconds[7] = t_values - t_planned;
     res->seconds[4] = t_cert - t_counted;
     res->seconds[5] = t_done - t_cert;
     if (res->config)
@@ -819,6 +830,36 @@ void solve_instances(bbtn_ctx* ctx, std::vector<Instance>& insts) {
     insts[i].ls_x = std::vector<uint8_t>();
     W[i] = Work();
   });
+}
+
+int order_candidates(bbtn_ctx* ctx, const Network& net) {
+  const auto shape = shape_of(net);
+  {
+    std::lock_guard<std::mutex> lk(ctx->tree_mu);
+    auto it = ctx->order_cands.find(shape);
+    if (it != ctx->order_cands.end()) return (int)it->second.size();
+  }
+  SearchOptions probe;
+  probe.log2_target = ctx->opt.log2_target;
+  probe.region_max = std::max(1, std::min(16, ctx->opt.region_max));
+  probe.values_only = ctx->opt.residues_per_pass == 0;
+  std::vector<Tree> ranked = rank_orders(net, std::max(1, ctx->opt.order_refine), probe);
+  std::vector<std::shared_ptr<const Tree>> keep;
+  for (Tree& t : ranked) keep.push_back(std::make_shared<const Tree>(std::move(t)));
+  std::lock_guard<std::mutex> lk(ctx->tree_mu);
+  if (ctx->order_cands.size() >= 8) ctx->order_cands.clear();
+  return (int)ctx->order_cands.emplace(shape, std::move(keep)).first->second.size();
+}
+
+void order_use(bbtn_ctx* ctx, const Network& net, int which) {
+  const auto shape = shape_of(net);
+  std::lock_guard<std::mutex> lk(ctx->tree_mu);
+  auto it = ctx->order_cands.find(shape);
+  BBTN_REQUIRE(it != ctx->order_cands.end(), "no order candidates for this structure");
+  BBTN_REQUIRE(which >= 0 && which < (int)it->second.size(), "order candidate out of range");
+  ctx->tree_cache.erase(shape);
+  if (ctx->tree_cache.size() >= 8) ctx->tree_cache.clear();
+  ctx->tree_cache.emplace(shape, bbtn_ctx::TreeEntry{it->second[which], next_id++});
 }
 
 }  // namespace bbtn

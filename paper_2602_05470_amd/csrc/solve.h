@@ -27,4 +27,12 @@ struct Instance {
 // status; a device failure throws and ends the call for every instance.
 void solve_instances(bbtn_ctx* ctx, std::vector<Instance>& insts);
 
+// Contraction orders measured by the caller: the candidates of net's
+// structure ranked by probe score (rank_orders with the context's
+// order_refine, T_target and region size), computed once per structure and
+// context; returns how many there are.  order_use installs candidate
+// `which` as the structure's order for every later solve on the context.
+int order_candidates(bbtn_ctx* ctx, const Network& net);
+void order_use(bbtn_ctx* ctx, const Network& net, int which);
+
 }  // namespace bbtn

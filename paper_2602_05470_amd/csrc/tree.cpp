@@ -318,8 +318,14 @@ Tree refine_tree(const Network& net, const Tree& in, const RefineOptions& o) {
       const int new_c = (int)u2.size();
       uni(nv, vb, u1);
       const int new_n = (int)u1.size();
-      const double lo = std::log2(std::ldexp(1.0, old_c) + std::ldexp(1.0, old_n));
-      const double ln = std::log2(std::ldexp(1.0, new_c) + std::ldexp(1.0, new_n));
+      // entries moved by the two contractions (the parts that change)
+      const double ka = o.kappa;
+      const double ea = std::ldexp(1.0, (int)va.size()), eb = std::ldexp(1.0, (int)vb.size());
+      const double er = std::ldexp(1.0, (int)vr.size());
+      const double mem_old = ka * (3 * ea + 3 * eb + 4 * std::ldexp(1.0, (int)vc.size()) + 3 * er);
+      const double mem_new = ka * (3 * ea + 3 * er + 4 * std::ldexp(1.0, (int)nv.size()) + 3 * eb);
+      const double lo = std::log2(std::ldexp(1.0, old_c) + std::ldexp(1.0, old_n) + mem_old);
+      const double ln = std::log2(std::ldexp(1.0, new_c) + std::ldexp(1.0, new_n) + mem_new);
       const double d = ln - lo + space((int)nv.size()) - space((int)vc.size());
       if (d > 0 && U(rng) >= std::exp(-beta * d)) continue;
       // apply: c keeps its id and becomes (a, r); n becomes (c, b)
@@ -412,6 +418,38 @@ Complexity complexity(const Tree& t, const std::vector<uint64_t>& fixed) {
     c.sc = std::max(c.sc, ro);
   }
   c.tc_log2 = tc > 0 ? std::log2(tc) : 0;
+  return c;
+}
+
+TimeCost time_cost(const Tree& t, const std::vector<uint64_t>& fixed, double kappa) {
+  TimeCost c;
+  const int N = (int)t.nodes.size();
+  std::vector<char> hasfix(N, 0);
+  std::vector<int> free_n(N, 0);
+  for (int i = 0; i < N; ++i) {
+    int f = 0;
+    for (int v : t.nodes[i].vars) {
+      const bool fx = bit_get(fixed, v);
+      f += !fx;
+      if (i < t.n_base && fx) hasfix[i] = 1;
+    }
+    free_n[i] = f;
+  }
+  std::vector<int32_t> u;
+  for (int id : t.postorder) {
+    const TNode& n = t.nodes[id];
+    hasfix[id] = hasfix[n.left] | hasfix[n.right];
+    const auto& A = t.nodes[n.left].vars;
+    const auto& B = t.nodes[n.right].vars;
+    u.clear();
+    std::set_union(A.begin(), A.end(), B.begin(), B.end(), std::back_inserter(u));
+    int ru = 0;
+    for (int v : u) ru += !bit_get(fixed, v);
+    const double cost = std::ldexp(1.0, ru) +
+                        kappa * (3 * std::ldexp(1.0, free_n[n.left]) +
+                                 3 * std::ldexp(1.0, free_n[n.right]) + std::ldexp(1.0, free_n[id]));
+    (hasfix[id] ? c.branch : c.shared) += cost;
+  }
   return c;
 }
 

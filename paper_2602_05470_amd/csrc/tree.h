@@ -51,6 +51,10 @@ struct RefineOptions {
   double rho_weight = 0.0; // per log2 entry above log2_target
   uint64_t seed = 1;
   double deadline = 0;     // absolute wall time (s) or 0: stop sweeping past it
+  // memory traffic in the move score: a contraction costs its
+  // multiply-accumulates plus kappa per entry it moves (operands read,
+  // permuted into layout and read again, output written); 0: MACs only
+  double kappa = 0;
 };
 Tree refine_tree(const Network& net, const Tree& t, const RefineOptions& o);
 
@@ -62,6 +66,17 @@ struct Complexity {
   int32_t sc = 0;
 };
 Complexity complexity(const Tree& t, const std::vector<uint64_t>& fixed);
+
+// Cost model of the tree with the variables in `fixed` sliced away, in
+// multiply-accumulate units: per contraction its multiply-accumulates plus
+// kappa per entry moved (3 |A| + 3 |B| + |C|: each operand read, permuted
+// into the product's layout and read again, the output written).  Splits
+// into the contractions of subtrees without a fixed variable, which run once
+// however many branches fix it ("shared"), and the others, once per branch.
+struct TimeCost {
+  double shared = 0, branch = 0;
+};
+TimeCost time_cost(const Tree& t, const std::vector<uint64_t>& fixed, double kappa);
 
 inline bool bit_get(const std::vector<uint64_t>& b, int v) {
   return (size_t)(v >> 6) < b.size() && ((b[v >> 6] >> (v & 63)) & 1);

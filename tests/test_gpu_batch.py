@@ -103,3 +103,26 @@ def test_failing_instance_reports_its_own_status(B):
             ctx.solve_batch(0, [bad])
     assert st[0] == -1 and st[1] == 0
     assert (rs[1].value, rs[1].count) == tm_c.spin_glass_lattice(8, 8, good["edges"], good["J"])
+
+
+@pytest.mark.parametrize("L,t,branching", [(20, 12, 1), (12, 0, 0)])
+def test_small_step_forest_matches_plain_launches(B, L, t, branching):
+    """Programs too large for the persistent executor run their small
+    once-per-pass steps as subtree tasks of one persistent launch
+    (batched = 1): the same exact results as every step its own launch
+    (batched = 2) and, without branching, as per-branch launches
+    (batched = 0), against the C
+    transfer matrix; several instances of one structure in one call (same
+    program, different base-tensor offsets) and a one-branch program
+    (branching off) included."""
+    gs = [I.spin_glass_square(L, s) for s in range(3)]
+    want = [tm_c.spin_glass_lattice(L, L, g["edges"], g["J"]) for g in gs]
+    insts = [(g["n"], g["edges"], g["J"], None) for g in gs]
+    for batched in ((1, 2, 0) if branching == 0 else (1, 2)):
+        opt = B.Options(log2_target=t, residues_per_pass=3, branching=branching, batched=batched)
+        with B.Context(opt) as ctx:
+            rs, st = ctx.solve_batch(0, insts)
+        assert st == [0] * len(gs)
+        for (n, e, J, _), r, w in zip(insts, rs, want):
+            assert (r.value, r.count) == w and r.certified, (batched, r.value, r.count, w)
+            assert config.spin_glass_energy(r.config, e, J) == r.value

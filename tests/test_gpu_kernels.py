@@ -27,6 +27,12 @@ SHAPES = [
     # thin products (power-of-two sizes, K <= 32, M or N below 32)
     (3, 1024, 8, 8), (2, 4, 2048, 16), (7, 2, 2, 32), (1, 16, 16, 4), (4, 256, 2, 1),
     (1, 1, 4096, 32),
+    # staged thin products (contiguous, at least 4096 outputs): rows form
+    # (N <= 16) with blocks inside a batch, spanning several batches, a
+    # ragged last block and K = 32; columns form (M <= 16, N >= 32) with
+    # several column blocks per batch
+    (3, 2048, 16, 32), (1000, 4, 2, 2), (2, 8192, 1, 1), (333, 1, 16, 8),
+    (5, 16, 1024, 32), (9, 1, 8192, 2), (33, 8, 64, 4), (2, 2, 4096, 1),
 ]
 
 
@@ -225,7 +231,7 @@ def test_bound_matches_oracle(ctx):
 VALUE_SHAPES = [
     (1, 128, 128, 32), (1, 130, 257, 45), (2, 256, 384, 96), (1, 64, 512, 1024),
     (3, 129, 131, 7), (1, 512, 512, 300), (2, 1, 200, 33), (1, 300, 2, 64),
-    (4, 512, 4, 16),
+    (4, 512, 4, 16), (1000, 4, 2, 2), (5, 16, 1024, 32), (3, 2048, 16, 32),
 ]
 
 

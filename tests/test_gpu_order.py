@@ -116,3 +116,27 @@ def test_field_and_weights_refined_order(B):
         r = ctx.solve_mwis(k["n"], k["edges"], k["w"])
     assert (r.value, r.count) == tuple(want) and r.certified
     assert config.independent_set_weight(r.config, k["edges"], k["w"]) == want[0]
+
+
+def test_measured_order_candidates(B):
+    """bbtn_order_candidates / bbtn_order_use: every ranked candidate order of
+    the 24 x 24 lattice, installed for the structure, gives the same exact
+    ground energy and degeneracy (both seeds, against the transfer matrix);
+    a candidate index out of range, or a structure without candidates, is an
+    argument error."""
+    want = {s: (e, d) for s, e, d in _golden("sg24.txt")}
+    gs = [I.spin_glass_square(24, s) for s in range(2)]
+    with B.Context(B.Options(log2_target=16, order_refine=4)) as ctx:
+        n = ctx.order_candidates(0, gs[0]["n"], gs[0]["edges"], gs[0]["J"])
+        assert 1 <= n <= 2 * 4 + 3
+        # the same structure: the list is built once
+        assert ctx.order_candidates(0, gs[1]["n"], gs[1]["edges"], gs[1]["J"]) == n
+        for i in range(min(n, 3)):
+            ctx.order_use(0, gs[0]["n"], gs[0]["edges"], gs[0]["J"], which=i)
+            for s, g in enumerate(gs):
+                _check_sg(ctx.solve_spinglass(g["n"], g["edges"], g["J"]), g, want[s])
+        with pytest.raises(B.BBTNError):
+            ctx.order_use(0, gs[0]["n"], gs[0]["edges"], gs[0]["J"], which=n)
+        other = I.spin_glass_square(20, 0)
+        with pytest.raises(B.BBTNError):
+            ctx.order_use(0, other["n"], other["edges"], other["J"], which=0)
