@@ -599,6 +599,8 @@ def main():
                     help="tile autotuner cache file for the headline run (products of 2^24 "
                          "MACs or more are timed over the tile candidates on first use, in "
                          "the warm-up)")
+    ap.add_argument("--head-log2-target", type=int, default=26,
+                    help="log2 T_target of the headline's branching")
     ap.add_argument("--order-refine", type=int, default=32,
                     help="annealed refinements among the headline's candidate orders")
     ap.add_argument("--order-tune", type=int, default=8,
@@ -645,7 +647,7 @@ def main():
     # ---- headline: +-J 32x32
     sg32 = golden_values("sg32_values.txt")
     scorer_sg = os.path.join(ROOT, "paper_2602_05470_amd", "scorer_sg.bin")
-    head_opts = B.Options(log2_target=26, residues_per_pass=args.residues,
+    head_opts = B.Options(log2_target=args.head_log2_target, residues_per_pass=args.residues,
                           branching=args.branching, batched=1, order_refine=args.order_refine,
                           time_limit_s=600,
                           spin_flip=1, scorer_weights=scorer_sg if args.branching == 2 else None,
@@ -676,18 +678,20 @@ def main():
         "dtype": "int32",
         "data": "synthetic",
         "config": {"workload": "+-J spin glass 32x32 open lattice, seeds 0-19 (step i solves "
-                               "seed i mod 20), zero field; BBTN T_target=2^26, %s, %s, "
+                               "seed i mod 20), zero field; BBTN T_target=2^%d, %s, %s, "
                                "spin-flip symmetry (one spin fixed, count doubled), %d primes "
                                "per pass plus a fused certification prime; one step = one "
                                "call solving one instance"
-                               % ("contraction order chosen by measurement in the warm-up"
+                               % (args.head_log2_target,
+                                  "contraction order chosen by measurement in the warm-up"
                                   if h["tuned"] is not None else "refined contraction order",
                                   "learned branching scorer" if args.branching == 2
                                   else "plain planner", args.residues),
                    "instances": h["n"], "exact": h["exact"],
                    "leaves_per_instance": h["leaves_per_instance"],
                    "macs_per_instance": h["macs_per_instance"],
-                   "log2_target": 26, "residues_per_pass": args.residues, "contraction_order":
+                   "log2_target": args.head_log2_target, "residues_per_pass": args.residues,
+                   "contraction_order":
                    order_desc,
                    "branching": "learned scorer" if args.branching == 2 else "plain planner",
                    "exactness": "certified count, E0 equal to the matching oracle's stored "

@@ -236,7 +236,7 @@ void run_group(bbtn_ctx* ctx, const Network& net, const GroupPlan& g, const Base
   if (part_entries > 0) ctx->partial.ensure((size_t)W * part_entries * 4);
   // values pass: every partial sum of the network is bounded by the sum of
   // its |couplings| and |fields| (or weights), so small networks take the
-  // packed 16-bit product for large steps
+  // packed 16-bit product for steps with M and N of at least 32
   const bool vals16 = k == 0 && net.abs_sum < kValues16Bound;
   // shared steps first (once), then the branch steps
   std::vector<size_t> order;
@@ -291,7 +291,7 @@ void run_group(bbtn_ctx* ctx, const Network& net, const GroupPlan& g, const Base
       const TuneVal tv = tvs[si];
       DevTensor part{};
       if (tv.splits > 1) part = DevTensor{ctx->partial.as<uint32_t>(), (int64_t)tv.splits * batch * M * N};
-      const bool packed = vals16 && M >= 128 && N >= 128;
+      const bool packed = vals16 && M >= 32 && N >= 32;
       const int kid = !packed && tgemm_is_thin(sh, tv.splits) ? K_THIN : K_TGEMM;
       const int ph = ctx->prof.begin(st, kid);
       if (packed)

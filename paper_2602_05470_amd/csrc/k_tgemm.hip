@@ -770,9 +770,11 @@ __global__ void __launch_bounds__((TM / RM) * (TN / RN)) tgemm_v16_kernel(const 
   }
 }
 
-// Tile of the packed kernel: 128 x 128 outputs, 8 x 8 per thread, 32-deep
-// slices.
+// Tiles of the packed kernel: 128 x 128 outputs, 8 x 8 per thread, 32-deep
+// slices; products with M or N below 128 take 64 x 64 tiles, 4 x 4 per
+// thread (less of the tile past the edge).
 constexpr int V16_TM = 128, V16_TN = 128, V16_RM = 8, V16_RN = 8, V16_TK = 32;
+constexpr int V16S_TM = 64, V16S_TN = 64, V16S_RM = 4, V16S_RN = 4;
 
 // LDS slice depth for KR residues: the configuration's TK, halved while the
 // tile's operand slices (values and KR residue planes) would pass 64 KiB.
@@ -906,16 +908,22 @@ void launch_tgemm_values16(const GemmShape& s, DevTensor A, DevTensor B, DevTens
     a.C = C.ptr; a.pC = C.pstride; a.sCb = s.sCb; a.sCsplit = 0;
   }
   a.splits = nsp; a.kchunk = kchunk;
-  a.tiles_m = (a.M + V16_TM - 1) / V16_TM;
-  a.tiles_n = (a.N + V16_TN - 1) / V16_TN;
+  const bool small = a.M < V16_TM || a.N < V16_TN;
+  const int tm = small ? V16S_TM : V16_TM, tn = small ? V16S_TN : V16_TN;
+  a.tiles_m = (a.M + tm - 1) / tm;
+  a.tiles_n = (a.N + tn - 1) / tn;
   a.total = a.tiles_m * a.tiles_n * a.splits * a.batch;
   auto al16 = [](const void* p) { return ((uintptr_t)p & 15u) == 0; };
   a.vec_a = a.K % 4 == 0 && a.kchunk % 4 == 0 && al16(a.A) && (a.batch == 1 || a.sAb % 4 == 0);
   a.vec_b = a.N % 4 == 0 && al16(a.B) && (a.batch == 1 || a.sBb % 4 == 0);
   const int64_t cap = 1ll << 20;
   dim3 grid((unsigned)(a.total <= cap ? a.total : cap));
-  launch_kernel((tgemm_v16_kernel<V16_TM, V16_TN, V16_RM, V16_RN, V16_TK>), grid,
-                dim3((V16_TM / V16_RM) * (V16_TN / V16_RN)), 0, st, nsp <= 1, a);
+  if (small)
+    launch_kernel((tgemm_v16_kernel<V16S_TM, V16S_TN, V16S_RM, V16S_RN, V16_TK>), grid,
+                  dim3((V16S_TM / V16S_RM) * (V16S_TN / V16S_RN)), 0, st, nsp <= 1, a);
+  else
+    launch_kernel((tgemm_v16_kernel<V16_TM, V16_TN, V16_RM, V16_RN, V16_TK>), grid,
+                  dim3((V16_TM / V16_RM) * (V16_TN / V16_RN)), 0, st, nsp <= 1, a);
   BBTN_LAUNCHED("tgemm (packed 16-bit values, grid " + std::to_string(a.total) + ")");
   if (nsp > 1) launch_reduce(0, a.mod, outer, nsp, outer, 1, partial, C, st);
 }

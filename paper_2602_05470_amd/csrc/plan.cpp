@@ -171,10 +171,28 @@ GroupPlan build_plan(const Network& net, const Tree& tree,
                        : free_vars(tree.nodes[rb_].vars, fixed);
     const auto C = dfr ? with_fx(free_vars(n.vars, fixed), id) : free_vars(n.vars, fixed);
     const auto AB = isect(A, B);
-    const auto batch = isect(AB, C);
-    const auto K = minus(AB, C);
-    const auto M = isect(minus(A, B), C);
-    const auto N = isect(minus(B, A), C);
+    auto batch = isect(AB, C);
+    auto K = minus(AB, C);
+    auto M = isect(minus(A, B), C);
+    auto N = isect(minus(B, A), C);
+    // Order within each index group: the product needs A as [K][M][batch]
+    // and B as [N][K][batch], any order inside a group.  Following the
+    // stored layouts makes an operand's permutation a regrouping of long
+    // runs, or no permutation at all: M follows A's layout, N follows B's,
+    // K and batch (shared by both) follow the larger operand's.
+    {
+      const auto& LA = status[ra] == BASE ? tree.nodes[ra].vars : layout[ra];
+      const auto& LB = status[rb_] == BASE ? tree.nodes[rb_].vars : layout[rb_];
+      auto by = [](std::vector<int32_t>& v, const std::vector<int32_t>& L) {
+        auto pos = [&](int32_t x) { return std::find(L.begin(), L.end(), x) - L.begin(); };
+        std::stable_sort(v.begin(), v.end(), [&](int32_t x, int32_t y) { return pos(x) < pos(y); });
+      };
+      const auto& LP = A.size() >= B.size() ? LA : LB;
+      by(K, LP);
+      by(batch, LP);
+      by(M, LA);
+      by(N, LB);
+    }
     if (!minus(minus(A, B), C).empty() || !minus(minus(B, A), C).empty())
       throw Error(BBTN_E_INTERNAL, "plan: variable private to one operand");
     Step s;

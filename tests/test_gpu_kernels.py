@@ -232,6 +232,7 @@ VALUE_SHAPES = [
     (1, 128, 128, 32), (1, 130, 257, 45), (2, 256, 384, 96), (1, 64, 512, 1024),
     (3, 129, 131, 7), (1, 512, 512, 300), (2, 1, 200, 33), (1, 300, 2, 64),
     (4, 512, 4, 16), (1000, 4, 2, 2), (5, 16, 1024, 32), (3, 2048, 16, 32),
+    (7, 96, 40, 50), (3, 33, 65, 300), (2, 64, 64, 256),
 ]
 
 
