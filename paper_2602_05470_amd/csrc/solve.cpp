@@ -725,7 +725,8 @@ void solve_instances(bbtn_ctx* ctx, std::vector<Instance>& insts) {
   }
   const double t_counted = now_s();
   // ---- certification: by size, else one further prime must agree with the
-  // CRT value; otherwise a full pass of k more primes, until max_primes
+  // CRT value; otherwise a pass of k more primes plus a check prime, until
+  // max_primes
   for (;;) {
     std::vector<size_t> need;
     std::vector<std::vector<int>> one;
@@ -754,8 +755,11 @@ void solve_instances(bbtn_ctx* ctx, std::vector<Instance>& insts) {
       w.residues.push_back(r);
       w.count = crt_garner(w.residues, primes_of(w.used, w.used.size()));
       if (agree) { w.certified = 1; return; }
+      // k more primes, and one more in the same pass (when the entry has
+      // room) that checks the CRT value of all the others: one pass instead
+      // of a pass of k primes followed by a one-prime check pass
       std::vector<int> m;
-      for (int p = 0; p < k && (int)w.used.size() + p < max_primes; ++p)
+      for (int p = 0; p < k + 1 && p < KMAX && (int)w.used.size() + p < max_primes; ++p)
         m.push_back((int)w.used.size() + p);
       if (!m.empty()) { more_idx.push_back(i); more.push_back(m); }
     });
@@ -764,6 +768,12 @@ void solve_instances(bbtn_ctx* ctx, std::vector<Instance>& insts) {
         Work& w = W[i];
         sum_into(i, w.pc, ids);
         for (int id : ids) w.used.push_back(id);
+        if (ids.size() >= 2 && (int)ids.size() == std::min(k + 1, KMAX)) {
+          const size_t nb = w.used.size() - 1;
+          const std::vector<uint32_t> head(w.residues.begin(), w.residues.begin() + nb);
+          const auto x = crt_garner(head, primes_of(w.used, nb));
+          if (bigint_mod(x, P[w.used[nb]]) == w.residues[nb]) w.certified = 1;
+        }
         w.count = crt_garner(w.residues, primes_of(w.used, w.used.size()));
       });
     bool progress = false;
