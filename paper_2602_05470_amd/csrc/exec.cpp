@@ -258,8 +258,53 @@ void run_group(bbtn_ctx* ctx, const Network& net, const GroupPlan& g, const Base
       DevTensor opnd[2];
       const Operand* ops[2] = {&s.a, &s.b};
       const int ranks[2] = {(int)s.a_vars.size(), (int)s.b_vars.size()};
+      const TuneVal tv = tvs[si];
+      const bool packed = vals16 && s.rm >= 5 && s.rn >= 5;
+      // packed products read a permuted intermediate operand in place (no
+      // gathered copy) when a tile's rows and k slice cover the 64 lowest
+      // source entries; lanes walk whichever of the two covers more
+      bool fuse[2] = {false, false};
+      FusedOp fop[2]{};
+      // (not in programs that keep every operand for the traceback)
+      if (packed && tv.splits <= 1 && !g.keep_all) {
+        const bool small = s.rm < 7 || s.rn < 7;  // 64-wide tiles, else 128
+        const int tb = small ? 6 : 7;
+        for (int w = 0; w < 2; ++w) {
+          const Operand& op = *ops[w];
+          if (op.base || op.direct || !op.fixed_pos.empty() ||
+              (int)op.src_bits.size() != op.r_in || op.r_in > 30)
+            continue;
+          // layout bits of the row index (m of A, n of B) and of k
+          const int row_lo = w == 0 ? s.rk : 0, row_n = std::min(tb, w == 0 ? s.rm : s.rn);
+          const int k_lo = w == 0 ? 0 : s.rn, k_n = std::min(5, s.rk);
+          // lowest source bits 0, 1, ... that are images of the given
+          // layout bit ranges
+          auto cover = [&](int lo1, int n1, int lo2, int n2) {
+            int c = 0;
+            for (;; ++c) {
+              bool hit = false;
+              for (int j = lo1; j < lo1 + n1; ++j) hit |= op.src_bits[j] == c;
+              for (int j = lo2; j < lo2 + n2; ++j) hit |= op.src_bits[j] == c;
+              if (!hit) return c;
+            }
+          };
+          // the tile's rows and k slice together cover the lowest 64 source
+          // entries: every source line a tile touches is used whole while
+          // the tile is staged
+          if (cover(row_lo, row_n, k_lo, k_n) < 6) continue;
+          const int cr = cover(row_lo, row_n, 0, 0), ck = cover(k_lo, k_n, 0, 0);
+          FusedOp& f = fop[w];
+          f.src = buf(op.id).ptr;
+          f.stride = g.buf_region[op.id] == R_SHARED ? 0 : (1ll << op.r_in);
+          f.rb = s.rb;
+          f.fast = cr >= ck ? 1 : 0;
+          for (int j = 0; j < op.r_in; ++j) f.bits[j] = (int8_t)op.src_bits[j];
+          fuse[w] = true;
+        }
+      }
       for (int w = 0; w < 2; ++w) {
         const Operand& op = *ops[w];
+        if (fuse[w]) continue;
         if (op.base) {
           const GatherPlan gp = make_gather_plan(op.r_in, ranks[w], op.src_bits.data());
           const DevTensor src{bd.t.ptr + bd.off[op.id], bd.total};
@@ -288,13 +333,14 @@ void run_group(bbtn_ctx* ctx, const Network& net, const GroupPlan& g, const Base
       const int64_t M = 1ll << s.rm, N = 1ll << s.rn, K = 1ll << s.rk;
       const int64_t batch = Ls << s.rb;
       GemmShape sh{batch, M, N, K, M * K, K * N, M * N};
-      const TuneVal tv = tvs[si];
       DevTensor part{};
       if (tv.splits > 1) part = DevTensor{ctx->partial.as<uint32_t>(), (int64_t)tv.splits * batch * M * N};
-      const bool packed = vals16 && M >= 32 && N >= 32;
       const int kid = !packed && tgemm_is_thin(sh, tv.splits) ? K_THIN : K_TGEMM;
       const int ph = ctx->prof.begin(st, kid);
-      if (packed)
+      if (fuse[0] || fuse[1])
+        launch_tgemm_values16_fused(sh, fuse[0] ? &fop[0] : nullptr, opnd[0],
+                                    fuse[1] ? &fop[1] : nullptr, opnd[1], buf(s.out), st);
+      else if (packed)
         launch_tgemm_values16(sh, opnd[0], opnd[1], buf(s.out), tv.splits, part, st);
       else
         launch_tgemm(k, mod, sh, opnd[0], opnd[1], buf(s.out), tv.cfg, tv.splits, part, st);

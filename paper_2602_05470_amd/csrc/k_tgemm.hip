@@ -661,13 +661,24 @@ __device__ __forceinline__ uint32_t to16(int32_t v) {
   return (uint32_t)(uint16_t)(int16_t)(v > NEG_CUT ? v : NEG16);
 }
 
-template <int TM, int TN, int RM, int RN, int TK>
-__device__ __forceinline__ void tgemm_v16_tile(const GemmArgs& a, int64_t w) {
+// perm of x over layout bits [lo, lo + n)
+__device__ __forceinline__ int64_t fperm(const FusedOp& f, int64_t x, int lo, int n) {
+  int64_t r = 0;
+  for (int j = 0; j < n; ++j)
+    if ((x >> j) & 1) r |= 1ll << f.bits[lo + j];
+  return r;
+}
+
+template <int TM, int TN, int RM, int RN, int TK, bool FA = false, bool FB = false>
+__device__ __forceinline__ void tgemm_v16_tile(const GemmArgs& a, int64_t w, const FusedOp& fa,
+                                               const FusedOp& fb) {
   constexpr int TX = TN / RN, TY = TM / RM, NT = TX * TY;
   constexpr int RP = RN / 2;          // packed column pairs per thread
   constexpr int TMP = TM + 4;         // padded rows of the transposed A tile
   __shared__ __attribute__((aligned(16))) uint32_t As[TK][TMP];
   __shared__ __attribute__((aligned(16))) uint32_t Bs[TK][TN / 2];
+  // fused operands: source offsets of the tile's low row and k indices
+  __shared__ int32_t a_row[FA ? TM : 1], a_k[FA ? TK : 1], b_col[FB ? TN : 1], b_k[FB ? TK : 1];
   int64_t tm_i, tn_i, t;
   tile_coords(xcd_remap(w, a.total), a.tiles_m, a.tiles_n, tm_i, tn_i, t);
   const int64_t sp = t % a.splits;
@@ -679,13 +690,56 @@ __device__ __forceinline__ void tgemm_v16_tile(const GemmArgs& a, int64_t w) {
   const int tx = tid % TX, ty = tid / TX;
   const uint32_t* Ab = a.A + b * a.sAb;
   const uint32_t* Bb = a.B + b * a.sBb;
+  // log2 sizes (M, N, K are powers of two on the fused paths)
+  int lm = 0, ln = 0, lk = 0;
+  const uint32_t* fsA = nullptr;
+  const uint32_t* fsB = nullptr;
+  if constexpr (FA || FB) {
+    while ((1ll << lm) < a.M) ++lm;
+    while ((1ll << ln) < a.N) ++ln;
+    while ((1ll << lk) < a.K) ++lk;
+  }
+  if constexpr (FA) {
+    // A layout bits: k [0, lk), m [lk, lk + lm), batch [lk + lm, + rb)
+    const int64_t l = b >> fa.rb, bb = b & ((1ll << fa.rb) - 1);
+    fsA = fa.src + l * fa.stride + (fperm(fa, m0, lk, lm) | fperm(fa, bb, lk + lm, fa.rb));
+    for (int i = tid; i < TM; i += NT) a_row[i] = (int32_t)fperm(fa, i, lk, lm);
+    for (int j = tid; j < TK; j += NT) a_k[j] = (int32_t)fperm(fa, j, 0, lk);
+  }
+  if constexpr (FB) {
+    // B layout bits: n [0, ln), k [ln, ln + lk), batch [ln + lk, + rb)
+    const int64_t l = b >> fb.rb, bb = b & ((1ll << fb.rb) - 1);
+    fsB = fb.src + l * fb.stride + (fperm(fb, n0, 0, ln) | fperm(fb, bb, ln + lk, fb.rb));
+    for (int i = tid; i < TN; i += NT) b_col[i] = (int32_t)fperm(fb, i, 0, ln);
+    for (int j = tid; j < TK; j += NT) b_k[j] = (int32_t)fperm(fb, j, ln, lk);
+  }
+  if constexpr (FA || FB) __syncthreads();
   s16x2 V[RM][RP];
 #pragma unroll
   for (int r = 0; r < RM; ++r)
 #pragma unroll
     for (int c = 0; c < RP; ++c) V[r][c] = s16x2{-32768, -32768};
   for (int64_t k0 = kbeg; k0 < kend; k0 += TK) {
-    if (a.vec_a) {
+    if constexpr (FA) {
+      const uint32_t* src = fsA + fperm(fa, k0, 0, lk);
+      if (fa.fast) {
+#pragma unroll 1
+        for (int idx = tid; idx < TM * TK; idx += NT) {
+          const int i = idx % TM, j = idx / TM;
+          const bool in = m0 + i < a.M && k0 + j < kend;
+          const int32_t v = in ? (int32_t)src[a_row[i] | a_k[j]] : NEG;
+          As[j][i] = to16(v) * 0x10001u;
+        }
+      } else {
+#pragma unroll 1
+        for (int idx = tid; idx < TM * TK; idx += NT) {
+          const int i = idx / TK, j = idx % TK;
+          const bool in = m0 + i < a.M && k0 + j < kend;
+          const int32_t v = in ? (int32_t)src[a_row[i] | a_k[j]] : NEG;
+          As[j][i] = to16(v) * 0x10001u;
+        }
+      }
+    } else if (a.vec_a) {
       constexpr int KV = TK / 4;
 #pragma unroll 1
       for (int idx = tid; idx < TM * KV; idx += NT) {
@@ -707,7 +761,28 @@ __device__ __forceinline__ void tgemm_v16_tile(const GemmArgs& a, int64_t w) {
         As[j][i] = to16(v) * 0x10001u;
       }
     }
-    if (a.vec_b) {
+    if constexpr (FB) {
+      const uint32_t* src = fsB + fperm(fb, k0, ln, lk);
+      if (fb.fast) {
+#pragma unroll 1
+        for (int idx = tid; idx < TK * (TN / 2); idx += NT) {
+          const int j = idx / (TN / 2), i = (idx % (TN / 2)) * 2;
+          const bool in = k0 + j < kend;
+          const int32_t v0 = (in && n0 + i < a.N) ? (int32_t)src[b_col[i] | b_k[j]] : NEG;
+          const int32_t v1 = (in && n0 + i + 1 < a.N) ? (int32_t)src[b_col[i + 1] | b_k[j]] : NEG;
+          Bs[j][i / 2] = to16(v0) | to16(v1) << 16;
+        }
+      } else {
+#pragma unroll 1
+        for (int idx = tid; idx < TK * (TN / 2); idx += NT) {
+          const int j = idx % TK, i = (idx / TK) * 2;
+          const bool in = k0 + j < kend;
+          const int32_t v0 = (in && n0 + i < a.N) ? (int32_t)src[b_col[i] | b_k[j]] : NEG;
+          const int32_t v1 = (in && n0 + i + 1 < a.N) ? (int32_t)src[b_col[i + 1] | b_k[j]] : NEG;
+          Bs[j][i / 2] = to16(v0) | to16(v1) << 16;
+        }
+      }
+    } else if (a.vec_b) {
       constexpr int NV = TN / 4;
 #pragma unroll 1
       for (int idx = tid; idx < TK * NV; idx += NT) {
@@ -764,8 +839,18 @@ __device__ __forceinline__ void tgemm_v16_tile(const GemmArgs& a, int64_t w) {
 
 template <int TM, int TN, int RM, int RN, int TK>
 __global__ void __launch_bounds__((TM / RM) * (TN / RN)) tgemm_v16_kernel(const GemmArgs a) {
+  const FusedOp none{};
   for (int64_t w = blockIdx.x; w < a.total; w += gridDim.x) {
-    tgemm_v16_tile<TM, TN, RM, RN, TK>(a, w);
+    tgemm_v16_tile<TM, TN, RM, RN, TK>(a, w, none, none);
+    __syncthreads();
+  }
+}
+
+template <int TM, int TN, int RM, int RN, int TK, bool FA, bool FB>
+__global__ void __launch_bounds__((TM / RM) * (TN / RN))
+tgemm_v16_fused_kernel(const GemmArgs a, const FusedOp fa, const FusedOp fb) {
+  for (int64_t w = blockIdx.x; w < a.total; w += gridDim.x) {
+    tgemm_v16_tile<TM, TN, RM, RN, TK, FA, FB>(a, w, fa, fb);
     __syncthreads();
   }
 }
@@ -926,6 +1011,50 @@ void launch_tgemm_values16(const GemmShape& s, DevTensor A, DevTensor B, DevTens
                   dim3((V16_TM / V16_RM) * (V16_TN / V16_RN)), 0, st, nsp <= 1, a);
   BBTN_LAUNCHED("tgemm (packed 16-bit values, grid " + std::to_string(a.total) + ")");
   if (nsp > 1) launch_reduce(0, a.mod, outer, nsp, outer, 1, partial, C, st);
+}
+
+void launch_tgemm_values16_fused(const GemmShape& s, const FusedOp* fa, DevTensor A,
+                                 const FusedOp* fb, DevTensor B, DevTensor C, hipStream_t st) {
+  BBTN_REQUIRE(s.M >= 1 && s.N >= 1 && s.K >= 1 && s.batch >= 1, "empty tgemm");
+  BBTN_REQUIRE(fa || fb, "fused product without a fused operand");
+  for (int64_t x : {s.M, s.N, s.K})
+    BBTN_REQUIRE((x & (x - 1)) == 0, "fused product needs power-of-two sizes");
+  GemmArgs a{};
+  a.A = A.ptr; a.B = B.ptr;
+  a.pA = A.pstride; a.pB = B.pstride;
+  a.M = s.M; a.N = s.N; a.K = s.K; a.batch = s.batch;
+  a.sAb = s.sAb; a.sBb = s.sBb;
+  a.mod = make_moduli(0, nullptr);
+  a.C = C.ptr; a.pC = C.pstride; a.sCb = s.sCb; a.sCsplit = 0;
+  a.splits = 1; a.kchunk = s.K;
+  const bool small = a.M < V16_TM || a.N < V16_TN;
+  const int tm = small ? V16S_TM : V16_TM, tn = small ? V16S_TN : V16_TN;
+  a.tiles_m = (a.M + tm - 1) / tm;
+  a.tiles_n = (a.N + tn - 1) / tn;
+  a.total = a.tiles_m * a.tiles_n * a.batch;
+  auto al16 = [](const void* p) { return ((uintptr_t)p & 15u) == 0; };
+  a.vec_a = !fa && a.K % 4 == 0 && al16(a.A) && (a.batch == 1 || a.sAb % 4 == 0);
+  a.vec_b = !fb && a.N % 4 == 0 && al16(a.B) && (a.batch == 1 || a.sBb % 4 == 0);
+  const FusedOp none{};
+  const FusedOp& ra = fa ? *fa : none;
+  const FusedOp& rbo = fb ? *fb : none;
+  const int64_t cap = 1ll << 20;
+  dim3 grid((unsigned)(a.total <= cap ? a.total : cap));
+#define BBTN_FV(TM_, TN_, RM_, RN_, FA_, FB_)                                                 \
+  launch_kernel((tgemm_v16_fused_kernel<TM_, TN_, RM_, RN_, V16_TK, FA_, FB_>), grid,        \
+                dim3((TM_ / RM_) * (TN_ / RN_)), 0, st, true, a, ra, rbo)
+  if (small) {
+    if (fa && fb) BBTN_FV(V16S_TM, V16S_TN, V16S_RM, V16S_RN, true, true);
+    else if (fa) BBTN_FV(V16S_TM, V16S_TN, V16S_RM, V16S_RN, true, false);
+    else BBTN_FV(V16S_TM, V16S_TN, V16S_RM, V16S_RN, false, true);
+  } else {
+    if (fa && fb) BBTN_FV(V16_TM, V16_TN, V16_RM, V16_RN, true, true);
+    else if (fa) BBTN_FV(V16_TM, V16_TN, V16_RM, V16_RN, true, false);
+    else BBTN_FV(V16_TM, V16_TN, V16_RM, V16_RN, false, true);
+  }
+#undef BBTN_FV
+  BBTN_LAUNCHED("tgemm (packed 16-bit values, permuted operands, grid " +
+                std::to_string(a.total) + ")");
 }
 
 void launch_tgemm_values(const GemmShape& s, const int32_t* A, const int32_t* B,

@@ -50,6 +50,28 @@ void launch_tgemm_values16(const GemmShape& s, DevTensor A, DevTensor B, DevTens
                            int splits, DevTensor partial, hipStream_t st);
 constexpr int64_t kValues16Bound = 1 << 12;  // |v| below this for the packed path
 
+// Operand read through a bit permutation instead of a gathered copy: entry
+// e of the operand's product layout ([K][M][batch] for A, [N][K][batch] for
+// B) is source entry l * stride + perm(e) of branch l = batch index >> rb,
+// where perm moves bit j of e to bit bits[j] (a bijection of the operand's
+// bits; OR-linear over disjoint bit sets, so perm(m0 + i) = perm(m0) |
+// perm(i) for tile-aligned m0).  `fast` = 1 when lanes should walk the
+// row index (m for A, n for B) to read consecutive source words, 0 when they
+// should walk k.
+struct FusedOp {
+  const uint32_t* src;
+  int64_t stride;      // entries between branches (0: one tensor for all)
+  int32_t rb;          // batch bits of the operand per branch
+  int32_t fast;
+  int8_t bits[40];     // source bit of layout bit j
+};
+
+// The packed values product (k = 0, |v| < kValues16Bound) with one or both
+// operands read through FusedOp instead of A / B (whose pointers are then
+// unused for that operand); power-of-two M, N, K, unsplit.
+void launch_tgemm_values16_fused(const GemmShape& s, const FusedOp* fa, DevTensor A,
+                                 const FusedOp* fb, DevTensor B, DevTensor C, hipStream_t st);
+
 // Entries of the split-K partial buffer launch_tgemm needs for `splits`
 // chunks of K with tile config `cfg` and outer = batch * M * N outputs (0 when
 // the product runs unsplit).
