@@ -247,7 +247,7 @@ void run_group(bbtn_ctx* ctx, const Network& net, const GroupPlan& g, const Base
   auto issue = [&]() {
     if (!fr.tasks.empty() && !shared_ready) {
       const int ph = ctx->prof.begin(st, K_PERSIST);
-      launch_small_forest(fr, k, mod, bd, fdev, st);
+      launch_small_forest(fr, k, mod, bd, fdev, st, ws);
       ctx->prof.end(ph, st, K_PERSIST, fr.ops, fr.bytes);
     }
     for (size_t si : order) {

@@ -475,7 +475,11 @@ SmallForest plan_small_forest(const GroupPlan& g, const std::vector<int64_t>& ba
   const int n = (int)g.steps.size();
   f.in.assign(n, 0);
   f.root_off.assign(g.buf_entries.size(), -1);
-  if (g.keep_all || n == 0) return f;
+  if (n == 0) return f;
+  // in place: a keep-all program of one branch, values only (its buffers
+  // are disjoint, W = 1)
+  f.in_place = g.keep_all;
+  if (g.keep_all && (L != 1 || k != 0)) return f;
   // operand staging within the default 64 KiB of LDS
   int rmax = 0;
   while (rmax < P_MAX_RANK &&
@@ -506,7 +510,7 @@ SmallForest plan_small_forest(const GroupPlan& g, const std::vector<int64_t>& ba
     const int c = cons[out];
     const bool root = c < 0 || !f.in[c] || out == g.root_buf;
     task_of[i] = root ? n_tasks++ : task_of[c];
-    if (root) {
+    if (root && !f.in_place) {
       f.root_off[out] = f.root_entries;
       f.root_entries += g.buf_entries[out];
     }
@@ -528,7 +532,7 @@ SmallForest plan_small_forest(const GroupPlan& g, const std::vector<int64_t>& ba
     for (int j = 0; j < (int)m.size(); ++j) local[m[j]] = j;
     int64_t peak = 0;
     std::vector<std::array<int64_t, 3>> busy;  // off, end, last use
-    for (int j = 0; j < (int)m.size(); ++j) {
+    for (int j = 0; j < (int)m.size() && !f.in_place; ++j) {
       const Step& s = g.steps[m[j]];
       if (f.root_off[s.out] >= 0) continue;
       const int last = local.at(cons[s.out]);
@@ -557,7 +561,10 @@ SmallForest plan_small_forest(const GroupPlan& g, const std::vector<int64_t>& ba
       const Step& s = g.steps[i];
       PStep ps{};
       ps.rb = s.rb; ps.rm = s.rm; ps.rn = s.rn; ps.rk = s.rk;
-      if (f.root_off[s.out] >= 0) {
+      if (f.in_place) {
+        ps.c_kind = PK_SCRATCH;  // the workspace (W = 1, one branch)
+        ps.c_off = g.buf_off[s.out];
+      } else if (f.root_off[s.out] >= 0) {
         ps.c_kind = PK_SHARED;
         ps.c_off = (int64_t)W * f.root_off[s.out];
         ps.c_stride = (int32_t)g.buf_entries[s.out];
@@ -577,12 +584,14 @@ SmallForest plan_small_forest(const GroupPlan& g, const std::vector<int64_t>& ba
           po.src_off = base_off[op.id];
         } else {
           po.kind = PK_SCRATCH;
-          po.src_off = scr_off[op.id];
+          po.src_off = f.in_place ? g.buf_off[op.id] : scr_off[op.id];
           if (po.src_off < 0) throw Error(BBTN_E_INTERNAL, "small forest: operand outside its task");
         }
         po.rank = rank;
         for (int j = 0; j < rank; ++j) po.bitpos[j / 4] |= (uint32_t)op.src_bits[j] << (8 * (j % 4));
-        po.mat_off = -1;
+        // in place, gathered operands are materialised where the traceback
+        // reads them
+        po.mat_off = (f.in_place && op.temp >= 0) ? g.buf_off[op.temp] : -1;
         po.slot = -1;
       }
       f.steps.push_back(ps);
@@ -626,7 +635,7 @@ size_t small_forest_bytes(const SmallForest& f, int k) {
 }
 
 void launch_small_forest(const SmallForest& f, int k, const Moduli& mod, const BaseDev& bd,
-                         uint8_t* dev, hipStream_t st) {
+                         uint8_t* dev, hipStream_t st, uint32_t* workspace) {
   if (f.tasks.empty()) return;
   const size_t o_prog = small_forest_prog_off(f, k);
   const size_t o_tasks = align_up(f.steps.size() * sizeof(PStep));
@@ -652,6 +661,14 @@ void launch_small_forest(const SmallForest& f, int k, const Moduli& mod, const B
   a.lds_entries = 1ll << f.max_rank;
   a.arena_entries = 0;
   a.per_task_scratch = 0;
+  if (f.in_place) {
+    // every task addresses the workspace itself: per-task scratch at a
+    // stride of zero entries (one plane, W = 1)
+    BBTN_REQUIRE(workspace != nullptr && k == 0, "in-place forest needs the values workspace");
+    a.scratch = workspace;
+    a.scratch_entries = 0;
+    a.per_task_scratch = 1;
+  }
   a.queue = (unsigned long long*)(dev + o_prog + o_queue);
   a.mod = mod;
   launch_persist(k, a, (int)forest_blocks(f, k), f.threads, st);

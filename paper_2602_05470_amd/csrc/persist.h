@@ -51,6 +51,11 @@ struct SmallForest {
   std::vector<PStep> steps;       // the tasks' steps, task after task
   std::vector<PTask> tasks;       // largest first
   double ops = 0, bytes = 0;      // semiring operations and operand bytes
+  // A program that keeps every intermediate (configuration recovery: one
+  // branch, values only) runs its forest in place: every output and every
+  // staged operand is written to its own buffer of the program's
+  // workspace, where the traceback reads it (no root region, no scratch).
+  bool in_place = false;
 };
 // base_off: entry offset of every base tensor in the base buffer; L: branches
 // the program runs for.
@@ -62,8 +67,9 @@ size_t small_forest_bytes(const SmallForest& f, int k);
 size_t small_forest_prog_off(const SmallForest& f, int k);
 std::vector<uint8_t> small_forest_image(const SmallForest& f);
 // Launch the forest (program already copied to the device buffer at dev);
-// base tensors as in BaseDev.
+// base tensors as in BaseDev; `workspace`: the program's workspace, for a
+// forest run in place.
 void launch_small_forest(const SmallForest& f, int k, const Moduli& mod, const BaseDev& bd,
-                         uint8_t* dev, hipStream_t st);
+                         uint8_t* dev, hipStream_t st, uint32_t* workspace = nullptr);
 
 }  // namespace bbtn
