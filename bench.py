@@ -608,6 +608,8 @@ def main():
                          "instances each and keep the fastest (0: probe score alone)")
     ap.add_argument("--ksg-seeds", type=int, default=8,
                     help="seeds of the 40x40 King's subgraph leg (0 .. n-1)")
+    ap.add_argument("--only-sg16", action="store_true",
+                    help="run the 16x16 leg alone and print its JSON (profiling)")
     ap.add_argument("--micro-only", action="store_true",
                     help="only the counting-product micro-benchmark and a copy of known size "
                          "(for hardware-counter runs)")
@@ -628,6 +630,18 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     import paper_2602_05470_amd as B
     import instances as I
+    if args.only_sg16:
+        # the 16x16 leg alone (for profiling the persistent executor)
+        ncpu = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+        leg = sg16_leg(B, I, torch, ncpu, args)
+        if args.calibration_copy:
+            x = torch.ones(128 << 20, dtype=torch.int32, device="cuda")
+            y = torch.empty_like(x)
+            y.copy_(x)
+            torch.cuda.synchronize()
+            leg["calibration_copy_bytes_each_way"] = 512 << 20
+        print(json.dumps(leg), flush=True)
+        return
     if args.micro_only:
         ctx = B.Context(B.Options())
         res = tgemm_micro(B, ctx, torch)
