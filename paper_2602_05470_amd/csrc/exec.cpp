@@ -364,7 +364,10 @@ void run_group(bbtn_ctx* ctx, const Network& net, const GroupPlan& g, const Base
   if (reuse && ctx->opt.graphs && !ctx->prof.on && g.steps.size() >= 2) {
     uint64_t off_hash = 1469598103934665603ull;  // FNV-1a over the base offsets
     for (int64_t o : bd.off) off_hash = (off_hash ^ (uint64_t)o) * 1099511628211ull;
-    const GraphKey key{(const void*)&g, L, k, ctx->work.p, ctx->partial.p, ctx->fixbits.p,
+    // keyed by the program's unique id, not its address: a program freed
+    // from the cache and another allocated at the same address must not
+    // replay the first one's graph
+    const GraphKey key{(const void*)(uintptr_t)g.uid, L, k, ctx->work.p, ctx->partial.p, ctx->fixbits.p,
                        ctx->leafconst.p, (void*)out.ptr, (void*)bd.t.ptr, mod.p[0],
                        ctx->shared_ws.p, (void*)fdev, off_hash, shared_ready};
     auto it = ctx->graphs.find(key);

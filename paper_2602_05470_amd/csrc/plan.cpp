@@ -2,6 +2,7 @@
 #include "kernels.h"
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <iterator>
 #include <map>
@@ -66,7 +67,9 @@ std::vector<int32_t> cat3(const std::vector<int32_t>& a, const std::vector<int32
 
 GroupPlan build_plan(const Network& net, const Tree& tree,
                      const std::vector<uint64_t>& fixed, bool keep_all, int defer_log2) {
+  static std::atomic<uint64_t> next_uid{1};
   GroupPlan g;
+  g.uid = next_uid++;
   g.fixed = fixed;
   g.keep_all = keep_all;
   for (int v = 0; v < net.n; ++v)

@@ -65,6 +65,7 @@ struct GroupPlan {
   double macs = 0;                  // per branch (branch steps)
   double shared_macs = 0;           // per pass (shared steps)
   int32_t n_branch_steps = 0;
+  uint64_t uid = 0;                 // unique over the process (keys of captured graphs)
 };
 
 // keep_all: never reuse buffers and materialise every operand in its
