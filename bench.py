@@ -722,13 +722,13 @@ def main():
         ko = B.Options(log2_target=28, residues_per_pass=3, branching=1, batched=1,
                        order_refine=8, time_limit_s=600, host_threads=max(1, ncpu // 2))
         kr = single_instance_run(B, I, torch, 1, 40, ko, list(range(args.ksg_seeds)), [100],
-                                 ksg, "ksg40x40", workers=2)
+                                 ksg, "ksg40x40", workers=3)
         line["ksg40x40"] = {
             "value": round(3600.0 * kr["exact"] / kr["dt"], 1), "unit": "instances/hour",
             "workload": "unweighted MIS on King's subgraph 40x40, fill 0.8, seeds 0-%d; BBTN "
                         "T_target=2^28, refined order chosen per instance (every seed is "
                         "another graph), 3 primes per pass plus a fused certification prime; "
-                        "one instance per call, 2 concurrent contexts" % (args.ksg_seeds - 1),
+                        "one instance per call, 3 concurrent contexts" % (args.ksg_seeds - 1),
             "instances": kr["n"], "exact": kr["exact"],
             "seconds": round(kr["dt"], 3),
             "leaves_per_instance": kr["leaves_per_instance"],
