@@ -50,8 +50,11 @@ __global__ void __launch_bounds__(256) gather_kernel(const GatherArgs g) {
     }
     if (g.fixed) src |= g.fixed[l] & g.fixed_mask;
     const int64_t s = (int64_t)src + l * g.in_stride;
+    uint32_t v[PLANES];  // every plane's load in flight before the stores
 #pragma unroll
-    for (int p = 0; p < PLANES; ++p) g.out[p * g.pout + e] = g.in[p * g.pin + s];
+    for (int p = 0; p < PLANES; ++p) v[p] = g.in[p * g.pin + s];
+#pragma unroll
+    for (int p = 0; p < PLANES; ++p) g.out[p * g.pout + e] = v[p];
   }
 }
 
@@ -116,7 +119,18 @@ __global__ void __launch_bounds__(256) gather_tiled_kernel(const GatherArgs g, c
 #pragma unroll 1
     for (int p = 0; p < PLANES; ++p) {
       const uint32_t* in = g.in + p * g.pin + ibase;
-      for (int x = tid; x < tsize; x += 256) buf[tile_slot(x)] = in[in_lo[x & 63] + in_hi[x >> 6]];
+      // all of a thread's loads in flight before the first LDS store
+      uint32_t v[(1 << TILE_MAX_BITS) / 256];
+#pragma unroll
+      for (int j = 0; j < (1 << TILE_MAX_BITS) / 256; ++j) {
+        const int x = tid + 256 * j;
+        if (x < tsize) v[j] = in[in_lo[x & 63] + in_hi[x >> 6]];
+      }
+#pragma unroll
+      for (int j = 0; j < (1 << TILE_MAX_BITS) / 256; ++j) {
+        const int x = tid + 256 * j;
+        if (x < tsize) buf[tile_slot(x)] = v[j];
+      }
       __syncthreads();
       uint32_t* out = g.out + p * g.pout + ob;
       for (int u = tid; u < tsize; u += 256)
@@ -196,7 +210,7 @@ void launch_gather(int k, const GatherPlan& gp, int64_t L, int64_t in_stride,
   const GatherTile t = choose_tile(gp);
   if (t.tb > 0) {
     const int64_t tiles = L << t.n_rest;
-    const int64_t blocks = std::min<int64_t>(tiles, 256 * 32);
+    const int64_t blocks = std::min<int64_t>(tiles, 256 * 256);
     dim3 grid((unsigned)blocks), block(256);
     switch (k) {
       case 0: launch_kernel(gather_tiled_kernel<1>, grid, block, 0, st, true, g, t); break;
@@ -210,7 +224,7 @@ void launch_gather(int k, const GatherPlan& gp, int64_t L, int64_t in_stride,
     BBTN_LAUNCHED("gather (tiled)");
     return;
   }
-  const int64_t blocks = std::min<int64_t>((total + 255) / 256, 256 * 64);
+  const int64_t blocks = std::min<int64_t>((total + 255) / 256, 256 * 256);
   dim3 grid((unsigned)blocks), block(256);
   switch (k) {
     case 0: launch_kernel(gather_kernel<1>, grid, block, 0, st, true, g); break;

@@ -151,6 +151,15 @@ def test_tgemm_rejects_bad_prime(ctx):
     dict(r_in=18, src=[9, 10, 11, 12, 13, 14, 15, 16, 17, 0, 2, 4, 6, 8], L=2, fixed="rand",
          per_leaf=True),
     dict(r_in=20, src=list(range(8, 20)) + list(range(2, 8)), L=1, fixed="rand"),
+    # direct and tiled paths with per-branch fixed bits above the runs,
+    # short low runs, a plane stride and a start that are not multiples of
+    # four entries
+    dict(r_in=10, src=[0, 1, 2, 3, 4, 5, 6, 7], L=5, fixed="rand"),
+    dict(r_in=9, src=[0, 1, 5, 6, 2, 3], L=3, fixed="rand", per_leaf=True),
+    dict(r_in=6, src=[0, 1], L=1, fixed="rand"),
+    dict(r_in=7, src=[0, 3, 1, 2], L=2, fixed="rand"),
+    dict(r_in=8, src=[0, 1, 2, 3, 4, 5, 6, 7], L=1, fixed=None, pad=1),
+    dict(r_in=8, src=[0, 1, 2, 3, 7, 6, 5], L=2, fixed="rand", shift=1),
 ])
 @pytest.mark.parametrize("k", [0, 3, 4])
 def test_gather_matches_oracle(ctx, case, k):
@@ -166,8 +175,15 @@ def test_gather_matches_oracle(ctx, case, k):
     fb = np.array([sum(b << j for j, b in fv.items()) for fv in fixed_vals], np.uint64)
     dfb = torch.from_numpy(fb.view(np.int64)).to("cuda") if free else None
     out = empty_dev(torch, k, L << len(src))
+    pad, shift = case.get("pad", 0), case.get("shift", 0)
+    pv = np.concatenate([v, np.zeros(pad, np.int32)])
+    pr = np.concatenate([r, np.zeros((k, pad), np.uint32)], axis=1)
+    din = to_dev(torch, np.concatenate([np.zeros(shift, np.int32), pv]),
+                 np.zeros((0, shift + pv.size), np.uint32))
+    if k:  # residue planes after the value plane, each n_in + pad entries
+        din = torch.cat([din, to_dev(torch, pr[0], pr[1:])])
     ctx.gather(k, r_in, len(src), src, L, (1 << r_in) if per_leaf else 0, dfb,
-               to_dev(torch, v, r), n_in, out)
+               din[shift:], n_in + pad, out)
     gv, gr = from_dev(out, k, L << len(src))
     for l in range(L):
         off = (l << r_in) if per_leaf else 0
