@@ -145,7 +145,7 @@ void reduce_dispatch(const ReduceArgs& a, hipStream_t st) {
     const int64_t blocks = std::min<int64_t>(a.outer, 4096);
     launch_kernel(reduce_block_kernel<KR>, dim3((unsigned)blocks), dim3(256), 0, st, true, a);
   } else {
-    const int64_t blocks = std::min<int64_t>((a.outer + 255) / 256, 256 * 64);
+    const int64_t blocks = std::min<int64_t>((a.outer + 255) / 256, 256 * 256);
     launch_kernel(reduce_thread_kernel<KR>, dim3((unsigned)blocks), dim3(256), 0, st, true, a);
   }
 }

@@ -429,6 +429,23 @@ __global__ void __launch_bounds__(256) tgemm_thin_kernel(const GemmArgs a, int l
   }
 }
 
+// Copies n <= 256 * PER words into LDS, word e from src[index(e)], with
+// every load of a thread issued before its first LDS store.
+template <int PER, typename F>
+__device__ __forceinline__ void stage_words(uint32_t* dst, int n, int tid, F src) {
+  uint32_t v[PER];
+#pragma unroll
+  for (int j = 0; j < PER; ++j) {
+    const int e = tid + 256 * j;
+    if (e < n) v[j] = src(e);
+  }
+#pragma unroll
+  for (int j = 0; j < PER; ++j) {
+    const int e = tid + 256 * j;
+    if (e < n) dst[e] = v[j];
+  }
+}
+
 // Staged thin products for large contiguous operands (A rows, B and C
 // without batch gaps).  The one-thread-per-output kernel above re-reads the
 // wide operand once per row of the narrow side, and with gigabyte operands
@@ -461,9 +478,9 @@ tgemm_thin_rows_kernel(const GemmArgs a, int lm, int ln, int lk, int lbr, int b_
 #pragma unroll
     for (int p = 0; p < W; ++p) {
       const uint32_t* srcA = a.A + p * a.pA + (r0 << lk);
-      for (int e = tid; e < na; e += 256) As[p * a_cap + e] = srcA[e];
+      stage_words<4>(As + p * a_cap, na, tid, [&](int e) { return srcA[e]; });
       const uint32_t* srcB = a.B + p * a.pB + (b0 << (lk + ln));
-      for (int e = tid; e < nbe; e += 256) Bs[p * b_cap + e] = srcB[e];
+      stage_words<4>(Bs + p * b_cap, nbe, tid, [&](int e) { return srcB[e]; });
     }
     __syncthreads();
     const int nout = rows << ln;
@@ -522,9 +539,11 @@ tgemm_thin_cols_kernel(const GemmArgs a, int lm, int ln, int lk, int lbn) {
 #pragma unroll
     for (int p = 0; p < W; ++p) {
       const uint32_t* srcA = a.A + p * a.pA + (b << (lm + lk));
-      for (int e = tid; e < a_cap; e += 256) As[p * a_cap + e] = srcA[e];
+      stage_words<2>(As + p * a_cap, a_cap, tid, [&](int e) { return srcA[e]; });
       const uint32_t* srcB = a.B + p * a.pB + (b << (lk + ln)) + n0;
-      for (int e = tid; e < b_cap; e += 256) Bs[p * b_cap + e] = srcB[((int64_t)(e >> lbn) << ln) + (e & (BN - 1))];
+      stage_words<8>(Bs + p * b_cap, b_cap, tid, [&](int e) {
+        return srcB[((int64_t)(e >> lbn) << ln) + (e & (BN - 1))];
+      });
     }
     __syncthreads();
     const int nout = 1 << (lm + lbn);
@@ -596,7 +615,7 @@ static bool launch_thin_staged(int k, const GemmArgs& a, int lm, int ln, int lk,
     const int b_cap = (lbr > lm ? (1 << (lbr - lm)) : 1) << (lk + ln);
     const size_t lds = (size_t)W * ((1u << (lbr + lk)) + b_cap) * 4;
     const int64_t tiles = (R + (1 << lbr) - 1) >> lbr;
-    dim3 grid((unsigned)std::min<int64_t>(tiles, 256 * 16)), block(256);
+    dim3 grid((unsigned)std::min<int64_t>(tiles, 256 * 256)), block(256);
     switch (k) {
 #define BBTN_TR(KK) case KK: launch_kernel(tgemm_thin_rows_kernel<KK>, grid, block, (uint32_t)lds, st, true, a, lm, ln, lk, lbr, b_cap); break;
       BBTN_TR(0) BBTN_TR(1) BBTN_TR(2) BBTN_TR(3) BBTN_TR(4) BBTN_TR(5)
@@ -612,7 +631,7 @@ static bool launch_thin_staged(int k, const GemmArgs& a, int lm, int ln, int lk,
     lbn = std::min(lbn, 10);
     const size_t lds = (size_t)W * ((1u << (lm + lk)) + (1u << (lk + lbn))) * 4;
     const int64_t tiles = a.batch << (ln - lbn);
-    dim3 grid((unsigned)std::min<int64_t>(tiles, 256 * 16)), block(256);
+    dim3 grid((unsigned)std::min<int64_t>(tiles, 256 * 256)), block(256);
     switch (k) {
 #define BBTN_TC(KK) case KK: launch_kernel(tgemm_thin_cols_kernel<KK>, grid, block, (uint32_t)lds, st, true, a, lm, ln, lk, lbn); break;
       BBTN_TC(0) BBTN_TC(1) BBTN_TC(2) BBTN_TC(3) BBTN_TC(4) BBTN_TC(5)
@@ -629,7 +648,7 @@ static void launch_thin(int k, const GemmArgs& a, hipStream_t st) {
   const int lm = exact_log2(a.M), ln = exact_log2(a.N), lk = exact_log2(a.K);
   if (launch_thin_staged(k, a, lm, ln, lk, st)) return;
   const int64_t total = a.batch << (lm + ln);
-  const int64_t blocks = std::min<int64_t>((total + 255) / 256, 256 * 64);
+  const int64_t blocks = std::min<int64_t>((total + 255) / 256, 256 * 256);
   dim3 grid((unsigned)blocks), block(256);
   switch (k) {
     case 0: launch_kernel(tgemm_thin_kernel<0>, grid, block, 0, st, true, a, lm, ln, lk); break;
