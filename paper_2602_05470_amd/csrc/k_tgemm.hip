@@ -680,6 +680,29 @@ __device__ __forceinline__ uint32_t to16(int32_t v) {
   return (uint32_t)(uint16_t)(int16_t)(v > NEG_CUT ? v : NEG16);
 }
 
+// Moves the N items of a tile slice through registers: thread tid handles
+// items tid, tid + NT, ..., loading G of them (all in flight together)
+// before storing those G, which bounds the registers the batch holds.
+template <int NT, int N, typename Load, typename Store, int G = 4>
+__device__ __forceinline__ void stage_tile(int tid, Load ld, Store stv) {
+  constexpr int PER = (N + NT - 1) / NT;
+  constexpr int GG = PER < G ? PER : G;
+#pragma unroll 1
+  for (int u0 = 0; u0 < PER; u0 += GG) {
+    decltype(ld(0)) v[GG];
+#pragma unroll
+    for (int u = 0; u < GG; ++u) {
+      const int idx = tid + (u0 + u) * NT;
+      if ((N % NT == 0 && PER % GG == 0) || (u0 + u < PER && idx < N)) v[u] = ld(idx);
+    }
+#pragma unroll
+    for (int u = 0; u < GG; ++u) {
+      const int idx = tid + (u0 + u) * NT;
+      if ((N % NT == 0 && PER % GG == 0) || (u0 + u < PER && idx < N)) stv(idx, v[u]);
+    }
+  }
+}
+
 // perm of x over layout bits [lo, lo + n)
 __device__ __forceinline__ int64_t fperm(const FusedOp& f, int64_t x, int lo, int n) {
   int64_t r = 0;
@@ -739,89 +762,87 @@ __device__ __forceinline__ void tgemm_v16_tile(const GemmArgs& a, int64_t w, con
 #pragma unroll
     for (int c = 0; c < RP; ++c) V[r][c] = s16x2{-32768, -32768};
   for (int64_t k0 = kbeg; k0 < kend; k0 += TK) {
+    // Staging: each thread issues all of its loads of the slice before its
+    // first LDS store (stage_tile), so they are in flight together.
     if constexpr (FA) {
       const uint32_t* src = fsA + fperm(fa, k0, 0, lk);
       if (fa.fast) {
-#pragma unroll 1
-        for (int idx = tid; idx < TM * TK; idx += NT) {
+        stage_tile<NT, TM * TK>(tid, [&](int idx) {
           const int i = idx % TM, j = idx / TM;
-          const bool in = m0 + i < a.M && k0 + j < kend;
-          const int32_t v = in ? (int32_t)src[a_row[i] | a_k[j]] : NEG;
-          As[j][i] = to16(v) * 0x10001u;
-        }
+          return (m0 + i < a.M && k0 + j < kend) ? (int32_t)src[a_row[i] | a_k[j]] : NEG;
+        }, [&](int idx, int32_t v) { As[idx / TM][idx % TM] = to16(v) * 0x10001u; });
       } else {
-#pragma unroll 1
-        for (int idx = tid; idx < TM * TK; idx += NT) {
+        stage_tile<NT, TM * TK>(tid, [&](int idx) {
           const int i = idx / TK, j = idx % TK;
-          const bool in = m0 + i < a.M && k0 + j < kend;
-          const int32_t v = in ? (int32_t)src[a_row[i] | a_k[j]] : NEG;
-          As[j][i] = to16(v) * 0x10001u;
-        }
+          return (m0 + i < a.M && k0 + j < kend) ? (int32_t)src[a_row[i] | a_k[j]] : NEG;
+        }, [&](int idx, int32_t v) { As[idx % TK][idx / TK] = to16(v) * 0x10001u; });
       }
     } else if (a.vec_a) {
       constexpr int KV = TK / 4;
-#pragma unroll 1
-      for (int idx = tid; idx < TM * KV; idx += NT) {
-        const int i = idx / KV, j = (idx % KV) * 4;
-        const int64_t m = m0 + i, q = k0 + j;
+      stage_tile<NT, TM * KV>(tid, [&](int idx) {
+        const int64_t m = m0 + idx / KV, q = k0 + (idx % KV) * 4;
         uint4 v = make_uint4((uint32_t)NEG, (uint32_t)NEG, (uint32_t)NEG, (uint32_t)NEG);
         if (m < a.M && q < kend) v = *(const uint4*)(Ab + m * a.K + q);
+        return v;
+      }, [&](int idx, uint4 v) {
+        const int i = idx / KV, j = (idx % KV) * 4;
         As[j][i] = to16((int32_t)v.x) * 0x10001u;
         As[j + 1][i] = to16((int32_t)v.y) * 0x10001u;
         As[j + 2][i] = to16((int32_t)v.z) * 0x10001u;
         As[j + 3][i] = to16((int32_t)v.w) * 0x10001u;
-      }
+      });
     } else {
-#pragma unroll 1
-      for (int idx = tid; idx < TM * TK; idx += NT) {
-        const int i = idx / TK, j = idx % TK;
-        const int64_t m = m0 + i, q = k0 + j;
-        const int32_t v = (m < a.M && q < kend) ? (int32_t)Ab[m * a.K + q] : NEG;
-        As[j][i] = to16(v) * 0x10001u;
-      }
+      stage_tile<NT, TM * TK>(tid, [&](int idx) {
+        const int64_t m = m0 + idx / TK, q = k0 + idx % TK;
+        return (m < a.M && q < kend) ? (int32_t)Ab[m * a.K + q] : NEG;
+      }, [&](int idx, int32_t v) { As[idx % TK][idx / TK] = to16(v) * 0x10001u; });
     }
     if constexpr (FB) {
       const uint32_t* src = fsB + fperm(fb, k0, ln, lk);
       if (fb.fast) {
-#pragma unroll 1
-        for (int idx = tid; idx < TK * (TN / 2); idx += NT) {
+        stage_tile<NT, TK * (TN / 2)>(tid, [&](int idx) {
           const int j = idx / (TN / 2), i = (idx % (TN / 2)) * 2;
           const bool in = k0 + j < kend;
           const int32_t v0 = (in && n0 + i < a.N) ? (int32_t)src[b_col[i] | b_k[j]] : NEG;
           const int32_t v1 = (in && n0 + i + 1 < a.N) ? (int32_t)src[b_col[i + 1] | b_k[j]] : NEG;
-          Bs[j][i / 2] = to16(v0) | to16(v1) << 16;
-        }
+          return make_int2(v0, v1);
+        }, [&](int idx, int2 v) {
+          Bs[idx / (TN / 2)][idx % (TN / 2)] = to16(v.x) | to16(v.y) << 16;
+        });
       } else {
-#pragma unroll 1
-        for (int idx = tid; idx < TK * (TN / 2); idx += NT) {
+        stage_tile<NT, TK * (TN / 2)>(tid, [&](int idx) {
           const int j = idx % TK, i = (idx / TK) * 2;
           const bool in = k0 + j < kend;
           const int32_t v0 = (in && n0 + i < a.N) ? (int32_t)src[b_col[i] | b_k[j]] : NEG;
           const int32_t v1 = (in && n0 + i + 1 < a.N) ? (int32_t)src[b_col[i + 1] | b_k[j]] : NEG;
-          Bs[j][i / 2] = to16(v0) | to16(v1) << 16;
-        }
+          return make_int2(v0, v1);
+        }, [&](int idx, int2 v) {
+          Bs[idx % TK][idx / TK] = to16(v.x) | to16(v.y) << 16;
+        });
       }
     } else if (a.vec_b) {
       constexpr int NV = TN / 4;
-#pragma unroll 1
-      for (int idx = tid; idx < TK * NV; idx += NT) {
-        const int j = idx / NV, i = (idx % NV) * 4;
-        const int64_t n = n0 + i, q = k0 + j;
+      stage_tile<NT, TK * NV>(tid, [&](int idx) {
+        const int64_t n = n0 + (idx % NV) * 4, q = k0 + idx / NV;
         uint4 v = make_uint4((uint32_t)NEG, (uint32_t)NEG, (uint32_t)NEG, (uint32_t)NEG);
         if (n < a.N && q < kend) v = *(const uint4*)(Bb + q * a.N + n);
-        *(uint2*)&Bs[j][i / 2] = make_uint2(to16((int32_t)v.x) | to16((int32_t)v.y) << 16,
-                                            to16((int32_t)v.z) | to16((int32_t)v.w) << 16);
-      }
+        return v;
+      }, [&](int idx, uint4 v) {
+        *(uint2*)&Bs[idx / NV][(idx % NV) * 2] =
+            make_uint2(to16((int32_t)v.x) | to16((int32_t)v.y) << 16,
+                       to16((int32_t)v.z) | to16((int32_t)v.w) << 16);
+      });
     } else {
-#pragma unroll 1
-      for (int idx = tid; idx < TK * (TN / 2); idx += NT) {
+      stage_tile<NT, TK * (TN / 2)>(tid, [&](int idx) {
         const int j = idx / (TN / 2), i = (idx % (TN / 2)) * 2;
         const int64_t n = n0 + i, q = k0 + j;
         const bool in = q < kend;
         const int32_t v0 = (in && n < a.N) ? (int32_t)Bb[q * a.N + n] : NEG;
         const int32_t v1 = (in && n + 1 < a.N) ? (int32_t)Bb[q * a.N + n + 1] : NEG;
-        Bs[j][i / 2] = to16(v0) | to16(v1) << 16;
-      }
+        return make_int2(v0, v1);
+      }, [&](int idx, int2 v) {
+        Bs[idx / (TN / 2)][idx % (TN / 2)] = to16(v.x) | to16(v.y) << 16;
+      });
     }
     __syncthreads();
 #pragma unroll 4
