@@ -37,24 +37,38 @@ struct GatherArgs {
 
 template <int PLANES>
 __global__ void __launch_bounds__(256) gather_kernel(const GatherArgs g) {
+  // U entries a grid stride apart per thread and step, so that a thread has
+  // about four loads in flight whatever the number of planes
+  constexpr int U = PLANES >= 4 ? 1 : 4 / PLANES;
   const int64_t total = g.L << g.r_out;
   const int64_t omask = (1ll << g.r_out) - 1;
-  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
-       e += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t l = e >> g.r_out;
-    const uint64_t i = (uint64_t)(e & omask);
-    uint64_t src = 0;
-    for (int r = 0; r < g.n_runs; ++r) {
-      const GatherRun run = g.runs[r];
-      src |= ((i >> run.out_lo) & ((1ull << run.len) - 1)) << run.in_lo;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t e0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e0 < total;
+       e0 += stride * U) {
+    uint32_t v[U][PLANES];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t e = e0 + u * stride;
+      if (u > 0 && e >= total) break;
+      const int64_t l = e >> g.r_out;
+      const uint64_t i = (uint64_t)(e & omask);
+      uint64_t src = 0;
+      for (int r = 0; r < g.n_runs; ++r) {
+        const GatherRun run = g.runs[r];
+        src |= ((i >> run.out_lo) & ((1ull << run.len) - 1)) << run.in_lo;
+      }
+      if (g.fixed) src |= g.fixed[l] & g.fixed_mask;
+      const int64_t s = (int64_t)src + l * g.in_stride;
+#pragma unroll
+      for (int p = 0; p < PLANES; ++p) v[u][p] = g.in[p * g.pin + s];
     }
-    if (g.fixed) src |= g.fixed[l] & g.fixed_mask;
-    const int64_t s = (int64_t)src + l * g.in_stride;
-    uint32_t v[PLANES];  // every plane's load in flight before the stores
 #pragma unroll
-    for (int p = 0; p < PLANES; ++p) v[p] = g.in[p * g.pin + s];
+    for (int u = 0; u < U; ++u) {
+      const int64_t e = e0 + u * stride;
+      if (u > 0 && e >= total) break;
 #pragma unroll
-    for (int p = 0; p < PLANES; ++p) g.out[p * g.pout + e] = v[p];
+      for (int p = 0; p < PLANES; ++p) g.out[p * g.pout + e] = v[u][p];
+    }
   }
 }
 
