@@ -683,7 +683,7 @@ __device__ __forceinline__ uint32_t to16(int32_t v) {
 // Moves the N items of a tile slice through registers: thread tid handles
 // items tid, tid + NT, ..., loading G of them (all in flight together)
 // before storing those G, which bounds the registers the batch holds.
-template <int NT, int N, typename Load, typename Store, int G = 4>
+template <int NT, int N, int G = 4, typename Load, typename Store>
 __device__ __forceinline__ void stage_tile(int tid, Load ld, Store stv) {
   constexpr int PER = (N + NT - 1) / NT;
   constexpr int GG = PER < G ? PER : G;
@@ -717,6 +717,10 @@ __device__ __forceinline__ void tgemm_v16_tile(const GemmArgs& a, int64_t w, con
   constexpr int TX = TN / RN, TY = TM / RM, NT = TX * TY;
   constexpr int RP = RN / 2;          // packed column pairs per thread
   constexpr int TMP = TM + 4;         // padded rows of the transposed A tile
+  // loads in flight per thread while staging: four for the 64-wide tiles,
+  // two (one when reading in place) for the 128-wide ones, whose 32
+  // accumulator registers leave less room (more would cut their occupancy)
+  constexpr int SG = TM < 128 ? 4 : (FA || FB) ? 1 : 2;
   __shared__ __attribute__((aligned(16))) uint32_t As[TK][TMP];
   __shared__ __attribute__((aligned(16))) uint32_t Bs[TK][TN / 2];
   // fused operands: source offsets of the tile's low row and k indices
@@ -767,19 +771,19 @@ __device__ __forceinline__ void tgemm_v16_tile(const GemmArgs& a, int64_t w, con
     if constexpr (FA) {
       const uint32_t* src = fsA + fperm(fa, k0, 0, lk);
       if (fa.fast) {
-        stage_tile<NT, TM * TK>(tid, [&](int idx) {
+        stage_tile<NT, TM * TK, SG>(tid, [&](int idx) {
           const int i = idx % TM, j = idx / TM;
           return (m0 + i < a.M && k0 + j < kend) ? (int32_t)src[a_row[i] | a_k[j]] : NEG;
         }, [&](int idx, int32_t v) { As[idx / TM][idx % TM] = to16(v) * 0x10001u; });
       } else {
-        stage_tile<NT, TM * TK>(tid, [&](int idx) {
+        stage_tile<NT, TM * TK, SG>(tid, [&](int idx) {
           const int i = idx / TK, j = idx % TK;
           return (m0 + i < a.M && k0 + j < kend) ? (int32_t)src[a_row[i] | a_k[j]] : NEG;
         }, [&](int idx, int32_t v) { As[idx % TK][idx / TK] = to16(v) * 0x10001u; });
       }
     } else if (a.vec_a) {
       constexpr int KV = TK / 4;
-      stage_tile<NT, TM * KV>(tid, [&](int idx) {
+      stage_tile<NT, TM * KV, SG>(tid, [&](int idx) {
         const int64_t m = m0 + idx / KV, q = k0 + (idx % KV) * 4;
         uint4 v = make_uint4((uint32_t)NEG, (uint32_t)NEG, (uint32_t)NEG, (uint32_t)NEG);
         if (m < a.M && q < kend) v = *(const uint4*)(Ab + m * a.K + q);
@@ -792,7 +796,7 @@ __device__ __forceinline__ void tgemm_v16_tile(const GemmArgs& a, int64_t w, con
         As[j + 3][i] = to16((int32_t)v.w) * 0x10001u;
       });
     } else {
-      stage_tile<NT, TM * TK>(tid, [&](int idx) {
+      stage_tile<NT, TM * TK, SG>(tid, [&](int idx) {
         const int64_t m = m0 + idx / TK, q = k0 + idx % TK;
         return (m < a.M && q < kend) ? (int32_t)Ab[m * a.K + q] : NEG;
       }, [&](int idx, int32_t v) { As[idx % TK][idx / TK] = to16(v) * 0x10001u; });
@@ -800,7 +804,7 @@ __device__ __forceinline__ void tgemm_v16_tile(const GemmArgs& a, int64_t w, con
     if constexpr (FB) {
       const uint32_t* src = fsB + fperm(fb, k0, ln, lk);
       if (fb.fast) {
-        stage_tile<NT, TK * (TN / 2)>(tid, [&](int idx) {
+        stage_tile<NT, TK * (TN / 2), SG>(tid, [&](int idx) {
           const int j = idx / (TN / 2), i = (idx % (TN / 2)) * 2;
           const bool in = k0 + j < kend;
           const int32_t v0 = (in && n0 + i < a.N) ? (int32_t)src[b_col[i] | b_k[j]] : NEG;
@@ -810,7 +814,7 @@ __device__ __forceinline__ void tgemm_v16_tile(const GemmArgs& a, int64_t w, con
           Bs[idx / (TN / 2)][idx % (TN / 2)] = to16(v.x) | to16(v.y) << 16;
         });
       } else {
-        stage_tile<NT, TK * (TN / 2)>(tid, [&](int idx) {
+        stage_tile<NT, TK * (TN / 2), SG>(tid, [&](int idx) {
           const int j = idx % TK, i = (idx / TK) * 2;
           const bool in = k0 + j < kend;
           const int32_t v0 = (in && n0 + i < a.N) ? (int32_t)src[b_col[i] | b_k[j]] : NEG;
@@ -822,7 +826,7 @@ __device__ __forceinline__ void tgemm_v16_tile(const GemmArgs& a, int64_t w, con
       }
     } else if (a.vec_b) {
       constexpr int NV = TN / 4;
-      stage_tile<NT, TK * NV>(tid, [&](int idx) {
+      stage_tile<NT, TK * NV, SG>(tid, [&](int idx) {
         const int64_t n = n0 + (idx % NV) * 4, q = k0 + idx / NV;
         uint4 v = make_uint4((uint32_t)NEG, (uint32_t)NEG, (uint32_t)NEG, (uint32_t)NEG);
         if (n < a.N && q < kend) v = *(const uint4*)(Bb + q * a.N + n);
@@ -833,7 +837,7 @@ __device__ __forceinline__ void tgemm_v16_tile(const GemmArgs& a, int64_t w, con
                        to16((int32_t)v.z) | to16((int32_t)v.w) << 16);
       });
     } else {
-      stage_tile<NT, TK * (TN / 2)>(tid, [&](int idx) {
+      stage_tile<NT, TK * (TN / 2), SG>(tid, [&](int idx) {
         const int j = idx / (TN / 2), i = (idx % (TN / 2)) * 2;
         const int64_t n = n0 + i, q = k0 + j;
         const bool in = q < kend;
