@@ -3,11 +3,13 @@
 Headline workload (the largest configuration the solver reaches on one GPU):
 +-J spin glass on a 32 x 32 open-boundary lattice, couplings +-1 from numpy
 seeds 0-19, zero field.  BBTN with T_target = 2^26 entries, the contraction
-order refined by annealing (chosen once for the lattice during the warm-up
-and cached), the learned branching scorer (its candidate variables added to
-the planner's), the spin-flip symmetry of the zero-field energy (one spin fixed
-to +1, the count doubled: half the contraction work), counts as residues
-modulo 3 primes per pass plus one fused certification prime.  One step = one call through the C ABI that fully
+order chosen among annealed refinements by timing them in the warm-up (once
+for the lattice, then cached), the learned branching scorer (its candidate
+variables added to the planner's), the spin-flip symmetry of the zero-field
+energy (one spin fixed to +1, the count doubled: half the contraction work),
+counts as residues modulo 4 primes per pass plus one fused certification
+prime (counts up to 124 bits need no further pass).  One step = one call
+through the C ABI that fully
 solves one instance: network build, order lookup, search, values-only pass,
 counting pass, CRT and certification, configuration recovery.  Step i solves
 seed i mod 20; the warm-up steps solve seeds 20, 21, ...  A result counts as
@@ -593,7 +595,7 @@ def main():
                     help="skip the 16x16 leg's second run with a refined order")
     ap.add_argument("--no-ksg", action="store_true", help="skip the 40x40 King's subgraph leg")
     ap.add_argument("--no-sg16", action="store_true", help="skip the 16x16 leg")
-    ap.add_argument("--residues", type=int, default=3,
+    ap.add_argument("--residues", type=int, default=4,
                     help="residues per pass of the headline run (a further certification "
                          "prime is fused into the pass)")
     ap.add_argument("--branching", type=int, default=2,
