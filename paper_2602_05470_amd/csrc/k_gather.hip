@@ -181,6 +181,10 @@ static GatherTile choose_tile(const GatherPlan& gp) {
   int tb = 0;
   for (int j = 0; j < r_out; ++j) tb += in_t[j];
   BBTN_REQUIRE(tb <= TILE_MAX_BITS, "gather tile too large");
+  // where the two sets overlap, the next lowest output bits fill the tile
+  // up to its 12 bits: longer output runs and fewer, larger tiles
+  for (int j = 0; j < r_out && tb < TILE_MAX_BITS; ++j)
+    if (!in_t[j]) { in_t[j] = true; ++tb; }
   t.tb = tb;
   // input order of the tile's variables
   int n = 0;
