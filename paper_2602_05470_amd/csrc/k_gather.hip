@@ -158,7 +158,7 @@ __global__ void __launch_bounds__(256) gather_tiled_kernel(const GatherArgs g, c
 // enough: small outputs, or lowest output bits that already read a run of
 // at least 64 (or all) of the lowest free input entries, a whole 256-byte
 // segment per wavefront and plane.
-static GatherTile choose_tile(const GatherPlan& gp) {
+static GatherTile choose_tile(const GatherPlan& gp, int k) {
   GatherTile t{};
   const int r_out = gp.r_out;
   if (r_out < 8) return t;
@@ -182,9 +182,11 @@ static GatherTile choose_tile(const GatherPlan& gp) {
   for (int j = 0; j < r_out; ++j) tb += in_t[j];
   BBTN_REQUIRE(tb <= TILE_MAX_BITS, "gather tile too large");
   // where the two sets overlap, the next lowest output bits fill the tile
-  // up to its 12 bits: longer output runs and fewer, larger tiles
-  for (int j = 0; j < r_out && tb < TILE_MAX_BITS; ++j)
-    if (!in_t[j]) { in_t[j] = true; ++tb; }
+  // up to its 12 bits: longer output runs and fewer, larger tiles (a tile
+  // of 11 bits with three or more planes moves faster as it is)
+  if (tb <= 10 || k <= 1)
+    for (int j = 0; j < r_out && tb < TILE_MAX_BITS; ++j)
+      if (!in_t[j]) { in_t[j] = true; ++tb; }
   t.tb = tb;
   // input order of the tile's variables
   int n = 0;
@@ -225,7 +227,7 @@ void launch_gather(int k, const GatherPlan& gp, int64_t L, int64_t in_stride,
   for (int r = 0; r < gp.n_runs; ++r) g.runs[r] = gp.runs[r];
   const int64_t total = L << gp.r_out;
   if (total == 0) return;
-  const GatherTile t = choose_tile(gp);
+  const GatherTile t = choose_tile(gp, k);
   if (t.tb > 0) {
     const int64_t tiles = L << t.n_rest;
     const int64_t blocks = std::min<int64_t>(tiles, 256 * 256);
