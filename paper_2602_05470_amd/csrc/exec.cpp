@@ -100,6 +100,7 @@ TuneVal cached_or_heuristic_tiles(const bbtn_ctx* ctx, int k, int64_t batch, int
   if (M == 1 && N >= 64) tv.cfg = 5;
   else if (N == 1 && M >= 64) tv.cfg = 6;
   // measured best for counting products (four-word staging when aligned)
+  else if (k >= 5 && M >= 32 && N >= 64) tv.cfg = 12;
   else if (k >= 4 && M >= 32 && N >= 64) tv.cfg = 11;
   else if (k >= 1 && M >= 64 && N >= 32) tv.cfg = 10;
   else if (k >= 1 && M >= 32 && N >= 64) tv.cfg = 8;

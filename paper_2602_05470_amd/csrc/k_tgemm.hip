@@ -35,6 +35,8 @@ const TileCfg kTileCfgs[N_TILE_CFGS] = {
     {64, 64, 4, 4, 24},   // 9: as 0, operands staged four words at a time
     {64, 32, 4, 2, 24},   // 10: as 7, four-word staging
     {32, 64, 2, 4, 24},   // 11: as 8, four-word staging
+    {32, 64, 2, 4, 12},   // 12: as 11, 12-deep slices (half the LDS): with
+                          // four or more residues, three waves per SIMD
 };
 
 struct GemmArgs {
@@ -362,8 +364,14 @@ __device__ __forceinline__ void tgemm_tile(const GemmArgs& a, int64_t w) {
   }
 }
 
+// Waves per SIMD the compiler must leave room for: three for the 32 x 64
+// tile with 12-deep slices and four or more residues (its LDS allows five
+// workgroups per CU; its registers alone would allow two), else no bound.
+template <int KR, int TM, int TN, int TK>
+constexpr int kMinWaves = (KR >= 4 && TM == 32 && TN == 64 && TK <= 12) ? 3 : 1;
+
 template <int KR, int TM, int TN, int RM, int RN, int TK, bool VEC>
-__global__ void __launch_bounds__((TM / RM) * (TN / RN))
+__global__ void __launch_bounds__((TM / RM) * (TN / RN), (kMinWaves<KR, TM, TN, TK>))
 tgemm_kernel(const GemmArgs a) {
   tgemm_tile<KR, TM, TN, RM, RN, TK, VEC>(a, blockIdx.x);
 }
@@ -372,7 +380,7 @@ tgemm_kernel(const GemmArgs a) {
 // stride (a dispatch must stay below 2^32 work-items).  The stride is a
 // multiple of 8, so every tile a workgroup takes maps to the same XCD.
 template <int KR, int TM, int TN, int RM, int RN, int TK, bool VEC>
-__global__ void __launch_bounds__((TM / RM) * (TN / RN))
+__global__ void __launch_bounds__((TM / RM) * (TN / RN), (kMinWaves<KR, TM, TN, TK>))
 tgemm_kernel_strided(const GemmArgs a) {
   for (int64_t w = blockIdx.x; w < a.total; w += gridDim.x) {
     tgemm_tile<KR, TM, TN, RM, RN, TK, VEC>(a, w);
@@ -941,6 +949,7 @@ static void launch_cfg(int cfg, dim3 grid, const GemmArgs& a, hipStream_t st, bo
     BBTN_TG_CASE(9, 64, 64, 4, 4, 24, true)
     BBTN_TG_CASE(10, 64, 32, 4, 2, 24, true)
     BBTN_TG_CASE(11, 32, 64, 2, 4, 24, true)
+    BBTN_TG_CASE(12, 32, 64, 2, 4, 12, true)
 #undef BBTN_TG_CASE
     default:
       throw Error(BBTN_E_INTERNAL, "bad tile config");

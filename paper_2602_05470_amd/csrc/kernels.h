@@ -20,7 +20,7 @@ TimedLaunch& timed_launch();  // this host thread's slot (launch_kernel in launc
 struct TileCfg {
   int tm, tn, rm, rn, tk;
 };
-constexpr int N_TILE_CFGS = 12;
+constexpr int N_TILE_CFGS = 13;
 extern const TileCfg kTileCfgs[N_TILE_CFGS];
 
 struct GemmShape {

@@ -62,7 +62,7 @@ def _bucket(x):
     return b
 
 
-N_TILE_CFGS = 12
+N_TILE_CFGS = 13
 
 
 @pytest.mark.parametrize("cfg", range(N_TILE_CFGS))
