@@ -889,8 +889,11 @@ __device__ __forceinline__ void tgemm_v16_tile(const GemmArgs& a, int64_t w, con
   }
 }
 
+// The 64-wide tiles are held to five waves per SIMD (at most 102 registers;
+// they need about 110 unbounded, which allows four).
 template <int TM, int TN, int RM, int RN, int TK>
-__global__ void __launch_bounds__((TM / RM) * (TN / RN)) tgemm_v16_kernel(const GemmArgs a) {
+__global__ void __launch_bounds__((TM / RM) * (TN / RN), (TM < 128 ? 5 : 1))
+tgemm_v16_kernel(const GemmArgs a) {
   const FusedOp none{};
   for (int64_t w = blockIdx.x; w < a.total; w += gridDim.x) {
     tgemm_v16_tile<TM, TN, RM, RN, TK>(a, w, none, none);
@@ -899,7 +902,7 @@ __global__ void __launch_bounds__((TM / RM) * (TN / RN)) tgemm_v16_kernel(const 
 }
 
 template <int TM, int TN, int RM, int RN, int TK, bool FA, bool FB>
-__global__ void __launch_bounds__((TM / RM) * (TN / RN))
+__global__ void __launch_bounds__((TM / RM) * (TN / RN), (TM < 128 ? 5 : 1))
 tgemm_v16_fused_kernel(const GemmArgs a, const FusedOp fa, const FusedOp fb) {
   for (int64_t w = blockIdx.x; w < a.total; w += gridDim.x) {
     tgemm_v16_tile<TM, TN, RM, RN, TK, FA, FB>(a, w, fa, fb);
