@@ -160,6 +160,11 @@ def test_tgemm_rejects_bad_prime(ctx):
     dict(r_in=7, src=[0, 3, 1, 2], L=2, fixed="rand"),
     dict(r_in=8, src=[0, 1, 2, 3, 4, 5, 6, 7], L=1, fixed=None, pad=1),
     dict(r_in=8, src=[0, 1, 2, 3, 7, 6, 5], L=2, fixed="rand", shift=1),
+    # tiles whose two low-bit sets overlap: 10 bits, filled to 12 with the
+    # next lowest output bits; 11 bits, filled for one or two planes only
+    dict(r_in=14, src=[0, 1] + list(range(8, 14)) + list(range(2, 8)), L=2, fixed=None,
+         per_leaf=True),
+    dict(r_in=15, src=[0] + list(range(8, 15)) + list(range(1, 7)), L=3, fixed="rand"),
 ])
 @pytest.mark.parametrize("k", [0, 3, 4])
 def test_gather_matches_oracle(ctx, case, k):
